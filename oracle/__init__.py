@@ -1,0 +1,359 @@
+"""FP64 CPU oracle for the CT projector operators -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It shares no code with the GPU library: geometry is
+composed here with numpy, and the ray loops live in ``oracle.c`` (loaded with
+ctypes).
+
+Geometry (PYRO-NN update, Sec. 2.3 "Flexible Trajectory Modeling"): a
+projection matrix is built from the source position, the detector position
+and the detector's two (scaled) pixel directions, after Graetz's method
+cited there.  With pixel (0, 0) at world position d00,
+
+    M = [e_u | e_v | d00 - S],   P = M^-1 [I | -S],
+
+so that pixel (c, r) maps to (U, V, W) = (c, r, 1) and u = U/W, v = V/W.
+The 2-D fan-beam analogue drops the v axis; parallel beams replace the
+source by a ray direction.  The circular trajectory of Listing 1 places view
+k at angle beta_k = k * range / N (counter-clockwise about +z); this oracle
+composes each view directly rather than by an incremental rotation.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# Mutation checks of the pins load a deliberately broken build from elsewhere.
+_LIB_LOAD = os.environ.get("ORACLE_LIB_OVERRIDE") or _LIB_PATH
+_lib = None
+
+
+def build(force=True):
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc (-O2, OpenMP)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if _LIB_LOAD == _LIB_PATH and not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_LOAD)
+        lib.oracle_ray_taps.restype = ctypes.c_int64
+        _lib = lib
+    return _lib
+
+
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_F64P = ctypes.POINTER(ctypes.c_double)
+
+
+def _i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(_I64P)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_F64P)
+
+
+def max_threads():
+    return int(_load().oracle_max_threads())
+
+
+# --------------------------------------------------------------- geometry --
+
+
+def cone_matrix(S, C, eu, ev, det_shape):
+    """3x4 matrix of a flat-panel cone-beam view.
+
+    S: source, C: detector centre, eu/ev: world step per column/row (mm),
+    det_shape: (rows, cols).  Pixel (c, r) sits at
+    C + (c - (cols-1)/2) eu + (r - (rows-1)/2) ev.
+    """
+    nv, nu = det_shape
+    S, C, eu, ev = (np.asarray(a, dtype=np.float64) for a in (S, C, eu, ev))
+    d00 = C - 0.5 * (nu - 1) * eu - 0.5 * (nv - 1) * ev
+    M = np.column_stack([eu, ev, d00 - S])
+    Mi = np.linalg.inv(M)
+    return np.hstack([Mi, -(Mi @ S)[:, None]])
+
+
+def fan_matrix(S, C, eu, n_cols):
+    """2x3 matrix of a flat-detector fan-beam view (2-D analogue of cone_matrix)."""
+    S, C, eu = (np.asarray(a, dtype=np.float64) for a in (S, C, eu))
+    d0 = C - 0.5 * (n_cols - 1) * eu
+    M = np.column_stack([eu, d0 - S])
+    Mi = np.linalg.inv(M)
+    return np.hstack([Mi, -(Mi @ S)[:, None]])
+
+
+def parallel2d_matrix(direction, C, eu, n_cols):
+    """2x3 matrix of a 2-D parallel-beam view: rays along ``direction``,
+    detector axis ``eu`` (mm per bin) through the point C (the central bin)."""
+    M = np.column_stack([np.asarray(eu, float), np.asarray(direction, float)])
+    Mi = np.linalg.inv(M)
+    row = np.concatenate([Mi[0], [-(Mi[0] @ np.asarray(C, float)) + 0.5 * (n_cols - 1)]])
+    return np.vstack([row, [0.0, 0.0, 1.0]])
+
+
+def parallel3d_matrix(direction, C, eu, ev, det_shape):
+    """3x4 matrix of a 3-D parallel-beam view (last row (0, 0, 0, 1))."""
+    nv, nu = det_shape
+    M = np.column_stack([np.asarray(eu, float), np.asarray(ev, float), np.asarray(direction, float)])
+    Mi = np.linalg.inv(M)
+    C = np.asarray(C, float)
+    r0 = np.concatenate([Mi[0], [-(Mi[0] @ C) + 0.5 * (nu - 1)]])
+    r1 = np.concatenate([Mi[1], [-(Mi[1] @ C) + 0.5 * (nv - 1)]])
+    return np.vstack([r0, r1, [0.0, 0.0, 0.0, 1.0]])
+
+
+def circular_cone_vectors(n_views, angular_range, sid, sdd, det_spacing):
+    """Source, detector centre and pixel steps of a circular orbit about +z.
+
+    det_spacing = (row spacing, column spacing) in mm.  Returns four arrays
+    of shape (n_views, 3).
+    """
+    dv, du = det_spacing
+    beta = np.arange(n_views, dtype=np.float64) * (angular_range / n_views)
+    cb, sb = np.cos(beta), np.sin(beta)
+    z = np.zeros_like(beta)
+    S = np.stack([sid * cb, sid * sb, z], axis=1)
+    C = np.stack([-(sdd - sid) * cb, -(sdd - sid) * sb, z], axis=1)
+    eu = np.stack([-du * sb, du * cb, z], axis=1)
+    ev = np.stack([z, z, dv + z], axis=1)
+    return S, C, eu, ev
+
+
+def cone_geometry(vol_shape, vol_spacing, det_shape, det_spacing, P, origin=None, parallel=False):
+    """Oracle geometry dict for a 3-D problem.
+
+    vol_shape/vol_spacing/origin in (z, y, x) order (as the array axes);
+    det_shape = (rows, cols); P has shape (n_views, 3, 4).
+    """
+    nz, ny, nx = (int(v) for v in vol_shape)
+    sz, sy, sx = (float(v) for v in vol_spacing)
+    if origin is None:
+        origin = (-0.5 * (nz - 1) * sz, -0.5 * (ny - 1) * sy, -0.5 * (nx - 1) * sx)
+    return dict(
+        dims=3,
+        parallel=bool(parallel),
+        n=(nx, ny, nz),
+        s=(sx, sy, sz),
+        o=(float(origin[2]), float(origin[1]), float(origin[0])),
+        P=np.ascontiguousarray(P, dtype=np.float64).reshape(-1, 3, 4),
+        det=(int(det_shape[0]), int(det_shape[1])),
+    )
+
+
+def image_geometry(img_shape, img_spacing, n_cols, P, origin=None, parallel=False):
+    """Oracle geometry dict for a 2-D problem.
+
+    img_shape/img_spacing/origin in (y, x) order; P has shape (n_views, 2, 3).
+    """
+    ny, nx = (int(v) for v in img_shape)
+    sy, sx = (float(v) for v in img_spacing)
+    if origin is None:
+        origin = (-0.5 * (ny - 1) * sy, -0.5 * (nx - 1) * sx)
+    return dict(
+        dims=2,
+        parallel=bool(parallel),
+        n=(nx, ny, 1),
+        s=(sx, sy, 1.0),
+        o=(float(origin[1]), float(origin[0]), 0.0),
+        P=np.ascontiguousarray(P, dtype=np.float64).reshape(-1, 2, 3),
+        det=(1, int(n_cols)),
+    )
+
+
+def circular_cone(vol_shape, vol_spacing, det_shape, det_spacing, n_views, angular_range, sid, sdd):
+    S, C, eu, ev = circular_cone_vectors(n_views, angular_range, sid, sdd, det_spacing)
+    P = np.stack([cone_matrix(S[k], C[k], eu[k], ev[k], det_shape) for k in range(n_views)])
+    return cone_geometry(vol_shape, vol_spacing, det_shape, det_spacing, P)
+
+
+def circular_fan(img_shape, img_spacing, n_cols, det_spacing, n_views, angular_range, sid, sdd):
+    beta = np.arange(n_views, dtype=np.float64) * (angular_range / n_views)
+    P = []
+    for b in beta:
+        c, s = math.cos(b), math.sin(b)
+        S = np.array([sid * c, sid * s])
+        C = np.array([-(sdd - sid) * c, -(sdd - sid) * s])
+        eu = det_spacing * np.array([-s, c])
+        P.append(fan_matrix(S, C, eu, n_cols))
+    return image_geometry(img_shape, img_spacing, n_cols, np.stack(P))
+
+
+def parallel_2d(img_shape, img_spacing, n_cols, det_spacing, n_views, angular_range):
+    theta = np.arange(n_views, dtype=np.float64) * (angular_range / n_views)
+    P = []
+    for t in theta:
+        c, s = math.cos(t), math.sin(t)
+        P.append(parallel2d_matrix([c, s], [0.0, 0.0], det_spacing * np.array([-s, c]), n_cols))
+    return image_geometry(img_shape, img_spacing, n_cols, np.stack(P), parallel=True)
+
+
+def trajectory_vectors(kind, n_views, angular_range, sid, sdd, det_shape, det_spacing, vol_shape,
+                       vol_spacing, pitch=0.5, draws=None):
+    """Vectors of the non-circular trajectories of the batched workload.
+
+    helical: source and detector rise together, S_z = h (beta/2pi - 1/2)
+      with h = pitch * rows * row_spacing * SID/SDD (table feed per turn);
+    sinusoidal: S_z = A sin(2 beta), A = nz * sz / 4, detector follows;
+    perturbed: circular orbit plus the Gaussian draws ``draws`` (dS, dC in
+      mm, dphi in rad rotating the detector axes within the panel).
+    """
+    S, C, eu, ev = circular_cone_vectors(n_views, angular_range, sid, sdd, det_spacing)
+    beta = np.arange(n_views, dtype=np.float64) * (angular_range / n_views)
+    if kind == "helical":
+        h = pitch * det_shape[0] * det_spacing[0] * sid / sdd
+        dz = h * (beta / (2 * math.pi) - 0.5)
+        S[:, 2] += dz
+        C[:, 2] += dz
+    elif kind == "sinusoidal":
+        amp = vol_shape[0] * vol_spacing[0] / 4.0
+        dz = amp * np.sin(2 * beta)
+        S[:, 2] += dz
+        C[:, 2] += dz
+    elif kind == "perturbed":
+        S = S + draws["dS"]
+        C = C + draws["dC"]
+        du = np.linalg.norm(eu, axis=1)[:, None]
+        dv = np.linalg.norm(ev, axis=1)[:, None]
+        uh, vh = eu / du, ev / dv
+        cp, sp = np.cos(draws["dphi"])[:, None], np.sin(draws["dphi"])[:, None]
+        eu = du * (cp * uh + sp * vh)
+        ev = dv * (-sp * uh + cp * vh)
+    elif kind != "circular":
+        raise ValueError(kind)
+    return S, C, eu, ev
+
+
+# -------------------------------------------------------------- operators --
+
+
+def _geo_args(g):
+    n, pn = _i64(np.array(g["n"]))
+    s, ps = _f64(np.array(g["s"]))
+    o, po = _f64(np.array(g["o"]))
+    P, pP = _f64(g["P"])
+    keep = (n, s, o, P)
+    return keep, pn, ps, po, pP
+
+
+def forward(vol, g, nthreads=0):
+    """A vol.  vol: [nz][ny][nx] (2-D: [1][ny][nx]); returns [n_views][rows][cols]."""
+    lib = _load()
+    keep, pn, ps, po, pP = _geo_args(g)
+    nv, nu = g["det"]
+    nviews = g["P"].shape[0]
+    v, pv = _f64(vol)
+    assert v.size == g["n"][0] * g["n"][1] * g["n"][2]
+    out = np.zeros((nviews, nv, nu), dtype=np.float64)
+    rc = lib.oracle_forward(
+        ctypes.c_int(g["dims"]), ctypes.c_int(int(g["parallel"])), pn, ps, po, ctypes.c_int64(nviews), pP,
+        ctypes.c_int64(nv), ctypes.c_int64(nu), pv, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads))
+    if rc:
+        raise MemoryError("oracle_forward")
+    return out
+
+
+def forward_rays(vol, g, view, row, col, nthreads=0):
+    """Selected entries of A vol at (view[t], row[t], col[t])."""
+    lib = _load()
+    keep, pn, ps, po, pP = _geo_args(g)
+    v, pv = _f64(vol)
+    vw, pvw = _i64(view)
+    rw, prw = _i64(row)
+    cl, pcl = _i64(col)
+    out = np.zeros(vw.size, dtype=np.float64)
+    rc = lib.oracle_forward_rays(
+        ctypes.c_int(g["dims"]), ctypes.c_int(int(g["parallel"])), pn, ps, po, pP, pv, ctypes.c_int64(vw.size),
+        pvw, prw, pcl, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads))
+    if rc:
+        raise MemoryError("oracle_forward_rays")
+    return out
+
+
+def adjoint(sino, g, box=None, nthreads=0):
+    """A^T sino, optionally restricted to box = (i0, i1, j0, j1, k0, k1)."""
+    lib = _load()
+    keep, pn, ps, po, pP = _geo_args(g)
+    nv, nu = g["det"]
+    nviews = g["P"].shape[0]
+    sn, psn = _f64(sino)
+    assert sn.size == nviews * nv * nu
+    nx, ny, nz = g["n"]
+    if box is None:
+        box = (0, nx, 0, ny, 0, nz)
+    b, pb = _i64(np.array(box))
+    out = np.zeros((b[5] - b[4], b[3] - b[2], b[1] - b[0]), dtype=np.float64)
+    rc = lib.oracle_adjoint(
+        ctypes.c_int(g["dims"]), ctypes.c_int(int(g["parallel"])), pn, ps, po, ctypes.c_int64(nviews), pP,
+        ctypes.c_int64(nv), ctypes.c_int64(nu), psn, pb, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads))
+    if rc:
+        raise MemoryError("oracle_adjoint")
+    return out
+
+
+def backproject(sino, g, nthreads=0):
+    """Voxel-driven (W0/W)^2-weighted back-projection; returns [nz][ny][nx]."""
+    lib = _load()
+    keep, pn, ps, po, pP = _geo_args(g)
+    nv, nu = g["det"]
+    nviews = g["P"].shape[0]
+    sn, psn = _f64(sino)
+    assert sn.size == nviews * nv * nu
+    nx, ny, nz = g["n"]
+    out = np.zeros((nz, ny, nx), dtype=np.float64)
+    lib.oracle_backproject(
+        ctypes.c_int(g["dims"]), pn, ps, po, ctypes.c_int64(nviews), pP, ctypes.c_int64(nv),
+        ctypes.c_int64(nu), psn, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads))
+    return out
+
+
+def backproject_voxels(sino, g, i, j, k, nthreads=0):
+    """Back-projection at voxels (i[t], j[t], k[t]) only."""
+    lib = _load()
+    keep, pn, ps, po, pP = _geo_args(g)
+    nv, nu = g["det"]
+    nviews = g["P"].shape[0]
+    sn, psn = _f64(sino)
+    ii, pi = _i64(i)
+    jj, pj = _i64(j)
+    kk, pk = _i64(k)
+    out = np.zeros(ii.size, dtype=np.float64)
+    lib.oracle_backproject_voxels(
+        ctypes.c_int(g["dims"]), pn, ps, po, ctypes.c_int64(nviews), pP, ctypes.c_int64(nv),
+        ctypes.c_int64(nu), psn, ctypes.c_int64(ii.size), pi, pj, pk, out.ctypes.data_as(_F64P),
+        ctypes.c_int(nthreads))
+    return out
+
+
+def ray_taps(g, view, row, col):
+    """(voxel linear indices, weights*ds) of one ray: a row of the matrix A."""
+    lib = _load()
+    keep, pn, ps, po, pP = _geo_args(g)
+    cap = 4 * max(g["n"]) + 4
+    idx = np.zeros(cap, dtype=np.int64)
+    w = np.zeros(cap, dtype=np.float64)
+    psz = 6 if g["dims"] == 2 else 12
+    Pv = np.ascontiguousarray(g["P"][view].reshape(psz))
+    cnt = lib.oracle_ray_taps(
+        ctypes.c_int(g["dims"]), ctypes.c_int(int(g["parallel"])), pn, ps, po, Pv.ctypes.data_as(_F64P),
+        ctypes.c_int64(row), ctypes.c_int64(col), idx.ctypes.data_as(_I64P), w.ctypes.data_as(_F64P))
+    return idx[:cnt].copy(), w[:cnt].copy()
