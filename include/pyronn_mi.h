@@ -1,0 +1,171 @@
+/*
+ * pyronn_mi.h -- C ABI of the MI355X (gfx950) CT projector library.
+ *
+ * The library computes the three operators of the differentiable CT layer
+ * described in the PYRO-NN update (arXiv 2511.08427):
+ *
+ *   pn_forward      the ray-driven forward projection A (Sec. 2.1: one ray per
+ *                   detector pixel, absorption values summed along it).  The
+ *                   sampling rule is Joseph's: the ray is cut by every volume
+ *                   plane perpendicular to its dominant index-space axis, the
+ *                   volume is bilinearly interpolated in that plane with zero
+ *                   padding, and the sum is scaled by the ray length per plane.
+ *   pn_adjoint      the exact adjoint A^T of pn_forward (Sec. 2.2 pairs the
+ *                   forward operator A with its adjoint A^T; it is the
+ *                   analytic gradient of A, Sec. 2 and Sec. 2.3 "PyTorch
+ *                   Integration").
+ *   pn_backproject  the voxel-driven back-projection (Sec. 2.1: each voxel is
+ *                   projected onto the detector and the measured values are
+ *                   accumulated), with bilinear detector interpolation and the
+ *                   distance weight (W0/W)^2 of the FDK algorithm, where W is
+ *                   the third homogeneous coordinate of the voxel centre and
+ *                   W0 that of the world origin.
+ *
+ * Geometry follows the paper's description (Listing 1 and Sec. 2.1/2.3):
+ * volume shape and spacing, detector shape and spacing, SID/SDD, and one
+ * projection matrix per view for arbitrary trajectories (calibrated matrices
+ * from real systems are accepted as they are).  The pn_*_matrices helpers
+ * compose matrices from source/detector positions and detector directions
+ * (Sec. 2.3 "Flexible Trajectory Modeling", after Graetz).
+ *
+ * Conventions
+ *   volume    C-contiguous [batch][nz][ny][nx]; voxel (i,j,k) centre at world
+ *             (ox + i*sx, oy + j*sy, oz + k*sz) mm.  2-D images are nz = 1.
+ *   detector  C-contiguous [batch][n_views][rows][cols]; pixel (column c,
+ *             row r) has image coordinates (u, v) = (c, r).  2-D: rows = 1.
+ *   matrices  3-D: 3x4 row-major, (U,V,W) = P (x,y,z,1), u = U/W, v = V/W;
+ *             parallel beam has last row (0,0,0,w).  2-D: 2x3 row-major,
+ *             (U,W) = P (x,y,1), u = U/W; parallel beam has last row (0,0,w).
+ *             A matrix is defined up to scale; the sign is normalised so that
+ *             W > 0 over the volume.
+ *   rays      the whole line through the pixel is integrated; the library
+ *             requires the entire volume (dilated by one voxel) to lie in
+ *             front of the source, so the line and the source-detector
+ *             segment agree inside the support.
+ *
+ * Memory and streams
+ *   vol/sino/in/out pointers are DEVICE pointers owned by the caller,
+ *   C-contiguous, 4-byte aligned (2-byte for 16-bit types) and must not
+ *   alias.  pg->proj is a HOST pointer owned by the caller; it is read during
+ *   the call only.  Work is enqueued asynchronously on `hip_stream` (a
+ *   hipStream_t; NULL = the default stream).  Outputs are overwritten, never
+ *   accumulated into.  The library keeps a cache of per-geometry plans
+ *   (per-view tables and work buffers in device memory); the first call with
+ *   a new geometry allocates and uploads synchronously, later calls with an
+ *   equal geometry allocate nothing.  Two calls that use the same geometry
+ *   and operator on different streams at the same time race on that plan's
+ *   work buffers: order them on one stream.
+ *
+ * Errors
+ *   Every function returns 0 on success or a negative PN_E* code; the text of
+ *   the last error of the calling thread is returned by pn_last_error().  All
+ *   argument and geometry checks happen before anything is enqueued; a fault
+ *   inside a kernel surfaces at the caller's next synchronisation.
+ */
+#ifndef PYRONN_MI_H
+#define PYRONN_MI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* element types of volumes and sinograms (storage only; arithmetic is FP32,
+ * per-ray set-up FP64) */
+typedef enum { PN_F32 = 0, PN_BF16 = 1, PN_F16 = 2 } pn_dtype;
+
+/* beam types: 2-D accepts PN_PARALLEL and PN_FAN, 3-D PN_PARALLEL and PN_CONE */
+typedef enum { PN_PARALLEL = 0, PN_FAN = 1, PN_CONE = 2 } pn_beam;
+
+enum {
+    PN_OK = 0,
+    PN_EINVAL = -1, /* null/misaligned pointer, bad shape, size or batch */
+    PN_EDTYPE = -2, /* unknown dtype */
+    PN_EGEOM = -3,  /* non-finite or singular matrix, volume not in front of the source */
+    PN_EHIP = -4,   /* HIP runtime error (text from hipGetErrorString) */
+    PN_ENOMEM = -5  /* device or host allocation failed */
+};
+
+typedef struct {
+    int32_t ndim;           /* 2 or 3 */
+    int32_t beam;           /* pn_beam */
+    int64_t vol_shape[3];   /* nz, ny, nx (> 0; 2-D: nz = 1) */
+    double vol_spacing[3];  /* sz, sy, sx in mm (> 0; 2-D: sz ignored) */
+    double vol_origin[3];   /* z, y, x world position of voxel (0,0,0) centre;
+                               NaN in an entry centres that axis on 0 */
+    int64_t det_shape[2];   /* rows, cols (> 0; 2-D: rows = 1) */
+    double det_spacing[2];  /* row, column pixel pitch in mm (informational) */
+    double sid, sdd;        /* source-isocentre, source-detector distance (informational) */
+    int64_t n_views;        /* >= 0 */
+    const double *proj;     /* host: n_views matrices, 3x4 (3-D) or 2x3 (2-D) */
+} pn_geometry;
+
+/* One volume/sinogram pair of a batched call (batch size 1 each). */
+typedef struct {
+    pn_geometry geom;
+    const void *in;
+    void *out;
+} pn_problem;
+
+/* A: vol [batch][nz][ny][nx] (in_dtype) -> sino [batch][n_views][rows][cols]
+ * (out_dtype).  batch >= 0; batch == 0 does nothing. */
+int pn_forward(const pn_geometry *pg, int64_t batch, const void *vol, void *sino,
+               int32_t in_dtype, int32_t out_dtype, void *hip_stream);
+
+/* A^T: sino [batch][n_views][rows][cols] (in_dtype) -> vol [batch][nz][ny][nx]
+ * (out_dtype).  Exact transpose of pn_forward up to FP32 rounding. */
+int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
+               int32_t in_dtype, int32_t out_dtype, void *hip_stream);
+
+/* Voxel-driven (W0/W)^2-weighted back-projection: sino -> vol, shapes as
+ * pn_adjoint.  A 16-bit output may overflow (F16 max 65504) for many views;
+ * request PN_F32 output in that case. */
+int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
+                   int32_t in_dtype, int32_t out_dtype, void *hip_stream);
+
+/* The same operators over n independent problems of uneven sizes in one
+ * persistent launch per operator, replayed from a captured HIP graph when the
+ * same problem set (geometries and pointers) is seen again.  Each problem's
+ * result equals its single-problem call. */
+int pn_forward_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
+                       void *hip_stream);
+int pn_adjoint_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
+                       void *hip_stream);
+int pn_backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
+                           void *hip_stream);
+
+/* Host-only validation of a geometry (no device work): 0 or a PN_E* code. */
+int pn_check_geometry(const pn_geometry *pg);
+
+/* Projection-matrix composition (Sec. 2.3, after Graetz), host only, FP64.
+ * Vectors are arrays of n_views rows, world mm.  S: source, C: detector
+ * centre (the point halfway between the outermost pixel centres), eu/ev:
+ * world step from one pixel centre to the next along a row / a column.
+ * Pixel (c, r) lies at C + (c - (cols-1)/2) eu + (r - (rows-1)/2) ev, and the
+ * matrix maps it to (u, v) = (c, r).  Output P_out: n_views x 3x4 (2-D: 2x3).
+ * Returns PN_EGEOM for a degenerate view. */
+int pn_cone_matrices(int64_t n_views, const double *S, const double *C, const double *eu,
+                     const double *ev, int64_t rows, int64_t cols, double *P_out);
+int pn_fan_matrices(int64_t n_views, const double *S, const double *C, const double *eu,
+                    int64_t cols, double *P_out);
+/* parallel beams: `dir` is the ray direction instead of a source */
+int pn_parallel2d_matrices(int64_t n_views, const double *dir, const double *C, const double *eu,
+                           int64_t cols, double *P_out);
+int pn_parallel3d_matrices(int64_t n_views, const double *dir, const double *C, const double *eu,
+                           const double *ev, int64_t rows, int64_t cols, double *P_out);
+
+/* Text of the calling thread's last error ("" if none). */
+const char *pn_last_error(void);
+
+/* Frees every cached plan, work buffer and graph; the next call rebuilds. */
+int pn_release_caches(void);
+
+/* Library version string. */
+const char *pn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PYRONN_MI_H */

@@ -149,7 +149,8 @@ static void ray_2d(int parallel, const double P[6], double u, ray_t *ray)
  * dims = 2 uses linear interpolation in the single in-plane axis (nz == 1),
  * dims = 3 bilinear interpolation in the two in-plane axes.  Taps outside
  * the grid are dropped (zero padding).  Capacity needed: 4 * max(n). */
-static int64_t ray_taps(const grid_t *g, int dims, const ray_t *ray, int64_t *idx, double *w)
+static int64_t ray_taps_planes(const grid_t *g, int dims, const ray_t *ray, const int64_t *plane_box,
+                               int64_t *idx, double *w)
 {
     double xi0[3], de[3];
     for (int i = 0; i < 3; ++i) {
@@ -170,7 +171,15 @@ static int64_t ray_taps(const grid_t *g, int dims, const ray_t *ray, int64_t *id
     int b = (a == 0) ? 1 : 0;
     int c = (a == 2) ? 1 : 2;
     int64_t cnt = 0;
-    for (int64_t m = 0; m < g->n[a]; ++m) {
+    /* plane_box (i0,i1,j0,j1,k0,k1), if given, limits the planes visited to
+       those of the box along the dominant axis: a tap of plane m lies in
+       plane m, so other planes cannot reach the box */
+    int64_t m_lo = 0, m_hi = g->n[a];
+    if (plane_box) {
+        if (plane_box[2 * a] > m_lo) m_lo = plane_box[2 * a];
+        if (plane_box[2 * a + 1] < m_hi) m_hi = plane_box[2 * a + 1];
+    }
+    for (int64_t m = m_lo; m < m_hi; ++m) {
         double t = ((double)m - xi0[a]) / de[a];
         double pb = xi0[b] + t * de[b];
         double fb = floor(pb), wb = pb - fb;
@@ -205,6 +214,11 @@ static int64_t ray_taps(const grid_t *g, int dims, const ray_t *ray, int64_t *id
         }
     }
     return cnt;
+}
+
+static int64_t ray_taps(const grid_t *g, int dims, const ray_t *ray, int64_t *idx, double *w)
+{
+    return ray_taps_planes(g, dims, ray, NULL, idx, w);
 }
 
 static void make_grid(grid_t *g, const int64_t n[3], const double s[3], const double o[3])
@@ -342,7 +356,7 @@ int oracle_adjoint(int dims, int parallel, const int64_t n[3], const double s[3]
                     double q = sino[(k * nv + r) * nu + c];
                     ray_t ray;
                     pixel_ray(&g, dims, parallel, P + k * psz, r, c, &ray);
-                    int64_t cnt = ray_taps(&g, dims, &ray, idx, w);
+                    int64_t cnt = ray_taps_planes(&g, dims, &ray, box, idx, w);
                     for (int64_t t = 0; t < cnt; ++t) {
                         int64_t e = idx[t];
                         int64_t i = e % g.n[0], j = (e / g.n[0]) % g.n[1], kk = e / (g.n[0] * g.n[1]);

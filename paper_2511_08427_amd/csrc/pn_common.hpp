@@ -1,0 +1,74 @@
+// Internal types shared by the host library (pn_host.cpp) and the gfx950
+// kernels (pn_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+
+namespace pn {
+
+// Work copies of the volume used by the forward projector: one per dominant
+// axis a, laid out [batch][n_a][rows][cols] with the in-plane "slow" axis as
+// rows and the "fast" axis as columns.  a = x: rows z, cols y; a = y: rows z,
+// cols x; a = z: rows y, cols x.  Rows are padded with PADR_LO zero rows
+// before and PADR_HI after, columns with PADC zeros on each side, so every
+// bilinear tap of a position clamped to [-1, n] is addressable.
+constexpr int PADR_LO = 1;
+constexpr int PADR_HI = 2;
+constexpr int PADC = 4;
+
+// Per-view FP64 tables in volume index space (x, y, z order).  Built on the
+// host from the view's projection matrix.
+struct ViewTab {
+    double A[9];   // ray direction:      delta(u, v) = A (u, v, 1)^T
+    double B[9];   // a point on the ray: p(u, v)     = B (u, v, 1)^T
+    double Pi[12]; // projection of index coordinates: (U,V,W) = Pi (i, j, k, 1)^T
+};
+
+// Per-view FP32 table for the voxel-driven back-projection.
+struct ViewTabF {
+    float Pi[12];  // as ViewTab::Pi, rounded
+    float W0;      // W of the world origin (distance weight reference)
+    int32_t axes;  // bit a set when some ray of the view may have dominant axis a
+    float pad[2];
+};
+
+enum DType : int32_t { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2 };
+
+struct FwdParams {
+    const ViewTab *tab;
+    int32_t n_views, nu, nv, batch;
+    int32_t n[3];          // nx, ny, nz
+    double s[3];           // sx, sy, sz (mm)
+    const void *lay[3];    // work copy per dominant axis (nullptr: not built)
+    int64_t lay_item[3];   // elements per batch item of each copy
+    int64_t lay_plane[3];  // elements per plane
+    int32_t lay_row[3];    // elements per row
+    const void *vol;       // caller's volume [batch][nz][ny][nx] (fallback path)
+    void *sino;            // [batch][n_views][nv][nu]
+    int32_t tile_u, tile_v;  // ray tile (tile_u * tile_v == block size)
+    int32_t tiles_u, tiles_v;
+};
+
+struct AdjParams {
+    const ViewTab *tab;
+    const int32_t *views;  // views processed by this pass
+    int32_t n_pass_views;
+    int32_t axis;          // dominant axis handled by this pass
+    int32_t nu, nv, n_views, batch;
+    int32_t n[3];
+    double s[3];
+    const void *sino;      // [batch][n_views][nv][nu]
+    float *out;            // FP32 [batch][nz][ny][nx]
+    int32_t accumulate;    // 0: overwrite, 1: add to existing values
+    int32_t blocks_a, blocks_s, blocks_f;
+};
+
+struct BpParams {
+    const ViewTabF *tabf;
+    int32_t n_views, nu, nv, batch;
+    int32_t n[3];
+    const void *sino;
+    void *vol;
+};
+
+}  // namespace pn

@@ -1,0 +1,565 @@
+// gfx950 kernels of the CT projector library: work-copy relayout, the
+// ray-driven Joseph forward projector A, its exact adjoint A^T and the
+// voxel-driven distance-weighted back-projection.
+//
+// Arithmetic contract: per-ray set-up (direction, dominant axis, slopes,
+// entry parameters, plane range) in FP64; the per-plane loop in FP32 with
+// positions formed as fma(m, slope, offset) from the plane index m (never
+// incrementally); FP32 accumulation; round-to-nearest-even on 16-bit stores.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pn_common.hpp"
+
+namespace pn {
+
+// ------------------------------------------------------------ dtypes ----
+
+struct bf16 {
+    uint16_t bits;
+};
+using f16 = _Float16;
+
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(bf16 v) { return __uint_as_float(static_cast<uint32_t>(v.bits) << 16); }
+__device__ __forceinline__ float to_f32(f16 v) { return static_cast<float>(v); }
+
+template <typename T>
+__device__ __forceinline__ T from_f32(float f);
+template <>
+__device__ __forceinline__ float from_f32<float>(float f) { return f; }
+template <>
+__device__ __forceinline__ bf16 from_f32<bf16>(float f)
+{
+    // round to nearest, ties to even; NaN stays a (quiet) NaN
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{static_cast<uint16_t>((u >> 16) | 0x40u)};
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return bf16{static_cast<uint16_t>(u >> 16)};
+}
+template <>
+__device__ __forceinline__ f16 from_f32<f16>(float f) { return static_cast<f16>(f); }  // v_cvt_f16_f32, RNE
+
+// ------------------------------------------------------ ray set-up -------
+
+// One ray's Joseph parameters for its dominant axis `axis`: in-plane
+// positions at plane m are (fma(m, gf, bf), fma(m, gs, bs)) along the "fast"
+// and "slow" in-plane axes; [m0, m1] is a conservative plane range outside
+// which every tap is zero; ds is the ray length (mm) per plane.
+struct RaySeg {
+    int axis, m0, m1;
+    float gf, gs, bf, bs, ds;
+};
+
+__device__ __forceinline__ int fast_axis(int a) { return a == 0 ? 1 : 0; }
+__device__ __forceinline__ int slow_axis(int a) { return a == 2 ? 1 : 2; }
+
+// Narrows [lo, hi] to the planes m where b + m*g lies in [lo_pos, hi_pos].
+__device__ __forceinline__ void clip_range(double b, double g, double lo_pos, double hi_pos, double &lo, double &hi)
+{
+    if (g == 0.0) {
+        if (!(b >= lo_pos && b <= hi_pos)) { lo = 1.0; hi = 0.0; }
+        return;
+    }
+    double t0 = (lo_pos - b) / g, t1 = (hi_pos - b) / g;
+    if (t0 > t1) { double t = t0; t0 = t1; t1 = t; }
+    lo = fmax(lo, t0);
+    hi = fmin(hi, t1);
+}
+
+__device__ __forceinline__ void ray_setup(const ViewTab &t, double u, double v, const int32_t n[3],
+                                          const double s[3], RaySeg &r)
+{
+    double d[3], p[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        d[i] = fma(t.A[3 * i], u, fma(t.A[3 * i + 1], v, t.A[3 * i + 2]));
+        p[i] = fma(t.B[3 * i], u, fma(t.B[3 * i + 1], v, t.B[3 * i + 2]));
+    }
+    double ax = fabs(d[0]), ay = fabs(d[1]), az = fabs(d[2]);
+    // dominant index-space axis; exact ties go to the lowest axis
+    int a = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+    int f = fast_axis(a), sl = slow_axis(a);
+    double inv = 1.0 / d[a];
+    double gf = d[f] * inv, gs = d[sl] * inv;
+    double bf = fma(-p[a], gf, p[f]);
+    double bs = fma(-p[a], gs, p[sl]);
+    double wx = d[0] * s[0], wy = d[1] * s[1], wz = d[2] * s[2];
+    double ds = sqrt(wx * wx + wy * wy + wz * wz) * fabs(inv);
+    double lo = 0.0, hi = static_cast<double>(n[a] - 1);
+    clip_range(bf, gf, -1.0, static_cast<double>(n[f]), lo, hi);
+    clip_range(bs, gs, -1.0, static_cast<double>(n[sl]), lo, hi);
+    r.axis = a;
+    r.gf = static_cast<float>(gf);
+    r.gs = static_cast<float>(gs);
+    r.bf = static_cast<float>(bf);
+    r.bs = static_cast<float>(bs);
+    r.ds = static_cast<float>(ds);
+    if (!(lo <= hi) || !isfinite(ds)) {
+        r.m0 = 1;
+        r.m1 = 0;
+        return;
+    }
+    // one plane of slack on each side: extra planes contribute exactly zero
+    r.m0 = static_cast<int>(fmax(floor(lo), 0.0));
+    r.m1 = static_cast<int>(fmin(ceil(hi), static_cast<double>(n[a] - 1)));
+}
+
+// ------------------------------------------------------- relayout --------
+
+// a = x: out[b][i][k + PADR_LO][j + PADC] = in[b][k][j][i] (tiled transpose)
+template <typename S>
+__global__ __launch_bounds__(256) void relayout_x_kernel(const S *__restrict__ in, S *__restrict__ out, int32_t nx,
+                                                        int32_t ny, int32_t nz, int64_t out_item, int32_t out_row,
+                                                        int64_t out_plane)
+{
+    __shared__ S tile[32][33];
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int k = blockIdx.z % nz, b = blockIdx.z / nz;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const S *src = in + (static_cast<int64_t>(b) * nz + k) * ny * static_cast<int64_t>(nx);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int j = j0 + ty + 8 * q, i = i0 + tx;
+        if (j < ny && i < nx) tile[ty + 8 * q][tx] = src[static_cast<int64_t>(j) * nx + i];
+    }
+    __syncthreads();
+    S *dst = out + b * out_item + static_cast<int64_t>(k + PADR_LO) * out_row + PADC;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int i = i0 + ty + 8 * q, j = j0 + tx;
+        if (j < ny && i < nx) dst[static_cast<int64_t>(i) * out_plane + j] = tile[tx][ty + 8 * q];
+    }
+}
+
+// a = y: out[b][j][k + PADR_LO][i + PADC] = in[b][k][j][i]
+// a = z: out[b][k][j + PADR_LO][i + PADC] = in[b][k][j][i]
+template <typename S>
+__global__ __launch_bounds__(256) void relayout_rows_kernel(const S *__restrict__ in, S *__restrict__ out,
+                                                           int32_t nx, int32_t ny, int32_t nz, int32_t axis,
+                                                           int64_t out_item, int32_t out_row, int64_t out_plane)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z % nz, b = blockIdx.z / nz;
+    if (i >= nx) return;
+    S v = in[((static_cast<int64_t>(b) * nz + k) * ny + j) * nx + i];
+    int64_t o = axis == 1 ? static_cast<int64_t>(j) * out_plane + static_cast<int64_t>(k + PADR_LO) * out_row
+                          : static_cast<int64_t>(k) * out_plane + static_cast<int64_t>(j + PADR_LO) * out_row;
+    out[b * out_item + o + PADC + i] = v;
+}
+
+// ------------------------------------------------------- forward A -------
+
+template <typename S>
+__device__ __forceinline__ float sample_padded(const S *__restrict__ plane, int32_t row, float pf, float ps,
+                                               float nf, float ns)
+{
+    pf = fminf(fmaxf(pf, -1.0f), nf);
+    ps = fminf(fmaxf(ps, -1.0f), ns);
+    float ff = floorf(pf), fs = floorf(ps);
+    float wf = pf - ff, ws = ps - fs;
+    const S *q = plane + static_cast<int64_t>(static_cast<int>(fs) + PADR_LO) * row + (static_cast<int>(ff) + PADC);
+    float v00 = to_f32(q[0]), v01 = to_f32(q[1]);
+    float v10 = to_f32(q[row]), v11 = to_f32(q[row + 1]);
+    float lo = fmaf(wf, v01 - v00, v00);
+    float hi = fmaf(wf, v11 - v10, v10);
+    return fmaf(ws, hi - lo, lo);
+}
+
+template <typename S, typename O>
+__global__ __launch_bounds__(256) void forward_kernel(FwdParams p)
+{
+    const int tiles = p.tiles_u * p.tiles_v;
+    const int wg = blockIdx.x;
+    const int tile = wg % tiles;
+    const int rest = wg / tiles;
+    const int view = rest % p.n_views;
+    const int b = rest / p.n_views;
+    const int c = (tile % p.tiles_u) * p.tile_u + static_cast<int>(threadIdx.x) % p.tile_u;
+    const int r = (tile / p.tiles_u) * p.tile_v + static_cast<int>(threadIdx.x) / p.tile_u;
+    if (c >= p.nu || r >= p.nv) return;
+
+    RaySeg seg;
+    ray_setup(p.tab[view], static_cast<double>(c), static_cast<double>(r), p.n, p.s, seg);
+    float acc = 0.0f;
+    if (seg.m0 <= seg.m1) {
+        const int a = seg.axis;
+        const float nf = static_cast<float>(p.n[fast_axis(a)]);
+        const float ns = static_cast<float>(p.n[slow_axis(a)]);
+        const S *lay = static_cast<const S *>(p.lay[a]);
+        if (lay != nullptr) {
+            const S *base = lay + b * p.lay_item[a];
+            const int32_t row = p.lay_row[a];
+            const int64_t pl = p.lay_plane[a];
+            for (int m = seg.m0; m <= seg.m1; ++m) {
+                const float fm = static_cast<float>(m);
+                acc += sample_padded(base + m * pl, row, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs), nf, ns);
+            }
+        } else {
+            // no work copy for this axis: gather from the caller's layout
+            const S *vol = static_cast<const S *>(p.vol) +
+                           static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
+            const int f = fast_axis(a), sl = slow_axis(a);
+            for (int m = seg.m0; m <= seg.m1; ++m) {
+                const float fm = static_cast<float>(m);
+                float pf = fmaf(fm, seg.gf, seg.bf), ps = fmaf(fm, seg.gs, seg.bs);
+                float ff = floorf(pf), fs = floorf(ps);
+                float wf = pf - ff, ws = ps - fs;
+                int i_f = static_cast<int>(fminf(fmaxf(ff, -2.0f), 70000.0f));
+                int i_s = static_cast<int>(fminf(fmaxf(fs, -2.0f), 70000.0f));
+                for (int ts = 0; ts < 2; ++ts)
+                    for (int tf = 0; tf < 2; ++tf) {
+                        int cf = i_f + tf, cs = i_s + ts;
+                        if (cf < 0 || cf >= p.n[f] || cs < 0 || cs >= p.n[sl]) continue;
+                        int idx[3];
+                        idx[a] = m;
+                        idx[f] = cf;
+                        idx[sl] = cs;
+                        float val = to_f32(vol[(static_cast<int64_t>(idx[2]) * p.n[1] + idx[1]) * p.n[0] + idx[0]]);
+                        acc += (tf ? wf : 1.0f - wf) * (ts ? ws : 1.0f - ws) * val;
+                    }
+            }
+        }
+        acc *= seg.ds;
+    }
+    O *out = static_cast<O *>(p.sino);
+    out[((static_cast<int64_t>(b) * p.n_views + view) * p.nv + r) * p.nu + c] = from_f32<O>(acc);
+}
+
+// ------------------------------------------------------- adjoint A^T -----
+
+// Each workgroup owns a block of L planes (dominant axis `axis`) x TS rows x
+// TF columns of the output, keeps it in LDS, visits every ray of every view
+// of the pass whose samples can touch it, scatters those samples' bilinear
+// taps into LDS with ds_add_f32, and writes the block once.  No global
+// atomics; each output voxel has exactly one writer per pass.
+template <typename Q, int L, int TS, int TF>
+__global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
+{
+    __shared__ float acc[L * TS * TF];
+    const int a = p.axis, f = fast_axis(a), sl = slow_axis(a);
+    int blk = blockIdx.x;
+    const int bf_ = blk % p.blocks_f;
+    blk /= p.blocks_f;
+    const int bs_ = blk % p.blocks_s;
+    blk /= p.blocks_s;
+    const int ba_ = blk % p.blocks_a;
+    const int b = blk / p.blocks_a;
+    const int a0 = ba_ * L, a1 = min(a0 + L, p.n[a]);
+    const int s0 = bs_ * TS, s1 = min(s0 + TS, p.n[sl]);
+    const int f0 = bf_ * TF, f1 = min(f0 + TF, p.n[f]);
+
+    for (int e = threadIdx.x; e < L * TS * TF; e += blockDim.x) acc[e] = 0.0f;
+    __syncthreads();
+
+    const Q *sino_b = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
+    for (int pv = 0; pv < p.n_pass_views; ++pv) {
+        const int view = p.views[pv];
+        const ViewTab &t = p.tab[view];
+        // detector bounding box of the block dilated by one voxel in-plane
+        double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+#pragma unroll
+        for (int corner = 0; corner < 8; ++corner) {
+            double ijk[3];
+            ijk[a] = (corner & 1) ? static_cast<double>(a1 - 1) : static_cast<double>(a0);
+            ijk[sl] = (corner & 2) ? static_cast<double>(s1) : static_cast<double>(s0 - 1);
+            ijk[f] = (corner & 4) ? static_cast<double>(f1) : static_cast<double>(f0 - 1);
+            double U = t.Pi[0] * ijk[0] + t.Pi[1] * ijk[1] + t.Pi[2] * ijk[2] + t.Pi[3];
+            double V = t.Pi[4] * ijk[0] + t.Pi[5] * ijk[1] + t.Pi[6] * ijk[2] + t.Pi[7];
+            double Wc = t.Pi[8] * ijk[0] + t.Pi[9] * ijk[1] + t.Pi[10] * ijk[2] + t.Pi[11];
+            double uu = U / Wc, vv = V / Wc;
+            umin = fmin(umin, uu);
+            umax = fmax(umax, uu);
+            vmin = fmin(vmin, vv);
+            vmax = fmax(vmax, vv);
+        }
+        // clamp before converting: the bounds are finite (W > 0 over the
+        // dilated volume) but may lie far outside the detector
+        const int cu0 = static_cast<int>(fmin(fmax(floor(umin), 0.0), static_cast<double>(p.nu)));
+        const int cu1 = static_cast<int>(fmax(fmin(ceil(umax), static_cast<double>(p.nu - 1)), -1.0));
+        const int cv0 = static_cast<int>(fmin(fmax(floor(vmin), 0.0), static_cast<double>(p.nv)));
+        const int cv1 = static_cast<int>(fmax(fmin(ceil(vmax), static_cast<double>(p.nv - 1)), -1.0));
+        if (cu0 > cu1 || cv0 > cv1) continue;
+        const int wu = cu1 - cu0 + 1;
+        const int64_t ncand = static_cast<int64_t>(wu) * (cv1 - cv0 + 1);
+        const Q *sino_v = sino_b + static_cast<int64_t>(view) * p.nv * p.nu;
+        for (int64_t idx = threadIdx.x; idx < ncand; idx += blockDim.x) {
+            const int c = cu0 + static_cast<int>(idx % wu), r = cv0 + static_cast<int>(idx / wu);
+            RaySeg seg;
+            ray_setup(t, static_cast<double>(c), static_cast<double>(r), p.n, p.s, seg);
+            if (seg.axis != a || seg.m0 > seg.m1) continue;
+            // planes of this block whose sample lies in the dilated block
+            double lo = fmax(static_cast<double>(seg.m0), static_cast<double>(a0));
+            double hi = fmin(static_cast<double>(seg.m1), static_cast<double>(a1 - 1));
+            clip_range(static_cast<double>(seg.bf), static_cast<double>(seg.gf), f0 - 1.0, static_cast<double>(f1),
+                       lo, hi);
+            clip_range(static_cast<double>(seg.bs), static_cast<double>(seg.gs), s0 - 1.0, static_cast<double>(s1),
+                       lo, hi);
+            if (!(lo <= hi)) continue;
+            const int m0 = max(static_cast<int>(floor(lo)), a0);
+            const int m1 = min(static_cast<int>(ceil(hi)), a1 - 1);
+            const float q = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]) * seg.ds;
+            for (int m = m0; m <= m1; ++m) {
+                const float fm = static_cast<float>(m);
+                const float pf = fmaf(fm, seg.gf, seg.bf), ps = fmaf(fm, seg.gs, seg.bs);
+                const float ff = floorf(pf), fs = floorf(ps);
+                const float wf = pf - ff, ws = ps - fs;
+                const int lf = static_cast<int>(fminf(fmaxf(ff, -2.0f), 70000.0f)) - f0;
+                const int ls = static_cast<int>(fminf(fmaxf(fs, -2.0f), 70000.0f)) - s0;
+                const int la = m - a0;
+                const float q0 = q * (1.0f - ws), q1 = q * ws;
+                float *row0 = acc + (la * TS + ls) * TF;
+                if (ls >= 0 && ls < TS && ls + s0 < s1) {
+                    if (lf >= 0 && lf < TF && lf + f0 < f1) atomicAdd(row0 + lf, q0 * (1.0f - wf));
+                    if (lf + 1 >= 0 && lf + 1 < TF && lf + 1 + f0 < f1) atomicAdd(row0 + lf + 1, q0 * wf);
+                }
+                if (ls + 1 >= 0 && ls + 1 < TS && ls + 1 + s0 < s1) {
+                    float *row1 = row0 + TF;
+                    if (lf >= 0 && lf < TF && lf + f0 < f1) atomicAdd(row1 + lf, q1 * (1.0f - wf));
+                    if (lf + 1 >= 0 && lf + 1 < TF && lf + 1 + f0 < f1) atomicAdd(row1 + lf + 1, q1 * wf);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // write the block; the memory-contiguous axis x runs fastest
+    const int na = a1 - a0, ns = s1 - s0, nf = f1 - f0;
+    const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
+    float *out = p.out + b * item;
+    for (int e = threadIdx.x; e < na * ns * nf; e += blockDim.x) {
+        int la, ls, lf;
+        if (a == 0) {  // x = a
+            la = e % na;
+            lf = (e / na) % nf;
+            ls = e / (na * nf);
+        } else {       // x = f
+            lf = e % nf;
+            la = (e / nf) % na;
+            ls = e / (nf * na);
+        }
+        int ijk[3];
+        ijk[a] = a0 + la;
+        ijk[sl] = s0 + ls;
+        ijk[f] = f0 + lf;
+        const int64_t o = (static_cast<int64_t>(ijk[2]) * p.n[1] + ijk[1]) * p.n[0] + ijk[0];
+        const float v = acc[(la * TS + ls) * TF + lf];
+        out[o] = p.accumulate ? out[o] + v : v;
+    }
+}
+
+// ------------------------------------------------ back-projection --------
+
+template <typename Q, typename O>
+__global__ __launch_bounds__(256) void backproject_kernel(BpParams p)
+{
+    const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (e >= item) return;
+    const int i = static_cast<int>(e % p.n[0]);
+    const int j = static_cast<int>((e / p.n[0]) % p.n[1]);
+    const int k = static_cast<int>(e / (static_cast<int64_t>(p.n[0]) * p.n[1]));
+    const float fi = static_cast<float>(i), fj = static_cast<float>(j), fk = static_cast<float>(k);
+    const Q *sino = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
+    float acc = 0.0f;
+    for (int view = 0; view < p.n_views; ++view) {
+        const ViewTabF &t = p.tabf[view];
+        const float U = fmaf(t.Pi[0], fi, fmaf(t.Pi[1], fj, fmaf(t.Pi[2], fk, t.Pi[3])));
+        const float V = fmaf(t.Pi[4], fi, fmaf(t.Pi[5], fj, fmaf(t.Pi[6], fk, t.Pi[7])));
+        const float Wc = fmaf(t.Pi[8], fi, fmaf(t.Pi[9], fj, fmaf(t.Pi[10], fk, t.Pi[11])));
+        const float rw = 1.0f / Wc;
+        const float u = U * rw, v = V * rw;
+        const float w = t.W0 * rw;
+        const float fu = floorf(u), fv = floorf(v);
+        const float wu = u - fu, wv = v - fv;
+        const int iu = static_cast<int>(fmaxf(fminf(fu, 1e9f), -2.0f));
+        const int iv = static_cast<int>(fmaxf(fminf(fv, 1e9f), -2.0f));
+        const Q *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
+        float v00 = 0.f, v01 = 0.f, v10 = 0.f, v11 = 0.f;
+        const bool c0 = iu >= 0 && iu < p.nu, c1 = iu + 1 >= 0 && iu + 1 < p.nu;
+        if (iv >= 0 && iv < p.nv) {
+            const Q *row = img + static_cast<int64_t>(iv) * p.nu;
+            if (c0) v00 = to_f32(row[iu]);
+            if (c1) v01 = to_f32(row[iu + 1]);
+        }
+        if (iv + 1 >= 0 && iv + 1 < p.nv) {
+            const Q *row = img + static_cast<int64_t>(iv + 1) * p.nu;
+            if (c0) v10 = to_f32(row[iu]);
+            if (c1) v11 = to_f32(row[iu + 1]);
+        }
+        const float lo = fmaf(wu, v01 - v00, v00);
+        const float hi = fmaf(wu, v11 - v10, v10);
+        acc = fmaf(w * w, fmaf(wv, hi - lo, lo), acc);
+    }
+    O *out = static_cast<O *>(p.vol);
+    out[b * item + e] = from_f32<O>(acc);
+}
+
+// ------------------------------------------------------- utilities -------
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t *__restrict__ dst, int64_t n_words)
+{
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n_words;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dst[e] = 0u;
+}
+
+__global__ void fill_zero_bytes_kernel(uint8_t *__restrict__ dst, int32_t n)
+{
+    if (static_cast<int32_t>(threadIdx.x) < n) dst[threadIdx.x] = 0u;
+}
+
+template <typename O>
+__global__ __launch_bounds__(256) void convert_kernel(const float *__restrict__ src, O *__restrict__ dst, int64_t n)
+{
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dst[e] = from_f32<O>(src[e]);
+}
+
+// ----------------------------------------------------------- launchers ---
+
+template <typename S>
+static hipError_t relayout_t(const void *in, void *out, const int32_t n[3], int axis, int32_t batch, int64_t item,
+                             int32_t row, int64_t plane, hipStream_t st)
+{
+    // grid.z carries (item, z); launch in batch chunks so that it stays <= 65535
+    const int32_t chunk = n[2] > 65535 ? 1 : 65535 / n[2];
+    for (int32_t b0 = 0; b0 < batch; b0 += chunk) {
+        const int32_t nb = batch - b0 < chunk ? batch - b0 : chunk;
+        const S *src = static_cast<const S *>(in) + static_cast<int64_t>(b0) * n[0] * n[1] * static_cast<int64_t>(n[2]);
+        S *dst = static_cast<S *>(out) + b0 * item;
+        if (axis == 0) {
+            dim3 grid((n[0] + 31) / 32, (n[1] + 31) / 32, n[2] * nb);
+            relayout_x_kernel<S><<<grid, 256, 0, st>>>(src, dst, n[0], n[1], n[2], item, row, plane);
+        } else {
+            dim3 grid((n[0] + 255) / 256, n[1], n[2] * nb);
+            relayout_rows_kernel<S><<<grid, 256, 0, st>>>(src, dst, n[0], n[1], n[2], axis, item, row, plane);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32_t n[3], int axis, int32_t batch,
+                           int64_t item, int32_t row, int64_t plane, hipStream_t st)
+{
+    switch (dtype) {
+    case DT_F32: return relayout_t<float>(in, out, n, axis, batch, item, row, plane, st);
+    case DT_BF16: return relayout_t<bf16>(in, out, n, axis, batch, item, row, plane, st);
+    default: return relayout_t<f16>(in, out, n, axis, batch, item, row, plane, st);
+    }
+}
+
+template <typename S, typename O>
+static hipError_t forward_t(const FwdParams &p, hipStream_t st)
+{
+    const int64_t blocks = static_cast<int64_t>(p.tiles_u) * p.tiles_v * p.n_views * p.batch;
+    forward_kernel<S, O><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+    return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t forward_s(const FwdParams &p, int32_t out_dt, hipStream_t st)
+{
+    switch (out_dt) {
+    case DT_F32: return forward_t<S, float>(p, st);
+    case DT_BF16: return forward_t<S, bf16>(p, st);
+    default: return forward_t<S, f16>(p, st);
+    }
+}
+
+hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    switch (in_dt) {
+    case DT_F32: return forward_s<float>(p, out_dt, st);
+    case DT_BF16: return forward_s<bf16>(p, out_dt, st);
+    default: return forward_s<f16>(p, out_dt, st);
+    }
+}
+
+void adjoint_block_shape(bool two_d, int32_t &L, int32_t &TS, int32_t &TF)
+{
+    if (two_d) { L = 64; TS = 1; TF = 128; }
+    else { L = 32; TS = 16; TF = 16; }
+}
+
+template <typename Q>
+static hipError_t adjoint_q(const AdjParams &p, bool two_d, hipStream_t st)
+{
+    const int64_t blocks = static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch;
+    if (two_d)
+        adjoint_kernel<Q, 64, 1, 128><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+    else
+        adjoint_kernel<Q, 32, 16, 16><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, bool two_d, hipStream_t st)
+{
+    switch (in_dt) {
+    case DT_F32: return adjoint_q<float>(p, two_d, st);
+    case DT_BF16: return adjoint_q<bf16>(p, two_d, st);
+    default: return adjoint_q<f16>(p, two_d, st);
+    }
+}
+
+template <typename Q, typename O>
+static hipError_t bp_t(const BpParams &p, hipStream_t st)
+{
+    const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
+    dim3 grid(static_cast<uint32_t>((item + 255) / 256), static_cast<uint32_t>(p.batch));
+    backproject_kernel<Q, O><<<grid, 256, 0, st>>>(p);
+    return hipGetLastError();
+}
+
+template <typename Q>
+static hipError_t bp_q(const BpParams &p, int32_t out_dt, hipStream_t st)
+{
+    switch (out_dt) {
+    case DT_F32: return bp_t<Q, float>(p, st);
+    case DT_BF16: return bp_t<Q, bf16>(p, st);
+    default: return bp_t<Q, f16>(p, st);
+    }
+}
+
+hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    switch (in_dt) {
+    case DT_F32: return bp_q<float>(p, out_dt, st);
+    case DT_BF16: return bp_q<bf16>(p, out_dt, st);
+    default: return bp_q<f16>(p, out_dt, st);
+    }
+}
+
+hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st)
+{
+    const int64_t words = bytes / 4;
+    if (words > 0) {
+        int64_t blocks = (words + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        fill_zero_kernel<<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(static_cast<uint32_t *>(dst), words);
+    }
+    if (bytes % 4)  // a trailing 16-bit element (odd count of 16-bit values)
+        fill_zero_bytes_kernel<<<1, 64, 0, st>>>(static_cast<uint8_t *>(dst) + words * 4,
+                                                 static_cast<int32_t>(bytes % 4));
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    if (out_dt == DT_BF16)
+        convert_kernel<bf16><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(src, static_cast<bf16 *>(dst), n);
+    else if (out_dt == DT_F16)
+        convert_kernel<f16><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(src, static_cast<f16 *>(dst), n);
+    else
+        convert_kernel<float><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(src, static_cast<float *>(dst), n);
+    return hipGetLastError();
+}
+
+}  // namespace pn

@@ -1,0 +1,210 @@
+"""PyTorch-facing operators (PYRO-NN update, Sec. 2.3 "PyTorch Integration").
+
+Torch supplies device memory and the current stream; every operator is one
+call into the native library, which runs the gfx950 kernels:
+
+  forward(vol, geom)      A     -> pn_forward
+  adjoint(sino, geom)     A^T   -> pn_adjoint
+  backproject(sino, geom)       -> pn_backproject (voxel-driven, (W0/W)^2)
+
+``Projection`` is the autograd pair: its backward is the exact adjoint
+kernel, so gradients of any loss of A x are analytic (Sec. 2).  The layer
+classes mirror the paper's naming (Listing 1).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native as N
+from .geometry import Geometry
+
+_DT = {torch.float32: N.PN_F32, torch.bfloat16: N.PN_BF16, torch.float16: N.PN_F16}
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _prep(t, name, tail):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU (the operators have no CPU implementation)")
+    if t.dtype not in _DT:
+        raise TypeError(f"{name}: unsupported dtype {t.dtype} (float32, bfloat16, float16)")
+    batched = t.dim() == len(tail) + 1
+    if not batched and t.dim() != len(tail):
+        raise ValueError(f"{name}: expected shape [B,]{list(tail)}, got {list(t.shape)}")
+    if tuple(t.shape[-len(tail):]) != tuple(tail):
+        raise ValueError(f"{name}: expected trailing shape {list(tail)}, got {list(t.shape)}")
+    t = t.contiguous()
+    tb = t if batched else t.unsqueeze(0)
+    return tb, batched
+
+
+def _run(fn, where, geom: Geometry, src, src_tail, dst_tail, out_dtype):
+    x, batched = _prep(src, where, src_tail)
+    out_dtype = out_dtype or x.dtype
+    if out_dtype not in _DT:
+        raise TypeError(f"unsupported output dtype {out_dtype}")
+    out = torch.empty((x.shape[0],) + tuple(dst_tail), dtype=out_dtype, device=x.device)
+    with torch.cuda.device(x.device):
+        rc = fn(geom.c_struct(), x.shape[0], ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                _DT[x.dtype], _DT[out_dtype], _stream(x.device))
+    N.check(rc, where)
+    return out if batched else out[0]
+
+
+def forward(vol, geom: Geometry, out_dtype=None):
+    """A vol: [B,]nz,ny,nx -> [B,]n_views,rows,cols (ray-driven Joseph)."""
+    return _run(N.lib.pn_forward, "pn_forward", geom, vol, geom.vol_shape, geom.sino_shape(), out_dtype)
+
+
+def adjoint(sino, geom: Geometry, out_dtype=None):
+    """A^T sino: [B,]n_views,rows,cols -> [B,]nz,ny,nx (exact adjoint of forward)."""
+    return _run(N.lib.pn_adjoint, "pn_adjoint", geom, sino, geom.sino_shape(), geom.vol_shape, out_dtype)
+
+
+def backproject(sino, geom: Geometry, out_dtype=None):
+    """Voxel-driven (W0/W)^2-weighted back-projection: sino -> volume."""
+    return _run(N.lib.pn_backproject, "pn_backproject", geom, sino, geom.sino_shape(), geom.vol_shape, out_dtype)
+
+
+def _batched(fn, where, pairs, src_tail_of, dst_tail_of, out_dtype):
+    """pairs: list of (tensor, geometry), one problem each (no batch axis)."""
+    if not pairs:
+        return []
+    dts = {t.dtype for t, _ in pairs}
+    devs = {t.device for t, _ in pairs}
+    if len(dts) != 1 or len(devs) != 1:
+        raise ValueError(f"{where}: all problems must share dtype and device")
+    dt = dts.pop()
+    dev = devs.pop()
+    out_dtype = out_dtype or dt
+    probs = (N.PnProblem * len(pairs))()
+    keep, outs = [], []
+    for i, (t, g) in enumerate(pairs):
+        x, batched = _prep(t, where, src_tail_of(g))
+        if batched:
+            raise ValueError(f"{where}: batched problems take one volume/sinogram each")
+        o = torch.empty(dst_tail_of(g), dtype=out_dtype, device=dev)
+        probs[i].geom = g.c_struct()
+        probs[i].in_ = x.data_ptr()
+        probs[i].out = o.data_ptr()
+        keep.append(x)
+        outs.append(o)
+    with torch.cuda.device(dev):
+        rc = fn(probs, len(pairs), _DT[dt], _DT[out_dtype], _stream(dev))
+    N.check(rc, where)
+    return outs
+
+
+def forward_batched(pairs, out_dtype=None):
+    return _batched(N.lib.pn_forward_batched, "pn_forward_batched", pairs, lambda g: g.vol_shape,
+                    lambda g: g.sino_shape(), out_dtype)
+
+
+def adjoint_batched(pairs, out_dtype=None):
+    return _batched(N.lib.pn_adjoint_batched, "pn_adjoint_batched", pairs, lambda g: g.sino_shape(),
+                    lambda g: g.vol_shape, out_dtype)
+
+
+def backproject_batched(pairs, out_dtype=None):
+    return _batched(N.lib.pn_backproject_batched, "pn_backproject_batched", pairs, lambda g: g.sino_shape(),
+                    lambda g: g.vol_shape, out_dtype)
+
+
+# --------------------------------------------------------------- autograd --
+
+
+class Projection(torch.autograd.Function):
+    """y = A x; dL/dx = A^T dL/dy (the adjoint kernel)."""
+
+    @staticmethod
+    def forward(ctx, vol, geom):
+        ctx.geom = geom
+        ctx.vol_dtype = vol.dtype
+        return forward(vol, geom)
+
+    @staticmethod
+    def backward(ctx, grad):
+        return adjoint(grad.contiguous(), ctx.geom, out_dtype=ctx.vol_dtype), None
+
+
+class AdjointProjection(torch.autograd.Function):
+    """x = A^T y; dL/dy = A dL/dx."""
+
+    @staticmethod
+    def forward(ctx, sino, geom):
+        ctx.geom = geom
+        ctx.sino_dtype = sino.dtype
+        return adjoint(sino, geom)
+
+    @staticmethod
+    def backward(ctx, grad):
+        return forward(grad.contiguous(), ctx.geom, out_dtype=ctx.sino_dtype), None
+
+
+class _BackProjection(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sino, geom):
+        return backproject(sino, geom)
+
+    @staticmethod
+    def backward(ctx, grad):
+        raise NotImplementedError(
+            "the gradient of the voxel-driven back-projection (a voxel-driven splat projector) is not "
+            "implemented; use AdjointProjection for a differentiable A^T")
+
+
+class _Layer(torch.nn.Module):
+    def __init__(self, geom: Geometry):
+        super().__init__()
+        self.geom = geom
+
+
+class ParallelProjection2D(_Layer):
+    def forward(self, x):
+        return Projection.apply(x, self.geom)
+
+
+class FanProjection2D(_Layer):
+    def forward(self, x):
+        return Projection.apply(x, self.geom)
+
+
+class ConeProjection3D(_Layer):
+    def forward(self, x):
+        return Projection.apply(x, self.geom)
+
+
+class ParallelBackProjection2D(_Layer):
+    def forward(self, y):
+        return _BackProjection.apply(y, self.geom)
+
+
+class FanBackProjection2D(_Layer):
+    def forward(self, y):
+        return _BackProjection.apply(y, self.geom)
+
+
+class ConeBackProjection3D(_Layer):
+    def forward(self, y):
+        return _BackProjection.apply(y, self.geom)
+
+
+def unrolled_gd(x0, y, geom: Geometry, alpha: float, steps: int, checkpoint: bool = True):
+    """``steps`` gradient steps x <- x - alpha A^T (A x - y) on 0.5||Ax - y||^2,
+    differentiable end to end.  With ``checkpoint`` each step's activations
+    are recomputed in the backward pass instead of stored."""
+    import torch.utils.checkpoint as cp
+
+    def step(x):
+        return x - alpha * AdjointProjection.apply(Projection.apply(x, geom) - y, geom)
+
+    x = x0
+    for _ in range(steps):
+        x = cp.checkpoint(step, x, use_reentrant=False) if checkpoint else step(x)
+    return x

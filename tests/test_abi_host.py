@@ -1,0 +1,162 @@
+"""Host-side checks of the C-ABI library that need no GPU: the library loads,
+exports every symbol the header declares, validates arguments and geometry
+before touching the device, and composes projection matrices that agree
+with the oracle's independent composition."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pn():
+    import paper_2511_08427_amd as pn
+
+    return pn
+
+
+@pytest.fixture(scope="module")
+def N(pn):
+    from paper_2511_08427_amd import _native
+
+    return _native
+
+
+def test_library_exports_every_header_symbol(N):
+    hdr = open(os.path.join(ROOT, "include", "pyronn_mi.h")).read()
+    declared = set(re.findall(r"\b(pn_[a-z0-9_]+)\s*\(", hdr))
+    assert declared == set(N.EXPORTS)
+    for name in declared:
+        assert hasattr(N.lib, name), name
+    assert N.lib.pn_version().decode().startswith("pyronn_mi")
+
+
+def _cone(pn, **kw):
+    args = dict(vol_shape=(16, 18, 20), vol_spacing=(1.0, 1.0, 1.0), det_shape=(24, 30), det_spacing=(1.5, 1.5),
+                n_views=8, sid=200.0, sdd=320.0)
+    args.update(kw)
+    return pn.cone_geometry(**args)
+
+
+def _rc(N, geom):
+    return N.lib.pn_check_geometry(geom.c_struct())
+
+
+def test_valid_geometries_pass(pn, N):
+    assert _rc(N, _cone(pn)) == 0
+    assert _rc(N, pn.fan_geometry((64, 60), (0.5, 0.5), 100, 0.5, 12, 300.0, 450.0)) == 0
+    assert _rc(N, pn.parallel_geometry((64, 64), (1.0, 1.0), 95, 1.0, 90)) == 0
+
+
+def test_geometry_errors(pn, N):
+    g = _cone(pn)
+    assert N.lib.pn_check_geometry(None) == N.PN_EINVAL
+    # bad ndim / beam
+    c = g.c_struct()
+    for field, bad in (("ndim", 4), ("beam", 7)):
+        old = getattr(c, field)
+        setattr(c, field, bad)
+        assert N.lib.pn_check_geometry(c) == N.PN_EINVAL
+        setattr(c, field, old)
+    # zero shape
+    old = c.vol_shape[1]
+    c.vol_shape[1] = 0
+    assert N.lib.pn_check_geometry(c) == N.PN_EINVAL
+    c.vol_shape[1] = old
+    # negative spacing
+    old = c.vol_spacing[2]
+    c.vol_spacing[2] = -1.0
+    assert N.lib.pn_check_geometry(c) == N.PN_EINVAL
+    assert "vol_spacing" in N.last_error()
+    c.vol_spacing[2] = old
+    assert N.lib.pn_check_geometry(c) == 0
+    # non-finite matrix entry
+    bad = pn.Geometry(3, "cone", g.vol_shape, g.vol_spacing, g.det_shape, g.matrices.copy())
+    bad.matrices[3, 1, 2] = math.nan
+    assert _rc(N, bad) == N.PN_EGEOM and "non-finite" in N.last_error()
+    # singular matrix
+    sing = pn.Geometry(3, "cone", g.vol_shape, g.vol_spacing, g.det_shape, g.matrices.copy())
+    sing.matrices[0, 2, :3] = sing.matrices[0, 0, :3]
+    assert _rc(N, sing) == N.PN_EGEOM and "singular" in N.last_error()
+    # source inside the volume: SID smaller than the volume half-diagonal
+    inside = _cone(pn, sid=5.0, sdd=50.0)
+    assert _rc(N, inside) == N.PN_EGEOM and "front of the source" in N.last_error()
+    # parallel beam with a perspective last row
+    par = pn.parallel_geometry((8, 8), (1.0, 1.0), 11, 1.0, 4)
+    persp = pn.Geometry(2, "parallel", par.vol_shape, par.vol_spacing, par.det_shape, par.matrices.copy())
+    persp.matrices[1, 1, 0] = 0.3
+    assert _rc(N, persp) == N.PN_EGEOM
+    # 2-D with nz != 1
+    two = pn.Geometry(2, "fan", (2, 8, 8), (1.0, 1.0, 1.0), (1, 11), par.matrices.copy())
+    assert _rc(N, two) == N.PN_EINVAL
+
+
+def test_entry_points_validate_before_device_work(pn, N):
+    g = _cone(pn).c_struct()
+    vp = ctypes.c_void_p
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.cast(buf, vp)
+    q = ctypes.cast(ctypes.byref(buf, 32), vp)
+    for fn in (N.lib.pn_forward, N.lib.pn_adjoint, N.lib.pn_backproject):
+        assert fn(g, 1, p, q, 9, 0, None) == N.PN_EDTYPE
+        assert fn(g, 1, p, q, 0, -1, None) == N.PN_EDTYPE
+        assert fn(g, 1, None, q, 0, 0, None) == N.PN_EINVAL
+        assert fn(g, 1, p, None, 0, 0, None) == N.PN_EINVAL
+        assert fn(g, -2, p, q, 0, 0, None) == N.PN_EINVAL
+        assert fn(g, 1, p, p, 0, 0, None) == N.PN_EINVAL
+        assert "alias" in N.last_error()
+        mis = ctypes.c_void_p(ctypes.cast(buf, vp).value + 2)
+        assert fn(g, 1, mis, q, 0, 0, None) == N.PN_EINVAL
+        assert fn(g, 0, None, None, 0, 0, None) == 0  # empty batch: nothing to do
+    probs = (N.PnProblem * 1)()
+    assert N.lib.pn_forward_batched(probs, -1, 0, 0, None) == N.PN_EINVAL
+    assert N.lib.pn_forward_batched(None, 3, 0, 0, None) == N.PN_EINVAL
+    assert N.lib.pn_forward_batched(probs, 0, 0, 0, None) == 0
+
+
+def test_matrix_composition_matches_oracle(pn, oracle_lib):
+    O = oracle_lib
+    g = pn.cone_geometry((32, 32, 32), (0.5, 0.5, 0.5), (40, 48), (1.0, 0.9), 17, 750.0, 1200.0)
+    go = O.circular_cone((32, 32, 32), (0.5, 0.5, 0.5), (40, 48), (1.0, 0.9), 17, 2 * math.pi, 750.0, 1200.0)
+    assert np.abs(g.matrices - go["P"]).max() <= 1e-13 * np.abs(go["P"]).max()
+    gf = pn.fan_geometry((30, 40), (0.5, 0.6), 101, 0.5, 13, 1000.0, 1500.0)
+    gof = O.circular_fan((30, 40), (0.5, 0.6), 101, 0.5, 13, 2 * math.pi, 1000.0, 1500.0)
+    assert np.abs(gf.matrices - gof["P"]).max() <= 1e-13 * np.abs(gof["P"]).max()
+    gp = pn.parallel_geometry((64, 64), (1.0, 1.0), 95, 1.0, 90)
+    gop = O.parallel_2d((64, 64), (1.0, 1.0), 95, 1.0, 90, math.pi)
+    assert np.abs(gp.matrices - gop["P"]).max() <= 1e-13
+    # the non-circular trajectories of the batched workload
+    import workloads as W
+
+    draws = W.perturbation_draws(9, 23)
+    for kind in ("helical", "sinusoidal", "perturbed"):
+        args = (kind, 23, 2 * math.pi, 750.0, 1200.0, (64, 64), (2.0, 2.0), (48, 48, 48), (1.0, 1.0, 1.0))
+        S, C, eu, ev = pn.trajectory_vectors(*args, pitch=0.5, draws=draws)
+        So, Co, euo, evo = O.trajectory_vectors(*args, pitch=0.5, draws=draws)
+        for a, b in ((S, So), (C, Co), (eu, euo), (ev, evo)):
+            assert np.abs(a - b).max() < 1e-12
+        P = pn.cone_matrices(S, C, eu, ev, (64, 64))
+        Po = np.stack([O.cone_matrix(So[k], Co[k], euo[k], evo[k], (64, 64)) for k in range(23)])
+        assert np.abs(P - Po).max() <= 1e-12 * np.abs(Po).max()
+    d = np.array([[0.3, 0.9, 0.1]])
+    P3 = pn.parallel3d_matrices(d, [[1.0, 2.0, 0.5]], [[0.0, 1.0, 0.2]], [[0.1, 0.0, 1.0]], (5, 7))
+    P3o = O.parallel3d_matrix(d[0], [1.0, 2.0, 0.5], [0.0, 1.0, 0.2], [0.1, 0.0, 1.0], (5, 7))
+    assert np.abs(P3[0] - P3o).max() < 1e-13
+
+
+def test_degenerate_vectors_rejected(pn, N):
+    with pytest.raises(N.PnError):
+        pn.cone_matrices([[0, 0, 0]], [[1, 0, 0]], [[0, 1, 0]], [[0, 2, 0]], (4, 4))
+
+
+def test_no_cpu_fallback(pn):
+    import torch
+
+    g = pn.parallel_geometry((8, 8), (1.0, 1.0), 11, 1.0, 4)
+    with pytest.raises(ValueError, match="GPU"):
+        pn.forward(torch.zeros(1, 8, 8), g)

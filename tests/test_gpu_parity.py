@@ -1,0 +1,337 @@
+"""GPU parity: the HIP kernels (through the C ABI) against the FP64 oracle.
+
+Tolerance: relative L2 <= 1e-5 for FP32 storage (the expected FP32
+rounding error of ray sums of a few hundred samples is ~1e-6), <= 1e-2 for
+BF16/FP16 storage.  Relative L2 is ||g - o|| / ||o|| in FP64 on the host.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL16 = 1e-2
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pn():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2511_08427_amd as pn
+
+    return pn
+
+
+def rel(g, o):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    return float(np.linalg.norm((g - o).ravel()) / max(np.linalg.norm(o.ravel()), 1e-300))
+
+
+def cpu(t):
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def gpu(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(dtype)
+
+
+# --------------------------------------------------------------- cases ----
+
+
+def make_case(pn, name):
+    """Returns (product geometry, oracle geometry, batch of FP64 volumes)."""
+    if name == "parallel2d_64":
+        gp = pn.parallel_geometry((64, 64), (1.0, 1.0), 95, 1.0, 90)
+        go = O.parallel_2d((64, 64), (1.0, 1.0), 95, 1.0, 90, math.pi)
+        vols = [W.ellipse_phantom_2d(1)[0]]
+    elif name == "fan2d_ragged":
+        gp = pn.fan_geometry((100, 90), (0.5, 0.5), 150, 0.5, 96, 1000.0, 1500.0)
+        go = O.circular_fan((100, 90), (0.5, 0.5), 150, 0.5, 96, 2 * math.pi, 1000.0, 1500.0)
+        vols = [W.ellipse_phantom_2d(s, (100, 90), (0.5, 0.5))[0] for s in (2, 3, 4)]
+    elif name == "cone3d_ragged":
+        shp, sp, det, ds = (36, 44, 40), (0.5, 0.5, 0.5), (37, 45), (1.0, 1.0)
+        gp = pn.cone_geometry(shp, sp, det, ds, 30, 750.0, 1200.0)
+        go = O.circular_cone(shp, sp, det, ds, 30, 2 * math.pi, 750.0, 1200.0)
+        vols = [W.ellipsoid_phantom_3d(3, shp, sp)[0]]
+    elif name == "cone3d_anisotropic":
+        shp, sp, det, ds = (20, 33, 29), (0.7, 0.5, 0.6), (30, 41), (0.9, 1.1)
+        gp = pn.cone_geometry(shp, sp, det, ds, 17, 300.0, 500.0, angular_range=1.7 * math.pi)
+        go = O.circular_cone(shp, sp, det, ds, 17, 1.7 * math.pi, 300.0, 500.0)
+        vols = [W.ellipsoid_phantom_3d(8, shp, sp, 6)[0] for _ in range(2)]
+    elif name in ("cone3d_perturbed", "cone3d_helical", "cone3d_sinusoidal"):
+        kind = name.split("_")[1]
+        shp, sp, det, ds, nv = (40, 40, 40), (0.8, 0.8, 0.8), (48, 48), (1.6, 1.6), 41
+        draws = W.perturbation_draws(77, nv)
+        S, C, eu, ev = pn.trajectory_vectors(kind, nv, 2 * math.pi, 750.0, 1200.0, det, ds, shp, sp, 0.5, draws)
+        gp = pn.Geometry(3, "cone", shp, sp, det, pn.cone_matrices(S, C, eu, ev, det), ds)
+        So, Co, euo, evo = O.trajectory_vectors(kind, nv, 2 * math.pi, 750.0, 1200.0, det, ds, shp, sp, 0.5, draws)
+        Po = np.stack([O.cone_matrix(So[k], Co[k], euo[k], evo[k], det) for k in range(nv)])
+        go = O.cone_geometry(shp, sp, det, ds, Po)
+        vols = [W.ellipsoid_phantom_3d(404, shp, sp)[0]]
+    elif name == "cone3d_parallel_beam":
+        shp, sp, det = (18, 21, 23), (1.0, 0.9, 1.1), (20, 26)
+        ts = np.linspace(0.1, 3.0, 11)
+        d = np.stack([np.cos(ts), np.sin(ts), 0.25 * np.ones_like(ts)], 1)
+        eu = np.stack([-np.sin(ts), np.cos(ts), np.zeros_like(ts)], 1)
+        ev = np.tile([0.0, -0.2, 1.0], (11, 1))
+        C = np.zeros((11, 3))
+        gp = pn.Geometry(3, "parallel", shp, sp, det, pn.parallel3d_matrices(d, C, eu, ev, det))
+        Po = np.stack([O.parallel3d_matrix(d[k], C[k], eu[k], ev[k], det) for k in range(11)])
+        go = O.cone_geometry(shp, sp, det, (1.0, 1.0), Po, parallel=True)
+        vols = [W.ellipsoid_phantom_3d(12, shp, sp, 5)[0]]
+    else:
+        raise KeyError(name)
+    return gp, go, vols
+
+
+CASES = ["parallel2d_64", "fan2d_ragged", "cone3d_ragged", "cone3d_anisotropic", "cone3d_perturbed",
+         "cone3d_helical", "cone3d_sinusoidal", "cone3d_parallel_beam"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_forward_adjoint_backproject_fp32(pn, name):
+    _say(f"case {name}: build")
+    gp, go, vols = make_case(pn, name)
+    x = gpu(np.stack(vols))
+    _say(f"case {name}: forward shape {tuple(x.shape)} -> {gp.sino_shape(len(vols))}")
+    y = pn.forward(x, gp)
+    torch.cuda.synchronize()
+    ref_y = np.stack([O.forward(v, go) for v in vols])
+    assert rel(cpu(y), ref_y) <= TOL32, rel(cpu(y), ref_y)
+    # adjoint and back-projection of the FP32-rounded oracle sinogram
+    q32 = ref_y.astype(np.float32).astype(np.float64)
+    _say(f"case {name}: adjoint")
+    at = pn.adjoint(gpu(q32), gp)
+    torch.cuda.synchronize()
+    ref_at = np.stack([O.adjoint(q, go) for q in q32])
+    assert rel(cpu(at), ref_at) <= TOL32, rel(cpu(at), ref_at)
+    _say(f"case {name}: backproject")
+    bp = pn.backproject(gpu(q32), gp)
+    torch.cuda.synchronize()
+    ref_bp = np.stack([O.backproject(q, go) for q in q32])
+    assert rel(cpu(bp), ref_bp) <= TOL32, rel(cpu(bp), ref_bp)
+
+
+@pytest.mark.parametrize("name", ["fan2d_ragged", "cone3d_ragged", "cone3d_perturbed"])
+def test_dot_product_adjoint_gpu(pn, name):
+    _say(f"dot test {name}")
+    gp, go, vols = make_case(pn, name)
+    rng = np.random.default_rng(5)
+    x = gpu(rng.random((1,) + gp.vol_shape))
+    yv = gpu(rng.random((1,) + gp.sino_shape()))
+    ax = cpu(pn.forward(x, gp))
+    aty = cpu(pn.adjoint(yv, gp))
+    lhs = float((ax * cpu(yv)).sum())
+    rhs = float((cpu(x) * aty).sum())
+    assert abs(lhs - rhs) <= TOL32 * np.linalg.norm(ax) * np.linalg.norm(cpu(yv))
+
+
+def test_adjoint_matches_explicit_transpose_tiny(pn):
+    """GPU A^T equals the transpose of the explicit oracle matrix A."""
+    _say("explicit transpose, tiny cone")
+    shp = (4, 5, 4)
+    gp = pn.cone_geometry(shp, (1.0, 1.0, 1.0), (5, 6), (1.1, 1.0), 3, 25.0, 40.0)
+    go = O.circular_cone(shp, (1.0, 1.0, 1.0), (5, 6), (1.1, 1.0), 3, 2 * math.pi, 25.0, 40.0)
+    nvox = int(np.prod(shp))
+    A = np.stack([O.forward(np.eye(nvox)[j].reshape(shp), go).ravel() for j in range(nvox)], 1)
+    nrays = A.shape[0]
+    E = gpu(np.eye(nrays).reshape((nrays,) + gp.sino_shape()))
+    At = cpu(pn.adjoint(E, gp)).reshape(nrays, nvox).T
+    assert np.abs(At - A.T).max() <= 1e-6 * np.abs(A).max()
+    Ag = cpu(pn.forward(gpu(np.eye(nvox).reshape((nvox,) + shp)), gp)).reshape(nvox, nrays).T
+    assert np.abs(Ag - A).max() <= 1e-6 * np.abs(A).max()
+
+
+def test_edge_cases(pn):
+    _say("edge cases")
+    # rays that miss the volume: detector shifted far off axis via the origin
+    shp = (8, 8, 8)
+    g = pn.cone_geometry(shp, (1.0, 1.0, 1.0), (6, 6), (1.0, 1.0), 5, 100.0, 160.0,
+                         vol_origin=(200.0, 0.0, 0.0))
+    y = pn.forward(torch.ones((1,) + shp, device="cuda"), g)
+    assert float(y.abs().max()) == 0.0
+    # empty batch, zero views
+    g0 = pn.Geometry(3, "cone", shp, (1.0,) * 3, (6, 6), np.zeros((0, 3, 4)))
+    z = pn.adjoint(torch.zeros((0,) + g0.sino_shape(), device="cuda"), g0)
+    assert z.shape == (0,) + shp
+    z = pn.adjoint(torch.zeros((1,) + g0.sino_shape(), device="cuda"), g0)
+    assert float(z.abs().max()) == 0.0
+    z = pn.backproject(torch.zeros((1,) + g0.sino_shape(), device="cuda"), g0)
+    assert float(z.abs().max()) == 0.0
+    # one-voxel volume and a one-pixel detector
+    g1 = pn.cone_geometry((1, 1, 1), (1.0, 1.0, 1.0), (1, 1), (1.0, 1.0), 4, 50.0, 80.0)
+    go1 = O.circular_cone((1, 1, 1), (1.0, 1.0, 1.0), (1, 1), (1.0, 1.0), 4, 2 * math.pi, 50.0, 80.0)
+    v = np.full((1, 1, 1), 2.5)
+    assert rel(cpu(pn.forward(gpu(v), g1)), O.forward(v, go1)) <= TOL32
+    s = np.full((4, 1, 1), 1.5)
+    assert rel(cpu(pn.adjoint(gpu(s), g1)), O.adjoint(s, go1)) <= TOL32
+    assert rel(cpu(pn.backproject(gpu(s), g1)), O.backproject(s, go1)) <= TOL32
+
+
+def test_determinism(pn):
+    _say("determinism")
+    gp, go, vols = make_case(pn, "cone3d_ragged")
+    x = gpu(np.stack(vols))
+    y1, y2 = pn.forward(x, gp), pn.forward(x, gp)
+    assert torch.equal(y1, y2)
+    b1, b2 = pn.backproject(y1, gp), pn.backproject(y1, gp)
+    assert torch.equal(b1, b2)
+    a1, a2 = pn.adjoint(y1, gp), pn.adjoint(y1, gp)
+    assert rel(cpu(a1), cpu(a2)) <= 1e-6
+
+
+@pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16])
+def test_reduced_precision_storage(pn, dt):
+    _say(f"reduced precision {dt}")
+    gp, go, vols = make_case(pn, "cone3d_ragged")
+    x32 = gpu(np.stack(vols))
+    x16 = x32.to(dt)
+    ref_y = np.stack([O.forward(v, go) for v in vols])
+    y16 = pn.forward(x16, gp)
+    assert y16.dtype == dt
+    assert rel(cpu(y16), ref_y) <= TOL16
+    # the stored result is the RNE rounding of the FP32 result
+    y32_of_16 = pn.forward(x16, gp, out_dtype=torch.float32)
+    assert torch.equal(y32_of_16.to(dt), y16)
+    # with the rounded input as the oracle's input, only output rounding remains
+    ref_q = np.stack([O.forward(v, go) for v in cpu(x16)])
+    assert rel(cpu(y32_of_16), ref_q) <= TOL32
+    q16 = gpu(ref_y, dt)
+    ref_at = np.stack([O.adjoint(q, go) for q in cpu(q16)])
+    at = pn.adjoint(q16, gp, out_dtype=torch.float32)
+    assert rel(cpu(at), ref_at) <= TOL32
+    at16 = pn.adjoint(q16, gp)
+    assert at16.dtype == dt and rel(cpu(at16), ref_at) <= TOL16
+    ref_bp = np.stack([O.backproject(q, go) for q in cpu(q16)])
+    bp = pn.backproject(q16, gp, out_dtype=torch.float32)
+    assert rel(cpu(bp), ref_bp) <= TOL32
+    bp16 = pn.backproject(q16, gp)
+    assert bp16.dtype == dt and rel(cpu(bp16), ref_bp) <= TOL16
+
+
+def test_batched_equals_single(pn):
+    _say("batched")
+    pairs, singles = [], []
+    for name in ("cone3d_ragged", "cone3d_helical", "cone3d_anisotropic"):
+        gp, go, vols = make_case(pn, name)
+        x = gpu(vols[0])
+        pairs.append((x, gp))
+        singles.append(pn.forward(x, gp))
+    outs = pn.forward_batched(pairs)
+    for o, s in zip(outs, singles):
+        assert torch.equal(o, s)
+    sp = [(s, g) for s, (_, g) in zip(singles, pairs)]
+    for o, (s, g) in zip(pn.backproject_batched(sp), sp):
+        assert torch.equal(o, pn.backproject(s, g))
+    for o, (s, g) in zip(pn.adjoint_batched(sp), sp):
+        assert rel(cpu(o), cpu(pn.adjoint(s, g))) <= 1e-6
+
+
+# ------------------------------------------------ full-size, sampled -----
+
+
+@pytest.fixture(scope="module")
+def cone256(pn):
+    cfg = W.CONFIGS["cone3d_256"]
+    shp, sp, det, ds = cfg["vol_shape"], cfg["vol_spacing"], cfg["det_shape"], cfg["det_spacing"]
+    gp = pn.cone_geometry(shp, sp, det, ds, cfg["n_views"], cfg["sid"], cfg["sdd"])
+    go = O.circular_cone(shp, sp, det, ds, cfg["n_views"], cfg["angular_range"], cfg["sid"], cfg["sdd"])
+    vol = W.ellipsoid_phantom_3d(cfg["seeds"][0], shp, sp, cfg["n_ellipsoids"])[0]
+    return gp, go, vol
+
+
+def test_full_size_cone256_sampled(pn, cone256):
+    gp, go, vol = cone256
+    _say("full-size cone 256^3 x 360: forward")
+    x = gpu(vol)
+    y = pn.forward(x, gp)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(123)
+    n = 4000
+    view, row, col = rng.integers(0, 360, n), rng.integers(0, 512, n), rng.integers(0, 512, n)
+    yc = y.cpu().numpy()
+    ref = O.forward_rays(vol, go, view, row, col)
+    got = yc[view, row, col]
+    assert rel(got, ref) <= TOL32
+    # rows through the middle of the detector for a few views, complete
+    mid = np.arange(512)
+    for v in (0, 45, 91, 200):
+        refm = O.forward_rays(vol, go, np.full(512, v), np.full(512, 256), mid)
+        assert rel(yc[v, 256], refm) <= TOL32
+    _say("full-size cone 256^3 x 360: backproject")
+    bp = pn.backproject(y, gp).cpu().numpy()
+    i, j, k = rng.integers(0, 256, 1500), rng.integers(0, 256, 1500), rng.integers(0, 256, 1500)
+    refb = O.backproject_voxels(yc.astype(np.float64), go, i, j, k)
+    assert rel(bp[k, j, i], refb) <= TOL32
+    _say("full-size cone 256^3 x 360: adjoint")
+    at = pn.adjoint(y, gp).cpu().numpy()
+    for box in ((120, 136, 120, 136, 120, 136), (0, 16, 240, 256, 100, 116)):
+        refa = O.adjoint(yc.astype(np.float64), go, box=box)
+        got = at[box[4]:box[5], box[2]:box[3], box[0]:box[1]]
+        assert rel(got, refa) <= TOL32
+    _say("full-size cone 256^3 x 360: dot test")
+    rs = np.random.default_rng(7)
+    yr = gpu(rs.random(gp.sino_shape()).astype(np.float32))
+    atr = pn.adjoint(yr, gp).double()
+    lhs = float((y.double() * yr.double()).sum())
+    rhs = float((x.double() * atr).sum())
+    assert abs(lhs - rhs) <= TOL32 * float(y.double().norm()) * float(yr.double().norm())
+
+
+# ------------------------------------------------------------ autograd ---
+
+
+def test_autograd_pair_finite_difference(pn):
+    """L(x) = 0.5 ||A x - y||^2 is quadratic, so the central difference equals
+    <A^T (A x - y), v> exactly up to rounding, for any step."""
+    _say("autograd finite differences (fan batch)")
+    gp = pn.fan_geometry((128, 128), (0.5, 0.5), 256, 0.5, 120, 1000.0, 1500.0)
+    imgs = np.stack([W.ellipse_phantom_2d(s, (128, 128), (0.5, 0.5))[0] for s in (2, 3)])
+    target = np.stack([W.ellipse_phantom_2d(18, (128, 128), (0.5, 0.5))[0]] * 2)
+    y = pn.forward(gpu(target), gp).detach()
+    x = gpu(imgs).requires_grad_(True)
+    loss = 0.5 * ((pn.Projection.apply(x, gp) - y) ** 2).sum()
+    loss.backward()
+    v = gpu(np.random.default_rng(19).standard_normal(imgs.shape))
+    eps = 1e-2 * float(x.detach().norm()) / float(v.norm())
+
+    def L(z):
+        r = (pn.forward(z, gp) - y).double()
+        return 0.5 * float((r * r).sum())
+
+    fd = (L(x.detach() + eps * v) - L(x.detach() - eps * v)) / (2 * eps)
+    an = float((x.grad.double() * v.double()).sum())
+    assert abs(fd - an) <= 1e-4 * abs(an)
+
+
+def test_unrolled_checkpointed_matches_stored(pn):
+    _say("unrolled gradient steps")
+    gp, go, vols = make_case(pn, "cone3d_ragged")
+    y = pn.forward(gpu(vols[0]), gp).detach()
+    x0 = torch.zeros(gp.vol_shape, device="cuda", requires_grad=True)
+    alpha = 1e-4
+    out_c = pn.unrolled_gd(x0, y, gp, alpha, 3, checkpoint=True)
+    out_c.square().sum().backward()
+    g_c = x0.grad.clone()
+    x0.grad = None
+    out_s = pn.unrolled_gd(x0, y, gp, alpha, 3, checkpoint=False)
+    out_s.square().sum().backward()
+    assert rel(cpu(out_c), cpu(out_s)) <= 1e-6
+    assert rel(cpu(g_c), cpu(x0.grad)) <= 1e-5
+    # the result is three explicit gradient steps
+    xs = torch.zeros(gp.vol_shape, device="cuda")
+    for _ in range(3):
+        xs = xs - alpha * pn.adjoint(pn.forward(xs, gp) - y, gp)
+    assert rel(cpu(out_c), cpu(xs)) <= 1e-5
