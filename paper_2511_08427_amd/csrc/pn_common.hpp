@@ -14,7 +14,13 @@ namespace pn {
 // bilinear tap of a position clamped to [-1, n] is addressable.
 constexpr int PADR_LO = 1;
 constexpr int PADR_HI = 2;
-constexpr int PADC = 4;
+constexpr int PADC = 8;
+
+// Elements per row of a work copy with `nf` columns: room for PADC zeros on
+// the left and for whole 16-byte vectors reaching up to column nf + 8 on the
+// right, rounded to a multiple of 8 elements (16-byte aligned rows for every
+// storage type).
+inline int32_t work_row(int32_t nf) { return (nf + PADC + 9 + 7) / 8 * 8; }
 
 // Per-view FP64 tables in volume index space (x, y, z order).  Built on the
 // host from the view's projection matrix.
@@ -51,6 +57,8 @@ struct FwdParams {
 
 struct AdjParams {
     const ViewTab *tab;
+    const uint32_t *maxabs;  // bit pattern of max |sino| (fixed-point scale)
+    float ds_bound;          // upper bound of the ray length per plane (mm)
     const int32_t *views;  // views processed by this pass
     int32_t n_pass_views;
     int32_t axis;          // dominant axis handled by this pass

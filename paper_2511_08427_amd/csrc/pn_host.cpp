@@ -26,6 +26,8 @@ hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, 
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 void adjoint_block_shape(bool two_d, int32_t &L, int32_t &TS, int32_t &TF);
+void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv);
+hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st);
 }  // namespace pn
 
 namespace {
@@ -285,6 +287,8 @@ struct Plan {
     // FP32 accumulation buffer of the adjoint for 16-bit outputs
     float *d_acc = nullptr;
     size_t acc_cap = 0;
+    // max |sinogram| of the current adjoint call (fixed-point scale)
+    uint32_t *d_maxabs = nullptr;
 
     ~Plan()
     {
@@ -295,6 +299,7 @@ struct Plan {
             dev_free(d_lay[a]);
         }
         dev_free(d_acc);
+        dev_free(d_maxabs);
     }
 };
 
@@ -391,6 +396,7 @@ int get_plan(const pn_geometry *pg, Plan **out)
     if ((rc = upload(&pl->d_tabf, pl->tabf))) return rc;
     for (int a = 0; a < 3; ++a)
         if ((rc = upload(&pl->d_views[a], pl->pass_views[a]))) return rc;
+    if ((rc = upload(&pl->d_maxabs, std::vector<uint32_t>(1, 0u)))) return rc;
     g_plans.push_front(std::move(pl));
     while (g_plans.size() > kMaxPlans) g_plans.pop_back();
     *out = g_plans.front().get();
@@ -405,24 +411,43 @@ int check_ptr(const void *p, int32_t dt, const char *name)
     return PN_OK;
 }
 
-int common_checks(int64_t batch, const void *in, const void *out, int32_t in_dt, int32_t out_dt)
+int common_checks(int64_t batch, int32_t in_dt, int32_t out_dt)
 {
     if (!dtype_ok(in_dt)) return fail(PN_EDTYPE, "unknown input dtype %d", in_dt);
     if (!dtype_ok(out_dt)) return fail(PN_EDTYPE, "unknown output dtype %d", out_dt);
     if (batch < 0 || batch > 65535) return fail(PN_EINVAL, "batch = %lld out of range", (long long)batch);
-    if (batch == 0) return PN_OK;
-    int rc;
-    if ((rc = check_ptr(in, in_dt, "input"))) return rc;
-    if ((rc = check_ptr(out, out_dt, "output"))) return rc;
-    if (in == out) return fail(PN_EINVAL, "input and output alias");
     return PN_OK;
+}
+
+// Pointer checks; a buffer with no elements may be NULL (as torch passes it).
+int buffer_checks(const void *in, bool in_empty, const void *out, bool out_empty, int32_t in_dt, int32_t out_dt)
+{
+    int rc;
+    if (!in_empty && (rc = check_ptr(in, in_dt, "input"))) return rc;
+    if (!out_empty && (rc = check_ptr(out, out_dt, "output"))) return rc;
+    if (!in_empty && in == out) return fail(PN_EINVAL, "input and output alias");
+    return PN_OK;
+}
+
+// Argument checks that need no device: dtypes, batch, then (after the
+// geometry) the pointers.  Runs before anything is allocated or enqueued.
+int preflight(const pn_geometry *pg, int64_t batch, const void *in, const void *out, int32_t in_dt, int32_t out_dt,
+              bool sino_is_input, Geo &g)
+{
+    int rc = common_checks(batch, in_dt, out_dt);
+    if (rc) return rc;
+    if (batch == 0) return PN_OK;
+    if ((rc = normalise_geometry(pg, g))) return rc;
+    const bool sino_empty = g.n_views == 0;
+    return sino_is_input ? buffer_checks(in, sino_empty, out, false, in_dt, out_dt)
+                         : buffer_checks(in, false, out, sino_empty, in_dt, out_dt);
 }
 
 int ensure_work_copy(Plan &pl, int a, int32_t dt, int64_t batch, hipStream_t st)
 {
     const Geo &g = pl.g;
     const int f = a == 0 ? 1 : 0, sl = a == 2 ? 1 : 2;
-    const int32_t row = g.n[f] + 2 * PADC;
+    const int32_t row = work_row(g.n[f]);
     const int64_t plane = (int64_t)row * (g.n[sl] + PADR_LO + PADR_HI);
     const int64_t item = plane * g.n[a];
     const size_t need = (size_t)(item * batch * esize(dt));
@@ -454,7 +479,8 @@ int ensure_work_copy(Plan &pl, int a, int32_t dt, int64_t batch, hipStream_t st)
 int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt, int32_t out_dt,
                  hipStream_t st)
 {
-    int rc = common_checks(batch, vol, sino, in_dt, out_dt);
+    Geo pre;
+    int rc = preflight(pg, batch, vol, sino, in_dt, out_dt, false, pre);
     if (rc || batch == 0) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *pl;
@@ -484,13 +510,7 @@ int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *si
     }
     p.vol = vol;
     p.sino = sino;
-    if (g.nv == 1) {
-        p.tile_u = 256;
-        p.tile_v = 1;
-    } else {
-        p.tile_u = 16;
-        p.tile_v = 16;
-    }
+    forward_tile_shape(g.ndim == 2, p.tile_u, p.tile_v);
     p.tiles_u = (g.nu + p.tile_u - 1) / p.tile_u;
     p.tiles_v = (g.nv + p.tile_v - 1) / p.tile_v;
     if ((int64_t)p.tiles_u * p.tiles_v * g.n_views * batch > INT32_MAX)
@@ -503,7 +523,8 @@ int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *si
 int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt, int32_t out_dt,
                  hipStream_t st)
 {
-    int rc = common_checks(batch, sino, vol, in_dt, out_dt);
+    Geo pre;
+    int rc = preflight(pg, batch, sino, vol, in_dt, out_dt, true, pre);
     if (rc || batch == 0) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *pl;
@@ -538,12 +559,19 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
     const bool two_d = g.ndim == 2;
     int32_t L, TS, TF;
     adjoint_block_shape(two_d, L, TS, TF);
+    {
+        hipError_t e = launch_maxabs(in_dt, sino, (int64_t)g.n_views * g.nv * g.nu * batch, pl->d_maxabs, st);
+        if (e != hipSuccess) return fail_hip(e, "maxabs launch");
+    }
+    const float ds_bound = (float)(std::sqrt(g.s[0] * g.s[0] + g.s[1] * g.s[1] + g.s[2] * g.s[2]) * 1.0001);
     int done = 0;
     for (int a = 0; a < 3; ++a) {
         if (pl->pass_views[a].empty()) continue;
         const int f = a == 0 ? 1 : 0, sl = a == 2 ? 1 : 2;
         AdjParams p{};
         p.tab = pl->d_tab;
+        p.maxabs = pl->d_maxabs;
+        p.ds_bound = ds_bound;
         p.views = pl->d_views[a];
         p.n_pass_views = (int32_t)pl->pass_views[a].size();
         p.axis = a;
@@ -577,7 +605,8 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
 int backproject_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt,
                      int32_t out_dt, hipStream_t st)
 {
-    int rc = common_checks(batch, sino, vol, in_dt, out_dt);
+    Geo pre;
+    int rc = preflight(pg, batch, sino, vol, in_dt, out_dt, true, pre);
     if (rc || batch == 0) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *pl;

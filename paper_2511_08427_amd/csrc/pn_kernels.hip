@@ -39,7 +39,14 @@ __device__ __forceinline__ bf16 from_f32<bf16>(float f)
     return bf16{static_cast<uint16_t>(u >> 16)};
 }
 template <>
-__device__ __forceinline__ f16 from_f32<f16>(float f) { return static_cast<f16>(f); }  // v_cvt_f16_f32, RNE
+__device__ __forceinline__ f16 from_f32<f16>(float f)
+{
+    // the empty asm pins the FP32 value, so the store is the RNE rounding of
+    // the FP32 result (without it the compiler may fuse the producing
+    // multiply into a mixed-precision instruction that rounds only once)
+    asm volatile("" : "+v"(f));
+    return static_cast<f16>(f);  // v_cvt_f16_f32, round to nearest even
+}
 
 // ------------------------------------------------------ ray set-up -------
 
@@ -152,6 +159,51 @@ __global__ __launch_bounds__(256) void relayout_rows_kernel(const S *__restrict_
 
 // ------------------------------------------------------- forward A -------
 
+// 16-byte vector of storage elements, widened to FP32.
+template <typename S>
+struct Vec;
+template <>
+struct Vec<float> {
+    static constexpr int N = 4;
+};
+template <>
+struct Vec<bf16> {
+    static constexpr int N = 8;
+};
+template <>
+struct Vec<f16> {
+    static constexpr int N = 8;
+};
+
+__device__ __forceinline__ void load16(const float *p, float *o)
+{
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+}
+__device__ __forceinline__ void load16(const bf16 *p, float *o)
+{
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        o[2 * i] = __uint_as_float(w[i] << 16);
+        o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+}
+__device__ __forceinline__ void load16(const f16 *p, float *o)
+{
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        o[2 * i] = static_cast<float>(__builtin_bit_cast(f16, static_cast<uint16_t>(w[i] & 0xffffu)));
+        o[2 * i + 1] = static_cast<float>(__builtin_bit_cast(f16, static_cast<uint16_t>(w[i] >> 16)));
+    }
+}
+
 template <typename S>
 __device__ __forceinline__ float sample_padded(const S *__restrict__ plane, int32_t row, float pf, float ps,
                                                float nf, float ns)
@@ -168,77 +220,243 @@ __device__ __forceinline__ float sample_padded(const S *__restrict__ plane, int3
     return fmaf(ws, hi - lo, lo);
 }
 
-template <typename S, typename O>
+// Gather from the caller's [nz][ny][nx] volume with bounds checks; used only
+// for a dominant axis whose work copy was not built.
+template <typename S>
+__device__ float sample_raw(const S *__restrict__ vol, const int32_t n[3], int a, int m, float pf, float ps)
+{
+    const int f = fast_axis(a), sl = slow_axis(a);
+    const float ff = floorf(pf), fs = floorf(ps);
+    const float wf = pf - ff, ws = ps - fs;
+    const int i_f = static_cast<int>(fminf(fmaxf(ff, -2.0f), 70000.0f));
+    const int i_s = static_cast<int>(fminf(fmaxf(fs, -2.0f), 70000.0f));
+    float acc = 0.0f;
+    for (int ts = 0; ts < 2; ++ts)
+        for (int tf = 0; tf < 2; ++tf) {
+            const int cf = i_f + tf, cs = i_s + ts;
+            if (cf < 0 || cf >= n[f] || cs < 0 || cs >= n[sl]) continue;
+            int idx[3];
+            idx[a] = m;
+            idx[f] = cf;
+            idx[sl] = cs;
+            const float val = to_f32(vol[(static_cast<int64_t>(idx[2]) * n[1] + idx[1]) * n[0] + idx[0]]);
+            acc += (tf ? wf : 1.0f - wf) * (ts ? ws : 1.0f - ws) * val;
+        }
+    return acc;
+}
+
+// Ray-driven forward projection.  A workgroup owns a TU x TV tile of
+// detector pixels of one view (one ray per thread).  For each dominant axis
+// present in the tile it walks the union of the rays' plane ranges in chunks
+// of C planes; per chunk it stages the box of volume that the tile's rays can
+// touch (bounded by the four corner rays, whose crossings with a plane
+// enclose those of every ray in between) from the padded work copy into LDS
+// with 16-byte loads, and every ray then samples its planes from LDS.  A box
+// larger than RCAP x FCAP falls back to gathers from the work copy.
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
 __global__ __launch_bounds__(256) void forward_kernel(FwdParams p)
 {
+    static_assert(TU * TV == 256, "one ray per thread");
+    constexpr int VE = Vec<S>::N;
+    constexpr int VPR = FCAP / VE;
+    constexpr int RPI = 256 / VPR;
+    static_assert(FCAP % VE == 0 && RPI >= 1, "box shape");
+    __shared__ float box[C * RCAP * FCAP];
+    __shared__ int s_axes, s_m0, s_m1;
+
+    const int t = threadIdx.x;
     const int tiles = p.tiles_u * p.tiles_v;
-    const int wg = blockIdx.x;
-    const int tile = wg % tiles;
-    const int rest = wg / tiles;
+    const int tile = blockIdx.x % tiles;
+    const int rest = blockIdx.x / tiles;
     const int view = rest % p.n_views;
     const int b = rest / p.n_views;
-    const int c = (tile % p.tiles_u) * p.tile_u + static_cast<int>(threadIdx.x) % p.tile_u;
-    const int r = (tile / p.tiles_u) * p.tile_v + static_cast<int>(threadIdx.x) / p.tile_u;
-    if (c >= p.nu || r >= p.nv) return;
+    const int c0 = (tile % p.tiles_u) * TU, r0 = (tile / p.tiles_u) * TV;
+    const int c = c0 + t % TU, r = r0 + t / TU;
+    const bool inside = c < p.nu && r < p.nv;
+    const ViewTab &tab = p.tab[view];
 
     RaySeg seg;
-    ray_setup(p.tab[view], static_cast<double>(c), static_cast<double>(r), p.n, p.s, seg);
+    seg.axis = 0;
+    seg.m0 = 1;
+    seg.m1 = 0;
+    seg.gf = seg.gs = seg.bf = seg.bs = seg.ds = 0.0f;
+    if (inside) ray_setup(tab, static_cast<double>(c), static_cast<double>(r), p.n, p.s, seg);
+    const bool live = inside && seg.m0 <= seg.m1;
+    if (t == 0) s_axes = 0;
+    __syncthreads();
+    if (live) atomicOr(&s_axes, 1 << seg.axis);
+    __syncthreads();
+    const int axes = s_axes;
+
+    const int c1 = min(c0 + TU, p.nu) - 1, r1 = min(r0 + TV, p.nv) - 1;
     float acc = 0.0f;
-    if (seg.m0 <= seg.m1) {
-        const int a = seg.axis;
-        const float nf = static_cast<float>(p.n[fast_axis(a)]);
-        const float ns = static_cast<float>(p.n[slow_axis(a)]);
-        const S *lay = static_cast<const S *>(p.lay[a]);
-        if (lay != nullptr) {
-            const S *base = lay + b * p.lay_item[a];
-            const int32_t row = p.lay_row[a];
-            const int64_t pl = p.lay_plane[a];
-            for (int m = seg.m0; m <= seg.m1; ++m) {
-                const float fm = static_cast<float>(m);
-                acc += sample_padded(base + m * pl, row, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs), nf, ns);
+    for (int a = 0; a < 3; ++a) {
+        if (!((axes >> a) & 1)) continue;
+        const bool part = live && seg.axis == a;
+        __syncthreads();
+        if (t == 0) {
+            s_m0 = 0x7fffffff;
+            s_m1 = -1;
+        }
+        __syncthreads();
+        if (part) {
+            atomicMin(&s_m0, seg.m0);
+            atomicMax(&s_m1, seg.m1);
+        }
+        __syncthreads();
+        const int M0 = s_m0, M1 = s_m1;
+        const int f = fast_axis(a), sl = slow_axis(a);
+        const float nf = static_cast<float>(p.n[f]), ns = static_cast<float>(p.n[sl]);
+
+        // corner rays of the tile, parametrised along axis a
+        float cgf[4], cbf[4], cgs[4], cbs[4];
+        bool box_ok = p.lay[a] != nullptr;
+        double sgn = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double u = (k & 1) ? c1 : c0, v = (k & 2) ? r1 : r0;
+            double d[3], q[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                d[i] = fma(tab.A[3 * i], u, fma(tab.A[3 * i + 1], v, tab.A[3 * i + 2]));
+                q[i] = fma(tab.B[3 * i], u, fma(tab.B[3 * i + 1], v, tab.B[3 * i + 2]));
             }
-        } else {
-            // no work copy for this axis: gather from the caller's layout
-            const S *vol = static_cast<const S *>(p.vol) +
-                           static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
-            const int f = fast_axis(a), sl = slow_axis(a);
-            for (int m = seg.m0; m <= seg.m1; ++m) {
-                const float fm = static_cast<float>(m);
-                float pf = fmaf(fm, seg.gf, seg.bf), ps = fmaf(fm, seg.gs, seg.bs);
-                float ff = floorf(pf), fs = floorf(ps);
-                float wf = pf - ff, ws = ps - fs;
-                int i_f = static_cast<int>(fminf(fmaxf(ff, -2.0f), 70000.0f));
-                int i_s = static_cast<int>(fminf(fmaxf(fs, -2.0f), 70000.0f));
-                for (int ts = 0; ts < 2; ++ts)
-                    for (int tf = 0; tf < 2; ++tf) {
-                        int cf = i_f + tf, cs = i_s + ts;
-                        if (cf < 0 || cf >= p.n[f] || cs < 0 || cs >= p.n[sl]) continue;
-                        int idx[3];
-                        idx[a] = m;
-                        idx[f] = cf;
-                        idx[sl] = cs;
-                        float val = to_f32(vol[(static_cast<int64_t>(idx[2]) * p.n[1] + idx[1]) * p.n[0] + idx[0]]);
-                        acc += (tf ? wf : 1.0f - wf) * (ts ? ws : 1.0f - ws) * val;
+            if (k == 0) sgn = d[a];
+            if (!(d[a] * sgn > 0.0)) box_ok = false;
+            const double inv = 1.0 / d[a];
+            const double gf = d[f] * inv, gs = d[sl] * inv;
+            cgf[k] = static_cast<float>(gf);
+            cgs[k] = static_cast<float>(gs);
+            cbf[k] = static_cast<float>(fma(-q[a], gf, q[f]));
+            cbs[k] = static_cast<float>(fma(-q[a], gs, q[sl]));
+        }
+        const S *base = box_ok ? static_cast<const S *>(p.lay[a]) + b * p.lay_item[a] : nullptr;
+        const int32_t row = p.lay_row[a];
+        const int64_t plane = p.lay_plane[a];
+
+        for (int mc = M0; mc <= M1; mc += C) {
+            const int me = min(mc + C - 1, M1);
+            bool use_lds = box_ok;
+            int f_al = 0, s_lo = 0, nvec = 0, ns_box = 0;
+            if (use_lds) {
+                float fmn = 3e38f, fmx = -3e38f, smn = 3e38f, smx = -3e38f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float pf0 = fmaf(static_cast<float>(mc), cgf[k], cbf[k]);
+                    const float pf1 = fmaf(static_cast<float>(me), cgf[k], cbf[k]);
+                    const float ps0 = fmaf(static_cast<float>(mc), cgs[k], cbs[k]);
+                    const float ps1 = fmaf(static_cast<float>(me), cgs[k], cbs[k]);
+                    fmn = fminf(fmn, fminf(pf0, pf1));
+                    fmx = fmaxf(fmx, fmaxf(pf0, pf1));
+                    smn = fminf(smn, fminf(ps0, ps1));
+                    smx = fmaxf(smx, fmaxf(ps0, ps1));
+                }
+                // samples are clamped to [-1, n]; widen for FP32 rounding
+                fmn = fminf(fmaxf(fmn - 1e-3f, -1.0f), nf);
+                fmx = fminf(fmaxf(fmx + 1e-3f, -1.0f), nf);
+                smn = fminf(fmaxf(smn - 1e-3f, -1.0f), ns);
+                smx = fminf(fmaxf(smx + 1e-3f, -1.0f), ns);
+                const int f_lo = static_cast<int>(floorf(fmn)), f_hi = static_cast<int>(floorf(fmx)) + 1;
+                s_lo = static_cast<int>(floorf(smn));
+                const int s_hi = static_cast<int>(floorf(smx)) + 1;
+                f_al = (f_lo + 2 * VE) / VE * VE - 2 * VE;  // f_lo >= -1: round down to a multiple of VE
+                nvec = (f_hi - f_al) / VE + 1;
+                ns_box = s_hi - s_lo + 1;
+                use_lds = nvec <= VPR && ns_box <= RCAP;
+            }
+            if (use_lds) {
+                __syncthreads();  // the previous chunk's samples have been read
+                const int vr = t % VPR;
+                const S *src0 = base + static_cast<int64_t>(s_lo + PADR_LO) * row + (f_al + PADC) + vr * VE;
+                for (int k = 0; k < C; ++k) {
+                    const int m = mc + k;
+                    if (m > me) break;
+                    const S *src = src0 + static_cast<int64_t>(m) * plane;
+                    for (int rr = t / VPR; rr < ns_box; rr += RPI) {
+                        if (vr < nvec) {
+                            float v[VE];
+                            load16(src + static_cast<int64_t>(rr) * row, v);
+                            float *dst = box + (k * RCAP + rr) * FCAP + vr * VE;
+#pragma unroll
+                            for (int e = 0; e < VE; e += 4)
+                                *reinterpret_cast<float4 *>(dst + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+                        }
                     }
+                }
+                __syncthreads();
+                if (part) {
+                    const int ma = max(mc, seg.m0), mb = min(me, seg.m1);
+                    const float fo = static_cast<float>(f_al), so = static_cast<float>(s_lo);
+                    const int imax_f = nvec * VE - 2, imax_s = ns_box - 2;
+                    for (int m = ma; m <= mb; ++m) {
+                        const float fm = static_cast<float>(m);
+                        const float pf = fminf(fmaxf(fmaf(fm, seg.gf, seg.bf), -1.0f), nf) - fo;
+                        const float ps = fminf(fmaxf(fmaf(fm, seg.gs, seg.bs), -1.0f), ns) - so;
+                        const float ff = floorf(pf), fs = floorf(ps);
+                        const float wf = pf - ff, ws = ps - fs;
+                        // the box holds every tap; the clamp only guards LDS addressing
+                        const int i_f = min(max(static_cast<int>(ff), 0), imax_f);
+                        const int i_s = min(max(static_cast<int>(fs), 0), imax_s);
+                        const float *q = box + ((m - mc) * RCAP + i_s) * FCAP + i_f;
+                        const float v00 = q[0], v01 = q[1], v10 = q[FCAP], v11 = q[FCAP + 1];
+                        const float lo = fmaf(wf, v01 - v00, v00);
+                        const float hi = fmaf(wf, v11 - v10, v10);
+                        acc += fmaf(ws, hi - lo, lo);
+                    }
+                }
+            } else if (part) {
+                const int ma = max(mc, seg.m0), mb = min(me, seg.m1);
+                if (p.lay[a] != nullptr) {
+                    const S *lay = static_cast<const S *>(p.lay[a]) + b * p.lay_item[a];
+                    for (int m = ma; m <= mb; ++m) {
+                        const float fm = static_cast<float>(m);
+                        acc += sample_padded(lay + m * plane, row, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs),
+                                             nf, ns);
+                    }
+                } else {
+                    const S *vol = static_cast<const S *>(p.vol) +
+                                   static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
+                    for (int m = ma; m <= mb; ++m) {
+                        const float fm = static_cast<float>(m);
+                        acc += sample_raw(vol, p.n, a, m, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs));
+                    }
+                }
             }
         }
-        acc *= seg.ds;
     }
+    if (!inside) return;
     O *out = static_cast<O *>(p.sino);
-    out[((static_cast<int64_t>(b) * p.n_views + view) * p.nv + r) * p.nu + c] = from_f32<O>(acc);
+    out[((static_cast<int64_t>(b) * p.n_views + view) * p.nv + r) * p.nu + c] = from_f32<O>(live ? acc * seg.ds : 0.0f);
 }
 
 // ------------------------------------------------------- adjoint A^T -----
 
+// Power-of-two scale that maps every contribution q*ds*w (|.| <= lim) into
+// [-2^29, 2^29].  Zero input: scale 1; non-finite input: scale 0.
+__device__ __forceinline__ float fixed_scale(float lim)
+{
+    if (!(lim > 0.0f)) return 1.0f;
+    if (!isfinite(lim)) return 0.0f;
+    const float e = fminf(fmaxf(floorf(log2f(536870912.0f / lim)), -126.0f), 126.0f);
+    return exp2f(e);
+}
+
 // Each workgroup owns a block of L planes (dominant axis `axis`) x TS rows x
-// TF columns of the output, keeps it in LDS, visits every ray of every view
-// of the pass whose samples can touch it, scatters those samples' bilinear
-// taps into LDS with ds_add_f32, and writes the block once.  No global
-// atomics; each output voxel has exactly one writer per pass.
+// TF columns of the output.  For every view of the pass it visits the rays
+// whose samples can touch the block (the detector bounding box of the block
+// dilated by one voxel in-plane), scatters the bilinear taps of their samples
+// into LDS, and writes the block once.  The LDS accumulators are 64-bit
+// fixed point (contributions scaled by a power of two so each fits in 30
+// bits, truncated to integers, added with ds_add_u64): integer addition is
+// exact and order-independent, so the result is deterministic, and integer
+// LDS atomics run at the LDS store rate.  Out-of-block taps go to a per-lane
+// discard cell.  Candidate rays are enumerated in pixel-parity classes so
+// that neighbouring lanes work on rays two pixels apart.
 template <typename Q, int L, int TS, int TF>
 __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
 {
-    __shared__ float acc[L * TS * TF];
+    constexpr int NCELL = L * TS * TF;
+    __shared__ unsigned long long acc[NCELL + 64];
     const int a = p.axis, f = fast_axis(a), sl = slow_axis(a);
     int blk = blockIdx.x;
     const int bf_ = blk % p.blocks_f;
@@ -250,15 +468,16 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
     const int a0 = ba_ * L, a1 = min(a0 + L, p.n[a]);
     const int s0 = bs_ * TS, s1 = min(s0 + TS, p.n[sl]);
     const int f0 = bf_ * TF, f1 = min(f0 + TF, p.n[f]);
+    const int discard = NCELL + (threadIdx.x & 63);
 
-    for (int e = threadIdx.x; e < L * TS * TF; e += blockDim.x) acc[e] = 0.0f;
+    for (int e = threadIdx.x; e < NCELL + 64; e += blockDim.x) acc[e] = 0ull;
+    const float scale = fixed_scale(__uint_as_float(*p.maxabs) * p.ds_bound);
     __syncthreads();
 
     const Q *sino_b = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
     for (int pv = 0; pv < p.n_pass_views; ++pv) {
         const int view = p.views[pv];
         const ViewTab &t = p.tab[view];
-        // detector bounding box of the block dilated by one voxel in-plane
         double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
 #pragma unroll
         for (int corner = 0; corner < 8; ++corner) {
@@ -266,10 +485,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
             ijk[a] = (corner & 1) ? static_cast<double>(a1 - 1) : static_cast<double>(a0);
             ijk[sl] = (corner & 2) ? static_cast<double>(s1) : static_cast<double>(s0 - 1);
             ijk[f] = (corner & 4) ? static_cast<double>(f1) : static_cast<double>(f0 - 1);
-            double U = t.Pi[0] * ijk[0] + t.Pi[1] * ijk[1] + t.Pi[2] * ijk[2] + t.Pi[3];
-            double V = t.Pi[4] * ijk[0] + t.Pi[5] * ijk[1] + t.Pi[6] * ijk[2] + t.Pi[7];
-            double Wc = t.Pi[8] * ijk[0] + t.Pi[9] * ijk[1] + t.Pi[10] * ijk[2] + t.Pi[11];
-            double uu = U / Wc, vv = V / Wc;
+            const double U = t.Pi[0] * ijk[0] + t.Pi[1] * ijk[1] + t.Pi[2] * ijk[2] + t.Pi[3];
+            const double V = t.Pi[4] * ijk[0] + t.Pi[5] * ijk[1] + t.Pi[6] * ijk[2] + t.Pi[7];
+            const double Wc = t.Pi[8] * ijk[0] + t.Pi[9] * ijk[1] + t.Pi[10] * ijk[2] + t.Pi[11];
+            const double uu = U / Wc, vv = V / Wc;
             umin = fmin(umin, uu);
             umax = fmax(umax, uu);
             vmin = fmin(vmin, vv);
@@ -282,11 +501,22 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         const int cv0 = static_cast<int>(fmin(fmax(floor(vmin), 0.0), static_cast<double>(p.nv)));
         const int cv1 = static_cast<int>(fmax(fmin(ceil(vmax), static_cast<double>(p.nv - 1)), -1.0));
         if (cu0 > cu1 || cv0 > cv1) continue;
-        const int wu = cu1 - cu0 + 1;
-        const int64_t ncand = static_cast<int64_t>(wu) * (cv1 - cv0 + 1);
+        const int wu = cu1 - cu0 + 1, wv = cv1 - cv0 + 1;
+        // parity classes (c - cu0, r - cv0) mod 2, each enumerated row-major
+        const int wu_e = (wu + 1) >> 1, wu_o = wu >> 1, wv_e = (wv + 1) >> 1, wv_o = wv >> 1;
+        const int64_t n00 = static_cast<int64_t>(wu_e) * wv_e, n10 = static_cast<int64_t>(wu_o) * wv_e;
+        const int64_t n01 = static_cast<int64_t>(wu_e) * wv_o;
+        const int64_t ncand = static_cast<int64_t>(wu) * wv;
         const Q *sino_v = sino_b + static_cast<int64_t>(view) * p.nv * p.nu;
         for (int64_t idx = threadIdx.x; idx < ncand; idx += blockDim.x) {
-            const int c = cu0 + static_cast<int>(idx % wu), r = cv0 + static_cast<int>(idx / wu);
+            int64_t j = idx;
+            int pc, pr, w;
+            if (j < n00) { pc = 0; pr = 0; w = wu_e; }
+            else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; }
+            else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; }
+            else { j -= n01; pc = 1; pr = 1; w = wu_o; }
+            const int c = cu0 + pc + 2 * static_cast<int>(j % w);
+            const int r = cv0 + pr + 2 * static_cast<int>(j / w);
             RaySeg seg;
             ray_setup(t, static_cast<double>(c), static_cast<double>(r), p.n, p.s, seg);
             if (seg.axis != a || seg.m0 > seg.m1) continue;
@@ -300,7 +530,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
             if (!(lo <= hi)) continue;
             const int m0 = max(static_cast<int>(floor(lo)), a0);
             const int m1 = min(static_cast<int>(ceil(hi)), a1 - 1);
-            const float q = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]) * seg.ds;
+            const float qs = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]) * seg.ds * scale;
             for (int m = m0; m <= m1; ++m) {
                 const float fm = static_cast<float>(m);
                 const float pf = fmaf(fm, seg.gf, seg.bf), ps = fmaf(fm, seg.gs, seg.bs);
@@ -308,24 +538,23 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
                 const float wf = pf - ff, ws = ps - fs;
                 const int lf = static_cast<int>(fminf(fmaxf(ff, -2.0f), 70000.0f)) - f0;
                 const int ls = static_cast<int>(fminf(fmaxf(fs, -2.0f), 70000.0f)) - s0;
-                const int la = m - a0;
-                const float q0 = q * (1.0f - ws), q1 = q * ws;
-                float *row0 = acc + (la * TS + ls) * TF;
-                if (ls >= 0 && ls < TS && ls + s0 < s1) {
-                    if (lf >= 0 && lf < TF && lf + f0 < f1) atomicAdd(row0 + lf, q0 * (1.0f - wf));
-                    if (lf + 1 >= 0 && lf + 1 < TF && lf + 1 + f0 < f1) atomicAdd(row0 + lf + 1, q0 * wf);
-                }
-                if (ls + 1 >= 0 && ls + 1 < TS && ls + 1 + s0 < s1) {
-                    float *row1 = row0 + TF;
-                    if (lf >= 0 && lf < TF && lf + f0 < f1) atomicAdd(row1 + lf, q1 * (1.0f - wf));
-                    if (lf + 1 >= 0 && lf + 1 < TF && lf + 1 + f0 < f1) atomicAdd(row1 + lf + 1, q1 * wf);
-                }
+                const int base = ((m - a0) * TS + ls) * TF + lf;
+                const bool f0ok = lf >= 0 && lf < f1 - f0, f1ok = lf + 1 >= 0 && lf + 1 < f1 - f0;
+                const bool s0ok = ls >= 0 && ls < s1 - s0, s1ok = ls + 1 >= 0 && ls + 1 < s1 - s0;
+                const float t0 = qs - qs * ws, t1 = qs * ws;
+                const long long c00 = static_cast<int>(t0 - t0 * wf), c01 = static_cast<int>(t0 * wf);
+                const long long c10 = static_cast<int>(t1 - t1 * wf), c11 = static_cast<int>(t1 * wf);
+                atomicAdd(&acc[(f0ok && s0ok) ? base : discard], static_cast<unsigned long long>(c00));
+                atomicAdd(&acc[(f1ok && s0ok) ? base + 1 : discard], static_cast<unsigned long long>(c01));
+                atomicAdd(&acc[(f0ok && s1ok) ? base + TF : discard], static_cast<unsigned long long>(c10));
+                atomicAdd(&acc[(f1ok && s1ok) ? base + TF + 1 : discard], static_cast<unsigned long long>(c11));
             }
         }
     }
     __syncthreads();
 
     // write the block; the memory-contiguous axis x runs fastest
+    const double inv_scale = scale > 0.0f ? 1.0 / static_cast<double>(scale) : 0.0;
     const int na = a1 - a0, ns = s1 - s0, nf = f1 - f0;
     const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
     float *out = p.out + b * item;
@@ -345,9 +574,24 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         ijk[sl] = s0 + ls;
         ijk[f] = f0 + lf;
         const int64_t o = (static_cast<int64_t>(ijk[2]) * p.n[1] + ijk[1]) * p.n[0] + ijk[0];
-        const float v = acc[(la * TS + ls) * TF + lf];
+        const long long sum = static_cast<long long>(acc[(la * TS + ls) * TF + lf]);
+        const float v = static_cast<float>(static_cast<double>(sum) * inv_scale);
         out[o] = p.accumulate ? out[o] + v : v;
     }
+}
+
+// max |x| over a buffer, as the bit pattern of a non-negative float
+// (integer order = float order), combined with a global atomic max.
+template <typename Q>
+__global__ __launch_bounds__(256) void maxabs_kernel(const Q *__restrict__ src, int64_t n, uint32_t *__restrict__ out)
+{
+    float m = 0.0f;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        m = fmaxf(m, fabsf(to_f32(src[e])));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
 // ------------------------------------------------ back-projection --------
@@ -457,7 +701,10 @@ template <typename S, typename O>
 static hipError_t forward_t(const FwdParams &p, hipStream_t st)
 {
     const int64_t blocks = static_cast<int64_t>(p.tiles_u) * p.tiles_v * p.n_views * p.batch;
-    forward_kernel<S, O><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+    if (p.tile_v == 1)
+        forward_kernel<S, O, 256, 1, 8, 4, 320><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+    else
+        forward_kernel<S, O, 16, 16, 8, 32, 32><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
     return hipGetLastError();
 }
 
@@ -480,10 +727,16 @@ hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hip
     }
 }
 
+void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv)
+{
+    if (two_d) { tu = 256; tv = 1; }
+    else { tu = 16; tv = 16; }
+}
+
 void adjoint_block_shape(bool two_d, int32_t &L, int32_t &TS, int32_t &TF)
 {
-    if (two_d) { L = 64; TS = 1; TF = 128; }
-    else { L = 32; TS = 16; TF = 16; }
+    if (two_d) { L = 64; TS = 1; TF = 64; }
+    else { L = 32; TS = 8; TF = 16; }
 }
 
 template <typename Q>
@@ -491,9 +744,9 @@ static hipError_t adjoint_q(const AdjParams &p, bool two_d, hipStream_t st)
 {
     const int64_t blocks = static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch;
     if (two_d)
-        adjoint_kernel<Q, 64, 1, 128><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+        adjoint_kernel<Q, 64, 1, 64><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
     else
-        adjoint_kernel<Q, 32, 16, 16><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+        adjoint_kernel<Q, 32, 8, 16><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
     return hipGetLastError();
 }
 
@@ -504,6 +757,21 @@ hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, bool two_d, hipStre
     case DT_BF16: return adjoint_q<bf16>(p, two_d, st);
     default: return adjoint_q<f16>(p, two_d, st);
     }
+}
+
+hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st)
+{
+    fill_zero_kernel<<<1, 64, 0, st>>>(out, 1);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    const dim3 g(static_cast<uint32_t>(blocks));
+    switch (in_dt) {
+    case DT_F32: maxabs_kernel<float><<<g, 256, 0, st>>>(static_cast<const float *>(src), n, out); break;
+    case DT_BF16: maxabs_kernel<bf16><<<g, 256, 0, st>>>(static_cast<const bf16 *>(src), n, out); break;
+    default: maxabs_kernel<f16><<<g, 256, 0, st>>>(static_cast<const f16 *>(src), n, out); break;
+    }
+    return hipGetLastError();
 }
 
 template <typename Q, typename O>

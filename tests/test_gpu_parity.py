@@ -188,8 +188,9 @@ def test_determinism(pn):
     assert torch.equal(y1, y2)
     b1, b2 = pn.backproject(y1, gp), pn.backproject(y1, gp)
     assert torch.equal(b1, b2)
+    # the adjoint accumulates in 64-bit fixed point: order-independent
     a1, a2 = pn.adjoint(y1, gp), pn.adjoint(y1, gp)
-    assert rel(cpu(a1), cpu(a2)) <= 1e-6
+    assert torch.equal(a1, a2)
 
 
 @pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16])
@@ -236,7 +237,7 @@ def test_batched_equals_single(pn):
     for o, (s, g) in zip(pn.backproject_batched(sp), sp):
         assert torch.equal(o, pn.backproject(s, g))
     for o, (s, g) in zip(pn.adjoint_batched(sp), sp):
-        assert rel(cpu(o), cpu(pn.adjoint(s, g))) <= 1e-6
+        assert torch.equal(o, pn.adjoint(s, g))
 
 
 # ------------------------------------------------ full-size, sampled -----
