@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=16, help="views of the oracle CPU sample")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB elementwise copy kernel (counter calibration)")
+    ap.add_argument("--profile-once", action="store_true",
+                    help="run one forward and one adjoint only (for counter collection)")
     return ap.parse_args()
 
 
@@ -84,6 +88,18 @@ def main():
         y = pn.forward(x, geom)
         a = pn.adjoint(y, geom)
         return y, a
+
+    if args.calib_copy:
+        src = torch.ones(64 * 1024 * 1024, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        log("calibration copy: 268435456 bytes read + 268435456 bytes written")
+    if args.profile_once:
+        step()
+        torch.cuda.synchronize()
+        log("profile-once: one forward + one adjoint done")
+        return
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):

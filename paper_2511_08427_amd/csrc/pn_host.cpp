@@ -27,6 +27,7 @@ hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 void adjoint_block_shape(bool two_d, int32_t &L, int32_t &TS, int32_t &TF);
 void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv);
+int64_t forward_blocks(const FwdParams &p);
 hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st);
 }  // namespace pn
 
@@ -513,7 +514,7 @@ int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *si
     forward_tile_shape(g.ndim == 2, p.tile_u, p.tile_v);
     p.tiles_u = (g.nu + p.tile_u - 1) / p.tile_u;
     p.tiles_v = (g.nv + p.tile_v - 1) / p.tile_v;
-    if ((int64_t)p.tiles_u * p.tiles_v * g.n_views * batch > INT32_MAX)
+    if (forward_blocks(p) > INT32_MAX)
         return fail(PN_EINVAL, "problem too large for one launch");
     hipError_t e = launch_forward(p, in_dt, out_dt, st);
     if (e != hipSuccess) return fail_hip(e, "forward launch");

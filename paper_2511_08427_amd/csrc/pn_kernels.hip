@@ -113,6 +113,52 @@ __device__ __forceinline__ void ray_setup(const ViewTab &t, double u, double v, 
     r.m1 = static_cast<int>(fmin(ceil(hi), static_cast<double>(n[a] - 1)));
 }
 
+// Set-up for the adjoint: as ray_setup but without the volume-wide plane
+// range (the caller clips to its block) and with the ray length per plane
+// from an FP32 square root (relative error ~1e-7).  seg.axis is the ray's
+// dominant axis; the slopes and offsets are for that axis.
+__device__ __forceinline__ void ray_setup_local(const ViewTab &t, double u, double v, const double s[3], int want,
+                                                RaySeg &r)
+{
+    double d[3], p[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        d[i] = fma(t.A[3 * i], u, fma(t.A[3 * i + 1], v, t.A[3 * i + 2]));
+        p[i] = fma(t.B[3 * i], u, fma(t.B[3 * i + 1], v, t.B[3 * i + 2]));
+    }
+    const double ax = fabs(d[0]), ay = fabs(d[1]), az = fabs(d[2]);
+    const int a = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+    r.axis = a;
+    r.m0 = 0;
+    r.m1 = -1;
+    if (a != want) return;
+    const int f = fast_axis(a), sl = slow_axis(a);
+    const double inv = 1.0 / d[a];
+    const double gf = d[f] * inv, gs = d[sl] * inv;
+    r.gf = static_cast<float>(gf);
+    r.gs = static_cast<float>(gs);
+    r.bf = static_cast<float>(fma(-p[a], gf, p[f]));
+    r.bs = static_cast<float>(fma(-p[a], gs, p[sl]));
+    const double wx = d[0] * s[0], wy = d[1] * s[1], wz = d[2] * s[2];
+    r.ds = sqrtf(static_cast<float>(wx * wx + wy * wy + wz * wz)) * static_cast<float>(fabs(inv));
+    if (!isfinite(r.ds)) r.axis = -1;
+}
+
+// FP32 version of clip_range with one plane of slack on each side (the
+// result only bounds loops whose every extra plane contributes zero).
+__device__ __forceinline__ void clip_range_f(float b, float g, float lo_pos, float hi_pos, float &lo, float &hi)
+{
+    if (g == 0.0f) {
+        if (!(b >= lo_pos && b <= hi_pos)) { lo = 1.0f; hi = 0.0f; }
+        return;
+    }
+    const float rg = __builtin_amdgcn_rcpf(g);
+    float t0 = (lo_pos - b) * rg, t1 = (hi_pos - b) * rg;
+    if (t0 > t1) { const float tt = t0; t0 = t1; t1 = tt; }
+    lo = fmaxf(lo, floorf(t0) - 1.0f);
+    hi = fminf(hi, ceilf(t1) + 1.0f);
+}
+
 // ------------------------------------------------------- relayout --------
 
 // a = x: out[b][i][k + PADR_LO][j + PADC] = in[b][k][j][i] (tiled transpose)
@@ -175,17 +221,20 @@ struct Vec<f16> {
     static constexpr int N = 8;
 };
 
-__device__ __forceinline__ void load16(const float *p, float *o)
+// Widens 16 bytes of storage elements (held in a uint4) to FP32.
+template <typename S>
+__device__ __forceinline__ void unpack16(const uint4 v, float *o);
+template <>
+__device__ __forceinline__ void unpack16<float>(const uint4 v, float *o)
 {
-    const float4 v = *reinterpret_cast<const float4 *>(p);
-    o[0] = v.x;
-    o[1] = v.y;
-    o[2] = v.z;
-    o[3] = v.w;
+    o[0] = __uint_as_float(v.x);
+    o[1] = __uint_as_float(v.y);
+    o[2] = __uint_as_float(v.z);
+    o[3] = __uint_as_float(v.w);
 }
-__device__ __forceinline__ void load16(const bf16 *p, float *o)
+template <>
+__device__ __forceinline__ void unpack16<bf16>(const uint4 v, float *o)
 {
-    const uint4 v = *reinterpret_cast<const uint4 *>(p);
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -193,9 +242,9 @@ __device__ __forceinline__ void load16(const bf16 *p, float *o)
         o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
     }
 }
-__device__ __forceinline__ void load16(const f16 *p, float *o)
+template <>
+__device__ __forceinline__ void unpack16<f16>(const uint4 v, float *o)
 {
-    const uint4 v = *reinterpret_cast<const uint4 *>(p);
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -245,31 +294,51 @@ __device__ float sample_raw(const S *__restrict__ vol, const int32_t n[3], int a
     return acc;
 }
 
+// Staged box of one chunk of planes: columns [f_al, f_al + nvec*VE) and rows
+// [s_lo, s_lo + ns) of planes [mc, me] of the work copy.
+struct Box {
+    int mc, me, f_al, s_lo, nvec, ns;
+    bool lds;
+};
+
 // Ray-driven forward projection.  A workgroup owns a TU x TV tile of
 // detector pixels of one view (one ray per thread).  For each dominant axis
 // present in the tile it walks the union of the rays' plane ranges in chunks
 // of C planes; per chunk it stages the box of volume that the tile's rays can
 // touch (bounded by the four corner rays, whose crossings with a plane
 // enclose those of every ray in between) from the padded work copy into LDS
-// with 16-byte loads, and every ray then samples its planes from LDS.  A box
-// larger than RCAP x FCAP falls back to gathers from the work copy.
+// with 16-byte loads, and every ray then samples its planes from LDS.  The
+// loads of chunk i+1 are issued into registers before chunk i is sampled.
+// A box larger than RCAP x FCAP falls back to gathers from the work copy.
+//
+// Workgroup order: consecutive workgroup ids go round-robin to the 8 XCDs;
+// each XCD gets every 8th tile and runs the views of a tile back to back, so
+// the workgroups resident on one XCD sample nearly the same beam of the
+// volume and share its L2.
 template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
-__global__ __launch_bounds__(256) void forward_kernel(FwdParams p)
+__global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
 {
     static_assert(TU * TV == 256, "one ray per thread");
     constexpr int VE = Vec<S>::N;
     constexpr int VPR = FCAP / VE;
     constexpr int RPI = 256 / VPR;
-    static_assert(FCAP % VE == 0 && RPI >= 1, "box shape");
+    static_assert(FCAP % VE == 0 && RPI >= RCAP, "one staged row per thread and plane");
     __shared__ float box[C * RCAP * FCAP];
+    __shared__ float s_corner[4][4];
+    __shared__ int s_dir[4];
     __shared__ int s_axes, s_m0, s_m1;
 
     const int t = threadIdx.x;
     const int tiles = p.tiles_u * p.tiles_v;
-    const int tile = blockIdx.x % tiles;
-    const int rest = blockIdx.x / tiles;
-    const int view = rest % p.n_views;
-    const int b = rest / p.n_views;
+    const int tpx = (tiles + 7) >> 3;
+    const int xcd = blockIdx.x & 7;
+    const int slot = blockIdx.x >> 3;
+    const int per_b = tpx * p.n_views;
+    const int b = slot / per_b;
+    const int rem = slot - b * per_b;
+    const int tile = (rem / p.n_views) * 8 + xcd;
+    const int view = rem % p.n_views;
+    if (tile >= tiles || b >= p.batch) return;  // padding workgroups (uniform exit)
     const int c0 = (tile % p.tiles_u) * TU, r0 = (tile / p.tiles_u) * TV;
     const int c = c0 + t % TU, r = r0 + t / TU;
     const bool inside = c < p.nu && r < p.nv;
@@ -289,10 +358,13 @@ __global__ __launch_bounds__(256) void forward_kernel(FwdParams p)
     const int axes = s_axes;
 
     const int c1 = min(c0 + TU, p.nu) - 1, r1 = min(r0 + TV, p.nv) - 1;
+    const int vr = t % VPR, rrow = t / VPR;  // this thread's vector and row of a staged plane
     float acc = 0.0f;
     for (int a = 0; a < 3; ++a) {
         if (!((axes >> a) & 1)) continue;
         const bool part = live && seg.axis == a;
+        const int f = fast_axis(a), sl = slow_axis(a);
+        const float nf = static_cast<float>(p.n[f]), ns = static_cast<float>(p.n[sl]);
         __syncthreads();
         if (t == 0) {
             s_m0 = 0x7fffffff;
@@ -303,49 +375,49 @@ __global__ __launch_bounds__(256) void forward_kernel(FwdParams p)
             atomicMin(&s_m0, seg.m0);
             atomicMax(&s_m1, seg.m1);
         }
-        __syncthreads();
-        const int M0 = s_m0, M1 = s_m1;
-        const int f = fast_axis(a), sl = slow_axis(a);
-        const float nf = static_cast<float>(p.n[f]), ns = static_cast<float>(p.n[sl]);
-
-        // corner rays of the tile, parametrised along axis a
-        float cgf[4], cbf[4], cgs[4], cbs[4];
-        bool box_ok = p.lay[a] != nullptr;
-        double sgn = 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double u = (k & 1) ? c1 : c0, v = (k & 2) ? r1 : r0;
+        if (t < 4) {
+            // corner ray t of the tile, parametrised along axis a
+            const double u = (t & 1) ? c1 : c0, v = (t & 2) ? r1 : r0;
             double d[3], q[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 d[i] = fma(tab.A[3 * i], u, fma(tab.A[3 * i + 1], v, tab.A[3 * i + 2]));
                 q[i] = fma(tab.B[3 * i], u, fma(tab.B[3 * i + 1], v, tab.B[3 * i + 2]));
             }
-            if (k == 0) sgn = d[a];
-            if (!(d[a] * sgn > 0.0)) box_ok = false;
             const double inv = 1.0 / d[a];
             const double gf = d[f] * inv, gs = d[sl] * inv;
-            cgf[k] = static_cast<float>(gf);
-            cgs[k] = static_cast<float>(gs);
-            cbf[k] = static_cast<float>(fma(-q[a], gf, q[f]));
-            cbs[k] = static_cast<float>(fma(-q[a], gs, q[sl]));
+            s_corner[t][0] = static_cast<float>(gf);
+            s_corner[t][1] = static_cast<float>(fma(-q[a], gf, q[f]));
+            s_corner[t][2] = static_cast<float>(gs);
+            s_corner[t][3] = static_cast<float>(fma(-q[a], gs, q[sl]));
+            s_dir[t] = d[a] > 0.0 ? 1 : (d[a] < 0.0 ? -1 : 0);
         }
+        __syncthreads();
+        const int M0 = s_m0, M1 = s_m1;
+        // the corner crossings bound the tile's crossings when no ray of the
+        // tile is parallel to the planes (same non-zero sign at the corners)
+        const bool box_ok = p.lay[a] != nullptr && s_dir[0] != 0 && s_dir[0] == s_dir[1] && s_dir[0] == s_dir[2] &&
+                            s_dir[0] == s_dir[3];
         const S *base = box_ok ? static_cast<const S *>(p.lay[a]) + b * p.lay_item[a] : nullptr;
         const int32_t row = p.lay_row[a];
         const int64_t plane = p.lay_plane[a];
 
-        for (int mc = M0; mc <= M1; mc += C) {
-            const int me = min(mc + C - 1, M1);
-            bool use_lds = box_ok;
-            int f_al = 0, s_lo = 0, nvec = 0, ns_box = 0;
-            if (use_lds) {
+        // the box of chunk [mc, min(mc + C - 1, M1)]
+        auto make_box = [&](int mc) {
+            Box bx;
+            bx.mc = mc;
+            bx.me = min(mc + C - 1, M1);
+            bx.lds = box_ok;
+            bx.f_al = bx.s_lo = bx.nvec = bx.ns = 0;
+            if (box_ok) {
                 float fmn = 3e38f, fmx = -3e38f, smn = 3e38f, smx = -3e38f;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const float pf0 = fmaf(static_cast<float>(mc), cgf[k], cbf[k]);
-                    const float pf1 = fmaf(static_cast<float>(me), cgf[k], cbf[k]);
-                    const float ps0 = fmaf(static_cast<float>(mc), cgs[k], cbs[k]);
-                    const float ps1 = fmaf(static_cast<float>(me), cgs[k], cbs[k]);
+                    const float4 cr = *reinterpret_cast<const float4 *>(s_corner[k]);
+                    const float pf0 = fmaf(static_cast<float>(bx.mc), cr.x, cr.y);
+                    const float pf1 = fmaf(static_cast<float>(bx.me), cr.x, cr.y);
+                    const float ps0 = fmaf(static_cast<float>(bx.mc), cr.z, cr.w);
+                    const float ps1 = fmaf(static_cast<float>(bx.me), cr.z, cr.w);
                     fmn = fminf(fmn, fminf(pf0, pf1));
                     fmx = fmaxf(fmx, fmaxf(pf0, pf1));
                     smn = fminf(smn, fminf(ps0, ps1));
@@ -357,69 +429,81 @@ __global__ __launch_bounds__(256) void forward_kernel(FwdParams p)
                 smn = fminf(fmaxf(smn - 1e-3f, -1.0f), ns);
                 smx = fminf(fmaxf(smx + 1e-3f, -1.0f), ns);
                 const int f_lo = static_cast<int>(floorf(fmn)), f_hi = static_cast<int>(floorf(fmx)) + 1;
-                s_lo = static_cast<int>(floorf(smn));
+                bx.s_lo = static_cast<int>(floorf(smn));
                 const int s_hi = static_cast<int>(floorf(smx)) + 1;
-                f_al = (f_lo + 2 * VE) / VE * VE - 2 * VE;  // f_lo >= -1: round down to a multiple of VE
-                nvec = (f_hi - f_al) / VE + 1;
-                ns_box = s_hi - s_lo + 1;
-                use_lds = nvec <= VPR && ns_box <= RCAP;
+                bx.f_al = (f_lo + 2 * VE) / VE * VE - 2 * VE;  // f_lo >= -1: round down to a multiple of VE
+                bx.nvec = (f_hi - bx.f_al) / VE + 1;
+                bx.ns = s_hi - bx.s_lo + 1;
+                bx.lds = bx.nvec <= VPR && bx.ns <= RCAP;
             }
-            if (use_lds) {
-                __syncthreads();  // the previous chunk's samples have been read
-                const int vr = t % VPR;
-                const S *src0 = base + static_cast<int64_t>(s_lo + PADR_LO) * row + (f_al + PADC) + vr * VE;
-                for (int k = 0; k < C; ++k) {
-                    const int m = mc + k;
-                    if (m > me) break;
-                    const S *src = src0 + static_cast<int64_t>(m) * plane;
-                    for (int rr = t / VPR; rr < ns_box; rr += RPI) {
-                        if (vr < nvec) {
-                            float v[VE];
-                            load16(src + static_cast<int64_t>(rr) * row, v);
-                            float *dst = box + (k * RCAP + rr) * FCAP + vr * VE;
+            return bx;
+        };
+        // 16-byte loads of this thread's share of a box (one row per plane)
+        uint4 pre[C];
+        auto issue = [&](const Box &bx) {
+            if (!bx.lds || rrow >= bx.ns || vr >= bx.nvec) return;
+            const S *src = base + static_cast<int64_t>(bx.s_lo + PADR_LO + rrow) * row + (bx.f_al + PADC) + vr * VE;
 #pragma unroll
-                            for (int e = 0; e < VE; e += 4)
-                                *reinterpret_cast<float4 *>(dst + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
-                        }
-                    }
+            for (int k = 0; k < C; ++k)
+                if (bx.mc + k <= bx.me)
+                    pre[k] = *reinterpret_cast<const uint4 *>(src + static_cast<int64_t>(bx.mc + k) * plane);
+        };
+
+        Box cur = make_box(M0);
+        issue(cur);
+        for (int mc = M0; mc <= M1; mc += C) {
+            __syncthreads();  // every ray is done with the previous box
+            if (cur.lds && rrow < cur.ns && vr < cur.nvec) {
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    if (cur.mc + k > cur.me) break;
+                    float v[VE];
+                    unpack16<S>(pre[k], v);
+                    float *dst = box + (k * RCAP + rrow) * FCAP + vr * VE;
+#pragma unroll
+                    for (int e = 0; e < VE; e += 4)
+                        *reinterpret_cast<float4 *>(dst + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
                 }
-                __syncthreads();
-                if (part) {
-                    const int ma = max(mc, seg.m0), mb = min(me, seg.m1);
-                    const float fo = static_cast<float>(f_al), so = static_cast<float>(s_lo);
-                    const int imax_f = nvec * VE - 2, imax_s = ns_box - 2;
-                    for (int m = ma; m <= mb; ++m) {
-                        const float fm = static_cast<float>(m);
-                        const float pf = fminf(fmaxf(fmaf(fm, seg.gf, seg.bf), -1.0f), nf) - fo;
-                        const float ps = fminf(fmaxf(fmaf(fm, seg.gs, seg.bs), -1.0f), ns) - so;
-                        const float ff = floorf(pf), fs = floorf(ps);
-                        const float wf = pf - ff, ws = ps - fs;
-                        // the box holds every tap; the clamp only guards LDS addressing
-                        const int i_f = min(max(static_cast<int>(ff), 0), imax_f);
-                        const int i_s = min(max(static_cast<int>(fs), 0), imax_s);
-                        const float *q = box + ((m - mc) * RCAP + i_s) * FCAP + i_f;
-                        const float v00 = q[0], v01 = q[1], v10 = q[FCAP], v11 = q[FCAP + 1];
-                        const float lo = fmaf(wf, v01 - v00, v00);
-                        const float hi = fmaf(wf, v11 - v10, v10);
-                        acc += fmaf(ws, hi - lo, lo);
-                    }
+            }
+            __syncthreads();
+            const Box now = cur;
+            if (mc + C <= M1) {
+                cur = make_box(mc + C);
+                issue(cur);  // in flight while this chunk is sampled
+            }
+            if (!part) continue;
+            const int ma = max(now.mc, seg.m0), mb = min(now.me, seg.m1);
+            if (now.lds) {
+                const float fo = static_cast<float>(now.f_al), so = static_cast<float>(now.s_lo);
+                const int imax_f = now.nvec * VE - 2, imax_s = now.ns - 2;
+                for (int m = ma; m <= mb; ++m) {
+                    const float fm = static_cast<float>(m);
+                    const float pf = fminf(fmaxf(fmaf(fm, seg.gf, seg.bf), -1.0f), nf) - fo;
+                    const float ps = fminf(fmaxf(fmaf(fm, seg.gs, seg.bs), -1.0f), ns) - so;
+                    const float ff = floorf(pf), fs = floorf(ps);
+                    const float wf = pf - ff, ws = ps - fs;
+                    // the box holds every tap; the clamp only guards LDS addressing
+                    const int i_f = min(max(static_cast<int>(ff), 0), imax_f);
+                    const int i_s = min(max(static_cast<int>(fs), 0), imax_s);
+                    const float *q = box + ((m - now.mc) * RCAP + i_s) * FCAP + i_f;
+                    const float v00 = q[0], v01 = q[1], v10 = q[FCAP], v11 = q[FCAP + 1];
+                    const float lo = fmaf(wf, v01 - v00, v00);
+                    const float hi = fmaf(wf, v11 - v10, v10);
+                    acc += fmaf(ws, hi - lo, lo);
                 }
-            } else if (part) {
-                const int ma = max(mc, seg.m0), mb = min(me, seg.m1);
-                if (p.lay[a] != nullptr) {
-                    const S *lay = static_cast<const S *>(p.lay[a]) + b * p.lay_item[a];
-                    for (int m = ma; m <= mb; ++m) {
-                        const float fm = static_cast<float>(m);
-                        acc += sample_padded(lay + m * plane, row, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs),
-                                             nf, ns);
-                    }
-                } else {
-                    const S *vol = static_cast<const S *>(p.vol) +
-                                   static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
-                    for (int m = ma; m <= mb; ++m) {
-                        const float fm = static_cast<float>(m);
-                        acc += sample_raw(vol, p.n, a, m, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs));
-                    }
+            } else if (p.lay[a] != nullptr) {
+                const S *lay = static_cast<const S *>(p.lay[a]) + b * p.lay_item[a];
+                for (int m = ma; m <= mb; ++m) {
+                    const float fm = static_cast<float>(m);
+                    acc += sample_padded(lay + m * plane, row, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs), nf,
+                                         ns);
+                }
+            } else {
+                const S *vol = static_cast<const S *>(p.vol) +
+                               static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
+                for (int m = ma; m <= mb; ++m) {
+                    const float fm = static_cast<float>(m);
+                    acc += sample_raw(vol, p.n, a, m, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs));
                 }
             }
         }
@@ -442,21 +526,40 @@ __device__ __forceinline__ float fixed_scale(float lim)
 }
 
 // Each workgroup owns a block of L planes (dominant axis `axis`) x TS rows x
-// TF columns of the output.  For every view of the pass it visits the rays
-// whose samples can touch the block (the detector bounding box of the block
-// dilated by one voxel in-plane), scatters the bilinear taps of their samples
-// into LDS, and writes the block once.  The LDS accumulators are 64-bit
-// fixed point (contributions scaled by a power of two so each fits in 30
-// bits, truncated to integers, added with ds_add_u64): integer addition is
-// exact and order-independent, so the result is deterministic, and integer
-// LDS atomics run at the LDS store rate.  Out-of-block taps go to a per-lane
-// discard cell.  Candidate rays are enumerated in pixel-parity classes so
-// that neighbouring lanes work on rays two pixels apart.
-template <typename Q, int L, int TS, int TF>
-__global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
+// TF columns of the output and keeps it in LDS as 64-bit fixed-point
+// accumulators with a halo of one cell below and two above in both in-plane
+// directions.  For every view of the pass:
+//   phase A  each thread takes one candidate pixel of the detector bounding
+//            box of the block (dilated by one voxel in-plane), does the ray's
+//            FP64 set-up and, if the ray has the pass axis as dominant axis
+//            and samples the dilated block, appends it to an LDS ray list
+//            together with its plane range cut into segments of <= K planes;
+//   phase B  each thread takes segments and scatters the bilinear taps of
+//            their samples.  Positions are clamped to the halo, where an
+//            out-of-block tap lands with an exactly-zero or discarded value.
+// Contributions q*ds*w are scaled by a power of two so that each fits in 30
+// bits, truncated to integers and added with ds_add_u64: integer addition is
+// exact and order-independent (the result is deterministic) and integer LDS
+// atomics run at the LDS store rate.  The block is written once per pass.
+//
+// SLO/SHI are the halo rows below/above the block in the slow in-plane
+// direction: 1/2 in general; 0/1 for 2-D problems, whose rays have z == 0
+// exactly (the tap at z = 0 has weight 1 and the one at z = 1 weight 0).
+template <typename Q, int L, int TS, int TF, int SLO, int SHI>
+__global__ __launch_bounds__(256, 2) void adjoint_kernel(AdjParams p)
 {
-    constexpr int NCELL = L * TS * TF;
-    __shared__ unsigned long long acc[NCELL + 64];
+    constexpr int K = 8;                       // planes per segment
+    constexpr int RW = TF + 3;                 // LDS row (halo: 1 before, 2 after)
+    constexpr int RP = TS + SLO + SHI;         // LDS rows per plane
+    constexpr int PL = RP * RW;                // LDS plane
+    constexpr int MAXSEG = 256 * ((L + K - 1) / K);
+    static_assert(L <= 64 && K <= 15, "segment record packing");
+    __shared__ unsigned long long acc[L * PL];
+    __shared__ float4 s_ray[256];              // gf, bf (halo-local), gs, bs (halo-local)
+    __shared__ float s_q[256];                 // q * ds * scale
+    __shared__ uint32_t s_seg[MAXSEG];         // ray | first plane << 8 | count << 16
+    __shared__ int s_cnt[2][2];                // [parity][rays, segments]
+
     const int a = p.axis, f = fast_axis(a), sl = slow_axis(a);
     int blk = blockIdx.x;
     const int bf_ = blk % p.blocks_f;
@@ -468,16 +571,21 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
     const int a0 = ba_ * L, a1 = min(a0 + L, p.n[a]);
     const int s0 = bs_ * TS, s1 = min(s0 + TS, p.n[sl]);
     const int f0 = bf_ * TF, f1 = min(f0 + TF, p.n[f]);
-    const int discard = NCELL + (threadIdx.x & 63);
+    // largest halo-local position whose two taps stay inside the LDS block
+    const float fmaxl = static_cast<float>(f1 - f0 + 1);
+    const float smaxl = static_cast<float>(min(s1 - s0 + 1, RP - 2));
+    const int t = threadIdx.x;
 
-    for (int e = threadIdx.x; e < NCELL + 64; e += blockDim.x) acc[e] = 0ull;
+    for (int e = t; e < L * PL; e += 256) acc[e] = 0ull;
+    if (t < 4) s_cnt[t >> 1][t & 1] = 0;
     const float scale = fixed_scale(__uint_as_float(*p.maxabs) * p.ds_bound);
     __syncthreads();
 
     const Q *sino_b = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
+    int parity = 0;
     for (int pv = 0; pv < p.n_pass_views; ++pv) {
         const int view = p.views[pv];
-        const ViewTab &t = p.tab[view];
+        const ViewTab &tv = p.tab[view];
         double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
 #pragma unroll
         for (int corner = 0; corner < 8; ++corner) {
@@ -485,14 +593,14 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
             ijk[a] = (corner & 1) ? static_cast<double>(a1 - 1) : static_cast<double>(a0);
             ijk[sl] = (corner & 2) ? static_cast<double>(s1) : static_cast<double>(s0 - 1);
             ijk[f] = (corner & 4) ? static_cast<double>(f1) : static_cast<double>(f0 - 1);
-            const double U = t.Pi[0] * ijk[0] + t.Pi[1] * ijk[1] + t.Pi[2] * ijk[2] + t.Pi[3];
-            const double V = t.Pi[4] * ijk[0] + t.Pi[5] * ijk[1] + t.Pi[6] * ijk[2] + t.Pi[7];
-            const double Wc = t.Pi[8] * ijk[0] + t.Pi[9] * ijk[1] + t.Pi[10] * ijk[2] + t.Pi[11];
-            const double uu = U / Wc, vv = V / Wc;
-            umin = fmin(umin, uu);
-            umax = fmax(umax, uu);
-            vmin = fmin(vmin, vv);
-            vmax = fmax(vmax, vv);
+            const double U = tv.Pi[0] * ijk[0] + tv.Pi[1] * ijk[1] + tv.Pi[2] * ijk[2] + tv.Pi[3];
+            const double V = tv.Pi[4] * ijk[0] + tv.Pi[5] * ijk[1] + tv.Pi[6] * ijk[2] + tv.Pi[7];
+            const double Wc = tv.Pi[8] * ijk[0] + tv.Pi[9] * ijk[1] + tv.Pi[10] * ijk[2] + tv.Pi[11];
+            const double iw = 1.0 / Wc;
+            umin = fmin(umin, U * iw);
+            umax = fmax(umax, U * iw);
+            vmin = fmin(vmin, V * iw);
+            vmax = fmax(vmax, V * iw);
         }
         // clamp before converting: the bounds are finite (W > 0 over the
         // dilated volume) but may lie far outside the detector
@@ -500,65 +608,96 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         const int cu1 = static_cast<int>(fmax(fmin(ceil(umax), static_cast<double>(p.nu - 1)), -1.0));
         const int cv0 = static_cast<int>(fmin(fmax(floor(vmin), 0.0), static_cast<double>(p.nv)));
         const int cv1 = static_cast<int>(fmax(fmin(ceil(vmax), static_cast<double>(p.nv - 1)), -1.0));
-        if (cu0 > cu1 || cv0 > cv1) continue;
+        if (cu0 > cu1 || cv0 > cv1) continue;  // uniform
         const int wu = cu1 - cu0 + 1, wv = cv1 - cv0 + 1;
-        // parity classes (c - cu0, r - cv0) mod 2, each enumerated row-major
-        const int wu_e = (wu + 1) >> 1, wu_o = wu >> 1, wv_e = (wv + 1) >> 1, wv_o = wv >> 1;
-        const int64_t n00 = static_cast<int64_t>(wu_e) * wv_e, n10 = static_cast<int64_t>(wu_o) * wv_e;
-        const int64_t n01 = static_cast<int64_t>(wu_e) * wv_o;
-        const int64_t ncand = static_cast<int64_t>(wu) * wv;
+        const int wu_e = (wu + 1) >> 1, wu_o = wu >> 1, wv_e = (wv + 1) >> 1;
+        const int n00 = wu_e * wv_e, n10 = wu_o * wv_e, n01 = wu_e * (wv >> 1);
+        const int ncand = wu * wv;
         const Q *sino_v = sino_b + static_cast<int64_t>(view) * p.nv * p.nu;
-        for (int64_t idx = threadIdx.x; idx < ncand; idx += blockDim.x) {
-            int64_t j = idx;
-            int pc, pr, w;
-            if (j < n00) { pc = 0; pr = 0; w = wu_e; }
-            else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; }
-            else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; }
-            else { j -= n01; pc = 1; pr = 1; w = wu_o; }
-            const int c = cu0 + pc + 2 * static_cast<int>(j % w);
-            const int r = cv0 + pr + 2 * static_cast<int>(j / w);
-            RaySeg seg;
-            ray_setup(t, static_cast<double>(c), static_cast<double>(r), p.n, p.s, seg);
-            if (seg.axis != a || seg.m0 > seg.m1) continue;
-            // planes of this block whose sample lies in the dilated block
-            double lo = fmax(static_cast<double>(seg.m0), static_cast<double>(a0));
-            double hi = fmin(static_cast<double>(seg.m1), static_cast<double>(a1 - 1));
-            clip_range(static_cast<double>(seg.bf), static_cast<double>(seg.gf), f0 - 1.0, static_cast<double>(f1),
-                       lo, hi);
-            clip_range(static_cast<double>(seg.bs), static_cast<double>(seg.gs), s0 - 1.0, static_cast<double>(s1),
-                       lo, hi);
-            if (!(lo <= hi)) continue;
-            const int m0 = max(static_cast<int>(floor(lo)), a0);
-            const int m1 = min(static_cast<int>(ceil(hi)), a1 - 1);
-            const float qs = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]) * seg.ds * scale;
-            for (int m = m0; m <= m1; ++m) {
-                const float fm = static_cast<float>(m);
-                const float pf = fmaf(fm, seg.gf, seg.bf), ps = fmaf(fm, seg.gs, seg.bs);
-                const float ff = floorf(pf), fs = floorf(ps);
-                const float wf = pf - ff, ws = ps - fs;
-                const int lf = static_cast<int>(fminf(fmaxf(ff, -2.0f), 70000.0f)) - f0;
-                const int ls = static_cast<int>(fminf(fmaxf(fs, -2.0f), 70000.0f)) - s0;
-                const int base = ((m - a0) * TS + ls) * TF + lf;
-                const bool f0ok = lf >= 0 && lf < f1 - f0, f1ok = lf + 1 >= 0 && lf + 1 < f1 - f0;
-                const bool s0ok = ls >= 0 && ls < s1 - s0, s1ok = ls + 1 >= 0 && ls + 1 < s1 - s0;
-                const float t0 = qs - qs * ws, t1 = qs * ws;
-                const long long c00 = static_cast<int>(t0 - t0 * wf), c01 = static_cast<int>(t0 * wf);
-                const long long c10 = static_cast<int>(t1 - t1 * wf), c11 = static_cast<int>(t1 * wf);
-                atomicAdd(&acc[(f0ok && s0ok) ? base : discard], static_cast<unsigned long long>(c00));
-                atomicAdd(&acc[(f1ok && s0ok) ? base + 1 : discard], static_cast<unsigned long long>(c01));
-                atomicAdd(&acc[(f0ok && s1ok) ? base + TF : discard], static_cast<unsigned long long>(c10));
-                atomicAdd(&acc[(f1ok && s1ok) ? base + TF + 1 : discard], static_cast<unsigned long long>(c11));
+        for (int cb = 0; cb < ncand; cb += 256) {
+            // ---- phase A: set-up of 256 candidates, compacted into LDS
+            const int idx = cb + t;
+            if (idx < ncand) {
+                // parity classes (c - cu0, r - cv0) mod 2, each row-major
+                int j = idx, pc, pr, w;
+                if (j < n00) { pc = 0; pr = 0; w = wu_e; }
+                else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; }
+                else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; }
+                else { j -= n01; pc = 1; pr = 1; w = wu_o; }
+                const int c = cu0 + pc + 2 * (j % w);
+                const int r = cv0 + pr + 2 * (j / w);
+                const float qraw = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]);  // in flight during set-up
+                RaySeg seg;
+                ray_setup_local(tv, static_cast<double>(c), static_cast<double>(r), p.s, a, seg);
+                if (seg.axis == a) {
+                    // halo-local offsets: local = global - (f0 - 1), global - (s0 - SLO)
+                    const float bfl = seg.bf - static_cast<float>(f0 - 1);
+                    const float bsl = seg.bs - static_cast<float>(s0 - SLO);
+                    // planes whose sample lies in the dilated block (+-1 plane slack)
+                    float lo = static_cast<float>(a0), hi = static_cast<float>(a1 - 1);
+                    clip_range_f(bfl, seg.gf, 0.0f, fmaxl, lo, hi);
+                    clip_range_f(bsl, seg.gs, 0.0f, smaxl, lo, hi);
+                    if (lo <= hi) {
+                        const int m0 = max(static_cast<int>(lo), a0);
+                        const int m1 = min(static_cast<int>(hi), a1 - 1);
+                        if (m0 <= m1) {
+                            const int slot = atomicAdd(&s_cnt[parity][0], 1);
+                            s_ray[slot] = make_float4(seg.gf, bfl, seg.gs, bsl);
+                            s_q[slot] = qraw * seg.ds * scale;
+                            const int nseg = (m1 - m0 + K) / K;
+                            const int sb = atomicAdd(&s_cnt[parity][1], nseg);
+                            for (int k = 0; k < nseg; ++k) {
+                                const int ms = m0 + k * K;
+                                const int cnt = min(K, m1 - ms + 1);
+                                s_seg[sb + k] = static_cast<uint32_t>(slot) | static_cast<uint32_t>(ms - a0) << 8 |
+                                                static_cast<uint32_t>(cnt) << 16;
+                            }
+                        }
+                    }
+                }
             }
+            __syncthreads();
+            // ---- phase B: scatter segments
+            const int nseg_all = s_cnt[parity][1];
+            if (t == 0) {
+                s_cnt[parity ^ 1][0] = 0;
+                s_cnt[parity ^ 1][1] = 0;
+            }
+            for (int e = t; e < nseg_all; e += 256) {
+                const uint32_t rec = s_seg[e];
+                const int slot = rec & 0xff, la0 = (rec >> 8) & 0xff, cnt = rec >> 16;
+                const float4 rp = s_ray[slot];
+                const float qs = s_q[slot];
+                for (int k = 0; k < cnt; ++k) {
+                    const int la = la0 + k;
+                    const float fm = static_cast<float>(a0 + la);
+                    const float pf = fminf(fmaxf(fmaf(fm, rp.x, rp.y), 0.0f), fmaxl);
+                    const float ps = fminf(fmaxf(fmaf(fm, rp.z, rp.w), 0.0f), smaxl);
+                    const float ff = floorf(pf), fs = floorf(ps);
+                    const float wf = pf - ff, ws = ps - fs;
+                    const int cell = (la * RP + static_cast<int>(fs)) * RW + static_cast<int>(ff);
+                    const float t1 = qs * ws, t0 = qs - t1;
+                    const float c01f = t0 * wf, c11f = t1 * wf;
+                    const long long c00 = static_cast<int>(t0 - c01f), c01 = static_cast<int>(c01f);
+                    const long long c10 = static_cast<int>(t1 - c11f), c11 = static_cast<int>(c11f);
+                    unsigned long long *q = acc + cell;
+                    atomicAdd(q, static_cast<unsigned long long>(c00));
+                    atomicAdd(q + 1, static_cast<unsigned long long>(c01));
+                    atomicAdd(q + RW, static_cast<unsigned long long>(c10));
+                    atomicAdd(q + RW + 1, static_cast<unsigned long long>(c11));
+                }
+            }
+            __syncthreads();
+            parity ^= 1;
         }
     }
-    __syncthreads();
 
     // write the block; the memory-contiguous axis x runs fastest
     const double inv_scale = scale > 0.0f ? 1.0 / static_cast<double>(scale) : 0.0;
     const int na = a1 - a0, ns = s1 - s0, nf = f1 - f0;
     const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
     float *out = p.out + b * item;
-    for (int e = threadIdx.x; e < na * ns * nf; e += blockDim.x) {
+    for (int e = t; e < na * ns * nf; e += 256) {
         int la, ls, lf;
         if (a == 0) {  // x = a
             la = e % na;
@@ -574,7 +713,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         ijk[sl] = s0 + ls;
         ijk[f] = f0 + lf;
         const int64_t o = (static_cast<int64_t>(ijk[2]) * p.n[1] + ijk[1]) * p.n[0] + ijk[0];
-        const long long sum = static_cast<long long>(acc[(la * TS + ls) * TF + lf]);
+        const long long sum = static_cast<long long>(acc[(la * RP + ls + SLO) * RW + lf + 1]);
         const float v = static_cast<float>(static_cast<double>(sum) * inv_scale);
         out[o] = p.accumulate ? out[o] + v : v;
     }
@@ -697,12 +836,18 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
     }
 }
 
+int64_t forward_blocks(const FwdParams &p)
+{
+    const int64_t tiles = static_cast<int64_t>(p.tiles_u) * p.tiles_v;
+    return 8 * ((tiles + 7) / 8) * p.n_views * p.batch;
+}
+
 template <typename S, typename O>
 static hipError_t forward_t(const FwdParams &p, hipStream_t st)
 {
-    const int64_t blocks = static_cast<int64_t>(p.tiles_u) * p.tiles_v * p.n_views * p.batch;
+    const int64_t blocks = forward_blocks(p);
     if (p.tile_v == 1)
-        forward_kernel<S, O, 256, 1, 8, 4, 320><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+        forward_kernel<S, O, 256, 1, 8, 3, 320><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
     else
         forward_kernel<S, O, 16, 16, 8, 32, 32><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
     return hipGetLastError();
@@ -735,7 +880,7 @@ void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv)
 
 void adjoint_block_shape(bool two_d, int32_t &L, int32_t &TS, int32_t &TF)
 {
-    if (two_d) { L = 64; TS = 1; TF = 64; }
+    if (two_d) { L = 32; TS = 1; TF = 64; }
     else { L = 32; TS = 8; TF = 16; }
 }
 
@@ -744,9 +889,9 @@ static hipError_t adjoint_q(const AdjParams &p, bool two_d, hipStream_t st)
 {
     const int64_t blocks = static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch;
     if (two_d)
-        adjoint_kernel<Q, 64, 1, 64><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+        adjoint_kernel<Q, 32, 1, 64, 0, 1><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
     else
-        adjoint_kernel<Q, 32, 8, 16><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+        adjoint_kernel<Q, 32, 8, 16, 1, 2><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
     return hipGetLastError();
 }
 
