@@ -57,6 +57,7 @@ struct FwdParams {
 
 struct AdjParams {
     const ViewTab *tab;
+    const ViewTabF *tabf;
     const uint32_t *maxabs;  // bit pattern of max |sino| (fixed-point scale)
     float ds_bound;          // upper bound of the ray length per plane (mm)
     const int32_t *views;  // views processed by this pass

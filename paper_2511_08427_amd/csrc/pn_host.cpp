@@ -571,6 +571,7 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
         const int f = a == 0 ? 1 : 0, sl = a == 2 ? 1 : 2;
         AdjParams p{};
         p.tab = pl->d_tab;
+        p.tabf = pl->d_tabf;
         p.maxabs = pl->d_maxabs;
         p.ds_bound = ds_bound;
         p.views = pl->d_views[a];

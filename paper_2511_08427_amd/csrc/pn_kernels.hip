@@ -474,18 +474,27 @@ __global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
             if (!part) continue;
             const int ma = max(now.mc, seg.m0), mb = min(now.me, seg.m1);
             if (now.lds) {
+                // box-local positions: the clamp to [-1, n] (zero padding
+                // outside the grid) is shifted into the box frame and also
+                // keeps both taps inside the staged box; positions are >= 0,
+                // so truncation is floor
                 const float fo = static_cast<float>(now.f_al), so = static_cast<float>(now.s_lo);
-                const int imax_f = now.nvec * VE - 2, imax_s = now.ns - 2;
-                for (int m = ma; m <= mb; ++m) {
-                    const float fm = static_cast<float>(m);
-                    const float pf = fminf(fmaxf(fmaf(fm, seg.gf, seg.bf), -1.0f), nf) - fo;
-                    const float ps = fminf(fmaxf(fmaf(fm, seg.gs, seg.bs), -1.0f), ns) - so;
-                    const float ff = floorf(pf), fs = floorf(ps);
-                    const float wf = pf - ff, ws = ps - fs;
-                    // the box holds every tap; the clamp only guards LDS addressing
-                    const int i_f = min(max(static_cast<int>(ff), 0), imax_f);
-                    const int i_s = min(max(static_cast<int>(fs), 0), imax_s);
-                    const float *q = box + ((m - now.mc) * RCAP + i_s) * FCAP + i_f;
+                const float bfl = seg.bf - fo, bsl = seg.bs - so;  // exact: integer shifts
+                // every position of the tile lies more than 1e-3 inside the
+                // box, so the upper limits just below the last staged column
+                // and row only guard LDS addressing
+                const float lo_f = fmaxf(-1.0f - fo, 0.0f);
+                const float hi_f = fminf(nf - fo, static_cast<float>(now.nvec * VE - 1) - 1e-3f);
+                const float lo_s = fmaxf(-1.0f - so, 0.0f);
+                const float hi_s = fminf(ns - so, static_cast<float>(now.ns - 1) - 1e-3f);
+                const float *pbox = box + (ma - now.mc) * (RCAP * FCAP);
+                float fm = static_cast<float>(ma);
+                for (int m = ma; m <= mb; ++m, fm += 1.0f, pbox += RCAP * FCAP) {
+                    const float pf = __builtin_amdgcn_fmed3f(fmaf(fm, seg.gf, bfl), lo_f, hi_f);
+                    const float ps = __builtin_amdgcn_fmed3f(fmaf(fm, seg.gs, bsl), lo_s, hi_s);
+                    const float wf = __builtin_amdgcn_fractf(pf), ws = __builtin_amdgcn_fractf(ps);
+                    const int i_f = static_cast<int>(pf), i_s = static_cast<int>(ps);
+                    const float *q = pbox + __mul24(i_s, FCAP) + i_f;
                     const float v00 = q[0], v01 = q[1], v10 = q[FCAP], v11 = q[FCAP + 1];
                     const float lo = fmaf(wf, v01 - v00, v00);
                     const float hi = fmaf(wf, v11 - v10, v10);
@@ -586,28 +595,41 @@ __global__ __launch_bounds__(256, 2) void adjoint_kernel(AdjParams p)
     for (int pv = 0; pv < p.n_pass_views; ++pv) {
         const int view = p.views[pv];
         const ViewTab &tv = p.tab[view];
-        double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+        // detector bounding box of the block dilated by one voxel in-plane:
+        // lanes 0-7 of every wave project one corner each (FP32; the 0.01
+        // pixel margin covers its rounding), then a butterfly min/max
+        float umin, umax, vmin, vmax;
+        {
+            const int lane = t & 63, corner = lane & 7;
+            float ijk[3];
+            ijk[a] = (corner & 1) ? static_cast<float>(a1 - 1) : static_cast<float>(a0);
+            ijk[sl] = (corner & 2) ? static_cast<float>(s1) : static_cast<float>(s0 - 1);
+            ijk[f] = (corner & 4) ? static_cast<float>(f1) : static_cast<float>(f0 - 1);
+            const ViewTabF &tf = p.tabf[view];
+            const float U = fmaf(tf.Pi[0], ijk[0], fmaf(tf.Pi[1], ijk[1], fmaf(tf.Pi[2], ijk[2], tf.Pi[3])));
+            const float V = fmaf(tf.Pi[4], ijk[0], fmaf(tf.Pi[5], ijk[1], fmaf(tf.Pi[6], ijk[2], tf.Pi[7])));
+            const float Wc = fmaf(tf.Pi[8], ijk[0], fmaf(tf.Pi[9], ijk[1], fmaf(tf.Pi[10], ijk[2], tf.Pi[11])));
+            const float uu = U / Wc, vv = V / Wc;
+            umin = umax = uu;
+            vmin = vmax = vv;
 #pragma unroll
-        for (int corner = 0; corner < 8; ++corner) {
-            double ijk[3];
-            ijk[a] = (corner & 1) ? static_cast<double>(a1 - 1) : static_cast<double>(a0);
-            ijk[sl] = (corner & 2) ? static_cast<double>(s1) : static_cast<double>(s0 - 1);
-            ijk[f] = (corner & 4) ? static_cast<double>(f1) : static_cast<double>(f0 - 1);
-            const double U = tv.Pi[0] * ijk[0] + tv.Pi[1] * ijk[1] + tv.Pi[2] * ijk[2] + tv.Pi[3];
-            const double V = tv.Pi[4] * ijk[0] + tv.Pi[5] * ijk[1] + tv.Pi[6] * ijk[2] + tv.Pi[7];
-            const double Wc = tv.Pi[8] * ijk[0] + tv.Pi[9] * ijk[1] + tv.Pi[10] * ijk[2] + tv.Pi[11];
-            const double iw = 1.0 / Wc;
-            umin = fmin(umin, U * iw);
-            umax = fmax(umax, U * iw);
-            vmin = fmin(vmin, V * iw);
-            vmax = fmax(vmax, V * iw);
+            for (int o = 1; o < 8; o <<= 1) {
+                umin = fminf(umin, __shfl_xor(umin, o));
+                umax = fmaxf(umax, __shfl_xor(umax, o));
+                vmin = fminf(vmin, __shfl_xor(vmin, o));
+                vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+            }
+            umin = __shfl(umin, 0) - 0.01f;
+            umax = __shfl(umax, 0) + 0.01f;
+            vmin = __shfl(vmin, 0) - 0.01f;
+            vmax = __shfl(vmax, 0) + 0.01f;
         }
         // clamp before converting: the bounds are finite (W > 0 over the
         // dilated volume) but may lie far outside the detector
-        const int cu0 = static_cast<int>(fmin(fmax(floor(umin), 0.0), static_cast<double>(p.nu)));
-        const int cu1 = static_cast<int>(fmax(fmin(ceil(umax), static_cast<double>(p.nu - 1)), -1.0));
-        const int cv0 = static_cast<int>(fmin(fmax(floor(vmin), 0.0), static_cast<double>(p.nv)));
-        const int cv1 = static_cast<int>(fmax(fmin(ceil(vmax), static_cast<double>(p.nv - 1)), -1.0));
+        const int cu0 = static_cast<int>(fminf(fmaxf(floorf(umin), 0.0f), static_cast<float>(p.nu)));
+        const int cu1 = static_cast<int>(fmaxf(fminf(ceilf(umax), static_cast<float>(p.nu - 1)), -1.0f));
+        const int cv0 = static_cast<int>(fminf(fmaxf(floorf(vmin), 0.0f), static_cast<float>(p.nv)));
+        const int cv1 = static_cast<int>(fmaxf(fminf(ceilf(vmax), static_cast<float>(p.nv - 1)), -1.0f));
         if (cu0 > cu1 || cv0 > cv1) continue;  // uniform
         const int wu = cu1 - cu0 + 1, wv = cv1 - cv0 + 1;
         const int wu_e = (wu + 1) >> 1, wu_o = wu >> 1, wv_e = (wv + 1) >> 1;
@@ -624,8 +646,10 @@ __global__ __launch_bounds__(256, 2) void adjoint_kernel(AdjParams p)
                 else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; }
                 else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; }
                 else { j -= n01; pc = 1; pr = 1; w = wu_o; }
-                const int c = cu0 + pc + 2 * (j % w);
-                const int r = cv0 + pr + 2 * (j / w);
+                // j / w via FP32: (j + 0.5) / w is >= 0.5/w away from an integer
+                const int jq = static_cast<int>((static_cast<float>(j) + 0.5f) / static_cast<float>(w));
+                const int c = cu0 + pc + 2 * (j - jq * w);
+                const int r = cv0 + pr + 2 * jq;
                 const float qraw = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]);  // in flight during set-up
                 RaySeg seg;
                 ray_setup_local(tv, static_cast<double>(c), static_cast<double>(r), p.s, a, seg);
@@ -668,19 +692,18 @@ __global__ __launch_bounds__(256, 2) void adjoint_kernel(AdjParams p)
                 const int slot = rec & 0xff, la0 = (rec >> 8) & 0xff, cnt = rec >> 16;
                 const float4 rp = s_ray[slot];
                 const float qs = s_q[slot];
-                for (int k = 0; k < cnt; ++k) {
-                    const int la = la0 + k;
-                    const float fm = static_cast<float>(a0 + la);
-                    const float pf = fminf(fmaxf(fmaf(fm, rp.x, rp.y), 0.0f), fmaxl);
-                    const float ps = fminf(fmaxf(fmaf(fm, rp.z, rp.w), 0.0f), smaxl);
-                    const float ff = floorf(pf), fs = floorf(ps);
-                    const float wf = pf - ff, ws = ps - fs;
-                    const int cell = (la * RP + static_cast<int>(fs)) * RW + static_cast<int>(ff);
+                unsigned long long *qrow = acc + __mul24(la0, PL);
+                float fm = static_cast<float>(a0 + la0);
+                for (int k = 0; k < cnt; ++k, fm += 1.0f, qrow += PL) {
+                    // halo-local positions are >= 0 after the clamp: truncation is floor
+                    const float pf = __builtin_amdgcn_fmed3f(fmaf(fm, rp.x, rp.y), 0.0f, fmaxl);
+                    const float ps = __builtin_amdgcn_fmed3f(fmaf(fm, rp.z, rp.w), 0.0f, smaxl);
+                    const float wf = __builtin_amdgcn_fractf(pf), ws = __builtin_amdgcn_fractf(ps);
+                    unsigned long long *q = qrow + __mul24(static_cast<int>(ps), RW) + static_cast<int>(pf);
                     const float t1 = qs * ws, t0 = qs - t1;
                     const float c01f = t0 * wf, c11f = t1 * wf;
                     const long long c00 = static_cast<int>(t0 - c01f), c01 = static_cast<int>(c01f);
                     const long long c10 = static_cast<int>(t1 - c11f), c11 = static_cast<int>(c11f);
-                    unsigned long long *q = acc + cell;
                     atomicAdd(q, static_cast<unsigned long long>(c00));
                     atomicAdd(q + 1, static_cast<unsigned long long>(c01));
                     atomicAdd(q + RW, static_cast<unsigned long long>(c10));
