@@ -58,8 +58,6 @@ struct FwdParams {
 struct AdjParams {
     const ViewTab *tab;
     const ViewTabF *tabf;
-    const uint32_t *maxabs;  // bit pattern of max |sino| (fixed-point scale)
-    float ds_bound;          // upper bound of the ray length per plane (mm)
     const int32_t *views;  // views processed by this pass
     int32_t n_pass_views;
     int32_t axis;          // dominant axis handled by this pass

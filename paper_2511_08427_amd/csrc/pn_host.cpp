@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <list>
 #include <memory>
@@ -21,14 +22,14 @@ namespace pn {
 hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32_t n[3], int axis, int32_t batch,
                            int64_t item, int32_t row, int64_t plane, hipStream_t st);
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
-hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, bool two_d, hipStream_t st);
+hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
 hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
-void adjoint_block_shape(bool two_d, int32_t &L, int32_t &TS, int32_t &TF);
+int adjoint_shape_count();
+void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF);
 void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv);
 int64_t forward_blocks(const FwdParams &p);
-hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st);
 }  // namespace pn
 
 namespace {
@@ -288,8 +289,6 @@ struct Plan {
     // FP32 accumulation buffer of the adjoint for 16-bit outputs
     float *d_acc = nullptr;
     size_t acc_cap = 0;
-    // max |sinogram| of the current adjoint call (fixed-point scale)
-    uint32_t *d_maxabs = nullptr;
 
     ~Plan()
     {
@@ -300,7 +299,6 @@ struct Plan {
             dev_free(d_lay[a]);
         }
         dev_free(d_acc);
-        dev_free(d_maxabs);
     }
 };
 
@@ -397,7 +395,6 @@ int get_plan(const pn_geometry *pg, Plan **out)
     if ((rc = upload(&pl->d_tabf, pl->tabf))) return rc;
     for (int a = 0; a < 3; ++a)
         if ((rc = upload(&pl->d_views[a], pl->pass_views[a]))) return rc;
-    if ((rc = upload(&pl->d_maxabs, std::vector<uint32_t>(1, 0u)))) return rc;
     g_plans.push_front(std::move(pl));
     while (g_plans.size() > kMaxPlans) g_plans.pop_back();
     *out = g_plans.front().get();
@@ -475,6 +472,18 @@ int ensure_work_copy(Plan &pl, int a, int32_t dt, int64_t batch, hipStream_t st)
     pl.lay_plane[a] = plane;
     pl.lay_row[a] = row;
     return PN_OK;
+}
+
+// 3-D adjoint block shape: PN_ADJ_SHAPE=<id> selects one of the compiled
+// shapes (1..count-1) for tuning; the default is shape 1 (32 x 16 x 16).
+int adjoint_shape_3d()
+{
+    static int shape = [] {
+        const char *e = std::getenv("PN_ADJ_SHAPE");
+        int v = e ? std::atoi(e) : 1;
+        return (v >= 1 && v < adjoint_shape_count()) ? v : 1;
+    }();
+    return shape;
 }
 
 int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt, int32_t out_dt,
@@ -558,13 +567,9 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
         target = pl->d_acc;
     }
     const bool two_d = g.ndim == 2;
+    const int shape = two_d ? 0 : adjoint_shape_3d();
     int32_t L, TS, TF;
-    adjoint_block_shape(two_d, L, TS, TF);
-    {
-        hipError_t e = launch_maxabs(in_dt, sino, (int64_t)g.n_views * g.nv * g.nu * batch, pl->d_maxabs, st);
-        if (e != hipSuccess) return fail_hip(e, "maxabs launch");
-    }
-    const float ds_bound = (float)(std::sqrt(g.s[0] * g.s[0] + g.s[1] * g.s[1] + g.s[2] * g.s[2]) * 1.0001);
+    adjoint_shape(shape, L, TS, TF);
     int done = 0;
     for (int a = 0; a < 3; ++a) {
         if (pl->pass_views[a].empty()) continue;
@@ -572,8 +577,6 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
         AdjParams p{};
         p.tab = pl->d_tab;
         p.tabf = pl->d_tabf;
-        p.maxabs = pl->d_maxabs;
-        p.ds_bound = ds_bound;
         p.views = pl->d_views[a];
         p.n_pass_views = (int32_t)pl->pass_views[a].size();
         p.axis = a;
@@ -593,7 +596,7 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
         p.blocks_f = (g.n[f] + TF - 1) / TF;
         if ((int64_t)p.blocks_a * p.blocks_s * p.blocks_f * batch > INT32_MAX)
             return fail(PN_EINVAL, "problem too large for one launch");
-        hipError_t e = launch_adjoint(p, in_dt, two_d, st);
+        hipError_t e = launch_adjoint(p, in_dt, shape, st);
         if (e != hipSuccess) return fail_hip(e, "adjoint launch");
         ++done;
     }

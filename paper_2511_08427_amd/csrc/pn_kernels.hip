@@ -133,7 +133,11 @@ __device__ __forceinline__ void ray_setup_local(const ViewTab &t, double u, doub
     r.m1 = -1;
     if (a != want) return;
     const int f = fast_axis(a), sl = slow_axis(a);
-    const double inv = 1.0 / d[a];
+    // 1/d[a]: hardware reciprocal refined by two Newton steps (full FP64
+    // accuracy; the results are rounded to FP32 anyway)
+    double inv = __builtin_amdgcn_rcp(d[a]);
+    inv = inv * fma(-d[a], inv, 2.0);
+    inv = inv * fma(-d[a], inv, 2.0);
     const double gf = d[f] * inv, gs = d[sl] * inv;
     r.gf = static_cast<float>(gf);
     r.gs = static_cast<float>(gs);
@@ -524,50 +528,58 @@ __global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
 
 // ------------------------------------------------------- adjoint A^T -----
 
-// Power-of-two scale that maps every contribution q*ds*w (|.| <= lim) into
-// [-2^29, 2^29].  Zero input: scale 1; non-finite input: scale 0.
-__device__ __forceinline__ float fixed_scale(float lim)
+// Round to nearest (halves up): v_cvt_rpi_i32_f32 computes floor(x + 0.5)
+// in one instruction; the compiler only forms it under fast-math.
+__device__ __forceinline__ int round_fixed(float x)
 {
-    if (!(lim > 0.0f)) return 1.0f;
-    if (!isfinite(lim)) return 0.0f;
-    const float e = fminf(fmaxf(floorf(log2f(536870912.0f / lim)), -126.0f), 126.0f);
-    return exp2f(e);
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
 }
 
 // Each workgroup owns a block of L planes (dominant axis `axis`) x TS rows x
-// TF columns of the output and keeps it in LDS as 64-bit fixed-point
-// accumulators with a halo of one cell below and two above in both in-plane
-// directions.  For every view of the pass:
-//   phase A  each thread takes one candidate pixel of the detector bounding
-//            box of the block (dilated by one voxel in-plane), does the ray's
-//            FP64 set-up and, if the ray has the pass axis as dominant axis
-//            and samples the dilated block, appends it to an LDS ray list
-//            together with its plane range cut into segments of <= K planes;
+// TF columns of the output.  Its FP32 sums live in registers (each thread
+// owns L*TS*TF/256 voxels); per batch of candidate rays they are gathered in
+// LDS as 32-bit fixed-point accumulators with a halo of one cell below and
+// two above in the fast in-plane direction (SLO/SHI in the slow one):
+//   phase A  each thread takes CPT candidate pixels of the detector bounding
+//            box of the block (dilated by one voxel in-plane), does the
+//            ray's FP64 set-up and, if the ray has the pass axis as dominant
+//            axis and samples the dilated block, appends it to an LDS ray
+//            list with its plane range cut into segments of <= K planes;
 //   phase B  each thread takes segments and scatters the bilinear taps of
-//            their samples.  Positions are clamped to the halo, where an
-//            out-of-block tap lands with an exactly-zero or discarded value.
-// Contributions q*ds*w are scaled by a power of two so that each fits in 30
-// bits, truncated to integers and added with ds_add_u64: integer addition is
-// exact and order-independent (the result is deterministic) and integer LDS
-// atomics run at the LDS store rate.  The block is written once per pass.
+//            their samples with ds_add_u32.  Positions are clamped to the
+//            halo, where an out-of-block tap lands with an exactly-zero or
+//            discarded value;
+//   flush    each thread moves its voxels' integer sums into its FP32
+//            registers and clears them.
+// A ray samples a voxel's plane once with weight <= 1, so a voxel's batch
+// sum is bounded by (rays in the batch) x max|q*ds|; the batch scale is the
+// power of two that maps that bound to 2^30.  Integer addition is exact and
+// order-independent and the flushes happen in a fixed order, so the result
+// is deterministic.  Contributions are rounded to nearest: the error per
+// contribution is <= 1/(2 scale) <= (rays x max|q*ds|) / 2^30.
 //
-// SLO/SHI are the halo rows below/above the block in the slow in-plane
-// direction: 1/2 in general; 0/1 for 2-D problems, whose rays have z == 0
-// exactly (the tap at z = 0 has weight 1 and the one at z = 1 weight 0).
-template <typename Q, int L, int TS, int TF, int SLO, int SHI>
-__global__ __launch_bounds__(256, 2) void adjoint_kernel(AdjParams p)
+// SLO/SHI: halo rows below/above the block in the slow in-plane direction,
+// 1/2 in general; 0/1 for 2-D problems, whose rays have z == 0 exactly (the
+// tap at z = 0 has weight 1 and the one at z = 1 weight 0).
+template <typename Q, int L, int TS, int TF, int SLO, int SHI, int CPT>
+__global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
 {
     constexpr int K = 8;                       // planes per segment
     constexpr int RW = TF + 3;                 // LDS row (halo: 1 before, 2 after)
     constexpr int RP = TS + SLO + SHI;         // LDS rows per plane
     constexpr int PL = RP * RW;                // LDS plane
-    constexpr int MAXSEG = 256 * ((L + K - 1) / K);
-    static_assert(L <= 64 && K <= 15, "segment record packing");
-    __shared__ unsigned long long acc[L * PL];
-    __shared__ float4 s_ray[256];              // gf, bf (halo-local), gs, bs (halo-local)
-    __shared__ float s_q[256];                 // q * ds * scale
-    __shared__ uint32_t s_seg[MAXSEG];         // ray | first plane << 8 | count << 16
-    __shared__ int s_cnt[2][2];                // [parity][rays, segments]
+    constexpr int NV = L * TS * TF;            // voxels of the block
+    constexpr int NQ = (NV + 255) / 256;       // voxels per thread
+    constexpr int MAXR = 256 * CPT;            // rays per batch
+    constexpr int MAXSEG = MAXR * ((L + K - 1) / K);
+    static_assert(L <= 64 && MAXR <= 65536, "segment record packing");
+    __shared__ int acc[L * PL];
+    __shared__ float4 s_ray[MAXR];             // gf, bf (halo-local), gs, bs (halo-local)
+    __shared__ float s_q[MAXR];                // q * ds
+    __shared__ uint32_t s_seg[MAXSEG];         // ray | first plane << 16 ... packed below
+    __shared__ uint32_t s_cnt[2][3];           // [parity][rays, segments, max |q*ds| bits]
 
     const int a = p.axis, f = fast_axis(a), sl = slow_axis(a);
     int blk = blockIdx.x;
@@ -585,9 +597,24 @@ __global__ __launch_bounds__(256, 2) void adjoint_kernel(AdjParams p)
     const float smaxl = static_cast<float>(min(s1 - s0 + 1, RP - 2));
     const int t = threadIdx.x;
 
-    for (int e = t; e < L * PL; e += 256) acc[e] = 0ull;
-    if (t < 4) s_cnt[t >> 1][t & 1] = 0;
-    const float scale = fixed_scale(__uint_as_float(*p.maxabs) * p.ds_bound);
+    // the voxels this thread owns: e = t + 256 q, x fastest (coalesced output)
+    float reg[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) reg[q] = 0.0f;
+    auto cell_of = [&](int e, int &la, int &ls, int &lf) {
+        if (a == 0) {  // x = a
+            la = e % L;
+            lf = (e / L) % TF;
+            ls = e / (L * TF);
+        } else {       // x = f
+            lf = e % TF;
+            la = (e / TF) % L;
+            ls = e / (TF * L);
+        }
+    };
+
+    for (int e = t; e < L * PL; e += 256) acc[e] = 0;
+    if (t < 6) s_cnt[t / 3][t % 3] = 0u;
     __syncthreads();
 
     const Q *sino_b = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
@@ -600,7 +627,7 @@ __global__ __launch_bounds__(256, 2) void adjoint_kernel(AdjParams p)
         // pixel margin covers its rounding), then a butterfly min/max
         float umin, umax, vmin, vmax;
         {
-            const int lane = t & 63, corner = lane & 7;
+            const int corner = t & 7;
             float ijk[3];
             ijk[a] = (corner & 1) ? static_cast<float>(a1 - 1) : static_cast<float>(a0);
             ijk[sl] = (corner & 2) ? static_cast<float>(s1) : static_cast<float>(s0 - 1);
@@ -609,9 +636,9 @@ __global__ __launch_bounds__(256, 2) void adjoint_kernel(AdjParams p)
             const float U = fmaf(tf.Pi[0], ijk[0], fmaf(tf.Pi[1], ijk[1], fmaf(tf.Pi[2], ijk[2], tf.Pi[3])));
             const float V = fmaf(tf.Pi[4], ijk[0], fmaf(tf.Pi[5], ijk[1], fmaf(tf.Pi[6], ijk[2], tf.Pi[7])));
             const float Wc = fmaf(tf.Pi[8], ijk[0], fmaf(tf.Pi[9], ijk[1], fmaf(tf.Pi[10], ijk[2], tf.Pi[11])));
-            const float uu = U / Wc, vv = V / Wc;
-            umin = umax = uu;
-            vmin = vmax = vv;
+            const float rw = __builtin_amdgcn_rcpf(Wc);
+            umin = umax = U * rw;
+            vmin = vmax = V * rw;
 #pragma unroll
             for (int o = 1; o < 8; o <<= 1) {
                 umin = fminf(umin, __shfl_xor(umin, o));
@@ -635,173 +662,308 @@ __global__ __launch_bounds__(256, 2) void adjoint_kernel(AdjParams p)
         const int wu_e = (wu + 1) >> 1, wu_o = wu >> 1, wv_e = (wv + 1) >> 1;
         const int n00 = wu_e * wv_e, n10 = wu_o * wv_e, n01 = wu_e * (wv >> 1);
         const int ncand = wu * wv;
+        const float rwe = __builtin_amdgcn_rcpf(static_cast<float>(wu_e));
+        const float rwo = wu_o > 0 ? __builtin_amdgcn_rcpf(static_cast<float>(wu_o)) : 0.0f;
         const Q *sino_v = sino_b + static_cast<int64_t>(view) * p.nv * p.nu;
-        for (int cb = 0; cb < ncand; cb += 256) {
-            // ---- phase A: set-up of 256 candidates, compacted into LDS
-            const int idx = cb + t;
-            if (idx < ncand) {
+        for (int cb = 0; cb < ncand; cb += MAXR) {
+            // ---- phase A: set-up of up to MAXR candidates, compacted into LDS
+#pragma unroll
+            for (int cq = 0; cq < CPT; ++cq) {
+                const int idx = cb + t + 256 * cq;
+                if (idx >= ncand) break;
                 // parity classes (c - cu0, r - cv0) mod 2, each row-major
                 int j = idx, pc, pr, w;
-                if (j < n00) { pc = 0; pr = 0; w = wu_e; }
-                else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; }
-                else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; }
-                else { j -= n01; pc = 1; pr = 1; w = wu_o; }
-                // j / w via FP32: (j + 0.5) / w is >= 0.5/w away from an integer
-                const int jq = static_cast<int>((static_cast<float>(j) + 0.5f) / static_cast<float>(w));
+                float rwc;
+                if (j < n00) { pc = 0; pr = 0; w = wu_e; rwc = rwe; }
+                else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; rwc = rwo; }
+                else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; rwc = rwe; }
+                else { j -= n01; pc = 1; pr = 1; w = wu_o; rwc = rwo; }
+                // j / w: reciprocal estimate, then an exact correction
+                int jq = static_cast<int>((static_cast<float>(j) + 0.5f) * rwc);
+                jq -= (jq * w > j) ? 1 : 0;
+                jq += ((jq + 1) * w <= j) ? 1 : 0;
                 const int c = cu0 + pc + 2 * (j - jq * w);
                 const int r = cv0 + pr + 2 * jq;
                 const float qraw = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]);  // in flight during set-up
                 RaySeg seg;
                 ray_setup_local(tv, static_cast<double>(c), static_cast<double>(r), p.s, a, seg);
-                if (seg.axis == a) {
-                    // halo-local offsets: local = global - (f0 - 1), global - (s0 - SLO)
-                    const float bfl = seg.bf - static_cast<float>(f0 - 1);
-                    const float bsl = seg.bs - static_cast<float>(s0 - SLO);
-                    // planes whose sample lies in the dilated block (+-1 plane slack)
-                    float lo = static_cast<float>(a0), hi = static_cast<float>(a1 - 1);
-                    clip_range_f(bfl, seg.gf, 0.0f, fmaxl, lo, hi);
-                    clip_range_f(bsl, seg.gs, 0.0f, smaxl, lo, hi);
-                    if (lo <= hi) {
-                        const int m0 = max(static_cast<int>(lo), a0);
-                        const int m1 = min(static_cast<int>(hi), a1 - 1);
-                        if (m0 <= m1) {
-                            const int slot = atomicAdd(&s_cnt[parity][0], 1);
-                            s_ray[slot] = make_float4(seg.gf, bfl, seg.gs, bsl);
-                            s_q[slot] = qraw * seg.ds * scale;
-                            const int nseg = (m1 - m0 + K) / K;
-                            const int sb = atomicAdd(&s_cnt[parity][1], nseg);
-                            for (int k = 0; k < nseg; ++k) {
-                                const int ms = m0 + k * K;
-                                const int cnt = min(K, m1 - ms + 1);
-                                s_seg[sb + k] = static_cast<uint32_t>(slot) | static_cast<uint32_t>(ms - a0) << 8 |
-                                                static_cast<uint32_t>(cnt) << 16;
-                            }
-                        }
-                    }
+                if (seg.axis != a) continue;
+                // halo-local offsets: local = global - (f0 - 1), global - (s0 - SLO)
+                const float bfl = seg.bf - static_cast<float>(f0 - 1);
+                const float bsl = seg.bs - static_cast<float>(s0 - SLO);
+                // planes whose sample lies in the dilated block (+-1 plane slack)
+                float lo = static_cast<float>(a0), hi = static_cast<float>(a1 - 1);
+                clip_range_f(bfl, seg.gf, 0.0f, fmaxl, lo, hi);
+                clip_range_f(bsl, seg.gs, 0.0f, smaxl, lo, hi);
+                if (!(lo <= hi)) continue;
+                const int m0 = max(static_cast<int>(lo), a0);
+                const int m1 = min(static_cast<int>(hi), a1 - 1);
+                if (m0 > m1) continue;
+                const float qs = qraw * seg.ds;
+                const int slot = static_cast<int>(atomicAdd(&s_cnt[parity][0], 1u));
+                s_ray[slot] = make_float4(seg.gf, bfl, seg.gs, bsl);
+                s_q[slot] = qs;
+                atomicMax(&s_cnt[parity][2], __float_as_uint(fabsf(qs)));
+                const int nseg = (m1 - m0 + K) / K;
+                const int sb = static_cast<int>(atomicAdd(&s_cnt[parity][1], static_cast<uint32_t>(nseg)));
+                for (int k = 0; k < nseg; ++k) {
+                    const int ms = m0 + k * K;
+                    const int cnt = min(K, m1 - ms + 1);
+                    s_seg[sb + k] = static_cast<uint32_t>(slot) | static_cast<uint32_t>(ms - a0) << 16 |
+                                    static_cast<uint32_t>(cnt) << 24;
                 }
             }
             __syncthreads();
-            // ---- phase B: scatter segments
-            const int nseg_all = s_cnt[parity][1];
+            // ---- phase B: scatter segments (fixed point)
+            const int nray = static_cast<int>(s_cnt[parity][0]);
+            const int nseg_all = static_cast<int>(s_cnt[parity][1]);
+            const float qmax = __uint_as_float(s_cnt[parity][2]);
             if (t == 0) {
-                s_cnt[parity ^ 1][0] = 0;
-                s_cnt[parity ^ 1][1] = 0;
+                s_cnt[parity ^ 1][0] = 0u;
+                s_cnt[parity ^ 1][1] = 0u;
+                s_cnt[parity ^ 1][2] = 0u;
             }
+            const float bound = static_cast<float>(nray) * qmax;
+            float scale = 1.0f;
+            if (bound > 0.0f)
+                scale = isfinite(bound) ? exp2f(fminf(fmaxf(floorf(log2f(1073741824.0f / bound)), -126.0f), 126.0f))
+                                        : 0.0f;
             for (int e = t; e < nseg_all; e += 256) {
                 const uint32_t rec = s_seg[e];
-                const int slot = rec & 0xff, la0 = (rec >> 8) & 0xff, cnt = rec >> 16;
+                const int slot = rec & 0xffff, la0 = (rec >> 16) & 0xff, cnt = rec >> 24;
                 const float4 rp = s_ray[slot];
-                const float qs = s_q[slot];
-                unsigned long long *qrow = acc + __mul24(la0, PL);
+                const float qs = s_q[slot] * scale;
+                int *qrow = acc + __mul24(la0, PL);
                 float fm = static_cast<float>(a0 + la0);
                 for (int k = 0; k < cnt; ++k, fm += 1.0f, qrow += PL) {
                     // halo-local positions are >= 0 after the clamp: truncation is floor
                     const float pf = __builtin_amdgcn_fmed3f(fmaf(fm, rp.x, rp.y), 0.0f, fmaxl);
                     const float ps = __builtin_amdgcn_fmed3f(fmaf(fm, rp.z, rp.w), 0.0f, smaxl);
                     const float wf = __builtin_amdgcn_fractf(pf), ws = __builtin_amdgcn_fractf(ps);
-                    unsigned long long *q = qrow + __mul24(static_cast<int>(ps), RW) + static_cast<int>(pf);
+                    int *q = qrow + __mul24(static_cast<int>(ps), RW) + static_cast<int>(pf);
                     const float t1 = qs * ws, t0 = qs - t1;
                     const float c01f = t0 * wf, c11f = t1 * wf;
-                    const long long c00 = static_cast<int>(t0 - c01f), c01 = static_cast<int>(c01f);
-                    const long long c10 = static_cast<int>(t1 - c11f), c11 = static_cast<int>(c11f);
-                    atomicAdd(q, static_cast<unsigned long long>(c00));
-                    atomicAdd(q + 1, static_cast<unsigned long long>(c01));
-                    atomicAdd(q + RW, static_cast<unsigned long long>(c10));
-                    atomicAdd(q + RW + 1, static_cast<unsigned long long>(c11));
+                    atomicAdd(q, round_fixed(t0 - c01f));
+                    atomicAdd(q + 1, round_fixed(c01f));
+                    atomicAdd(q + RW, round_fixed(t1 - c11f));
+                    atomicAdd(q + RW + 1, round_fixed(c11f));
                 }
             }
             __syncthreads();
+            // ---- flush: integer batch sums -> FP32 registers
+            if (nray > 0) {
+                const float inv_scale = scale > 0.0f ? 1.0f / scale : 0.0f;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int e = t + 256 * q;
+                    if (e < NV) {
+                        int la, ls, lf;
+                        cell_of(e, la, ls, lf);
+                        int *cellp = acc + (la * RP + ls + SLO) * RW + lf + 1;
+                        reg[q] = fmaf(static_cast<float>(*cellp), inv_scale, reg[q]);
+                        *cellp = 0;
+                    }
+                }
+            }
+            // the next batch's scatter starts after the next phase A barrier;
+            // halo cells are never read, so they are not cleared
             parity ^= 1;
         }
     }
 
     // write the block; the memory-contiguous axis x runs fastest
-    const double inv_scale = scale > 0.0f ? 1.0 / static_cast<double>(scale) : 0.0;
-    const int na = a1 - a0, ns = s1 - s0, nf = f1 - f0;
     const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
     float *out = p.out + b * item;
-    for (int e = t; e < na * ns * nf; e += 256) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int e = t + 256 * q;
+        if (e >= NV) continue;
         int la, ls, lf;
-        if (a == 0) {  // x = a
-            la = e % na;
-            lf = (e / na) % nf;
-            ls = e / (na * nf);
-        } else {       // x = f
-            lf = e % nf;
-            la = (e / nf) % na;
-            ls = e / (nf * na);
-        }
+        cell_of(e, la, ls, lf);
+        if (a0 + la >= a1 || s0 + ls >= s1 || f0 + lf >= f1) continue;
         int ijk[3];
         ijk[a] = a0 + la;
         ijk[sl] = s0 + ls;
         ijk[f] = f0 + lf;
         const int64_t o = (static_cast<int64_t>(ijk[2]) * p.n[1] + ijk[1]) * p.n[0] + ijk[0];
-        const long long sum = static_cast<long long>(acc[(la * RP + ls + SLO) * RW + lf + 1]);
-        const float v = static_cast<float>(static_cast<double>(sum) * inv_scale);
-        out[o] = p.accumulate ? out[o] + v : v;
+        out[o] = p.accumulate ? out[o] + reg[q] : reg[q];
     }
-}
-
-// max |x| over a buffer, as the bit pattern of a non-negative float
-// (integer order = float order), combined with a global atomic max.
-template <typename Q>
-__global__ __launch_bounds__(256) void maxabs_kernel(const Q *__restrict__ src, int64_t n, uint32_t *__restrict__ out)
-{
-    float m = 0.0f;
-    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
-         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        m = fmaxf(m, fabsf(to_f32(src[e])));
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
 // ------------------------------------------------ back-projection --------
 
-template <typename Q, typename O>
+// Voxel-driven back-projection.  A workgroup owns a BX x BY x BZ block of
+// voxels; each thread accumulates a column of BZ voxels along z in
+// registers (one writer per voxel, no atomics).  Per view, the detector
+// rectangle that the block's voxel centres project into (the projection of
+// the block's corner box, widened by one tap) is staged into LDS, zero-
+// filled outside the detector, so every bilinear tap is an unchecked LDS
+// read; the next view's rectangle is loaded into registers while the
+// current one is used.  Rectangles larger than RCAP x CCAP fall back to
+// bounds-checked gathers from the sinogram.
+template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
 __global__ __launch_bounds__(256) void backproject_kernel(BpParams p)
 {
-    const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (e >= item) return;
-    const int i = static_cast<int>(e % p.n[0]);
-    const int j = static_cast<int>((e / p.n[0]) % p.n[1]);
-    const int k = static_cast<int>(e / (static_cast<int64_t>(p.n[0]) * p.n[1]));
-    const float fi = static_cast<float>(i), fj = static_cast<float>(j), fk = static_cast<float>(k);
+    static_assert(BX * BY == 256, "one voxel column per thread");
+    constexpr int NE = RCAP * CCAP;
+    constexpr int PER = (NE + 255) / 256;
+    __shared__ float s_det[2][NE];
+    const int t = threadIdx.x;
+    const int nbx = (p.n[0] + BX - 1) / BX, nby = (p.n[1] + BY - 1) / BY, nbz = (p.n[2] + BZ - 1) / BZ;
+    int blk = blockIdx.x;
+    const int bx = blk % nbx;
+    blk /= nbx;
+    const int by = blk % nby;
+    blk /= nby;
+    const int bz = blk % nbz;
+    const int b = blk / nbz;
+    const int i0 = bx * BX, j0 = by * BY, k0 = bz * BZ;
+    const int i1 = min(i0 + BX, p.n[0]) - 1, j1 = min(j0 + BY, p.n[1]) - 1, k1 = min(k0 + BZ, p.n[2]) - 1;
+    const int i = i0 + t % BX, j = j0 + t / BX;
+    const bool own = i <= i1 && j <= j1;
+    const float fi = static_cast<float>(i), fj = static_cast<float>(j), fk0 = static_cast<float>(k0);
     const Q *sino = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
-    float acc = 0.0f;
-    for (int view = 0; view < p.n_views; ++view) {
-        const ViewTabF &t = p.tabf[view];
-        const float U = fmaf(t.Pi[0], fi, fmaf(t.Pi[1], fj, fmaf(t.Pi[2], fk, t.Pi[3])));
-        const float V = fmaf(t.Pi[4], fi, fmaf(t.Pi[5], fj, fmaf(t.Pi[6], fk, t.Pi[7])));
-        const float Wc = fmaf(t.Pi[8], fi, fmaf(t.Pi[9], fj, fmaf(t.Pi[10], fk, t.Pi[11])));
-        const float rw = 1.0f / Wc;
-        const float u = U * rw, v = V * rw;
-        const float w = t.W0 * rw;
-        const float fu = floorf(u), fv = floorf(v);
-        const float wu = u - fu, wv = v - fv;
-        const int iu = static_cast<int>(fmaxf(fminf(fu, 1e9f), -2.0f));
-        const int iv = static_cast<int>(fmaxf(fminf(fv, 1e9f), -2.0f));
+    const float fnu = static_cast<float>(p.nu), fnv = static_cast<float>(p.nv);
+
+    struct Rect {
+        int u0, v0, nc, nr;
+        bool lds, any;
+    };
+    // detector rectangle of the block for one view (uniform)
+    auto rect_of = [&](int view) {
+        const ViewTabF &tf = p.tabf[view];
+        const int lane = t & 63, corner = lane & 7;
+        const float ci = (corner & 1) ? static_cast<float>(i1) : static_cast<float>(i0);
+        const float cj = (corner & 2) ? static_cast<float>(j1) : static_cast<float>(j0);
+        const float ck = (corner & 4) ? static_cast<float>(k1) : static_cast<float>(k0);
+        const float U = fmaf(tf.Pi[0], ci, fmaf(tf.Pi[1], cj, fmaf(tf.Pi[2], ck, tf.Pi[3])));
+        const float V = fmaf(tf.Pi[4], ci, fmaf(tf.Pi[5], cj, fmaf(tf.Pi[6], ck, tf.Pi[7])));
+        const float Wc = fmaf(tf.Pi[8], ci, fmaf(tf.Pi[9], cj, fmaf(tf.Pi[10], ck, tf.Pi[11])));
+        float umin = U / Wc, vmin = V / Wc;
+        float umax = umin, vmax = vmin;
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+            umin = fminf(umin, __shfl_xor(umin, o));
+            umax = fmaxf(umax, __shfl_xor(umax, o));
+            vmin = fminf(vmin, __shfl_xor(vmin, o));
+            vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+        }
+        // voxel positions are clamped to [-1, n] (zero padding), so the
+        // rectangle is clamped likewise; 0.01 px covers FP32 rounding
+        umin = fminf(fmaxf(__shfl(umin, 0) - 0.01f, -1.0f), fnu);
+        umax = fminf(fmaxf(__shfl(umax, 0) + 0.01f, -1.0f), fnu);
+        vmin = fminf(fmaxf(__shfl(vmin, 0) - 0.01f, -1.0f), fnv);
+        vmax = fminf(fmaxf(__shfl(vmax, 0) + 0.01f, -1.0f), fnv);
+        Rect rc;
+        rc.u0 = static_cast<int>(floorf(umin));
+        rc.v0 = static_cast<int>(floorf(vmin));
+        rc.nc = static_cast<int>(floorf(umax)) + 2 - rc.u0;
+        rc.nr = static_cast<int>(floorf(vmax)) + 2 - rc.v0;
+        // entirely outside the detector: every tap is zero
+        rc.any = !(umax <= -1.0f || umin >= fnu || vmax <= -1.0f || vmin >= fnv);
+        rc.lds = rc.nc <= CCAP && rc.nr <= RCAP;
+        return rc;
+    };
+    float pre[PER];
+    auto issue = [&](int view, const Rect &rc) {
+        if (!rc.lds || !rc.any) return;
         const Q *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
-        float v00 = 0.f, v01 = 0.f, v10 = 0.f, v11 = 0.f;
-        const bool c0 = iu >= 0 && iu < p.nu, c1 = iu + 1 >= 0 && iu + 1 < p.nu;
-        if (iv >= 0 && iv < p.nv) {
-            const Q *row = img + static_cast<int64_t>(iv) * p.nu;
-            if (c0) v00 = to_f32(row[iu]);
-            if (c1) v01 = to_f32(row[iu + 1]);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q;
+            const int rr = e / CCAP, cc = e % CCAP;
+            const int r = rc.v0 + rr, c = rc.u0 + cc;
+            float v = 0.0f;
+            if (rr < rc.nr && cc < rc.nc && r >= 0 && r < p.nv && c >= 0 && c < p.nu)
+                v = to_f32(img[static_cast<int64_t>(r) * p.nu + c]);
+            pre[q] = v;
         }
-        if (iv + 1 >= 0 && iv + 1 < p.nv) {
-            const Q *row = img + static_cast<int64_t>(iv + 1) * p.nu;
-            if (c0) v10 = to_f32(row[iu]);
-            if (c1) v11 = to_f32(row[iu + 1]);
+    };
+
+    float acc[BZ];
+#pragma unroll
+    for (int z = 0; z < BZ; ++z) acc[z] = 0.0f;
+    Rect cur = p.n_views > 0 ? rect_of(0) : Rect{0, 0, 0, 0, false, false};
+    if (p.n_views > 0) issue(0, cur);
+    for (int view = 0; view < p.n_views; ++view) {
+        const int buf = view & 1;
+        if (cur.lds && cur.any) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (t + 256 * q < NE) s_det[buf][t + 256 * q] = pre[q];
         }
-        const float lo = fmaf(wu, v01 - v00, v00);
-        const float hi = fmaf(wu, v11 - v10, v10);
-        acc = fmaf(w * w, fmaf(wv, hi - lo, lo), acc);
+        __syncthreads();  // staged rectangle visible; the other buffer is free
+        const Rect now = cur;
+        if (view + 1 < p.n_views) {
+            cur = rect_of(view + 1);
+            issue(view + 1, cur);
+        }
+        if (own && now.any) {
+            const ViewTabF &tf = p.tabf[view];
+            const float U0 = fmaf(tf.Pi[0], fi, fmaf(tf.Pi[1], fj, fmaf(tf.Pi[2], fk0, tf.Pi[3])));
+            const float V0 = fmaf(tf.Pi[4], fi, fmaf(tf.Pi[5], fj, fmaf(tf.Pi[6], fk0, tf.Pi[7])));
+            const float Wb = fmaf(tf.Pi[8], fi, fmaf(tf.Pi[9], fj, fmaf(tf.Pi[10], fk0, tf.Pi[11])));
+            if (now.lds) {
+                const float uo = static_cast<float>(now.u0), vo = static_cast<float>(now.v0);
+                const float hu = fminf(fnu - uo, static_cast<float>(now.nc - 1) - 1e-3f);
+                const float hv = fminf(fnv - vo, static_cast<float>(now.nr - 1) - 1e-3f);
+                const float lu = fmaxf(-1.0f - uo, 0.0f), lv = fmaxf(-1.0f - vo, 0.0f);
+                const float *det = s_det[buf];
+#pragma unroll
+                for (int z = 0; z < BZ; ++z) {
+                    const float fz = static_cast<float>(z);
+                    const float rw = __builtin_amdgcn_rcpf(fmaf(fz, tf.Pi[10], Wb));
+                    const float u = __builtin_amdgcn_fmed3f(fmaf(fmaf(fz, tf.Pi[2], U0), rw, -uo), lu, hu);
+                    const float v = __builtin_amdgcn_fmed3f(fmaf(fmaf(fz, tf.Pi[6], V0), rw, -vo), lv, hv);
+                    const float wu = __builtin_amdgcn_fractf(u), wv = __builtin_amdgcn_fractf(v);
+                    const float *q = det + __mul24(static_cast<int>(v), CCAP) + static_cast<int>(u);
+                    const float d00 = q[0], d01 = q[1], d10 = q[CCAP], d11 = q[CCAP + 1];
+                    const float lo = fmaf(wu, d01 - d00, d00);
+                    const float hi = fmaf(wu, d11 - d10, d10);
+                    const float w = tf.W0 * rw;
+                    acc[z] = fmaf(w * w, fmaf(wv, hi - lo, lo), acc[z]);
+                }
+            } else {
+                const Q *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
+#pragma unroll
+                for (int z = 0; z < BZ; ++z) {
+                    const float fz = static_cast<float>(z);
+                    const float Wc = fmaf(fz, tf.Pi[10], Wb);
+                    const float rw = 1.0f / Wc;
+                    const float u = fminf(fmaxf(fmaf(fz, tf.Pi[2], U0) * rw, -1.0f), fnu);
+                    const float v = fminf(fmaxf(fmaf(fz, tf.Pi[6], V0) * rw, -1.0f), fnv);
+                    const float fu = floorf(u), fv = floorf(v);
+                    const float wu = u - fu, wv = v - fv;
+                    const int iu = static_cast<int>(fu), iv = static_cast<int>(fv);
+                    float d00 = 0.f, d01 = 0.f, d10 = 0.f, d11 = 0.f;
+                    const bool c0 = iu >= 0 && iu < p.nu, c1 = iu + 1 < p.nu;
+                    if (iv >= 0 && iv < p.nv) {
+                        const Q *row = img + static_cast<int64_t>(iv) * p.nu;
+                        if (c0) d00 = to_f32(row[iu]);
+                        if (c1) d01 = to_f32(row[iu + 1]);
+                    }
+                    if (iv + 1 < p.nv) {
+                        const Q *row = img + static_cast<int64_t>(iv + 1) * p.nu;
+                        if (c0) d10 = to_f32(row[iu]);
+                        if (c1) d11 = to_f32(row[iu + 1]);
+                    }
+                    const float lo = fmaf(wu, d01 - d00, d00);
+                    const float hi = fmaf(wu, d11 - d10, d10);
+                    const float w = tf.W0 * rw;
+                    acc[z] = fmaf(w * w, fmaf(wv, hi - lo, lo), acc[z]);
+                }
+            }
+        }
+        __syncthreads();  // every voxel is done with this view's rectangle
     }
-    O *out = static_cast<O *>(p.vol);
-    out[b * item + e] = from_f32<O>(acc);
+    if (!own) return;
+    const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
+    O *out = static_cast<O *>(p.vol) + b * item;
+#pragma unroll
+    for (int z = 0; z < BZ; ++z) {
+        const int k = k0 + z;
+        if (k <= k1) out[(static_cast<int64_t>(k) * p.n[1] + j) * p.n[0] + i] = from_f32<O>(acc[z]);
+    }
 }
 
 // ------------------------------------------------------- utilities -------
@@ -901,53 +1063,54 @@ void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv)
     else { tu = 16; tv = 16; }
 }
 
-void adjoint_block_shape(bool two_d, int32_t &L, int32_t &TS, int32_t &TF)
+// Compiled adjoint block shapes (planes x rows x columns, candidates per
+// thread per batch); index 0 is 2-D.
+static const int32_t kAdjShapes[][4] = {{32, 1, 64, 1}, {32, 16, 16, 2}, {32, 8, 16, 1}, {16, 16, 16, 2}, {32, 16, 16, 1}};
+constexpr int kNumAdjShapes = 5;
+
+int adjoint_shape_count() { return kNumAdjShapes; }
+
+void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF)
 {
-    if (two_d) { L = 32; TS = 1; TF = 64; }
-    else { L = 32; TS = 8; TF = 16; }
+    L = kAdjShapes[id][0];
+    TS = kAdjShapes[id][1];
+    TF = kAdjShapes[id][2];
 }
 
 template <typename Q>
-static hipError_t adjoint_q(const AdjParams &p, bool two_d, hipStream_t st)
+static hipError_t adjoint_q(const AdjParams &p, int shape, hipStream_t st)
 {
-    const int64_t blocks = static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch;
-    if (two_d)
-        adjoint_kernel<Q, 32, 1, 64, 0, 1><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
-    else
-        adjoint_kernel<Q, 32, 8, 16, 1, 2><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+    const dim3 g(static_cast<uint32_t>(static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch));
+    switch (shape) {
+    case 0: adjoint_kernel<Q, 32, 1, 64, 0, 1, 1><<<g, 256, 0, st>>>(p); break;
+    case 1: adjoint_kernel<Q, 32, 16, 16, 1, 2, 2><<<g, 256, 0, st>>>(p); break;
+    case 2: adjoint_kernel<Q, 32, 8, 16, 1, 2, 1><<<g, 256, 0, st>>>(p); break;
+    case 3: adjoint_kernel<Q, 16, 16, 16, 1, 2, 2><<<g, 256, 0, st>>>(p); break;
+    default: adjoint_kernel<Q, 32, 16, 16, 1, 2, 1><<<g, 256, 0, st>>>(p); break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, bool two_d, hipStream_t st)
+hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st)
 {
     switch (in_dt) {
-    case DT_F32: return adjoint_q<float>(p, two_d, st);
-    case DT_BF16: return adjoint_q<bf16>(p, two_d, st);
-    default: return adjoint_q<f16>(p, two_d, st);
+    case DT_F32: return adjoint_q<float>(p, shape, st);
+    case DT_BF16: return adjoint_q<bf16>(p, shape, st);
+    default: return adjoint_q<f16>(p, shape, st);
     }
-}
-
-hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st)
-{
-    fill_zero_kernel<<<1, 64, 0, st>>>(out, 1);
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    const dim3 g(static_cast<uint32_t>(blocks));
-    switch (in_dt) {
-    case DT_F32: maxabs_kernel<float><<<g, 256, 0, st>>>(static_cast<const float *>(src), n, out); break;
-    case DT_BF16: maxabs_kernel<bf16><<<g, 256, 0, st>>>(static_cast<const bf16 *>(src), n, out); break;
-    default: maxabs_kernel<f16><<<g, 256, 0, st>>>(static_cast<const f16 *>(src), n, out); break;
-    }
-    return hipGetLastError();
 }
 
 template <typename Q, typename O>
 static hipError_t bp_t(const BpParams &p, hipStream_t st)
 {
-    const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
-    dim3 grid(static_cast<uint32_t>((item + 255) / 256), static_cast<uint32_t>(p.batch));
-    backproject_kernel<Q, O><<<grid, 256, 0, st>>>(p);
+    if (p.n[2] == 1) {
+        const int64_t blocks = static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * p.batch;
+        backproject_kernel<Q, O, 16, 16, 1, 4, 64><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+    } else {
+        const int64_t blocks =
+            static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * ((p.n[2] + 7) / 8) * p.batch;
+        backproject_kernel<Q, O, 16, 16, 8, 16, 32><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+    }
     return hipGetLastError();
 }
 
