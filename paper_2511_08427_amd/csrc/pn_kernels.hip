@@ -113,56 +113,6 @@ __device__ __forceinline__ void ray_setup(const ViewTab &t, double u, double v, 
     r.m1 = static_cast<int>(fmin(ceil(hi), static_cast<double>(n[a] - 1)));
 }
 
-// Set-up for the adjoint: as ray_setup but without the volume-wide plane
-// range (the caller clips to its block) and with the ray length per plane
-// from an FP32 square root (relative error ~1e-7).  seg.axis is the ray's
-// dominant axis; the slopes and offsets are for that axis.
-__device__ __forceinline__ void ray_setup_local(const ViewTab &t, double u, double v, const double s[3], int want,
-                                                RaySeg &r)
-{
-    double d[3], p[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        d[i] = fma(t.A[3 * i], u, fma(t.A[3 * i + 1], v, t.A[3 * i + 2]));
-        p[i] = fma(t.B[3 * i], u, fma(t.B[3 * i + 1], v, t.B[3 * i + 2]));
-    }
-    const double ax = fabs(d[0]), ay = fabs(d[1]), az = fabs(d[2]);
-    const int a = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
-    r.axis = a;
-    r.m0 = 0;
-    r.m1 = -1;
-    if (a != want) return;
-    const int f = fast_axis(a), sl = slow_axis(a);
-    // 1/d[a]: hardware reciprocal refined by two Newton steps (full FP64
-    // accuracy; the results are rounded to FP32 anyway)
-    double inv = __builtin_amdgcn_rcp(d[a]);
-    inv = inv * fma(-d[a], inv, 2.0);
-    inv = inv * fma(-d[a], inv, 2.0);
-    const double gf = d[f] * inv, gs = d[sl] * inv;
-    r.gf = static_cast<float>(gf);
-    r.gs = static_cast<float>(gs);
-    r.bf = static_cast<float>(fma(-p[a], gf, p[f]));
-    r.bs = static_cast<float>(fma(-p[a], gs, p[sl]));
-    const double wx = d[0] * s[0], wy = d[1] * s[1], wz = d[2] * s[2];
-    r.ds = sqrtf(static_cast<float>(wx * wx + wy * wy + wz * wz)) * static_cast<float>(fabs(inv));
-    if (!isfinite(r.ds)) r.axis = -1;
-}
-
-// FP32 version of clip_range with one plane of slack on each side (the
-// result only bounds loops whose every extra plane contributes zero).
-__device__ __forceinline__ void clip_range_f(float b, float g, float lo_pos, float hi_pos, float &lo, float &hi)
-{
-    if (g == 0.0f) {
-        if (!(b >= lo_pos && b <= hi_pos)) { lo = 1.0f; hi = 0.0f; }
-        return;
-    }
-    const float rg = __builtin_amdgcn_rcpf(g);
-    float t0 = (lo_pos - b) * rg, t1 = (hi_pos - b) * rg;
-    if (t0 > t1) { const float tt = t0; t0 = t1; t1 = tt; }
-    lo = fmaxf(lo, floorf(t0) - 1.0f);
-    hi = fminf(hi, ceilf(t1) + 1.0f);
-}
-
 // ------------------------------------------------------- relayout --------
 
 // a = x: out[b][i][k + PADR_LO][j + PADC] = in[b][k][j][i] (tiled transpose)
@@ -311,9 +261,15 @@ struct Box {
 // of C planes; per chunk it stages the box of volume that the tile's rays can
 // touch (bounded by the four corner rays, whose crossings with a plane
 // enclose those of every ray in between) from the padded work copy into LDS
-// with 16-byte loads, and every ray then samples its planes from LDS.  The
-// loads of chunk i+1 are issued into registers before chunk i is sampled.
-// A box larger than RCAP x FCAP falls back to gathers from the work copy.
+// with 16-byte loads, and every ray then samples the chunk's planes from
+// LDS.  The loads of chunk i+1 are issued into registers before chunk i is
+// sampled, and the boxes of up to 256 chunks are computed at once, one
+// chunk per thread.  A box larger than RCAP x FCAP falls back to gathers
+// from the work copy.
+//
+// A ray samples every plane of a chunk, also planes outside its own range:
+// there its position lies outside [-1, n] in some in-plane axis and the
+// clamp puts all weight on a zero padding cell, so the sample is exactly 0.
 //
 // Workgroup order: consecutive workgroup ids go round-robin to the 8 XCDs;
 // each XCD gets every 8th tile and runs the views of a tile back to back, so
@@ -326,8 +282,10 @@ __global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
     constexpr int VE = Vec<S>::N;
     constexpr int VPR = FCAP / VE;
     constexpr int RPI = 256 / VPR;
+    constexpr int PLANE = RCAP * FCAP;
     static_assert(FCAP % VE == 0 && RPI >= RCAP, "one staged row per thread and plane");
-    __shared__ float box[C * RCAP * FCAP];
+    __shared__ float box[C * PLANE];
+    __shared__ int4 s_box[256];  // boxes of a window of chunks: f_al, s_lo, nvec | ns << 16, lds
     __shared__ float s_corner[4][4];
     __shared__ int s_dir[4];
     __shared__ int s_axes, s_m0, s_m1;
@@ -427,36 +385,70 @@ __global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
                     smn = fminf(smn, fminf(ps0, ps1));
                     smx = fmaxf(smx, fmaxf(ps0, ps1));
                 }
-                // samples are clamped to [-1, n]; widen for FP32 rounding
-                fmn = fminf(fmaxf(fmn - 1e-3f, -1.0f), nf);
-                fmx = fminf(fmaxf(fmx + 1e-3f, -1.0f), nf);
-                smn = fminf(fmaxf(smn - 1e-3f, -1.0f), ns);
-                smx = fminf(fmaxf(smx + 1e-3f, -1.0f), ns);
+                // widen for FP32 rounding; a box far outside the grid
+                // (which the staging fills with zeros) is cut to a size that
+                // cannot overflow the integer conversions below
+                fmn = fmaxf(fmn - 1e-3f, -1e6f);
+                fmx = fminf(fmx + 1e-3f, 1e6f);
+                smn = fmaxf(smn - 1e-3f, -1e6f);
+                smx = fminf(smx + 1e-3f, 1e6f);
                 const int f_lo = static_cast<int>(floorf(fmn)), f_hi = static_cast<int>(floorf(fmx)) + 1;
                 bx.s_lo = static_cast<int>(floorf(smn));
                 const int s_hi = static_cast<int>(floorf(smx)) + 1;
-                bx.f_al = (f_lo + 2 * VE) / VE * VE - 2 * VE;  // f_lo >= -1: round down to a multiple of VE
+                bx.f_al = f_lo >= 0 ? f_lo / VE * VE : -((VE - 1 - f_lo) / VE) * VE;  // round down to a multiple of VE
                 bx.nvec = (f_hi - bx.f_al) / VE + 1;
                 bx.ns = s_hi - bx.s_lo + 1;
-                bx.lds = bx.nvec <= VPR && bx.ns <= RCAP;
+                bx.lds = fmn <= fmx && smn <= smx && bx.nvec <= VPR && bx.ns <= RCAP;
             }
             return bx;
         };
-        // 16-byte loads of this thread's share of a box (one row per plane)
+        // boxes of chunks wb .. wb + 255, one per thread
+        auto window = [&](int wb) {
+            const int mc = M0 + (wb + t) * C;
+            if (mc <= M1) {
+                const Box bx = make_box(mc);
+                s_box[t] = make_int4(bx.f_al, bx.s_lo, bx.nvec | bx.ns << 16, bx.lds ? 1 : 0);
+            }
+        };
+        auto box_at = [&](int ci, int wb) {
+            const int mc = M0 + ci * C;
+            if (ci - wb >= 256) return make_box(mc);
+            const int4 v = s_box[ci - wb];
+            Box bx;
+            bx.mc = mc;
+            bx.me = min(mc + C - 1, M1);
+            bx.f_al = v.x;
+            bx.s_lo = v.y;
+            bx.nvec = v.z & 0xffff;
+            bx.ns = v.z >> 16;
+            bx.lds = v.w != 0;
+            return bx;
+        };
+        // 16-byte loads of this thread's share of a box (one row per plane);
+        // rows and vectors outside the padded work copy are zeros
+        const int32_t srows = p.n[sl] + PADR_LO + PADR_HI;
         uint4 pre[C];
         auto issue = [&](const Box &bx) {
             if (!bx.lds || rrow >= bx.ns || vr >= bx.nvec) return;
-            const S *src = base + static_cast<int64_t>(bx.s_lo + PADR_LO + rrow) * row + (bx.f_al + PADC) + vr * VE;
+            const int wr = bx.s_lo + PADR_LO + rrow;  // row of the work copy
+            const int wc = bx.f_al + PADC + vr * VE;  // column of the work copy (multiple of VE)
+            const bool in = wr >= 0 && wr < srows && wc >= 0 && wc + VE <= row;
+            const S *src = base + static_cast<int64_t>(in ? wr : 0) * row + (in ? wc : 0);
 #pragma unroll
-            for (int k = 0; k < C; ++k)
-                if (bx.mc + k <= bx.me)
+            for (int k = 0; k < C; ++k) {
+                pre[k] = make_uint4(0u, 0u, 0u, 0u);
+                if (in && bx.mc + k <= bx.me)
                     pre[k] = *reinterpret_cast<const uint4 *>(src + static_cast<int64_t>(bx.mc + k) * plane);
+            }
         };
 
-        Box cur = make_box(M0);
+        int wb = 0;
+        window(0);
+        __syncthreads();
+        Box cur = box_at(0, 0);
         issue(cur);
-        for (int mc = M0; mc <= M1; mc += C) {
-            __syncthreads();  // every ray is done with the previous box
+        for (int ci = 0, mc = M0; mc <= M1; ++ci, mc += C) {
+            __syncthreads();  // every ray is done with the previous box and window
             if (cur.lds && rrow < cur.ns && vr < cur.nvec) {
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
@@ -469,54 +461,84 @@ __global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
                         *reinterpret_cast<float4 *>(dst + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
                 }
             }
+            if (ci + 1 - wb == 256) {  // uniform
+                wb += 256;
+                window(wb);
+            }
             __syncthreads();
             const Box now = cur;
             if (mc + C <= M1) {
-                cur = make_box(mc + C);
+                cur = box_at(ci + 1, wb);
                 issue(cur);  // in flight while this chunk is sampled
             }
             if (!part) continue;
-            const int ma = max(now.mc, seg.m0), mb = min(now.me, seg.m1);
             if (now.lds) {
-                // box-local positions: the clamp to [-1, n] (zero padding
-                // outside the grid) is shifted into the box frame and also
-                // keeps both taps inside the staged box; positions are >= 0,
-                // so truncation is floor
+                // box-local positions (the shifts by the integer box origin
+                // are exact): every position of the tile lies more than 1e-3
+                // inside the box, which holds zeros outside the padded grid,
+                // so no clamp is needed; positions are >= 0, so truncation
+                // is floor.  The offset is capped to keep the reads inside
+                // the box array whatever the positions.
                 const float fo = static_cast<float>(now.f_al), so = static_cast<float>(now.s_lo);
-                const float bfl = seg.bf - fo, bsl = seg.bs - so;  // exact: integer shifts
-                // every position of the tile lies more than 1e-3 inside the
-                // box, so the upper limits just below the last staged column
-                // and row only guard LDS addressing
-                const float lo_f = fmaxf(-1.0f - fo, 0.0f);
-                const float hi_f = fminf(nf - fo, static_cast<float>(now.nvec * VE - 1) - 1e-3f);
-                const float lo_s = fmaxf(-1.0f - so, 0.0f);
-                const float hi_s = fminf(ns - so, static_cast<float>(now.ns - 1) - 1e-3f);
-                const float *pbox = box + (ma - now.mc) * (RCAP * FCAP);
-                float fm = static_cast<float>(ma);
-                for (int m = ma; m <= mb; ++m, fm += 1.0f, pbox += RCAP * FCAP) {
-                    const float pf = __builtin_amdgcn_fmed3f(fmaf(fm, seg.gf, bfl), lo_f, hi_f);
-                    const float ps = __builtin_amdgcn_fmed3f(fmaf(fm, seg.gs, bsl), lo_s, hi_s);
-                    const float wf = __builtin_amdgcn_fractf(pf), ws = __builtin_amdgcn_fractf(ps);
-                    const int i_f = static_cast<int>(pf), i_s = static_cast<int>(ps);
-                    const float *q = pbox + __mul24(i_s, FCAP) + i_f;
-                    const float v00 = q[0], v01 = q[1], v10 = q[FCAP], v11 = q[FCAP + 1];
-                    const float lo = fmaf(wf, v01 - v00, v00);
-                    const float hi = fmaf(wf, v11 - v10, v10);
-                    acc += fmaf(ws, hi - lo, lo);
-                }
-            } else if (p.lay[a] != nullptr) {
-                const S *lay = static_cast<const S *>(p.lay[a]) + b * p.lay_item[a];
-                for (int m = ma; m <= mb; ++m) {
-                    const float fm = static_cast<float>(m);
-                    acc += sample_padded(lay + m * plane, row, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs), nf,
-                                         ns);
+                const float fmc = static_cast<float>(now.mc);
+                const float pf0 = fmaf(fmc, seg.gf, seg.bf - fo);
+                const float ps0 = fmaf(fmc, seg.gs, seg.bs - so);
+                const int kn = now.me - now.mc;
+                // taps of plane k: the reads of plane k + 1 are issued
+                // before plane k is interpolated (planes past the chunk's
+                // last read stale in-bounds LDS and are not used)
+                float tv[2][4], twf[2], tws[2];
+                auto fetch = [&](int k, int slot) {
+                    const float pf = fmaf(static_cast<float>(k), seg.gf, pf0);
+                    const float ps = fmaf(static_cast<float>(k), seg.gs, ps0);
+                    twf[slot] = __builtin_amdgcn_fractf(pf);
+                    tws[slot] = __builtin_amdgcn_fractf(ps);
+                    uint32_t off = __mul24(static_cast<uint32_t>(ps), static_cast<uint32_t>(FCAP * 4)) +
+                                   static_cast<uint32_t>(k * PLANE * 4);
+                    off = min(off + (static_cast<uint32_t>(pf) << 2), static_cast<uint32_t>((C * PLANE - FCAP - 2) * 4));
+                    asm volatile("" : "+v"(off));  // one base register for all four taps
+                    const float *q = reinterpret_cast<const float *>(reinterpret_cast<const char *>(box) + off);
+                    tv[slot][0] = q[0];
+                    tv[slot][1] = q[1];
+                    tv[slot][2] = q[FCAP];
+                    tv[slot][3] = q[FCAP + 1];
+                };
+                auto interp = [&](int slot) {
+                    const float lo = fmaf(twf[slot], tv[slot][1] - tv[slot][0], tv[slot][0]);
+                    const float hi = fmaf(twf[slot], tv[slot][3] - tv[slot][2], tv[slot][2]);
+                    acc += fmaf(tws[slot], hi - lo, lo);
+                };
+                fetch(0, 0);
+                if (kn == C - 1) {  // whole chunk (uniform): straight-line code
+#pragma unroll
+                    for (int k = 0; k < C; ++k) {
+                        if (k + 1 < C) fetch(k + 1, (k + 1) & 1);
+                        interp(k & 1);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < C; ++k) {
+                        if (k > kn) break;  // uniform
+                        if (k + 1 < C) fetch(k + 1, (k + 1) & 1);
+                        interp(k & 1);
+                    }
                 }
             } else {
-                const S *vol = static_cast<const S *>(p.vol) +
-                               static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
-                for (int m = ma; m <= mb; ++m) {
-                    const float fm = static_cast<float>(m);
-                    acc += sample_raw(vol, p.n, a, m, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs));
+                const int ma = max(now.mc, seg.m0), mb = min(now.me, seg.m1);
+                if (p.lay[a] != nullptr) {
+                    const S *lay = static_cast<const S *>(p.lay[a]) + b * p.lay_item[a];
+                    for (int m = ma; m <= mb; ++m) {
+                        const float fm = static_cast<float>(m);
+                        acc += sample_padded(lay + m * plane, row, fmaf(fm, seg.gf, seg.bf),
+                                             fmaf(fm, seg.gs, seg.bs), nf, ns);
+                    }
+                } else {
+                    const S *vol = static_cast<const S *>(p.vol) +
+                                   static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
+                    for (int m = ma; m <= mb; ++m) {
+                        const float fm = static_cast<float>(m);
+                        acc += sample_raw(vol, p.n, a, m, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs));
+                    }
                 }
             }
         }
@@ -537,16 +559,64 @@ __device__ __forceinline__ int round_fixed(float x)
     return r;
 }
 
-// Each workgroup owns a block of L planes (dominant axis `axis`) x TS rows x
-// TF columns of the output.  Its FP32 sums live in registers (each thread
-// owns L*TS*TF/256 voxels); per batch of candidate rays they are gathered in
-// LDS as 32-bit fixed-point accumulators with a halo of one cell below and
-// two above in the fast in-plane direction (SLO/SHI in the slow one):
+// Wave-wide helpers for the adjoint's ray-list compaction.  They are called
+// with every lane of the wave active.
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), o)));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Axes of a pass: a is the dominant (plane) axis, f and s the in-plane fast
+// and slow axes.  A ray belongs to pass a when |delta_a| is the largest
+// component, exact ties going to the lowest axis.
+template <int A>
+struct PassAxes {
+    static constexpr int F = A == 0 ? 1 : 0;
+    static constexpr int S = A == 2 ? 1 : 2;
+    __device__ static bool dominant(double da, double df, double ds)
+    {
+        const double aa = fabs(da), af = fabs(df), as = fabs(ds);
+        // f < a unless A == 0; s > a unless A == 2
+        const bool vs_f = A == 0 ? aa >= af : aa > af;
+        const bool vs_s = A == 2 ? aa > as : aa >= as;
+        return vs_f && vs_s;
+    }
+};
+
+// Narrows the local plane range [lo, hi] to the planes m where b + m*g lies
+// in [0, hi_pos] (widened by 1e-3), with one plane of slack on each side.
+// The extra planes contribute exactly zero: their clamped positions put all
+// weight on discarded halo cells.  Branch-free: a zero slope is replaced by
+// a tiny positive one, which keeps or empties the whole range as the exact
+// test would (the widening keeps b == 0 or b == hi_pos inside).
+__device__ __forceinline__ void clip_local(float b, float g, float hi_pos, float &lo, float &hi)
+{
+    const float gg = fabsf(g) < 1e-30f ? 1e-30f : g;
+    const float rg = __builtin_amdgcn_rcpf(gg);
+    const float t0 = (-1e-3f - b) * rg, t1 = (hi_pos + 1e-3f - b) * rg;
+    lo = fmaxf(lo, floorf(fminf(t0, t1)) - 1.0f);
+    hi = fminf(hi, ceilf(fmaxf(t0, t1)) + 1.0f);
+}
+
+// Each workgroup owns a block of L planes (dominant axis A) x TS rows x TF
+// columns of the output.  Its FP32 sums live in registers (each thread owns
+// L*TS*TF/256 voxels); per batch of candidate rays they are gathered in LDS
+// as 32-bit fixed-point accumulators with a halo of one cell below and two
+// above in the fast in-plane direction (SLO/SHI in the slow one):
 //   phase A  each thread takes CPT candidate pixels of the detector bounding
 //            box of the block (dilated by one voxel in-plane), does the
-//            ray's FP64 set-up and, if the ray has the pass axis as dominant
-//            axis and samples the dilated block, appends it to an LDS ray
-//            list with its plane range cut into segments of <= K planes;
+//            ray's FP64 set-up in the block's local frame and, if the ray
+//            has A as dominant axis and samples the dilated block, appends
+//            it to an LDS ray list (wave-aggregated compaction) with its
+//            plane range cut into segments of <= K planes;
 //   phase B  each thread takes segments and scatters the bilinear taps of
 //            their samples with ds_add_u32.  Positions are clamped to the
 //            halo, where an out-of-block tap lands with an exactly-zero or
@@ -563,9 +633,11 @@ __device__ __forceinline__ int round_fixed(float x)
 // SLO/SHI: halo rows below/above the block in the slow in-plane direction,
 // 1/2 in general; 0/1 for 2-D problems, whose rays have z == 0 exactly (the
 // tap at z = 0 has weight 1 and the one at z = 1 weight 0).
-template <typename Q, int L, int TS, int TF, int SLO, int SHI, int CPT>
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
 __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
 {
+    using AX = PassAxes<A>;
+    constexpr int F = AX::F, S = AX::S;
     constexpr int K = 8;                       // planes per segment
     constexpr int RW = TF + 3;                 // LDS row (halo: 1 before, 2 after)
     constexpr int RP = TS + SLO + SHI;         // LDS rows per plane
@@ -573,15 +645,16 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
     constexpr int NV = L * TS * TF;            // voxels of the block
     constexpr int NQ = (NV + 255) / 256;       // voxels per thread
     constexpr int MAXR = 256 * CPT;            // rays per batch
-    constexpr int MAXSEG = MAXR * ((L + K - 1) / K);
-    static_assert(L <= 64 && MAXR <= 65536, "segment record packing");
+    constexpr int SPR = (L + K - 1) / K;       // segments per ray, at most
+    constexpr int MAXSEG = MAXR * SPR;
+    static_assert(L <= 32 && SPR <= 4, "segment record packing");
+    static_assert(MAXR <= 1024 && MAXSEG < 65536, "packed counters");
     __shared__ int acc[L * PL];
-    __shared__ float4 s_ray[MAXR];             // gf, bf (halo-local), gs, bs (halo-local)
+    __shared__ float4 s_ray[MAXR];             // gf, bf, gs, bs (block-local frame)
     __shared__ float s_q[MAXR];                // q * ds
-    __shared__ uint32_t s_seg[MAXSEG];         // ray | first plane << 16 ... packed below
-    __shared__ uint32_t s_cnt[2][3];           // [parity][rays, segments, max |q*ds| bits]
+    __shared__ uint32_t s_seg[MAXSEG];         // slot | first local plane << 16 | planes << 24
+    __shared__ uint32_t s_cnt[2][2];           // [parity][rays | segments << 16, max |q*ds| bits]
 
-    const int a = p.axis, f = fast_axis(a), sl = slow_axis(a);
     int blk = blockIdx.x;
     const int bf_ = blk % p.blocks_f;
     blk /= p.blocks_f;
@@ -589,20 +662,23 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
     blk /= p.blocks_s;
     const int ba_ = blk % p.blocks_a;
     const int b = blk / p.blocks_a;
-    const int a0 = ba_ * L, a1 = min(a0 + L, p.n[a]);
-    const int s0 = bs_ * TS, s1 = min(s0 + TS, p.n[sl]);
-    const int f0 = bf_ * TF, f1 = min(f0 + TF, p.n[f]);
+    const int a0 = ba_ * L, a1 = min(a0 + L, p.n[A]);
+    const int s0 = bs_ * TS, s1 = min(s0 + TS, p.n[S]);
+    const int f0 = bf_ * TF, f1 = min(f0 + TF, p.n[F]);
     // largest halo-local position whose two taps stay inside the LDS block
     const float fmaxl = static_cast<float>(f1 - f0 + 1);
     const float smaxl = static_cast<float>(min(s1 - s0 + 1, RP - 2));
-    const int t = threadIdx.x;
+    const float amaxl = static_cast<float>(a1 - a0 - 1);
+    const int t = threadIdx.x, lane = t & 63;
+    // block-local frame: local = global - origin (halo origin in-plane)
+    const double oa = a0, of = f0 - 1, os = s0 - SLO;
 
     // the voxels this thread owns: e = t + 256 q, x fastest (coalesced output)
     float reg[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) reg[q] = 0.0f;
-    auto cell_of = [&](int e, int &la, int &ls, int &lf) {
-        if (a == 0) {  // x = a
+    auto cell_of = [](int e, int &la, int &ls, int &lf) {
+        if (A == 0) {  // x = a
             la = e % L;
             lf = (e / L) % TF;
             ls = e / (L * TF);
@@ -614,14 +690,13 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
     };
 
     for (int e = t; e < L * PL; e += 256) acc[e] = 0;
-    if (t < 6) s_cnt[t / 3][t % 3] = 0u;
+    if (t < 4) s_cnt[t >> 1][t & 1] = 0u;
     __syncthreads();
 
     const Q *sino_b = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
     int parity = 0;
     for (int pv = 0; pv < p.n_pass_views; ++pv) {
-        const int view = p.views[pv];
-        const ViewTab &tv = p.tab[view];
+        const int view = __builtin_amdgcn_readfirstlane(p.views[pv]);
         // detector bounding box of the block dilated by one voxel in-plane:
         // lanes 0-7 of every wave project one corner each (FP32; the 0.01
         // pixel margin covers its rounding), then a butterfly min/max
@@ -629,9 +704,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         {
             const int corner = t & 7;
             float ijk[3];
-            ijk[a] = (corner & 1) ? static_cast<float>(a1 - 1) : static_cast<float>(a0);
-            ijk[sl] = (corner & 2) ? static_cast<float>(s1) : static_cast<float>(s0 - 1);
-            ijk[f] = (corner & 4) ? static_cast<float>(f1) : static_cast<float>(f0 - 1);
+            ijk[A] = (corner & 1) ? static_cast<float>(a1 - 1) : static_cast<float>(a0);
+            ijk[S] = (corner & 2) ? static_cast<float>(s1) : static_cast<float>(s0 - 1);
+            ijk[F] = (corner & 4) ? static_cast<float>(f1) : static_cast<float>(f0 - 1);
             const ViewTabF &tf = p.tabf[view];
             const float U = fmaf(tf.Pi[0], ijk[0], fmaf(tf.Pi[1], ijk[1], fmaf(tf.Pi[2], ijk[2], tf.Pi[3])));
             const float V = fmaf(tf.Pi[4], ijk[0], fmaf(tf.Pi[5], ijk[1], fmaf(tf.Pi[6], ijk[2], tf.Pi[7])));
@@ -646,10 +721,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
                 vmin = fminf(vmin, __shfl_xor(vmin, o));
                 vmax = fmaxf(vmax, __shfl_xor(vmax, o));
             }
-            umin = __shfl(umin, 0) - 0.01f;
-            umax = __shfl(umax, 0) + 0.01f;
-            vmin = __shfl(vmin, 0) - 0.01f;
-            vmax = __shfl(vmax, 0) + 0.01f;
+            umin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umin))) - 0.01f;
+            umax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umax))) + 0.01f;
+            vmin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmin))) - 0.01f;
+            vmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmax))) + 0.01f;
         }
         // clamp before converting: the bounds are finite (W > 0 over the
         // dilated volume) but may lie far outside the detector
@@ -658,6 +733,15 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         const int cv0 = static_cast<int>(fminf(fmaxf(floorf(vmin), 0.0f), static_cast<float>(p.nv)));
         const int cv1 = static_cast<int>(fmaxf(fminf(ceilf(vmax), static_cast<float>(p.nv - 1)), -1.0f));
         if (cu0 > cu1 || cv0 > cv1) continue;  // uniform
+        // the view's FP64 ray tables, needed rows only (uniform loads)
+        const ViewTab &tv = p.tab[view];
+        const double Aa0 = tv.A[3 * A], Aa1 = tv.A[3 * A + 1], Aa2 = tv.A[3 * A + 2];
+        const double Af0 = tv.A[3 * F], Af1 = tv.A[3 * F + 1], Af2 = tv.A[3 * F + 2];
+        const double As0 = tv.A[3 * S], As1 = tv.A[3 * S + 1], As2 = tv.A[3 * S + 2];
+        // points on the rays, in the block-local frame
+        const double Ba0 = tv.B[3 * A], Ba1 = tv.B[3 * A + 1], Ba2 = tv.B[3 * A + 2] - oa;
+        const double Bf0 = tv.B[3 * F], Bf1 = tv.B[3 * F + 1], Bf2 = tv.B[3 * F + 2] - of;
+        const double Bs0 = tv.B[3 * S], Bs1 = tv.B[3 * S + 1], Bs2 = tv.B[3 * S + 2] - os;
         const int wu = cu1 - cu0 + 1, wv = cv1 - cv0 + 1;
         const int wu_e = (wu + 1) >> 1, wu_o = wu >> 1, wv_e = (wv + 1) >> 1;
         const int n00 = wu_e * wv_e, n10 = wu_o * wv_e, n01 = wu_e * (wv >> 1);
@@ -667,98 +751,147 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         const Q *sino_v = sino_b + static_cast<int64_t>(view) * p.nv * p.nu;
         for (int cb = 0; cb < ncand; cb += MAXR) {
             // ---- phase A: set-up of up to MAXR candidates, compacted into LDS
-#pragma unroll
+#pragma unroll 1
             for (int cq = 0; cq < CPT; ++cq) {
                 const int idx = cb + t + 256 * cq;
-                if (idx >= ncand) break;
-                // parity classes (c - cu0, r - cv0) mod 2, each row-major
-                int j = idx, pc, pr, w;
-                float rwc;
-                if (j < n00) { pc = 0; pr = 0; w = wu_e; rwc = rwe; }
-                else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; rwc = rwo; }
-                else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; rwc = rwe; }
-                else { j -= n01; pc = 1; pr = 1; w = wu_o; rwc = rwo; }
-                // j / w: reciprocal estimate, then an exact correction
-                int jq = static_cast<int>((static_cast<float>(j) + 0.5f) * rwc);
-                jq -= (jq * w > j) ? 1 : 0;
-                jq += ((jq + 1) * w <= j) ? 1 : 0;
-                const int c = cu0 + pc + 2 * (j - jq * w);
-                const int r = cv0 + pr + 2 * jq;
-                const float qraw = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]);  // in flight during set-up
-                RaySeg seg;
-                ray_setup_local(tv, static_cast<double>(c), static_cast<double>(r), p.s, a, seg);
-                if (seg.axis != a) continue;
-                // halo-local offsets: local = global - (f0 - 1), global - (s0 - SLO)
-                const float bfl = seg.bf - static_cast<float>(f0 - 1);
-                const float bsl = seg.bs - static_cast<float>(s0 - SLO);
-                // planes whose sample lies in the dilated block (+-1 plane slack)
-                float lo = static_cast<float>(a0), hi = static_cast<float>(a1 - 1);
-                clip_range_f(bfl, seg.gf, 0.0f, fmaxl, lo, hi);
-                clip_range_f(bsl, seg.gs, 0.0f, smaxl, lo, hi);
-                if (!(lo <= hi)) continue;
-                const int m0 = max(static_cast<int>(lo), a0);
-                const int m1 = min(static_cast<int>(hi), a1 - 1);
-                if (m0 > m1) continue;
-                const float qs = qraw * seg.ds;
-                const int slot = static_cast<int>(atomicAdd(&s_cnt[parity][0], 1u));
-                s_ray[slot] = make_float4(seg.gf, bfl, seg.gs, bsl);
-                s_q[slot] = qs;
-                atomicMax(&s_cnt[parity][2], __float_as_uint(fabsf(qs)));
-                const int nseg = (m1 - m0 + K) / K;
-                const int sb = static_cast<int>(atomicAdd(&s_cnt[parity][1], static_cast<uint32_t>(nseg)));
-                for (int k = 0; k < nseg; ++k) {
-                    const int ms = m0 + k * K;
-                    const int cnt = min(K, m1 - ms + 1);
-                    s_seg[sb + k] = static_cast<uint32_t>(slot) | static_cast<uint32_t>(ms - a0) << 16 |
-                                    static_cast<uint32_t>(cnt) << 24;
+                bool ok = false;
+                float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                float qs = 0.0f;
+                int m0 = 0, nseg = 0;
+                if (idx < ncand) {
+                    // parity classes (c - cu0, r - cv0) mod 2, each row-major
+                    int j = idx, pc, pr, w;
+                    float rwc;
+                    if (j < n00) { pc = 0; pr = 0; w = wu_e; rwc = rwe; }
+                    else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; rwc = rwo; }
+                    else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; rwc = rwe; }
+                    else { j -= n01; pc = 1; pr = 1; w = wu_o; rwc = rwo; }
+                    // j / w: reciprocal estimate, then an exact correction
+                    int jq = static_cast<int>((static_cast<float>(j) + 0.5f) * rwc);
+                    jq -= (jq * w > j) ? 1 : 0;
+                    jq += ((jq + 1) * w <= j) ? 1 : 0;
+                    const int c = cu0 + pc + 2 * (j - jq * w);
+                    const int r = cv0 + pr + 2 * jq;
+                    const float qraw = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]);
+                    const double u = c, v = r;
+                    const double da = fma(Aa0, u, fma(Aa1, v, Aa2));
+                    const double df = fma(Af0, u, fma(Af1, v, Af2));
+                    const double dsl = fma(As0, u, fma(As1, v, As2));
+                    if (AX::dominant(da, df, dsl)) {
+                        // 1/da: hardware reciprocal refined by two Newton steps
+                        double inv = __builtin_amdgcn_rcp(da);
+                        inv = inv * fma(-da, inv, 2.0);
+                        inv = inv * fma(-da, inv, 2.0);
+                        const double gf = df * inv, gs = dsl * inv;
+                        const double pa = fma(Ba0, u, fma(Ba1, v, Ba2));
+                        const double pf = fma(Bf0, u, fma(Bf1, v, Bf2));
+                        const double ps = fma(Bs0, u, fma(Bs1, v, Bs2));
+                        // in-plane position at local plane 0
+                        const float bfl = static_cast<float>(fma(-pa, gf, pf));
+                        const float bsl = static_cast<float>(fma(-pa, gs, ps));
+                        const float gf32 = static_cast<float>(gf), gs32 = static_cast<float>(gs);
+                        // ray length per plane (mm), FP32
+                        const float wx = static_cast<float>(A == 0 ? da : df) * static_cast<float>(p.s[0]);
+                        const float wy = static_cast<float>(A == 1 ? da : (A == 0 ? df : dsl)) * static_cast<float>(p.s[1]);
+                        const float wz = static_cast<float>(A == 2 ? da : dsl) * static_cast<float>(p.s[2]);
+                        const float dsm = __builtin_amdgcn_sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz))) *
+                                          fabsf(static_cast<float>(inv));
+                        float lo = 0.0f, hi = amaxl;
+                        clip_local(bfl, gf32, fmaxl, lo, hi);
+                        clip_local(bsl, gs32, smaxl, lo, hi);
+                        m0 = static_cast<int>(fmaxf(lo, 0.0f));
+                        const int m1 = static_cast<int>(fminf(hi, amaxl));
+                        if (m0 <= m1 && isfinite(dsm)) {
+                            ok = true;
+                            rec = make_float4(gf32, bfl, gs32, bsl);
+                            qs = qraw * dsm;
+                            nseg = (m1 - m0 + K) / K;
+                            // pack the last segment's length with the count
+                            nseg |= (m1 - m0 + 1 - (nseg - 1) * K) << 8;
+                        }
+                    }
+                }
+                // wave-aggregated append (all lanes active here)
+                const int ns = nseg & 0xff;
+                const uint64_t mr = __ballot(ok);
+                const uint64_t m1b = __ballot(ns & 1), m2b = __ballot(ns & 2), m4b = __ballot(ns & 4);
+                const uint32_t nr = static_cast<uint32_t>(__popcll(mr));
+                const uint32_t nsw = static_cast<uint32_t>(__popcll(m1b) + 2 * __popcll(m2b) + 4 * __popcll(m4b));
+                const uint32_t qbits = wave_max_u32(ok ? __float_as_uint(fabsf(qs)) : 0u);
+                uint32_t base = 0;
+                if (lane == 0 && nr > 0) {
+                    base = atomicAdd(&s_cnt[parity][0], nr | nsw << 16);
+                    atomicMax(&s_cnt[parity][1], qbits);
+                }
+                base = __builtin_amdgcn_readfirstlane(base);
+                if (ok) {
+                    const int slot = static_cast<int>((base & 0xffff) + lane_rank(mr));
+                    const int sb = static_cast<int>((base >> 16) + lane_rank(m1b) + 2 * lane_rank(m2b) +
+                                                    4 * lane_rank(m4b));
+                    s_ray[slot] = rec;
+                    s_q[slot] = qs;
+                    const int last = nseg >> 8;
+                    for (int k = 0; k < ns; ++k) {
+                        const int cnt = k == ns - 1 ? last : K;
+                        s_seg[sb + k] = static_cast<uint32_t>(slot) | static_cast<uint32_t>(m0 + k * K) << 16 |
+                                        static_cast<uint32_t>(cnt) << 24;
+                    }
                 }
             }
             __syncthreads();
             // ---- phase B: scatter segments (fixed point)
-            const int nray = static_cast<int>(s_cnt[parity][0]);
-            const int nseg_all = static_cast<int>(s_cnt[parity][1]);
-            const float qmax = __uint_as_float(s_cnt[parity][2]);
-            if (t == 0) {
-                s_cnt[parity ^ 1][0] = 0u;
-                s_cnt[parity ^ 1][1] = 0u;
-                s_cnt[parity ^ 1][2] = 0u;
-            }
+            const uint32_t cnts = s_cnt[parity][0];
+            const int nray = static_cast<int>(cnts & 0xffff);
+            const int nseg_all = static_cast<int>(cnts >> 16);
+            const float qmax = __uint_as_float(s_cnt[parity][1]);
+            if (t < 2) s_cnt[parity ^ 1][t] = 0u;
             const float bound = static_cast<float>(nray) * qmax;
-            float scale = 1.0f;
+            // scale = 2^e with bound * 2^e <= 2^30: bound = m 2^x with
+            // m in [0.5, 1), e = 30 - x (clamped to normal scales)
+            float e = 0.0f;
             if (bound > 0.0f)
-                scale = isfinite(bound) ? exp2f(fminf(fmaxf(floorf(log2f(1073741824.0f / bound)), -126.0f), 126.0f))
-                                        : 0.0f;
-            for (int e = t; e < nseg_all; e += 256) {
-                const uint32_t rec = s_seg[e];
-                const int slot = rec & 0xffff, la0 = (rec >> 16) & 0xff, cnt = rec >> 24;
+                e = isfinite(bound) ? fminf(fmaxf(static_cast<float>(30 - __builtin_amdgcn_frexp_expf(bound)), -126.0f), 126.0f)
+                                    : 200.0f;
+            const float scale = e > 150.0f ? 0.0f : exp2f(e);
+            for (int se = t; se < nseg_all; se += 256) {
+                const uint32_t srec = s_seg[se];
+                const int slot = srec & 0xffff, la0 = (srec >> 16) & 0xff, cnt = srec >> 24;
                 const float4 rp = s_ray[slot];
                 const float qs = s_q[slot] * scale;
-                int *qrow = acc + __mul24(la0, PL);
-                float fm = static_cast<float>(a0 + la0);
-                for (int k = 0; k < cnt; ++k, fm += 1.0f, qrow += PL) {
-                    // halo-local positions are >= 0 after the clamp: truncation is floor
-                    const float pf = __builtin_amdgcn_fmed3f(fmaf(fm, rp.x, rp.y), 0.0f, fmaxl);
-                    const float ps = __builtin_amdgcn_fmed3f(fmaf(fm, rp.z, rp.w), 0.0f, smaxl);
-                    const float wf = __builtin_amdgcn_fractf(pf), ws = __builtin_amdgcn_fractf(ps);
-                    int *q = qrow + __mul24(static_cast<int>(ps), RW) + static_cast<int>(pf);
-                    const float t1 = qs * ws, t0 = qs - t1;
-                    const float c01f = t0 * wf, c11f = t1 * wf;
-                    atomicAdd(q, round_fixed(t0 - c01f));
-                    atomicAdd(q + 1, round_fixed(c01f));
-                    atomicAdd(q + RW, round_fixed(t1 - c11f));
-                    atomicAdd(q + RW + 1, round_fixed(c11f));
+                int *qplane = acc + __mul24(la0, PL);
+                const float fm0 = static_cast<float>(la0);
+                // every segment has >= 1 plane: the first sample is taken
+                // unconditionally (so the record loads are waited for once,
+                // before any branch)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (k == 0 || k < cnt) {
+                        const float fm = fm0 + static_cast<float>(k);
+                        // halo-local positions are >= 0 after the clamp: truncation is floor
+                        const float pf = __builtin_amdgcn_fmed3f(fmaf(fm, rp.x, rp.y), 0.0f, fmaxl);
+                        const float ps = __builtin_amdgcn_fmed3f(fmaf(fm, rp.z, rp.w), 0.0f, smaxl);
+                        const float wf = __builtin_amdgcn_fractf(pf), ws = __builtin_amdgcn_fractf(ps);
+                        int *q = qplane + k * PL + __mul24(static_cast<int>(ps), RW) + static_cast<int>(pf);
+                        const float t1 = qs * ws, t0 = qs - t1;
+                        const float c01f = t0 * wf, c11f = t1 * wf;
+                        atomicAdd(q, round_fixed(t0 - c01f));
+                        atomicAdd(q + 1, round_fixed(c01f));
+                        atomicAdd(q + RW, round_fixed(t1 - c11f));
+                        atomicAdd(q + RW + 1, round_fixed(c11f));
+                    }
                 }
             }
             __syncthreads();
-            // ---- flush: integer batch sums -> FP32 registers
+            // ---- flush: integer batch sums -> FP32 registers; a non-finite
+            // sinogram value (no scale) turns the block's voxels into NaN
             if (nray > 0) {
-                const float inv_scale = scale > 0.0f ? 1.0f / scale : 0.0f;
+                const float inv_scale = e > 150.0f ? __int_as_float(0x7fc00000) : exp2f(-e);
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    const int e = t + 256 * q;
-                    if (e < NV) {
+                    const int el = t + 256 * q;
+                    if (el < NV) {
                         int la, ls, lf;
-                        cell_of(e, la, ls, lf);
+                        cell_of(el, la, ls, lf);
                         int *cellp = acc + (la * RP + ls + SLO) * RW + lf + 1;
                         reg[q] = fmaf(static_cast<float>(*cellp), inv_scale, reg[q]);
                         *cellp = 0;
@@ -776,15 +909,15 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
     float *out = p.out + b * item;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int e = t + 256 * q;
-        if (e >= NV) continue;
+        const int el = t + 256 * q;
+        if (el >= NV) continue;
         int la, ls, lf;
-        cell_of(e, la, ls, lf);
+        cell_of(el, la, ls, lf);
         if (a0 + la >= a1 || s0 + ls >= s1 || f0 + lf >= f1) continue;
         int ijk[3];
-        ijk[a] = a0 + la;
-        ijk[sl] = s0 + ls;
-        ijk[f] = f0 + lf;
+        ijk[A] = a0 + la;
+        ijk[S] = s0 + ls;
+        ijk[F] = f0 + lf;
         const int64_t o = (static_cast<int64_t>(ijk[2]) * p.n[1] + ijk[1]) * p.n[0] + ijk[0];
         out[o] = p.accumulate ? out[o] + reg[q] : reg[q];
     }
@@ -1034,7 +1167,7 @@ static hipError_t forward_t(const FwdParams &p, hipStream_t st)
     if (p.tile_v == 1)
         forward_kernel<S, O, 256, 1, 8, 3, 320><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
     else
-        forward_kernel<S, O, 16, 16, 8, 32, 32><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+        forward_kernel<S, O, 16, 16, 8, 25, 40><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
     return hipGetLastError();
 }
 
@@ -1065,7 +1198,7 @@ void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv)
 
 // Compiled adjoint block shapes (planes x rows x columns, candidates per
 // thread per batch); index 0 is 2-D.
-static const int32_t kAdjShapes[][4] = {{32, 1, 64, 1}, {32, 16, 16, 2}, {32, 8, 16, 1}, {16, 16, 16, 2}, {32, 16, 16, 1}};
+static const int32_t kAdjShapes[][4] = {{32, 1, 64, 1}, {16, 16, 16, 2}, {32, 8, 16, 1}, {32, 16, 16, 2}, {16, 16, 32, 2}};
 constexpr int kNumAdjShapes = 5;
 
 int adjoint_shape_count() { return kNumAdjShapes; }
@@ -1077,18 +1210,34 @@ void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF)
     TF = kAdjShapes[id][2];
 }
 
+template <typename Q, int L, int TS, int TF, int SLO, int SHI, int CPT>
+static hipError_t adjoint_axes(const AdjParams &p, hipStream_t st)
+{
+    const dim3 g(static_cast<uint32_t>(static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch));
+    switch (p.axis) {
+    case 0: adjoint_kernel<Q, 0, L, TS, TF, SLO, SHI, CPT><<<g, 256, 0, st>>>(p); break;
+    case 1: adjoint_kernel<Q, 1, L, TS, TF, SLO, SHI, CPT><<<g, 256, 0, st>>>(p); break;
+    default:
+        if constexpr (TS == 1) {
+            return hipErrorInvalidValue;  // 2-D rays never have z dominant
+        } else {
+            adjoint_kernel<Q, 2, L, TS, TF, SLO, SHI, CPT><<<g, 256, 0, st>>>(p);
+        }
+        break;
+    }
+    return hipGetLastError();
+}
+
 template <typename Q>
 static hipError_t adjoint_q(const AdjParams &p, int shape, hipStream_t st)
 {
-    const dim3 g(static_cast<uint32_t>(static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch));
     switch (shape) {
-    case 0: adjoint_kernel<Q, 32, 1, 64, 0, 1, 1><<<g, 256, 0, st>>>(p); break;
-    case 1: adjoint_kernel<Q, 32, 16, 16, 1, 2, 2><<<g, 256, 0, st>>>(p); break;
-    case 2: adjoint_kernel<Q, 32, 8, 16, 1, 2, 1><<<g, 256, 0, st>>>(p); break;
-    case 3: adjoint_kernel<Q, 16, 16, 16, 1, 2, 2><<<g, 256, 0, st>>>(p); break;
-    default: adjoint_kernel<Q, 32, 16, 16, 1, 2, 1><<<g, 256, 0, st>>>(p); break;
+    case 0: return adjoint_axes<Q, 32, 1, 64, 0, 1, 1>(p, st);
+    case 1: return adjoint_axes<Q, 16, 16, 16, 1, 2, 2>(p, st);
+    case 2: return adjoint_axes<Q, 32, 8, 16, 1, 2, 1>(p, st);
+    case 3: return adjoint_axes<Q, 32, 16, 16, 1, 2, 2>(p, st);
+    default: return adjoint_axes<Q, 16, 16, 32, 1, 2, 2>(p, st);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st)
