@@ -35,7 +35,8 @@ struct ViewTabF {
     float Pi[12];  // as ViewTab::Pi, rounded
     float W0;      // W of the world origin (distance weight reference)
     int32_t axes;  // bit a set when some ray of the view may have dominant axis a
-    float pad[2];
+    float kcell;   // bound on the rays of the view that sample one voxel's 2x2 neighbourhood in one plane
+    float pad;
 };
 
 enum DType : int32_t { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2 };
@@ -58,6 +59,9 @@ struct FwdParams {
 struct AdjParams {
     const ViewTab *tab;
     const ViewTabF *tabf;
+    const uint32_t *maxabs;  // bit pattern of max |sino| (fixed-point scale)
+    float ds_bound;          // upper bound of the ray length per plane (mm)
+    float kunits;            // rays x max|q ds| units a flush period holds (>= every kcell)
     const int32_t *views;  // views processed by this pass
     int32_t n_pass_views;
     int32_t axis;          // dominant axis handled by this pass

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -24,6 +25,7 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
 hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
+hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st);
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 int adjoint_shape_count();
@@ -289,6 +291,10 @@ struct Plan {
     // FP32 accumulation buffer of the adjoint for 16-bit outputs
     float *d_acc = nullptr;
     size_t acc_cap = 0;
+    // max |sinogram| of the current adjoint call (fixed-point scale)
+    uint32_t *d_maxabs = nullptr;
+    // largest per-view bound on the rays that sample one voxel's neighbourhood
+    float kmax = 1.0f;
 
     ~Plan()
     {
@@ -299,12 +305,46 @@ struct Plan {
             dev_free(d_lay[a]);
         }
         dev_free(d_acc);
+        dev_free(d_maxabs);
     }
 };
 
 std::mutex g_mu;
 std::list<std::unique_ptr<Plan>> g_plans;  // most recently used first
 const size_t kMaxPlans = 32;
+
+// Upper bound on the number of rays of one view whose sample in some plane
+// lies within one voxel, in both in-plane axes, of a given voxel (the rays
+// that can add to that voxel in the adjoint).  Such a sample lies in a 2 x 2
+// square of the plane around the voxel; the ray's pixel is the projection
+// of the sample, so it lies in the projection of the square, which fits in
+// a detector box of 2 Du x 2 Dv pixels, Du bounding |du/df| + |du/ds| over
+// the dilated volume (mean value theorem).  With u = U/W,
+// du/dx_c = (Pi_0c - u Pi_2c) / W, and over the box W >= Wmin > 0 and
+// |u| <= max |u| at the corners (u is linear-fractional).  The box holds at
+// most (floor(2 Du) + 1) (floor(2 Dv) + 1) pixel centres.  The sum over all
+// three axes covers every pass.
+double cell_ray_bound(const double *Pi, const Geo &g)
+{
+    double wmin = std::numeric_limits<double>::infinity(), umax = 0.0, vmax = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const double x = (c & 1) ? g.n[0] : -1.0, y = (c & 2) ? g.n[1] : -1.0, z = (c & 4) ? g.n[2] : -1.0;
+        const double U = Pi[0] * x + Pi[1] * y + Pi[2] * z + Pi[3];
+        const double V = Pi[4] * x + Pi[5] * y + Pi[6] * z + Pi[7];
+        const double W = Pi[8] * x + Pi[9] * y + Pi[10] * z + Pi[11];
+        wmin = std::min(wmin, W);
+        umax = std::max(umax, std::fabs(U / W));
+        vmax = std::max(vmax, std::fabs(V / W));
+    }
+    double du = 0.0, dv = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        du += (std::fabs(Pi[c]) + umax * std::fabs(Pi[8 + c])) / wmin;
+        dv += (std::fabs(Pi[4 + c]) + vmax * std::fabs(Pi[8 + c])) / wmin;
+    }
+    const double cu = std::min(std::ceil(2.0 * du * (1.0 + 1e-9)) + 1.0, (double)g.nu);
+    const double cv = std::min(std::ceil(2.0 * dv * (1.0 + 1e-9)) + 1.0, (double)g.nv);
+    return std::max(cu * cv, 1.0);
+}
 
 void build_tables(Plan &pl)
 {
@@ -353,7 +393,9 @@ void build_tables(Plan &pl)
         for (int e = 0; e < 12; ++e) tf.Pi[e] = (float)t.Pi[e];
         tf.W0 = (float)P[11];
         tf.axes = axis_mask(t.A, g.nu, g.nv);
-        tf.pad[0] = tf.pad[1] = 0;
+        tf.kcell = (float)cell_ray_bound(t.Pi, g);
+        tf.pad = 0;
+        pl.kmax = std::max(pl.kmax, tf.kcell);
         pl.axes_union |= tf.axes;
         for (int a = 0; a < 3; ++a)
             if (tf.axes >> a & 1) pl.pass_views[a].push_back(k);
@@ -395,6 +437,7 @@ int get_plan(const pn_geometry *pg, Plan **out)
     if ((rc = upload(&pl->d_tabf, pl->tabf))) return rc;
     for (int a = 0; a < 3; ++a)
         if ((rc = upload(&pl->d_views[a], pl->pass_views[a]))) return rc;
+    if ((rc = upload(&pl->d_maxabs, std::vector<uint32_t>(1, 0u)))) return rc;
     g_plans.push_front(std::move(pl));
     while (g_plans.size() > kMaxPlans) g_plans.pop_back();
     *out = g_plans.front().get();
@@ -570,6 +613,12 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
     const int shape = two_d ? 0 : adjoint_shape_3d();
     int32_t L, TS, TF;
     adjoint_shape(shape, L, TS, TF);
+    {
+        hipError_t e = launch_maxabs(in_dt, sino, (int64_t)g.n_views * g.nv * g.nu * batch, pl->d_maxabs, st);
+        if (e != hipSuccess) return fail_hip(e, "maxabs launch");
+    }
+    // |s (.) delta| / |delta_a| <= |s| because delta_a is the largest component
+    const float ds_bound = (float)(std::sqrt(g.s[0] * g.s[0] + g.s[1] * g.s[1] + g.s[2] * g.s[2]) * 1.0001);
     int done = 0;
     for (int a = 0; a < 3; ++a) {
         if (pl->pass_views[a].empty()) continue;
@@ -577,6 +626,12 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
         AdjParams p{};
         p.tab = pl->d_tab;
         p.tabf = pl->d_tabf;
+        p.maxabs = pl->d_maxabs;
+        p.ds_bound = ds_bound;
+        // a flush period holds >= 256 units of max|q ds| (and one view's
+        // worth at least); the rounding error of a contribution is
+        // <= kunits max|q ds| / 2^30
+        p.kunits = std::max(256.0f, pl->kmax);
         p.views = pl->d_views[a];
         p.n_pass_views = (int32_t)pl->pass_views[a].size();
         p.axis = a;

@@ -621,14 +621,22 @@ __device__ __forceinline__ void clip_local(float b, float g, float hi_pos, float
 //            their samples with ds_add_u32.  Positions are clamped to the
 //            halo, where an out-of-block tap lands with an exactly-zero or
 //            discarded value;
-//   flush    each thread moves its voxels' integer sums into its FP32
-//            registers and clears them.
-// A ray samples a voxel's plane once with weight <= 1, so a voxel's batch
-// sum is bounded by (rays in the batch) x max|q*ds|; the batch scale is the
-// power of two that maps that bound to 2^30.  Integer addition is exact and
-// order-independent and the flushes happen in a fixed order, so the result
-// is deterministic.  Contributions are rounded to nearest: the error per
-// contribution is <= 1/(2 scale) <= (rays x max|q*ds|) / 2^30.
+//   flush    when the next batch could overflow the integers, each thread
+//            moves its voxels' integer sums into its FP32 registers and
+//            clears them (and once at the end).
+// A ray samples a voxel's plane once with weight <= 1, and at most kcell
+// rays of a view sample within one voxel of a given voxel (a per-view bound
+// from the geometry), so a batch adds at most min(rays, kcell) x max|q*ds|
+// to any voxel; the flush keeps the sum of these bounds since the last
+// flush, times the fixed-point scale, below 2^30.  The scale is one power
+// of two for the launch: it maps kunits (>= 256, >= every kcell) times the
+// largest possible |q*ds| (max|q| over the sinogram times the ray length
+// bound |s|) into [2^29, 2^30), so the rounding error of a contribution is
+// at most kunits max|q*ds| / 2^30 (2.4e-7 max|q*ds| for kunits = 256;
+// round to nearest, so the errors of a voxel's contributions partly
+// cancel).  Integer addition is exact and order-independent and the
+// flushes happen at the same points in every run, so the result is
+// deterministic.
 //
 // SLO/SHI: halo rows below/above the block in the slow in-plane direction,
 // 1/2 in general; 0/1 for 2-D problems, whose rays have z == 0 exactly (the
@@ -693,6 +701,35 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
     if (t < 4) s_cnt[t >> 1][t & 1] = 0u;
     __syncthreads();
 
+    // fixed-point scale of the launch: 2^e with kunits qlim 2^e in [2^29, 2^30)
+    const float qlim = __uint_as_float(*p.maxabs) * p.ds_bound;
+    const float ulim = qlim * p.kunits;
+    float e = 0.0f;
+    if (ulim > 0.0f)
+        e = isfinite(ulim) ? fminf(fmaxf(static_cast<float>(30 - __builtin_amdgcn_frexp_expf(ulim)), -126.0f), 126.0f)
+                           : 200.0f;
+    const float scale = e > 150.0f ? 0.0f : exp2f(e);
+    // a non-finite sinogram value (no scale) turns every voxel into NaN
+    const float inv_scale = e > 150.0f ? __int_as_float(0x7fc00000) : exp2f(-e);
+    float pending = 0.0f;  // bound of |integer sum| since the last flush
+    auto flush = [&]() {
+        // flushes are rare: recompute the cell addresses rather than keep
+        // them in registers across the whole kernel
+        int tt = t;
+        asm volatile("" : "+v"(tt));
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int el = tt + 256 * q;
+            if (el < NV) {
+                int la, ls, lf;
+                cell_of(el, la, ls, lf);
+                int *cellp = acc + (la * RP + ls + SLO) * RW + lf + 1;
+                reg[q] = fmaf(static_cast<float>(*cellp), inv_scale, reg[q]);
+                *cellp = 0;
+            }
+        }
+    };
+
     const Q *sino_b = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
     int parity = 0;
     for (int pv = 0; pv < p.n_pass_views; ++pv) {
@@ -733,6 +770,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         const int cv0 = static_cast<int>(fminf(fmaxf(floorf(vmin), 0.0f), static_cast<float>(p.nv)));
         const int cv1 = static_cast<int>(fmaxf(fminf(ceilf(vmax), static_cast<float>(p.nv - 1)), -1.0f));
         if (cu0 > cu1 || cv0 > cv1) continue;  // uniform
+        const float kcell = p.tabf[view].kcell;
         // the view's FP64 ray tables, needed rows only (uniform loads)
         const ViewTab &tv = p.tab[view];
         const double Aa0 = tv.A[3 * A], Aa1 = tv.A[3 * A + 1], Aa2 = tv.A[3 * A + 2];
@@ -845,14 +883,14 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
             const int nseg_all = static_cast<int>(cnts >> 16);
             const float qmax = __uint_as_float(s_cnt[parity][1]);
             if (t < 2) s_cnt[parity ^ 1][t] = 0u;
-            const float bound = static_cast<float>(nray) * qmax;
-            // scale = 2^e with bound * 2^e <= 2^30: bound = m 2^x with
-            // m in [0.5, 1), e = 30 - x (clamped to normal scales)
-            float e = 0.0f;
-            if (bound > 0.0f)
-                e = isfinite(bound) ? fminf(fmaxf(static_cast<float>(30 - __builtin_amdgcn_frexp_expf(bound)), -126.0f), 126.0f)
-                                    : 200.0f;
-            const float scale = e > 150.0f ? 0.0f : exp2f(e);
+            // the batch adds at most min(nray, kcell) x qmax to a voxel
+            const float add = fminf(static_cast<float>(nray), kcell) * qmax * scale;
+            if (pending + add > 1073741824.0f) {
+                flush();
+                pending = 0.0f;
+                __syncthreads();  // cells cleared before the scatter
+            }
+            pending += add;
             for (int se = t; se < nseg_all; se += 256) {
                 const uint32_t srec = s_seg[se];
                 const int slot = srec & 0xffff, la0 = (srec >> 16) & 0xff, cnt = srec >> 24;
@@ -882,27 +920,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
                 }
             }
             __syncthreads();
-            // ---- flush: integer batch sums -> FP32 registers; a non-finite
-            // sinogram value (no scale) turns the block's voxels into NaN
-            if (nray > 0) {
-                const float inv_scale = e > 150.0f ? __int_as_float(0x7fc00000) : exp2f(-e);
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    const int el = t + 256 * q;
-                    if (el < NV) {
-                        int la, ls, lf;
-                        cell_of(el, la, ls, lf);
-                        int *cellp = acc + (la * RP + ls + SLO) * RW + lf + 1;
-                        reg[q] = fmaf(static_cast<float>(*cellp), inv_scale, reg[q]);
-                        *cellp = 0;
-                    }
-                }
-            }
-            // the next batch's scatter starts after the next phase A barrier;
-            // halo cells are never read, so they are not cleared
+            // halo cells are never read, so they are never cleared
             parity ^= 1;
         }
     }
+    flush();
 
     // write the block; the memory-contiguous axis x runs fastest
     const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
@@ -921,6 +943,20 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         const int64_t o = (static_cast<int64_t>(ijk[2]) * p.n[1] + ijk[1]) * p.n[0] + ijk[0];
         out[o] = p.accumulate ? out[o] + reg[q] : reg[q];
     }
+}
+
+// max |x| over a buffer, as the bit pattern of a non-negative float
+// (integer order = float order; NaN compares above +inf), combined with a
+// global atomic max.
+template <typename Q>
+__global__ __launch_bounds__(256) void maxabs_kernel(const Q *__restrict__ src, int64_t n, uint32_t *__restrict__ out)
+{
+    uint32_t m = 0u;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        m = max(m, __float_as_uint(fabsf(to_f32(src[e]))));
+    m = wave_max_u32(m);
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
 // ------------------------------------------------ back-projection --------
@@ -1280,6 +1316,21 @@ hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, 
     case DT_BF16: return bp_q<bf16>(p, out_dt, st);
     default: return bp_q<f16>(p, out_dt, st);
     }
+}
+
+hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st)
+{
+    fill_zero_kernel<<<1, 64, 0, st>>>(out, 1);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    const dim3 g(static_cast<uint32_t>(blocks));
+    switch (in_dt) {
+    case DT_F32: maxabs_kernel<float><<<g, 256, 0, st>>>(static_cast<const float *>(src), n, out); break;
+    case DT_BF16: maxabs_kernel<bf16><<<g, 256, 0, st>>>(static_cast<const bf16 *>(src), n, out); break;
+    default: maxabs_kernel<f16><<<g, 256, 0, st>>>(static_cast<const f16 *>(src), n, out); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st)
