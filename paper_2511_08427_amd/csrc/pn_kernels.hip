@@ -592,25 +592,26 @@ struct PassAxes {
 };
 
 // Narrows the local plane range [lo, hi] to the planes m where b + m*g lies
-// in [0, hi_pos] (widened by 1e-3), with one plane of slack on each side.
-// The extra planes contribute exactly zero: their clamped positions put all
-// weight on discarded halo cells.  Branch-free: a zero slope is replaced by
-// a tiny positive one, which keeps or empties the whole range as the exact
-// test would (the widening keeps b == 0 or b == hi_pos inside).
+// in [0.5, hi_pos].  The band has half a cell of margin on both sides of the
+// positions whose taps can reach a voxel of the block, so the FP32 rounding
+// of the bounds (far below half a cell of position) neither drops a plane
+// that matters nor admits a position whose taps leave the LDS block.
+// Branch-free: a zero slope is replaced by a tiny positive one, which keeps
+// or empties the whole range as the exact test would.
 __device__ __forceinline__ void clip_local(float b, float g, float hi_pos, float &lo, float &hi)
 {
     const float gg = fabsf(g) < 1e-30f ? 1e-30f : g;
     const float rg = __builtin_amdgcn_rcpf(gg);
-    const float t0 = (-1e-3f - b) * rg, t1 = (hi_pos + 1e-3f - b) * rg;
-    lo = fmaxf(lo, floorf(fminf(t0, t1)) - 1.0f);
-    hi = fminf(hi, ceilf(fmaxf(t0, t1)) + 1.0f);
+    const float t0 = (0.5f - b) * rg, t1 = (hi_pos - b) * rg;
+    lo = fmaxf(lo, ceilf(fminf(t0, t1)));
+    hi = fminf(hi, floorf(fmaxf(t0, t1)));
 }
 
 // Each workgroup owns a block of L planes (dominant axis A) x TS rows x TF
 // columns of the output.  Its FP32 sums live in registers (each thread owns
 // L*TS*TF/256 voxels); per batch of candidate rays they are gathered in LDS
-// as 32-bit fixed-point accumulators with a halo of one cell below and two
-// above in the fast in-plane direction (SLO/SHI in the slow one):
+// as 32-bit fixed-point accumulators with a halo of two cells below and two
+// above in the fast in-plane direction (SLO + 1 and SHI in the slow one):
 //   phase A  each thread takes CPT candidate pixels of the detector bounding
 //            box of the block (dilated by one voxel in-plane), does the
 //            ray's FP64 set-up in the block's local frame and, if the ray
@@ -618,9 +619,11 @@ __device__ __forceinline__ void clip_local(float b, float g, float hi_pos, float
 //            it to an LDS ray list (wave-aggregated compaction) with its
 //            plane range cut into segments of <= K planes;
 //   phase B  each thread takes segments and scatters the bilinear taps of
-//            their samples with ds_add_u32.  Positions are clamped to the
-//            halo, where an out-of-block tap lands with an exactly-zero or
-//            discarded value;
+//            their samples with ds_add_u32.  A segment's planes are those
+//            where the ray's position lies within half a cell of the block
+//            dilated by one voxel, so every tap lands in the block or its
+//            halo (no clamp); taps of positions outside the dilated block
+//            land in halo cells, which are discarded;
 //   flush    when the next batch could overflow the integers, each thread
 //            moves its voxels' integer sums into its FP32 registers and
 //            clears them (and once at the end).
@@ -638,17 +641,18 @@ __device__ __forceinline__ void clip_local(float b, float g, float hi_pos, float
 // flushes happen at the same points in every run, so the result is
 // deterministic.
 //
-// SLO/SHI: halo rows below/above the block in the slow in-plane direction,
-// 1/2 in general; 0/1 for 2-D problems, whose rays have z == 0 exactly (the
-// tap at z = 0 has weight 1 and the one at z = 1 weight 0).
+// SLO/SHI: halo rows below/above the block in the slow in-plane direction
+// besides the extra row below, 1/2 in general; 0/1 for 2-D problems, whose
+// rays have z == 0 exactly (the tap at z = 0 has weight 1 and the one at
+// z = 1 weight 0).
 template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
-__global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
+__global__ __launch_bounds__(256, (L * TS * TF <= 4096 ? 4 : 2)) void adjoint_kernel(AdjParams p)
 {
     using AX = PassAxes<A>;
     constexpr int F = AX::F, S = AX::S;
     constexpr int K = 8;                       // planes per segment
-    constexpr int RW = TF + 3;                 // LDS row (halo: 1 before, 2 after)
-    constexpr int RP = TS + SLO + SHI;         // LDS rows per plane
+    constexpr int RW = TF + 4;                 // LDS row (halo: 2 before, 2 after)
+    constexpr int RP = TS + SLO + SHI + 1;     // LDS rows per plane
     constexpr int PL = RP * RW;                // LDS plane
     constexpr int NV = L * TS * TF;            // voxels of the block
     constexpr int NQ = (NV + 255) / 256;       // voxels per thread
@@ -673,13 +677,16 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
     const int a0 = ba_ * L, a1 = min(a0 + L, p.n[A]);
     const int s0 = bs_ * TS, s1 = min(s0 + TS, p.n[S]);
     const int f0 = bf_ * TF, f1 = min(f0 + TF, p.n[F]);
-    // largest halo-local position whose two taps stay inside the LDS block
-    const float fmaxl = static_cast<float>(f1 - f0 + 1);
-    const float smaxl = static_cast<float>(min(s1 - s0 + 1, RP - 2));
+    // block-local frame: local = global - origin, the origin being the
+    // first halo cell.  The dilated block (one voxel around it, the reach of
+    // a bilinear tap) spans local [1, f1 - f0 + 2] and [1, smax]; positions
+    // within half a cell of it, [0.5, fhi] x [0.5, shi], have both taps
+    // inside the LDS block.
+    const float fhi = static_cast<float>(f1 - f0) + 2.5f;
+    const float shi = static_cast<float>(min(s1 - s0 + 1, RP - 3)) + 1.5f;
     const float amaxl = static_cast<float>(a1 - a0 - 1);
     const int t = threadIdx.x, lane = t & 63;
-    // block-local frame: local = global - origin (halo origin in-plane)
-    const double oa = a0, of = f0 - 1, os = s0 - SLO;
+    const double oa = a0, of = f0 - 2, os = s0 - SLO - 1;
 
     // the voxels this thread owns: e = t + 256 q, x fastest (coalesced output)
     float reg[NQ];
@@ -723,7 +730,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
             if (el < NV) {
                 int la, ls, lf;
                 cell_of(el, la, ls, lf);
-                int *cellp = acc + (la * RP + ls + SLO) * RW + lf + 1;
+                int *cellp = acc + (la * RP + ls + SLO + 1) * RW + lf + 2;
                 reg[q] = fmaf(static_cast<float>(*cellp), inv_scale, reg[q]);
                 *cellp = 0;
             }
@@ -788,14 +795,17 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
         const float rwo = wu_o > 0 ? __builtin_amdgcn_rcpf(static_cast<float>(wu_o)) : 0.0f;
         const Q *sino_v = sino_b + static_cast<int64_t>(view) * p.nv * p.nu;
         for (int cb = 0; cb < ncand; cb += MAXR) {
-            // ---- phase A: set-up of up to MAXR candidates, compacted into LDS
-#pragma unroll 1
+            // ---- phase A: set-up of up to MAXR candidates, compacted into LDS.
+            // The candidates' pixels are decoded and their sinogram values
+            // requested first, so the loads are in flight during the set-up.
+            int cc[CPT], cr[CPT];
+            float qv[CPT];
+#pragma unroll
             for (int cq = 0; cq < CPT; ++cq) {
                 const int idx = cb + t + 256 * cq;
-                bool ok = false;
-                float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                float qs = 0.0f;
-                int m0 = 0, nseg = 0;
+                cc[cq] = -1;
+                cr[cq] = 0;
+                qv[cq] = 0.0f;
                 if (idx < ncand) {
                     // parity classes (c - cu0, r - cv0) mod 2, each row-major
                     int j = idx, pc, pr, w;
@@ -804,14 +814,25 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
                     else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; rwc = rwo; }
                     else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; rwc = rwe; }
                     else { j -= n01; pc = 1; pr = 1; w = wu_o; rwc = rwo; }
-                    // j / w: reciprocal estimate, then an exact correction
+                    // j / w (both < 2^24): reciprocal estimate, exact correction
                     int jq = static_cast<int>((static_cast<float>(j) + 0.5f) * rwc);
-                    jq -= (jq * w > j) ? 1 : 0;
-                    jq += ((jq + 1) * w <= j) ? 1 : 0;
-                    const int c = cu0 + pc + 2 * (j - jq * w);
-                    const int r = cv0 + pr + 2 * jq;
-                    const float qraw = to_f32(sino_v[static_cast<int64_t>(r) * p.nu + c]);
-                    const double u = c, v = r;
+                    jq -= (__mul24(jq, w) > j) ? 1 : 0;
+                    jq += (__mul24(jq + 1, w) <= j) ? 1 : 0;
+                    cc[cq] = cu0 + pc + 2 * (j - __mul24(jq, w));
+                    cr[cq] = cv0 + pr + 2 * jq;
+                    // r * nu + c < 2^31 (sinogram views are validated)
+                    qv[cq] = to_f32(sino_v[__umul24(static_cast<uint32_t>(cr[cq]), static_cast<uint32_t>(p.nu)) +
+                                           static_cast<uint32_t>(cc[cq])]);
+                }
+            }
+#pragma unroll
+            for (int cq = 0; cq < CPT; ++cq) {
+                bool ok = false;
+                float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                float dsm = 0.0f;
+                int m0 = 0, nseg = 0;
+                if (cc[cq] >= 0) {
+                    const double u = cc[cq], v = cr[cq];
                     const double da = fma(Aa0, u, fma(Aa1, v, Aa2));
                     const double df = fma(Af0, u, fma(Af1, v, Af2));
                     const double dsl = fma(As0, u, fma(As1, v, As2));
@@ -832,23 +853,22 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
                         const float wx = static_cast<float>(A == 0 ? da : df) * static_cast<float>(p.s[0]);
                         const float wy = static_cast<float>(A == 1 ? da : (A == 0 ? df : dsl)) * static_cast<float>(p.s[1]);
                         const float wz = static_cast<float>(A == 2 ? da : dsl) * static_cast<float>(p.s[2]);
-                        const float dsm = __builtin_amdgcn_sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz))) *
-                                          fabsf(static_cast<float>(inv));
+                        dsm = __builtin_amdgcn_sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz))) * fabsf(static_cast<float>(inv));
                         float lo = 0.0f, hi = amaxl;
-                        clip_local(bfl, gf32, fmaxl, lo, hi);
-                        clip_local(bsl, gs32, smaxl, lo, hi);
-                        m0 = static_cast<int>(fmaxf(lo, 0.0f));
-                        const int m1 = static_cast<int>(fminf(hi, amaxl));
+                        clip_local(bfl, gf32, fhi, lo, hi);
+                        clip_local(bsl, gs32, shi, lo, hi);
+                        m0 = static_cast<int>(lo);
+                        const int m1 = static_cast<int>(hi);
                         if (m0 <= m1 && isfinite(dsm)) {
                             ok = true;
                             rec = make_float4(gf32, bfl, gs32, bsl);
-                            qs = qraw * dsm;
                             nseg = (m1 - m0 + K) / K;
                             // pack the last segment's length with the count
                             nseg |= (m1 - m0 + 1 - (nseg - 1) * K) << 8;
                         }
                     }
                 }
+                const float qs = ok ? qv[cq] * dsm : 0.0f;
                 // wave-aggregated append (all lanes active here)
                 const int ns = nseg & 0xff;
                 const uint64_t mr = __ballot(ok);
@@ -896,20 +916,26 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p)
                 const int slot = srec & 0xffff, la0 = (srec >> 16) & 0xff, cnt = srec >> 24;
                 const float4 rp = s_ray[slot];
                 const float qs = s_q[slot] * scale;
-                int *qplane = acc + __mul24(la0, PL);
+                // positions at the segment's first plane, then fma(k, slope, .):
+                // inside the LDS block by construction of the plane range
                 const float fm0 = static_cast<float>(la0);
+                const float pf0 = fmaf(fm0, rp.x, rp.y), ps0 = fmaf(fm0, rp.z, rp.w);
+                const uint32_t base0 = static_cast<uint32_t>(la0 * PL * 4);
                 // every segment has >= 1 plane: the first sample is taken
                 // unconditionally (so the record loads are waited for once,
                 // before any branch)
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     if (k == 0 || k < cnt) {
-                        const float fm = fm0 + static_cast<float>(k);
-                        // halo-local positions are >= 0 after the clamp: truncation is floor
-                        const float pf = __builtin_amdgcn_fmed3f(fmaf(fm, rp.x, rp.y), 0.0f, fmaxl);
-                        const float ps = __builtin_amdgcn_fmed3f(fmaf(fm, rp.z, rp.w), 0.0f, smaxl);
+                        const float pf = fmaf(static_cast<float>(k), rp.x, pf0);
+                        const float ps = fmaf(static_cast<float>(k), rp.z, ps0);
                         const float wf = __builtin_amdgcn_fractf(pf), ws = __builtin_amdgcn_fractf(ps);
-                        int *q = qplane + k * PL + __mul24(static_cast<int>(ps), RW) + static_cast<int>(pf);
+                        // positions are >= 0.5: truncation is floor
+                        uint32_t off = __umul24(static_cast<uint32_t>(ps), static_cast<uint32_t>(RW * 4)) +
+                                       (base0 + static_cast<uint32_t>(k * PL * 4));
+                        off += static_cast<uint32_t>(pf) << 2;
+                        asm volatile("" : "+v"(off));  // one base register for all four taps
+                        int *q = reinterpret_cast<int *>(reinterpret_cast<char *>(acc) + off);
                         const float t1 = qs * ws, t0 = qs - t1;
                         const float c01f = t0 * wf, c11f = t1 * wf;
                         atomicAdd(q, round_fixed(t0 - c01f));
