@@ -82,4 +82,15 @@ struct BpParams {
     void *vol;
 };
 
+// Work list of a batched launch, passed by value as the kernel argument
+// (no device allocation or copy, so a batched call can be captured in a
+// graph): workgroups [start[i], start[i+1]) run problem i.
+constexpr int kMaxBatch = 12;
+template <typename P>
+struct Batch {
+    P p[kMaxBatch];
+    uint32_t start[kMaxBatch + 1];
+    int32_t n;
+};
+
 }  // namespace pn

@@ -32,6 +32,12 @@ int adjoint_shape_count();
 void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF);
 void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv);
 int64_t forward_blocks(const FwdParams &p);
+int64_t adjoint_blocks(const AdjParams &p);
+int64_t backproject_blocks(const BpParams &p);
+hipError_t launch_forward_batch(const Batch<FwdParams> &w, bool two_d, int32_t in_dt, int32_t out_dt, hipStream_t st);
+hipError_t launch_adjoint_batch(const Batch<AdjParams> &w, int axis, int32_t in_dt, int shape, hipStream_t st);
+hipError_t launch_backproject_batch(const Batch<BpParams> &w, bool two_d, int32_t in_dt, int32_t out_dt,
+                                    hipStream_t st);
 }  // namespace pn
 
 namespace {
@@ -518,7 +524,7 @@ int ensure_work_copy(Plan &pl, int a, int32_t dt, int64_t batch, hipStream_t st)
 }
 
 // 3-D adjoint block shape: PN_ADJ_SHAPE=<id> selects one of the compiled
-// shapes (1..count-1) for tuning; the default is shape 1 (32 x 16 x 16).
+// shapes (1..count-1) for tuning; the default is shape 1 (16 x 16 x 16).
 int adjoint_shape_3d()
 {
     static int shape = [] {
@@ -529,23 +535,34 @@ int adjoint_shape_3d()
     return shape;
 }
 
-int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt, int32_t out_dt,
-                 hipStream_t st)
+// ---------------------------------------------------- prepared problems --
+//
+// Every call is validated and prepared problem by problem (plan, work
+// copies, pre-passes, kernel parameters); the main kernels of a single call
+// are then launched directly, and those of a batched call in work lists of
+// up to kMaxBatch problems per launch.  A prepared problem owns its plan's
+// work buffers until its launch, so a work list never holds two problems of
+// one plan.  Callers hold g_mu.
+
+struct FwdJob {
+    FwdParams p;
+    bool two_d;
+    Plan *plan;
+};
+
+int forward_prepare(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt,
+                    hipStream_t st, Plan *pl, FwdJob &job, bool &none)
 {
-    Geo pre;
-    int rc = preflight(pg, batch, vol, sino, in_dt, out_dt, false, pre);
-    if (rc || batch == 0) return rc;
-    std::lock_guard<std::mutex> lk(g_mu);
-    Plan *pl;
-    if ((rc = get_plan(pg, &pl))) return rc;
     const Geo &g = pl->g;
-    if (g.n_views == 0) return PN_OK;
+    none = g.n_views == 0;
+    if (none) return PN_OK;
     FwdParams p{};
     p.tab = pl->d_tab;
     p.n_views = g.n_views;
     p.nu = g.nu;
     p.nv = g.nv;
     p.batch = (int32_t)batch;
+    int rc;
     for (int a = 0; a < 3; ++a) {
         p.n[a] = g.n[a];
         p.s[a] = g.s[a];
@@ -566,28 +583,35 @@ int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *si
     forward_tile_shape(g.ndim == 2, p.tile_u, p.tile_v);
     p.tiles_u = (g.nu + p.tile_u - 1) / p.tile_u;
     p.tiles_v = (g.nv + p.tile_v - 1) / p.tile_v;
-    if (forward_blocks(p) > INT32_MAX)
-        return fail(PN_EINVAL, "problem too large for one launch");
-    hipError_t e = launch_forward(p, in_dt, out_dt, st);
-    if (e != hipSuccess) return fail_hip(e, "forward launch");
+    if (forward_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
+    (void)pg;
+    job.p = p;
+    job.two_d = g.ndim == 2;
+    job.plan = pl;
     return PN_OK;
 }
 
-int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt, int32_t out_dt,
-                 hipStream_t st)
+struct AdjJob {
+    AdjParams pass[3];  // per dominant axis; pass[a].n_pass_views == 0: none
+    bool two_d;
+    int shape;
+    Plan *plan;
+    float *acc;         // FP32 accumulation target
+    void *out;          // caller's output, converted from acc when not FP32
+    int32_t out_dt;
+    int64_t total;
+};
+
+int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, int32_t out_dt, hipStream_t st,
+                    Plan *pl, AdjJob &job, bool &none)
 {
-    Geo pre;
-    int rc = preflight(pg, batch, sino, vol, in_dt, out_dt, true, pre);
-    if (rc || batch == 0) return rc;
-    std::lock_guard<std::mutex> lk(g_mu);
-    Plan *pl;
-    if ((rc = get_plan(pg, &pl))) return rc;
     const Geo &g = pl->g;
     const int64_t item = (int64_t)g.n[0] * g.n[1] * g.n[2];
     const int64_t total = item * batch;
     int npass = 0;
     for (int a = 0; a < 3; ++a) npass += pl->pass_views[a].empty() ? 0 : 1;
-    if (npass == 0) {
+    none = npass == 0;
+    if (none) {
         hipError_t e = launch_fill_zero(vol, total * esize(out_dt), st);
         return e == hipSuccess ? PN_OK : fail_hip(e, "fill");
     }
@@ -621,9 +645,10 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
     const float ds_bound = (float)(std::sqrt(g.s[0] * g.s[0] + g.s[1] * g.s[1] + g.s[2] * g.s[2]) * 1.0001);
     int done = 0;
     for (int a = 0; a < 3; ++a) {
+        AdjParams &p = job.pass[a];
+        p = AdjParams{};
         if (pl->pass_views[a].empty()) continue;
         const int f = a == 0 ? 1 : 0, sl = a == 2 ? 1 : 2;
-        AdjParams p{};
         p.tab = pl->d_tab;
         p.tabf = pl->d_tabf;
         p.maxabs = pl->d_maxabs;
@@ -649,17 +674,86 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
         p.blocks_a = (g.n[a] + L - 1) / L;
         p.blocks_s = (g.n[sl] + TS - 1) / TS;
         p.blocks_f = (g.n[f] + TF - 1) / TF;
-        if ((int64_t)p.blocks_a * p.blocks_s * p.blocks_f * batch > INT32_MAX)
-            return fail(PN_EINVAL, "problem too large for one launch");
-        hipError_t e = launch_adjoint(p, in_dt, shape, st);
-        if (e != hipSuccess) return fail_hip(e, "adjoint launch");
+        if (adjoint_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
         ++done;
     }
-    if (out_dt != PN_F32) {
-        hipError_t e = launch_convert(target, vol, out_dt, total, st);
-        if (e != hipSuccess) return fail_hip(e, "convert launch");
-    }
+    job.two_d = two_d;
+    job.shape = shape;
+    job.plan = pl;
+    job.acc = target;
+    job.out = vol;
+    job.out_dt = out_dt;
+    job.total = total;
     return PN_OK;
+}
+
+int adjoint_finish(const AdjJob &job, hipStream_t st)
+{
+    if (job.out_dt == PN_F32) return PN_OK;
+    hipError_t e = launch_convert(job.acc, job.out, job.out_dt, job.total, st);
+    return e == hipSuccess ? PN_OK : fail_hip(e, "convert launch");
+}
+
+struct BpJob {
+    BpParams p;
+    bool two_d;
+    Plan *plan;
+};
+
+void backproject_prepare(int64_t batch, const void *sino, void *vol, Plan *pl, BpJob &job)
+{
+    const Geo &g = pl->g;
+    BpParams p{};
+    p.tabf = pl->d_tabf;
+    p.n_views = g.n_views;
+    p.nu = g.nu;
+    p.nv = g.nv;
+    p.batch = (int32_t)batch;
+    for (int a = 0; a < 3; ++a) p.n[a] = g.n[a];
+    p.sino = sino;
+    p.vol = vol;
+    job.p = p;
+    job.two_d = g.n[2] == 1;
+    job.plan = pl;
+}
+
+// ------------------------------------------------------------ single calls
+
+int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt, int32_t out_dt,
+                 hipStream_t st)
+{
+    Geo pre;
+    int rc = preflight(pg, batch, vol, sino, in_dt, out_dt, false, pre);
+    if (rc || batch == 0) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *pl;
+    if ((rc = get_plan(pg, &pl))) return rc;
+    FwdJob job;
+    bool none;
+    if ((rc = forward_prepare(pg, batch, vol, sino, in_dt, st, pl, job, none)) || none) return rc;
+    hipError_t e = launch_forward(job.p, in_dt, out_dt, st);
+    if (e != hipSuccess) return fail_hip(e, "forward launch");
+    return PN_OK;
+}
+
+int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt, int32_t out_dt,
+                 hipStream_t st)
+{
+    Geo pre;
+    int rc = preflight(pg, batch, sino, vol, in_dt, out_dt, true, pre);
+    if (rc || batch == 0) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *pl;
+    if ((rc = get_plan(pg, &pl))) return rc;
+    AdjJob job;
+    bool none;
+    if ((rc = adjoint_prepare(batch, sino, vol, in_dt, out_dt, st, pl, job, none)) || none) return rc;
+    for (int a = 0; a < 3; ++a) {
+        if (job.pass[a].n_pass_views == 0) continue;
+        hipError_t e = launch_adjoint(job.pass[a], in_dt, job.shape, st);
+        if (e != hipSuccess) return fail_hip(e, "adjoint launch");
+    }
+    return adjoint_finish(job, st);
 }
 
 int backproject_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt,
@@ -671,35 +765,189 @@ int backproject_impl(const pn_geometry *pg, int64_t batch, const void *sino, voi
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *pl;
     if ((rc = get_plan(pg, &pl))) return rc;
-    const Geo &g = pl->g;
-    BpParams p{};
-    p.tabf = pl->d_tabf;
-    p.n_views = g.n_views;
-    p.nu = g.nu;
-    p.nv = g.nv;
-    p.batch = (int32_t)batch;
-    for (int a = 0; a < 3; ++a) p.n[a] = g.n[a];
-    p.sino = sino;
-    p.vol = vol;
-    hipError_t e = launch_backproject(p, in_dt, out_dt, st);
+    BpJob job;
+    backproject_prepare(batch, sino, vol, pl, job);
+    hipError_t e = launch_backproject(job.p, in_dt, out_dt, st);
     if (e != hipSuccess) return fail_hip(e, "backproject launch");
     return PN_OK;
 }
 
-typedef int (*op_fn)(const pn_geometry *, int64_t, const void *, void *, int32_t, int32_t, hipStream_t);
+// ---------------------------------------------------------- batched calls
 
-int batched(op_fn fn, const pn_problem *probs, int32_t n, int32_t in_dt, int32_t out_dt, hipStream_t st)
+// Validates every problem (nothing is launched on a failure) and orders
+// them by estimated cost, largest first (rays x planes), so the long
+// problems start first in each launch.
+int batch_order(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t out_dt, bool sino_is_input,
+                std::vector<int32_t> &order)
 {
     if (n < 0) return fail(PN_EINVAL, "negative problem count");
     if (n > 0 && !probs) return fail(PN_EINVAL, "problem array is NULL");
+    std::vector<double> cost(n);
     for (int32_t i = 0; i < n; ++i) {
-        int rc = fn(&probs[i].geom, 1, probs[i].in, probs[i].out, in_dt, out_dt, st);
+        Geo g;
+        int rc = preflight(&probs[i].geom, 1, probs[i].in, probs[i].out, in_dt, out_dt, sino_is_input, g);
         if (rc) {
             std::string msg = t_err;
             return fail(rc, "problem %d: %s", i, msg.c_str());
         }
+        cost[i] = (double)g.n_views * g.nu * g.nv * std::max(g.n[0], std::max(g.n[1], g.n[2]));
     }
+    order.resize(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
     return PN_OK;
+}
+
+// Builds the work list of the jobs in `idx` with `blocks(job)` workgroups
+// each, starting every problem at a multiple of `align`.
+template <typename P, typename Job, typename BlocksFn, typename ParamFn>
+int make_batch(const std::vector<Job> &jobs, const std::vector<int> &idx, BlocksFn blocks, ParamFn param,
+               int64_t align, Batch<P> &w)
+{
+    w.n = (int32_t)idx.size();
+    int64_t at = 0;
+    for (int32_t i = 0; i < w.n; ++i) {
+        w.p[i] = param(jobs[idx[i]]);
+        w.start[i] = (uint32_t)at;
+        at += (blocks(w.p[i]) + align - 1) / align * align;
+        if (at > INT32_MAX) return fail(PN_EINVAL, "batched launch too large");
+    }
+    w.start[w.n] = (uint32_t)at;
+    return PN_OK;
+}
+
+// The problems of a batched call in work lists: `prepare(i, plan)` readies
+// problem i, and `launch(pending)` runs a list of prepared problems, at
+// most kMaxBatch and no plan twice.
+template <typename Prepare, typename Launch>
+int run_batched(const pn_problem *probs, const std::vector<int32_t> &order, Prepare prepare, Launch launch)
+{
+    std::vector<int32_t> pending;
+    std::vector<Plan *> plans;
+    for (int32_t i : order) {
+        Plan *pl;
+        int rc = get_plan(&probs[i].geom, &pl);
+        if (rc) {
+            std::string msg = t_err;
+            return fail(rc, "problem %d: %s", i, msg.c_str());
+        }
+        const bool seen = std::find(plans.begin(), plans.end(), pl) != plans.end();
+        if (seen || (int)pending.size() == kMaxBatch) {
+            if ((rc = launch(pending))) return rc;
+            pending.clear();
+            plans.clear();
+        }
+        if ((rc = prepare(i, pl))) {
+            std::string msg = t_err;
+            return fail(rc, "problem %d: %s", i, msg.c_str());
+        }
+        pending.push_back(i);
+        plans.push_back(pl);
+    }
+    return pending.empty() ? PN_OK : launch(pending);
+}
+
+int forward_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    std::vector<int32_t> order;
+    int rc = batch_order(probs, n, in_dt, out_dt, false, order);
+    if (rc || n == 0) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::vector<FwdJob> jobs(n);
+    std::vector<char> live(n, 0);
+    auto prepare = [&](int32_t i, Plan *pl) -> int {
+        bool none;
+        int r = forward_prepare(&probs[i].geom, 1, probs[i].in, probs[i].out, in_dt, st, pl, jobs[i], none);
+        live[i] = !none;
+        return r;
+    };
+    auto launch = [&](const std::vector<int32_t> &pending) -> int {
+        for (int two_d = 0; two_d < 2; ++two_d) {
+            std::vector<int> idx;
+            for (int32_t i : pending)
+                if (live[i] && jobs[i].two_d == (two_d != 0)) idx.push_back(i);
+            if (idx.empty()) continue;
+            Batch<FwdParams> w;
+            // problems start at multiples of 8 workgroups: the kernel's
+            // XCD-aware tile order stays intact
+            int r = make_batch<FwdParams>(jobs, idx, [](const FwdParams &p) { return forward_blocks(p); },
+                                          [](const FwdJob &j) { return j.p; }, 8, w);
+            if (r) return r;
+            hipError_t e = launch_forward_batch(w, two_d != 0, in_dt, out_dt, st);
+            if (e != hipSuccess) return fail_hip(e, "batched forward launch");
+        }
+        return (int)PN_OK;
+    };
+    return run_batched(probs, order, prepare, launch);
+}
+
+int adjoint_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    std::vector<int32_t> order;
+    int rc = batch_order(probs, n, in_dt, out_dt, true, order);
+    if (rc || n == 0) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::vector<AdjJob> jobs(n);
+    std::vector<char> live(n, 0);
+    auto prepare = [&](int32_t i, Plan *pl) -> int {
+        bool none;
+        int r = adjoint_prepare(1, probs[i].in, probs[i].out, in_dt, out_dt, st, pl, jobs[i], none);
+        live[i] = !none;
+        return r;
+    };
+    auto launch = [&](const std::vector<int32_t> &pending) -> int {
+        // passes in axis order: a problem's later passes add to its earlier ones
+        for (int a = 0; a < 3; ++a) {
+            for (int two_d = 0; two_d < 2; ++two_d) {
+                std::vector<int> idx;
+                for (int32_t i : pending)
+                    if (live[i] && jobs[i].two_d == (two_d != 0) && jobs[i].pass[a].n_pass_views > 0) idx.push_back(i);
+                if (idx.empty()) continue;
+                Batch<AdjParams> w;
+                int r = make_batch<AdjParams>(jobs, idx, [](const AdjParams &p) { return adjoint_blocks(p); },
+                                              [a](const AdjJob &j) { return j.pass[a]; }, 1, w);
+                if (r) return r;
+                hipError_t e = launch_adjoint_batch(w, a, in_dt, jobs[idx[0]].shape, st);
+                if (e != hipSuccess) return fail_hip(e, "batched adjoint launch");
+            }
+        }
+        for (int32_t i : pending) {
+            if (!live[i]) continue;
+            int r = adjoint_finish(jobs[i], st);
+            if (r) return r;
+        }
+        return (int)PN_OK;
+    };
+    return run_batched(probs, order, prepare, launch);
+}
+
+int backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    std::vector<int32_t> order;
+    int rc = batch_order(probs, n, in_dt, out_dt, true, order);
+    if (rc || n == 0) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::vector<BpJob> jobs(n);
+    auto prepare = [&](int32_t i, Plan *pl) -> int {
+        backproject_prepare(1, probs[i].in, probs[i].out, pl, jobs[i]);
+        return PN_OK;
+    };
+    auto launch = [&](const std::vector<int32_t> &pending) -> int {
+        for (int two_d = 0; two_d < 2; ++two_d) {
+            std::vector<int> idx;
+            for (int32_t i : pending)
+                if (jobs[i].two_d == (two_d != 0)) idx.push_back(i);
+            if (idx.empty()) continue;
+            Batch<BpParams> w;
+            int r = make_batch<BpParams>(jobs, idx, [](const BpParams &p) { return backproject_blocks(p); },
+                                         [](const BpJob &j) { return j.p; }, 1, w);
+            if (r) return r;
+            hipError_t e = launch_backproject_batch(w, two_d != 0, in_dt, out_dt, st);
+            if (e != hipSuccess) return fail_hip(e, "batched backproject launch");
+        }
+        return (int)PN_OK;
+    };
+    return run_batched(probs, order, prepare, launch);
 }
 
 // ------------------------------------------------ matrix composition -----
@@ -752,20 +1000,20 @@ int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void 
 int pn_forward_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype, void *hip_stream)
 {
     t_err.clear();
-    return batched(forward_impl, probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
+    return forward_batched(probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_adjoint_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype, void *hip_stream)
 {
     t_err.clear();
-    return batched(adjoint_impl, probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
+    return adjoint_batched(probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
                            void *hip_stream)
 {
     t_err.clear();
-    return batched(backproject_impl, probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
+    return backproject_batched(probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_check_geometry(const pn_geometry *pg)

@@ -113,6 +113,20 @@ __device__ __forceinline__ void ray_setup(const ViewTab &t, double u, double v, 
     r.m1 = static_cast<int>(fmin(ceil(hi), static_cast<double>(n[a] - 1)));
 }
 
+// Problem of a workgroup in a batched launch: the last i with start[i] <= bid
+// (start[0] = 0, increasing).
+template <typename P>
+__device__ __forceinline__ int batch_item(const Batch<P> &w, int bid)
+{
+    int lo = 0, hi = w.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (static_cast<int>(w.start[mid]) <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------- relayout --------
 
 // a = x: out[b][i][k + PADR_LO][j + PADC] = in[b][k][j][i] (tiled transpose)
@@ -276,7 +290,7 @@ struct Box {
 // the workgroups resident on one XCD sample nearly the same beam of the
 // volume and share its L2.
 template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
-__global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
+__device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
 {
     static_assert(TU * TV == 256, "one ray per thread");
     constexpr int VE = Vec<S>::N;
@@ -293,8 +307,8 @@ __global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
     const int t = threadIdx.x;
     const int tiles = p.tiles_u * p.tiles_v;
     const int tpx = (tiles + 7) >> 3;
-    const int xcd = blockIdx.x & 7;
-    const int slot = blockIdx.x >> 3;
+    const int xcd = bid & 7;
+    const int slot = bid >> 3;
     const int per_b = tpx * p.n_views;
     const int b = slot / per_b;
     const int rem = slot - b * per_b;
@@ -548,6 +562,19 @@ __global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
     out[((static_cast<int64_t>(b) * p.n_views + view) * p.nv + r) * p.nu + c] = from_f32<O>(live ? acc * seg.ds : 0.0f);
 }
 
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
+__global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
+{
+    forward_block<S, O, TU, TV, C, RCAP, FCAP>(p, blockIdx.x);
+}
+
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
+__global__ __launch_bounds__(256, 4) void forward_batch_kernel(Batch<FwdParams> w)
+{
+    const int i = batch_item(w, blockIdx.x);
+    forward_block<S, O, TU, TV, C, RCAP, FCAP>(w.p[i], blockIdx.x - w.start[i]);
+}
+
 // ------------------------------------------------------- adjoint A^T -----
 
 // Round to nearest (halves up): v_cvt_rpi_i32_f32 computes floor(x + 0.5)
@@ -646,7 +673,7 @@ __device__ __forceinline__ void clip_local(float b, float g, float hi_pos, float
 // rays have z == 0 exactly (the tap at z = 0 has weight 1 and the one at
 // z = 1 weight 0).
 template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
-__global__ __launch_bounds__(256, (L * TS * TF <= 4096 ? 4 : 2)) void adjoint_kernel(AdjParams p)
+__device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
 {
     using AX = PassAxes<A>;
     constexpr int F = AX::F, S = AX::S;
@@ -667,7 +694,7 @@ __global__ __launch_bounds__(256, (L * TS * TF <= 4096 ? 4 : 2)) void adjoint_ke
     __shared__ uint32_t s_seg[MAXSEG];         // slot | first local plane << 16 | planes << 24
     __shared__ uint32_t s_cnt[2][2];           // [parity][rays | segments << 16, max |q*ds| bits]
 
-    int blk = blockIdx.x;
+    int blk = bid;
     const int bf_ = blk % p.blocks_f;
     blk /= p.blocks_f;
     const int bs_ = blk % p.blocks_s;
@@ -971,6 +998,19 @@ __global__ __launch_bounds__(256, (L * TS * TF <= 4096 ? 4 : 2)) void adjoint_ke
     }
 }
 
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
+__global__ __launch_bounds__(256, (L * TS * TF <= 4096 ? 4 : 2)) void adjoint_kernel(AdjParams p)
+{
+    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT>(p, blockIdx.x);
+}
+
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
+__global__ __launch_bounds__(256, (L * TS * TF <= 4096 ? 4 : 2)) void adjoint_batch_kernel(Batch<AdjParams> w)
+{
+    const int i = batch_item(w, blockIdx.x);
+    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT>(w.p[i], blockIdx.x - w.start[i]);
+}
+
 // max |x| over a buffer, as the bit pattern of a non-negative float
 // (integer order = float order; NaN compares above +inf), combined with a
 // global atomic max.
@@ -997,7 +1037,7 @@ __global__ __launch_bounds__(256) void maxabs_kernel(const Q *__restrict__ src, 
 // current one is used.  Rectangles larger than RCAP x CCAP fall back to
 // bounds-checked gathers from the sinogram.
 template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
-__global__ __launch_bounds__(256) void backproject_kernel(BpParams p)
+__device__ __forceinline__ void backproject_block(const BpParams &p, const int bid)
 {
     static_assert(BX * BY == 256, "one voxel column per thread");
     constexpr int NE = RCAP * CCAP;
@@ -1005,7 +1045,7 @@ __global__ __launch_bounds__(256) void backproject_kernel(BpParams p)
     __shared__ float s_det[2][NE];
     const int t = threadIdx.x;
     const int nbx = (p.n[0] + BX - 1) / BX, nby = (p.n[1] + BY - 1) / BY, nbz = (p.n[2] + BZ - 1) / BZ;
-    int blk = blockIdx.x;
+    int blk = bid;
     const int bx = blk % nbx;
     blk /= nbx;
     const int by = blk % nby;
@@ -1161,6 +1201,19 @@ __global__ __launch_bounds__(256) void backproject_kernel(BpParams p)
     }
 }
 
+template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
+__global__ __launch_bounds__(256) void backproject_kernel(BpParams p)
+{
+    backproject_block<Q, O, BX, BY, BZ, RCAP, CCAP>(p, blockIdx.x);
+}
+
+template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
+__global__ __launch_bounds__(256) void backproject_batch_kernel(Batch<BpParams> w)
+{
+    const int i = batch_item(w, blockIdx.x);
+    backproject_block<Q, O, BX, BY, BZ, RCAP, CCAP>(w.p[i], blockIdx.x - w.start[i]);
+}
+
 // ------------------------------------------------------- utilities -------
 
 __global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t *__restrict__ dst, int64_t n_words)
@@ -1222,34 +1275,57 @@ int64_t forward_blocks(const FwdParams &p)
     return 8 * ((tiles + 7) / 8) * p.n_views * p.batch;
 }
 
-template <typename S, typename O>
-static hipError_t forward_t(const FwdParams &p, hipStream_t st)
+// Launch dispatch: a single problem passes its parameters, a batch its work
+// list; the kernel templates are the same.
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
+static void fwd_go(const FwdParams &p, uint32_t blocks, hipStream_t st)
 {
-    const int64_t blocks = forward_blocks(p);
-    if (p.tile_v == 1)
-        forward_kernel<S, O, 256, 1, 8, 3, 320><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+    forward_kernel<S, O, TU, TV, C, RCAP, FCAP><<<dim3(blocks), 256, 0, st>>>(p);
+}
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
+static void fwd_go(const Batch<FwdParams> &w, uint32_t blocks, hipStream_t st)
+{
+    forward_batch_kernel<S, O, TU, TV, C, RCAP, FCAP><<<dim3(blocks), 256, 0, st>>>(w);
+}
+
+template <typename S, typename O, typename Arg>
+static hipError_t forward_t(const Arg &a, bool two_d, uint32_t blocks, hipStream_t st)
+{
+    if (two_d)
+        fwd_go<S, O, 256, 1, 8, 3, 320>(a, blocks, st);
     else
-        forward_kernel<S, O, 16, 16, 8, 25, 40><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
+        fwd_go<S, O, 16, 16, 8, 25, 40>(a, blocks, st);
     return hipGetLastError();
 }
 
-template <typename S>
-static hipError_t forward_s(const FwdParams &p, int32_t out_dt, hipStream_t st)
+template <typename S, typename Arg>
+static hipError_t forward_s(const Arg &a, bool two_d, uint32_t blocks, int32_t out_dt, hipStream_t st)
 {
     switch (out_dt) {
-    case DT_F32: return forward_t<S, float>(p, st);
-    case DT_BF16: return forward_t<S, bf16>(p, st);
-    default: return forward_t<S, f16>(p, st);
+    case DT_F32: return forward_t<S, float>(a, two_d, blocks, st);
+    case DT_BF16: return forward_t<S, bf16>(a, two_d, blocks, st);
+    default: return forward_t<S, f16>(a, two_d, blocks, st);
+    }
+}
+
+template <typename Arg>
+static hipError_t forward_any(const Arg &a, bool two_d, uint32_t blocks, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    switch (in_dt) {
+    case DT_F32: return forward_s<float>(a, two_d, blocks, out_dt, st);
+    case DT_BF16: return forward_s<bf16>(a, two_d, blocks, out_dt, st);
+    default: return forward_s<f16>(a, two_d, blocks, out_dt, st);
     }
 }
 
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st)
 {
-    switch (in_dt) {
-    case DT_F32: return forward_s<float>(p, out_dt, st);
-    case DT_BF16: return forward_s<bf16>(p, out_dt, st);
-    default: return forward_s<f16>(p, out_dt, st);
-    }
+    return forward_any(p, p.tile_v == 1, static_cast<uint32_t>(forward_blocks(p)), in_dt, out_dt, st);
+}
+
+hipError_t launch_forward_batch(const Batch<FwdParams> &w, bool two_d, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    return forward_any(w, two_d, w.start[w.n], in_dt, out_dt, st);
 }
 
 void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv)
@@ -1260,8 +1336,8 @@ void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv)
 
 // Compiled adjoint block shapes (planes x rows x columns, candidates per
 // thread per batch); index 0 is 2-D.
-static const int32_t kAdjShapes[][4] = {{32, 1, 64, 1}, {16, 16, 16, 2}, {32, 8, 16, 1}, {32, 16, 16, 2}, {16, 16, 32, 2}};
-constexpr int kNumAdjShapes = 5;
+static const int32_t kAdjShapes[][4] = {{32, 1, 64, 1}, {16, 16, 16, 2}, {32, 8, 16, 1}};
+constexpr int kNumAdjShapes = 3;
 
 int adjoint_shape_count() { return kNumAdjShapes; }
 
@@ -1272,76 +1348,125 @@ void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF)
     TF = kAdjShapes[id][2];
 }
 
-template <typename Q, int L, int TS, int TF, int SLO, int SHI, int CPT>
-static hipError_t adjoint_axes(const AdjParams &p, hipStream_t st)
+int64_t adjoint_blocks(const AdjParams &p)
 {
-    const dim3 g(static_cast<uint32_t>(static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch));
-    switch (p.axis) {
-    case 0: adjoint_kernel<Q, 0, L, TS, TF, SLO, SHI, CPT><<<g, 256, 0, st>>>(p); break;
-    case 1: adjoint_kernel<Q, 1, L, TS, TF, SLO, SHI, CPT><<<g, 256, 0, st>>>(p); break;
+    return static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch;
+}
+
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
+static void adj_go(const AdjParams &p, uint32_t blocks, hipStream_t st)
+{
+    adjoint_kernel<Q, A, L, TS, TF, SLO, SHI, CPT><<<dim3(blocks), 256, 0, st>>>(p);
+}
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
+static void adj_go(const Batch<AdjParams> &w, uint32_t blocks, hipStream_t st)
+{
+    adjoint_batch_kernel<Q, A, L, TS, TF, SLO, SHI, CPT><<<dim3(blocks), 256, 0, st>>>(w);
+}
+
+template <typename Q, int L, int TS, int TF, int SLO, int SHI, int CPT, typename Arg>
+static hipError_t adjoint_axes(const Arg &a, int axis, uint32_t blocks, hipStream_t st)
+{
+    switch (axis) {
+    case 0: adj_go<Q, 0, L, TS, TF, SLO, SHI, CPT>(a, blocks, st); break;
+    case 1: adj_go<Q, 1, L, TS, TF, SLO, SHI, CPT>(a, blocks, st); break;
     default:
         if constexpr (TS == 1) {
             return hipErrorInvalidValue;  // 2-D rays never have z dominant
         } else {
-            adjoint_kernel<Q, 2, L, TS, TF, SLO, SHI, CPT><<<g, 256, 0, st>>>(p);
+            adj_go<Q, 2, L, TS, TF, SLO, SHI, CPT>(a, blocks, st);
         }
         break;
     }
     return hipGetLastError();
 }
 
-template <typename Q>
-static hipError_t adjoint_q(const AdjParams &p, int shape, hipStream_t st)
+template <typename Q, typename Arg>
+static hipError_t adjoint_q(const Arg &a, int axis, int shape, uint32_t blocks, hipStream_t st)
 {
     switch (shape) {
-    case 0: return adjoint_axes<Q, 32, 1, 64, 0, 1, 1>(p, st);
-    case 1: return adjoint_axes<Q, 16, 16, 16, 1, 2, 2>(p, st);
-    case 2: return adjoint_axes<Q, 32, 8, 16, 1, 2, 1>(p, st);
-    case 3: return adjoint_axes<Q, 32, 16, 16, 1, 2, 2>(p, st);
-    default: return adjoint_axes<Q, 16, 16, 32, 1, 2, 2>(p, st);
+    case 0: return adjoint_axes<Q, 32, 1, 64, 0, 1, 1>(a, axis, blocks, st);
+    case 1: return adjoint_axes<Q, 16, 16, 16, 1, 2, 2>(a, axis, blocks, st);
+    default: return adjoint_axes<Q, 32, 8, 16, 1, 2, 1>(a, axis, blocks, st);
+    }
+}
+
+template <typename Arg>
+static hipError_t adjoint_any(const Arg &a, int axis, int32_t in_dt, int shape, uint32_t blocks, hipStream_t st)
+{
+    switch (in_dt) {
+    case DT_F32: return adjoint_q<float>(a, axis, shape, blocks, st);
+    case DT_BF16: return adjoint_q<bf16>(a, axis, shape, blocks, st);
+    default: return adjoint_q<f16>(a, axis, shape, blocks, st);
     }
 }
 
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st)
 {
-    switch (in_dt) {
-    case DT_F32: return adjoint_q<float>(p, shape, st);
-    case DT_BF16: return adjoint_q<bf16>(p, shape, st);
-    default: return adjoint_q<f16>(p, shape, st);
-    }
+    return adjoint_any(p, p.axis, in_dt, shape, static_cast<uint32_t>(adjoint_blocks(p)), st);
 }
 
-template <typename Q, typename O>
-static hipError_t bp_t(const BpParams &p, hipStream_t st)
+hipError_t launch_adjoint_batch(const Batch<AdjParams> &w, int axis, int32_t in_dt, int shape, hipStream_t st)
 {
-    if (p.n[2] == 1) {
-        const int64_t blocks = static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * p.batch;
-        backproject_kernel<Q, O, 16, 16, 1, 4, 64><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
-    } else {
-        const int64_t blocks =
-            static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * ((p.n[2] + 7) / 8) * p.batch;
-        backproject_kernel<Q, O, 16, 16, 8, 16, 32><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(p);
-    }
+    return adjoint_any(w, axis, in_dt, shape, w.start[w.n], st);
+}
+
+int64_t backproject_blocks(const BpParams &p)
+{
+    if (p.n[2] == 1) return static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * p.batch;
+    return static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * ((p.n[2] + 7) / 8) * p.batch;
+}
+
+template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
+static void bp_go(const BpParams &p, uint32_t blocks, hipStream_t st)
+{
+    backproject_kernel<Q, O, BX, BY, BZ, RCAP, CCAP><<<dim3(blocks), 256, 0, st>>>(p);
+}
+template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
+static void bp_go(const Batch<BpParams> &w, uint32_t blocks, hipStream_t st)
+{
+    backproject_batch_kernel<Q, O, BX, BY, BZ, RCAP, CCAP><<<dim3(blocks), 256, 0, st>>>(w);
+}
+
+template <typename Q, typename O, typename Arg>
+static hipError_t bp_t(const Arg &a, bool two_d, uint32_t blocks, hipStream_t st)
+{
+    if (two_d)
+        bp_go<Q, O, 16, 16, 1, 4, 64>(a, blocks, st);
+    else
+        bp_go<Q, O, 16, 16, 8, 16, 32>(a, blocks, st);
     return hipGetLastError();
 }
 
-template <typename Q>
-static hipError_t bp_q(const BpParams &p, int32_t out_dt, hipStream_t st)
+template <typename Q, typename Arg>
+static hipError_t bp_q(const Arg &a, bool two_d, uint32_t blocks, int32_t out_dt, hipStream_t st)
 {
     switch (out_dt) {
-    case DT_F32: return bp_t<Q, float>(p, st);
-    case DT_BF16: return bp_t<Q, bf16>(p, st);
-    default: return bp_t<Q, f16>(p, st);
+    case DT_F32: return bp_t<Q, float>(a, two_d, blocks, st);
+    case DT_BF16: return bp_t<Q, bf16>(a, two_d, blocks, st);
+    default: return bp_t<Q, f16>(a, two_d, blocks, st);
+    }
+}
+
+template <typename Arg>
+static hipError_t bp_any(const Arg &a, bool two_d, uint32_t blocks, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    switch (in_dt) {
+    case DT_F32: return bp_q<float>(a, two_d, blocks, out_dt, st);
+    case DT_BF16: return bp_q<bf16>(a, two_d, blocks, out_dt, st);
+    default: return bp_q<f16>(a, two_d, blocks, out_dt, st);
     }
 }
 
 hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st)
 {
-    switch (in_dt) {
-    case DT_F32: return bp_q<float>(p, out_dt, st);
-    case DT_BF16: return bp_q<bf16>(p, out_dt, st);
-    default: return bp_q<f16>(p, out_dt, st);
-    }
+    return bp_any(p, p.n[2] == 1, static_cast<uint32_t>(backproject_blocks(p)), in_dt, out_dt, st);
+}
+
+hipError_t launch_backproject_batch(const Batch<BpParams> &w, bool two_d, int32_t in_dt, int32_t out_dt,
+                                    hipStream_t st)
+{
+    return bp_any(w, two_d, w.start[w.n], in_dt, out_dt, st);
 }
 
 hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st)
