@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--profile-once", action="store_true",
                     help="run one forward and one adjoint only (for counter collection)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-problem batched variant")
+    ap.add_argument("--unrolled512", action="store_true",
+                    help="also time the 512^3 x 720 unrolled 10-step reconstruction (FP32 and BF16 storage)")
     return ap.parse_args()
 
 
@@ -112,6 +114,60 @@ def batched_variant(pn, W, np, torch, stream):
         "batched_adjoint_ms": ta,
         "batched_updates": upd,
     }
+
+
+def unrolled_variant(pn, W, np, torch):
+    """Ten checkpointed gradient steps x <- x - alpha A^T (A x - y) on the
+    512^3 x 720 workload (1024^2 detector at 0.5 mm), forward and backward
+    through the loop, with FP32 and with BF16 storage.  y is Poisson data
+    (I0 = 1e5, kappa = 4 / max(A x_true), counts drawn on the GPU from a
+    generator seeded 55); alpha = 1/L from 20 power iterations of A^T A."""
+    cfg = W.CONFIGS["cone3d_512"]
+    shp, sp, det, ds = cfg["vol_shape"], cfg["vol_spacing"], cfg["det_shape"], cfg["det_spacing"]
+    log("unrolled512: phantom")
+    geom = pn.cone_geometry(shp, sp, det, ds, cfg["n_views"], cfg["sid"], cfg["sdd"])
+    x_true = torch.from_numpy(W.ellipsoid_phantom_3d(cfg["seeds"][0], shp, sp, cfg["n_ellipsoids"])[0]).float().cuda()
+    with torch.no_grad():
+        p = pn.forward(x_true, geom)
+        kappa = 4.0 / float(p.max())
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(cfg["poisson_seed"])
+        counts = torch.poisson(cfg["I0"] * torch.exp(-kappa * p), generator=gen)
+        y = -torch.log(torch.clamp(counts, min=1.0) / cfg["I0"]) / kappa
+        del p, counts
+        gen.manual_seed(cfg["poisson_seed"] + 1)
+        v = torch.randn(x_true.shape, device="cuda", generator=gen)
+        log("unrolled512: power iterations")
+        for _ in range(20):
+            w = pn.adjoint(pn.forward(v, geom), geom)
+            lam = float(w.norm() / v.norm())
+            v = w / w.norm()
+        del v, w
+    alpha = 1.0 / lam
+    upd = float(np.prod(shp)) * cfg["n_views"]
+    steps = cfg["unrolled_steps"]
+    out = {"alpha": alpha, "steps": steps, "kappa": kappa}
+    results = {}
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        x0 = torch.zeros(shp, device="cuda", dtype=dt, requires_grad=True)
+        yd = y.to(dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xk = pn.unrolled_gd(x0, yd, geom, alpha, steps, checkpoint=True)
+        loss = 0.5 * (xk.float() - x_true).square().sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        # operator calls: 2 per step forward; recompute (2) + backward (2) per step
+        calls = 6 * steps
+        results[name] = xk.detach().float()
+        out[f"{name}_seconds"] = round(dt_s, 3)
+        out[f"{name}_operator_gups"] = round(calls * upd / dt_s / 1e9, 1)
+        out[f"{name}_rel_error_vs_truth"] = float((xk.detach().float() - x_true).norm() / x_true.norm())
+        log(f"unrolled512 {name}: {dt_s:.2f} s, {out[f'{name}_operator_gups']} GUPS over {calls} operator calls")
+        del x0, xk, loss
+    out["bf16_vs_f32_rel"] = float((results["bf16"] - results["f32"]).norm() / results["f32"].norm())
+    return out
 
 
 def main():
@@ -196,6 +252,8 @@ def main():
 
     if not args.no_variants and not args.no_batched:
         variants.update(batched_variant(pn, W, np, torch, stream))
+    if args.unrolled512:
+        variants["unrolled512"] = unrolled_variant(pn, W, np, torch)
 
     # roofline of the dominant operator under the per-view streaming model:
     # each voxel-view update moves the stored voxel once plus its share of
