@@ -301,6 +301,8 @@ struct Plan {
     uint32_t *d_maxabs = nullptr;
     // largest per-view bound on the rays that sample one voxel's neighbourhood
     float kmax = 1.0f;
+    // 3-D adjoint block shape chosen by the autotuner (0: not tuned)
+    int adj_shape = 0;
 
     ~Plan()
     {
@@ -535,6 +537,70 @@ int adjoint_shape_3d()
     return shape;
 }
 
+// ------------------------------------------------------------ autotuner --
+//
+// With PN_AUTOTUNE=1 the first 3-D adjoint of a plan (outside graph
+// capture) times every compiled block shape on the caller's stream and keeps
+// the fastest for the plan.  PN_TUNE_CACHE=<file> keeps the choices across
+// processes, one line per geometry: "nz ny nx rows cols views beam shape".
+// Different shapes round the fixed-point sums at different points, so with
+// tuning on, the last bits of the adjoint can differ between processes
+// whose choices differ; without it the shape is fixed (PN_ADJ_SHAPE or 16^3).
+
+bool autotune_on()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("PN_AUTOTUNE");
+        return e && std::atoi(e) != 0;
+    }();
+    return on;
+}
+
+std::string tune_key(const Geo &g)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d", g.n[2], g.n[1], g.n[0], g.nv, g.nu, g.n_views,
+                  g.parallel ? 0 : 1);
+    return buf;
+}
+
+int tune_cache_lookup(const Geo &g)
+{
+    const char *path = std::getenv("PN_TUNE_CACHE");
+    if (!path) return 0;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return 0;
+    const std::string key = tune_key(g);
+    char line[256];
+    int found = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        const std::string l(line);
+        if (l.compare(0, key.size(), key) == 0 && l.size() > key.size() && l[key.size()] == ' ') {
+            const int v = std::atoi(l.c_str() + key.size() + 1);
+            if (v >= 1 && v < adjoint_shape_count()) found = v;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_store(const Geo &g, int shape)
+{
+    const char *path = std::getenv("PN_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", tune_key(g).c_str(), shape);
+    std::fclose(f);
+}
+
+// The 3-D adjoint block shape of a plan: tuned, cached, or the fixed one.
+int plan_adjoint_shape(Plan *pl)
+{
+    if (pl->adj_shape == 0 && autotune_on()) pl->adj_shape = tune_cache_lookup(pl->g);
+    return pl->adj_shape ? pl->adj_shape : adjoint_shape_3d();
+}
+
 // ---------------------------------------------------- prepared problems --
 //
 // Every call is validated and prepared problem by problem (plan, work
@@ -603,7 +669,7 @@ struct AdjJob {
 };
 
 int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, int32_t out_dt, hipStream_t st,
-                    Plan *pl, AdjJob &job, bool &none)
+                    Plan *pl, AdjJob &job, bool &none, int force_shape = 0)
 {
     const Geo &g = pl->g;
     const int64_t item = (int64_t)g.n[0] * g.n[1] * g.n[2];
@@ -634,7 +700,7 @@ int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, i
         target = pl->d_acc;
     }
     const bool two_d = g.ndim == 2;
-    const int shape = two_d ? 0 : adjoint_shape_3d();
+    const int shape = two_d ? 0 : (force_shape ? force_shape : plan_adjoint_shape(pl));
     int32_t L, TS, TF;
     adjoint_shape(shape, L, TS, TF);
     {
@@ -747,12 +813,58 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
     if ((rc = get_plan(pg, &pl))) return rc;
     AdjJob job;
     bool none;
-    if ((rc = adjoint_prepare(batch, sino, vol, in_dt, out_dt, st, pl, job, none)) || none) return rc;
-    for (int a = 0; a < 3; ++a) {
-        if (job.pass[a].n_pass_views == 0) continue;
-        hipError_t e = launch_adjoint(job.pass[a], in_dt, job.shape, st);
-        if (e != hipSuccess) return fail_hip(e, "adjoint launch");
+    auto run = [&](int force) -> int {
+        int r = adjoint_prepare(batch, sino, vol, in_dt, out_dt, st, pl, job, none, force);
+        if (r || none) return r;
+        for (int a = 0; a < 3; ++a) {
+            if (job.pass[a].n_pass_views == 0) continue;
+            hipError_t e = launch_adjoint(job.pass[a], in_dt, job.shape, st);
+            if (e != hipSuccess) return fail_hip(e, "adjoint launch");
+        }
+        return PN_OK;
+    };
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (autotune_on() && pl->g.ndim == 3 && plan_adjoint_shape(pl) && pl->adj_shape == 0 &&
+        hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+        // time every shape (each run overwrites the output), keep the fastest
+        const int ns = adjoint_shape_count();
+        std::vector<hipEvent_t> ev(2 * ns, nullptr);
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int k = 1; k < ns && rc == PN_OK; ++k) {
+            if (hipEventCreate(&ev[2 * k]) != hipSuccess || hipEventCreate(&ev[2 * k + 1]) != hipSuccess) {
+                rc = fail(PN_EHIP, "autotune: hipEventCreate failed");
+                break;
+            }
+            if (hipEventRecord(ev[2 * k], st) != hipSuccess) {
+                rc = fail(PN_EHIP, "autotune: hipEventRecord failed");
+                break;
+            }
+            if ((rc = run(k))) break;
+            if (hipEventRecord(ev[2 * k + 1], st) != hipSuccess) {
+                rc = fail(PN_EHIP, "autotune: hipEventRecord failed");
+                break;
+            }
+        }
+        for (int k = 1; k < ns && rc == PN_OK; ++k) {
+            float ms = 0.0f;
+            if (hipEventSynchronize(ev[2 * k + 1]) != hipSuccess ||
+                hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) {
+                rc = fail(PN_EHIP, "autotune: event timing failed");
+                break;
+            }
+            if (best == 0 || ms < best_ms) {
+                best = k;
+                best_ms = ms;
+            }
+        }
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (rc) return rc;
+        pl->adj_shape = best;
+        tune_cache_store(pl->g, best);
     }
+    if ((rc = run(0)) || none) return rc;
     return adjoint_finish(job, st);
 }
 
@@ -898,16 +1010,16 @@ int adjoint_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t o
     auto launch = [&](const std::vector<int32_t> &pending) -> int {
         // passes in axis order: a problem's later passes add to its earlier ones
         for (int a = 0; a < 3; ++a) {
-            for (int two_d = 0; two_d < 2; ++two_d) {
+            for (int shape = 0; shape < adjoint_shape_count(); ++shape) {  // 2-D problems use shape 0
                 std::vector<int> idx;
                 for (int32_t i : pending)
-                    if (live[i] && jobs[i].two_d == (two_d != 0) && jobs[i].pass[a].n_pass_views > 0) idx.push_back(i);
+                    if (live[i] && jobs[i].shape == shape && jobs[i].pass[a].n_pass_views > 0) idx.push_back(i);
                 if (idx.empty()) continue;
                 Batch<AdjParams> w;
                 int r = make_batch<AdjParams>(jobs, idx, [](const AdjParams &p) { return adjoint_blocks(p); },
                                               [a](const AdjJob &j) { return j.pass[a]; }, 1, w);
                 if (r) return r;
-                hipError_t e = launch_adjoint_batch(w, a, in_dt, jobs[idx[0]].shape, st);
+                hipError_t e = launch_adjoint_batch(w, a, in_dt, shape, st);
                 if (e != hipSuccess) return fail_hip(e, "batched adjoint launch");
             }
         }
