@@ -53,7 +53,8 @@ struct FwdParams {
     const void *vol;       // caller's volume [batch][nz][ny][nx] (fallback path)
     void *sino;            // [batch][n_views][nv][nu]
     int32_t tile_u, tile_v;  // ray tile (tile_u * tile_v == block size)
-    int32_t tiles_u, tiles_v;
+    int32_t tiles_u, tiles_v;  // tiles covering the detector window [c_lo, nu) x [r_lo, nv) that is launched
+    int32_t c_lo, r_lo;        // first column and row of the window
 };
 
 struct AdjParams {

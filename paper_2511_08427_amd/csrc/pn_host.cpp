@@ -303,6 +303,9 @@ struct Plan {
     float kmax = 1.0f;
     // 3-D adjoint block shape chosen by the autotuner (0: not tuned)
     int adj_shape = 0;
+    // detector window that holds every ray meeting the dilated volume in
+    // some view (inclusive pixel bounds; c0 > c1: no ray meets it)
+    int32_t win_c0 = 0, win_c1 = -1, win_r0 = 0, win_r1 = -1;
 
     ~Plan()
     {
@@ -361,6 +364,7 @@ void build_tables(Plan &pl)
     pl.tabf.resize(g.n_views);
     for (int a = 0; a < 3; ++a) pl.pass_views[a].clear();
     pl.axes_union = 0;
+    double umin = HUGE_VAL, umax = -HUGE_VAL, vmin = HUGE_VAL, vmax = -HUGE_VAL;
     for (int k = 0; k < g.n_views; ++k) {
         const double *P = &g.P[(size_t)12 * k];
         ViewTab &t = pl.tab[k];
@@ -405,8 +409,32 @@ void build_tables(Plan &pl)
         tf.pad = 0;
         pl.kmax = std::max(pl.kmax, tf.kcell);
         pl.axes_union |= tf.axes;
+        // the dilated volume [-1, n] projects into the convex hull of its
+        // corners' projections (W > 0 there): rays outside it sum to zero
+        for (int c = 0; c < 8; ++c) {
+            const double x = (c & 1) ? g.n[0] : -1.0, y = (c & 2) ? g.n[1] : -1.0, z = (c & 4) ? g.n[2] : -1.0;
+            const double U = t.Pi[0] * x + t.Pi[1] * y + t.Pi[2] * z + t.Pi[3];
+            const double V = t.Pi[4] * x + t.Pi[5] * y + t.Pi[6] * z + t.Pi[7];
+            const double W = t.Pi[8] * x + t.Pi[9] * y + t.Pi[10] * z + t.Pi[11];
+            umin = std::min(umin, U / W);
+            umax = std::max(umax, U / W);
+            vmin = std::min(vmin, V / W);
+            vmax = std::max(vmax, V / W);
+        }
         for (int a = 0; a < 3; ++a)
             if (tf.axes >> a & 1) pl.pass_views[a].push_back(k);
+    }
+    // one pixel of margin for the rounding of the bounds
+    if (g.n_views > 0 && std::isfinite(umin) && std::isfinite(umax) && std::isfinite(vmin) && std::isfinite(vmax)) {
+        pl.win_c0 = (int32_t)std::max(0.0, std::min((double)g.nu, std::floor(umin) - 1.0));
+        pl.win_c1 = (int32_t)std::min((double)g.nu - 1.0, std::max(-1.0, std::ceil(umax) + 1.0));
+        pl.win_r0 = (int32_t)std::max(0.0, std::min((double)g.nv, std::floor(vmin) - 1.0));
+        pl.win_r1 = (int32_t)std::min((double)g.nv - 1.0, std::max(-1.0, std::ceil(vmax) + 1.0));
+    } else {
+        pl.win_c0 = 0;
+        pl.win_c1 = g.nu - 1;
+        pl.win_r0 = 0;
+        pl.win_r1 = g.nv - 1;
     }
 }
 
@@ -617,7 +645,7 @@ struct FwdJob {
 };
 
 int forward_prepare(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt,
-                    hipStream_t st, Plan *pl, FwdJob &job, bool &none)
+                    int32_t out_dt, hipStream_t st, Plan *pl, FwdJob &job, bool &none)
 {
     const Geo &g = pl->g;
     none = g.n_views == 0;
@@ -647,9 +675,20 @@ int forward_prepare(const pn_geometry *pg, int64_t batch, const void *vol, void 
     p.vol = vol;
     p.sino = sino;
     forward_tile_shape(g.ndim == 2, p.tile_u, p.tile_v);
-    p.tiles_u = (g.nu + p.tile_u - 1) / p.tile_u;
-    p.tiles_v = (g.nv + p.tile_v - 1) / p.tile_v;
+    // only the tiles of the detector window that can see the volume are
+    // launched; the rest of the sinogram is zero
+    const bool full = pl->win_c0 == 0 && pl->win_r0 == 0 && pl->win_c1 == g.nu - 1 && pl->win_r1 == g.nv - 1;
+    if (!full) {
+        hipError_t e = launch_fill_zero(sino, (int64_t)g.n_views * g.nv * g.nu * batch * esize(out_dt), st);
+        if (e != hipSuccess) return fail_hip(e, "fill");
+    }
+    const bool empty = pl->win_c0 > pl->win_c1 || pl->win_r0 > pl->win_r1;
+    p.c_lo = empty ? 0 : pl->win_c0;
+    p.r_lo = empty ? 0 : pl->win_r0;
+    p.tiles_u = empty ? 0 : (pl->win_c1 - pl->win_c0 + p.tile_u) / p.tile_u;
+    p.tiles_v = empty ? 0 : (pl->win_r1 - pl->win_r0 + p.tile_v) / p.tile_v;
     if (forward_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
+    none = forward_blocks(p) == 0;
     (void)pg;
     job.p = p;
     job.two_d = g.ndim == 2;
@@ -796,7 +835,7 @@ int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *si
     if ((rc = get_plan(pg, &pl))) return rc;
     FwdJob job;
     bool none;
-    if ((rc = forward_prepare(pg, batch, vol, sino, in_dt, st, pl, job, none)) || none) return rc;
+    if ((rc = forward_prepare(pg, batch, vol, sino, in_dt, out_dt, st, pl, job, none)) || none) return rc;
     hipError_t e = launch_forward(job.p, in_dt, out_dt, st);
     if (e != hipSuccess) return fail_hip(e, "forward launch");
     return PN_OK;
@@ -969,7 +1008,7 @@ int forward_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t o
     std::vector<char> live(n, 0);
     auto prepare = [&](int32_t i, Plan *pl) -> int {
         bool none;
-        int r = forward_prepare(&probs[i].geom, 1, probs[i].in, probs[i].out, in_dt, st, pl, jobs[i], none);
+        int r = forward_prepare(&probs[i].geom, 1, probs[i].in, probs[i].out, in_dt, out_dt, st, pl, jobs[i], none);
         live[i] = !none;
         return r;
     };

@@ -315,7 +315,7 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
     const int tile = (rem / p.n_views) * 8 + xcd;
     const int view = rem % p.n_views;
     if (tile >= tiles || b >= p.batch) return;  // padding workgroups (uniform exit)
-    const int c0 = (tile % p.tiles_u) * TU, r0 = (tile / p.tiles_u) * TV;
+    const int c0 = p.c_lo + (tile % p.tiles_u) * TU, r0 = p.r_lo + (tile / p.tiles_u) * TV;
     const int c = c0 + t % TU, r = r0 + t / TU;
     const bool inside = c < p.nu && r < p.nv;
     const ViewTab &tab = p.tab[view];
@@ -1013,14 +1013,25 @@ __global__ __launch_bounds__(256, (L * TS * TF <= 4096 ? 4 : 2)) void adjoint_ba
 
 // max |x| over a buffer, as the bit pattern of a non-negative float
 // (integer order = float order; NaN compares above +inf), combined with a
-// global atomic max.
+// global atomic max.  A 16-byte aligned buffer is read as 16-byte vectors
+// (`vec`), the tail and unaligned buffers element by element.
 template <typename Q>
-__global__ __launch_bounds__(256) void maxabs_kernel(const Q *__restrict__ src, int64_t n, uint32_t *__restrict__ out)
+__global__ __launch_bounds__(256) void maxabs_kernel(const Q *__restrict__ src, int64_t n, int32_t vec,
+                                                     uint32_t *__restrict__ out)
 {
+    constexpr int VE = Vec<Q>::N;
+    const int64_t nvec = vec ? n / VE : 0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     uint32_t m = 0u;
-    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
-         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        m = max(m, __float_as_uint(fabsf(to_f32(src[e]))));
+    const uint4 *v = reinterpret_cast<const uint4 *>(src);
+    for (int64_t e = t0; e < nvec; e += stride) {
+        float f[VE];
+        unpack16<Q>(v[e], f);
+#pragma unroll
+        for (int k = 0; k < VE; ++k) m = max(m, __float_as_uint(fabsf(f[k])));
+    }
+    for (int64_t e = nvec * VE + t0; e < n; e += stride) m = max(m, __float_as_uint(fabsf(to_f32(src[e]))));
     m = wave_max_u32(m);
     if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
@@ -1472,14 +1483,15 @@ hipError_t launch_backproject_batch(const Batch<BpParams> &w, bool two_d, int32_
 hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st)
 {
     fill_zero_kernel<<<1, 64, 0, st>>>(out, 1);
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    int64_t blocks = (n / 8 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     const dim3 g(static_cast<uint32_t>(blocks));
+    const int32_t vec = reinterpret_cast<uintptr_t>(src) % 16 == 0;
     switch (in_dt) {
-    case DT_F32: maxabs_kernel<float><<<g, 256, 0, st>>>(static_cast<const float *>(src), n, out); break;
-    case DT_BF16: maxabs_kernel<bf16><<<g, 256, 0, st>>>(static_cast<const bf16 *>(src), n, out); break;
-    default: maxabs_kernel<f16><<<g, 256, 0, st>>>(static_cast<const f16 *>(src), n, out); break;
+    case DT_F32: maxabs_kernel<float><<<g, 256, 0, st>>>(static_cast<const float *>(src), n, vec, out); break;
+    case DT_BF16: maxabs_kernel<bf16><<<g, 256, 0, st>>>(static_cast<const bf16 *>(src), n, vec, out); break;
+    default: maxabs_kernel<f16><<<g, 256, 0, st>>>(static_cast<const f16 *>(src), n, vec, out); break;
     }
     return hipGetLastError();
 }
