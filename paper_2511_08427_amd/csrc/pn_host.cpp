@@ -26,6 +26,7 @@ hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hip
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
 hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st);
+hipError_t launch_cbox(const AdjParams &ap, int32_t L, int32_t TS, int32_t TF, uint32_t *out, hipStream_t st);
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 int adjoint_shape_count();
@@ -303,6 +304,9 @@ struct Plan {
     float kmax = 1.0f;
     // 3-D adjoint block shape chosen by the autotuner (0: not tuned)
     int adj_shape = 0;
+    // adjoint candidate pixel boxes per pass axis, for block shape cbox_shape
+    uint32_t *d_cbox[3] = {nullptr, nullptr, nullptr};
+    int cbox_shape[3] = {-1, -1, -1};
     // detector window that holds every ray meeting the dilated volume in
     // some view (inclusive pixel bounds; c0 > c1: no ray meets it)
     int32_t win_c0 = 0, win_c1 = -1, win_r0 = 0, win_r1 = -1;
@@ -317,6 +321,7 @@ struct Plan {
         }
         dev_free(d_acc);
         dev_free(d_maxabs);
+        for (int a = 0; a < 3; ++a) dev_free(d_cbox[a]);
     }
 };
 
@@ -780,6 +785,22 @@ int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, i
         p.blocks_s = (g.n[sl] + TS - 1) / TS;
         p.blocks_f = (g.n[f] + TF - 1) / TF;
         if (adjoint_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
+        // candidate boxes depend on the geometry and the block shape only:
+        // built once per plan and shape (a kernel on the caller's stream)
+        if (pl->cbox_shape[a] != shape) {
+            dev_free(pl->d_cbox[a]);
+            pl->d_cbox[a] = nullptr;
+            pl->cbox_shape[a] = -1;
+            const size_t need = (size_t)p.blocks_a * p.blocks_s * p.blocks_f * p.n_pass_views * 8;
+            hipError_t e = hipMalloc((void **)&pl->d_cbox[a], need);
+            if (e != hipSuccess) {
+                pl->d_cbox[a] = nullptr;
+                return fail(PN_ENOMEM, "candidate box hipMalloc(%zu): %s", need, hipGetErrorString(e));
+            }
+            if ((e = launch_cbox(p, L, TS, TF, pl->d_cbox[a], st)) != hipSuccess) return fail_hip(e, "cbox launch");
+            pl->cbox_shape[a] = shape;
+        }
+        p.cbox = pl->d_cbox[a];
         ++done;
     }
     job.two_d = two_d;

@@ -634,6 +634,91 @@ __device__ __forceinline__ void clip_local(float b, float g, float hi_pos, float
     hi = fminf(hi, floorf(fmaxf(t0, t1)));
 }
 
+// Candidate pixel boxes of the adjoint: for every block of a pass and
+// every view of the pass, the detector bounding box of the block dilated by
+// one voxel in-plane, i.e. of the projections of its 8 corners (FP32 from
+// the rounded index-space matrix; the 0.01 pixel margin covers the
+// rounding), clamped to the detector.  The projection of a convex box in
+// front of the source is the convex hull of its corners' projections, so
+// every ray that can sample the block has its pixel in the box.  Stored as
+// 2 words: first column | first row << 16, columns | rows << 16 (0: empty).
+struct CboxParams {
+    const ViewTabF *tabf;
+    const int32_t *views;
+    int32_t n_pass_views, axis, nu, nv;
+    int32_t n[3];
+    int32_t L, TS, TF;
+    int32_t blocks_a, blocks_s, blocks_f;
+    uint32_t *out;
+};
+
+__global__ __launch_bounds__(256) void cbox_kernel(CboxParams p)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nb = static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f;
+    if (e >= nb * p.n_pass_views) return;
+    const int pv = static_cast<int>(e % p.n_pass_views);
+    int blk = static_cast<int>(e / p.n_pass_views);
+    const int bf_ = blk % p.blocks_f;
+    blk /= p.blocks_f;
+    const int bs_ = blk % p.blocks_s;
+    const int ba_ = blk / p.blocks_s;
+    const int a = p.axis, f = a == 0 ? 1 : 0, sl = a == 2 ? 1 : 2;
+    const int a0 = ba_ * p.L, a1 = min(a0 + p.L, p.n[a]);
+    const int s0 = bs_ * p.TS, s1 = min(s0 + p.TS, p.n[sl]);
+    const int f0 = bf_ * p.TF, f1 = min(f0 + p.TF, p.n[f]);
+    const ViewTabF &tf = p.tabf[p.views[pv]];
+    float umin = 3e38f, umax = -3e38f, vmin = 3e38f, vmax = -3e38f;
+    for (int corner = 0; corner < 8; ++corner) {
+        float ijk[3];
+        ijk[a] = (corner & 1) ? static_cast<float>(a1 - 1) : static_cast<float>(a0);
+        ijk[sl] = (corner & 2) ? static_cast<float>(s1) : static_cast<float>(s0 - 1);
+        ijk[f] = (corner & 4) ? static_cast<float>(f1) : static_cast<float>(f0 - 1);
+        const float U = fmaf(tf.Pi[0], ijk[0], fmaf(tf.Pi[1], ijk[1], fmaf(tf.Pi[2], ijk[2], tf.Pi[3])));
+        const float V = fmaf(tf.Pi[4], ijk[0], fmaf(tf.Pi[5], ijk[1], fmaf(tf.Pi[6], ijk[2], tf.Pi[7])));
+        const float Wc = fmaf(tf.Pi[8], ijk[0], fmaf(tf.Pi[9], ijk[1], fmaf(tf.Pi[10], ijk[2], tf.Pi[11])));
+        const float rw = __builtin_amdgcn_rcpf(Wc);
+        umin = fminf(umin, U * rw);
+        umax = fmaxf(umax, U * rw);
+        vmin = fminf(vmin, V * rw);
+        vmax = fmaxf(vmax, V * rw);
+    }
+    // clamp before converting: the bounds are finite (W > 0 over the
+    // dilated volume) but may lie far outside the detector
+    const int cu0 = static_cast<int>(fminf(fmaxf(floorf(umin - 0.01f), 0.0f), static_cast<float>(p.nu)));
+    const int cu1 = static_cast<int>(fmaxf(fminf(ceilf(umax + 0.01f), static_cast<float>(p.nu - 1)), -1.0f));
+    const int cv0 = static_cast<int>(fminf(fmaxf(floorf(vmin - 0.01f), 0.0f), static_cast<float>(p.nv)));
+    const int cv1 = static_cast<int>(fmaxf(fminf(ceilf(vmax + 0.01f), static_cast<float>(p.nv - 1)), -1.0f));
+    const bool empty = cu0 > cu1 || cv0 > cv1;
+    const uint32_t w0 = empty ? 0u : static_cast<uint32_t>(cu0) | static_cast<uint32_t>(cv0) << 16;
+    const uint32_t w1 = empty ? 0u : static_cast<uint32_t>(cu1 - cu0 + 1) | static_cast<uint32_t>(cv1 - cv0 + 1) << 16;
+    p.out[2 * e] = w0;
+    p.out[2 * e + 1] = w1;
+}
+
+hipError_t launch_cbox(const AdjParams &ap, int32_t L, int32_t TS, int32_t TF, uint32_t *out, hipStream_t st)
+{
+    CboxParams p{};
+    p.tabf = ap.tabf;
+    p.views = ap.views;
+    p.n_pass_views = ap.n_pass_views;
+    p.axis = ap.axis;
+    p.nu = ap.nu;
+    p.nv = ap.nv;
+    for (int i = 0; i < 3; ++i) p.n[i] = ap.n[i];
+    p.L = L;
+    p.TS = TS;
+    p.TF = TF;
+    p.blocks_a = ap.blocks_a;
+    p.blocks_s = ap.blocks_s;
+    p.blocks_f = ap.blocks_f;
+    p.out = out;
+    const int64_t total = static_cast<int64_t>(ap.blocks_a) * ap.blocks_s * ap.blocks_f * ap.n_pass_views;
+    if (total == 0) return hipSuccess;
+    cbox_kernel<<<dim3(static_cast<uint32_t>((total + 255) / 256)), 256, 0, st>>>(p);
+    return hipGetLastError();
+}
+
 // Each workgroup owns a block of L planes (dominant axis A) x TS rows x TF
 // columns of the output.  Its FP32 sums live in registers (each thread owns
 // L*TS*TF/256 voxels); per batch of candidate rays they are gathered in LDS
@@ -766,44 +851,24 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
 
     const Q *sino_b = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
     int parity = 0;
+    // per view: its index and the block's candidate pixel box (precomputed
+    // by cbox_kernel), loaded one view ahead so the loads are in flight
+    // while the current view is processed
+    const int nbi = p.blocks_a * p.blocks_s * p.blocks_f;
+    const uint32_t *cbox = p.cbox + 2 * static_cast<int64_t>(bid % nbi) * p.n_pass_views;
+    int nx_view = p.n_pass_views > 0 ? p.views[0] : 0;
+    uint32_t nx_b0 = p.n_pass_views > 0 ? cbox[0] : 0u, nx_b1 = p.n_pass_views > 0 ? cbox[1] : 0u;
     for (int pv = 0; pv < p.n_pass_views; ++pv) {
-        const int view = __builtin_amdgcn_readfirstlane(p.views[pv]);
-        // detector bounding box of the block dilated by one voxel in-plane:
-        // lanes 0-7 of every wave project one corner each (FP32; the 0.01
-        // pixel margin covers its rounding), then a butterfly min/max
-        float umin, umax, vmin, vmax;
-        {
-            const int corner = t & 7;
-            float ijk[3];
-            ijk[A] = (corner & 1) ? static_cast<float>(a1 - 1) : static_cast<float>(a0);
-            ijk[S] = (corner & 2) ? static_cast<float>(s1) : static_cast<float>(s0 - 1);
-            ijk[F] = (corner & 4) ? static_cast<float>(f1) : static_cast<float>(f0 - 1);
-            const ViewTabF &tf = p.tabf[view];
-            const float U = fmaf(tf.Pi[0], ijk[0], fmaf(tf.Pi[1], ijk[1], fmaf(tf.Pi[2], ijk[2], tf.Pi[3])));
-            const float V = fmaf(tf.Pi[4], ijk[0], fmaf(tf.Pi[5], ijk[1], fmaf(tf.Pi[6], ijk[2], tf.Pi[7])));
-            const float Wc = fmaf(tf.Pi[8], ijk[0], fmaf(tf.Pi[9], ijk[1], fmaf(tf.Pi[10], ijk[2], tf.Pi[11])));
-            const float rw = __builtin_amdgcn_rcpf(Wc);
-            umin = umax = U * rw;
-            vmin = vmax = V * rw;
-#pragma unroll
-            for (int o = 1; o < 8; o <<= 1) {
-                umin = fminf(umin, __shfl_xor(umin, o));
-                umax = fmaxf(umax, __shfl_xor(umax, o));
-                vmin = fminf(vmin, __shfl_xor(vmin, o));
-                vmax = fmaxf(vmax, __shfl_xor(vmax, o));
-            }
-            umin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umin))) - 0.01f;
-            umax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umax))) + 0.01f;
-            vmin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmin))) - 0.01f;
-            vmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmax))) + 0.01f;
+        const int view = __builtin_amdgcn_readfirstlane(nx_view);
+        const uint32_t b0 = __builtin_amdgcn_readfirstlane(nx_b0), b1 = __builtin_amdgcn_readfirstlane(nx_b1);
+        if (pv + 1 < p.n_pass_views) {
+            nx_view = p.views[pv + 1];
+            nx_b0 = cbox[2 * (pv + 1)];
+            nx_b1 = cbox[2 * (pv + 1) + 1];
         }
-        // clamp before converting: the bounds are finite (W > 0 over the
-        // dilated volume) but may lie far outside the detector
-        const int cu0 = static_cast<int>(fminf(fmaxf(floorf(umin), 0.0f), static_cast<float>(p.nu)));
-        const int cu1 = static_cast<int>(fmaxf(fminf(ceilf(umax), static_cast<float>(p.nu - 1)), -1.0f));
-        const int cv0 = static_cast<int>(fminf(fmaxf(floorf(vmin), 0.0f), static_cast<float>(p.nv)));
-        const int cv1 = static_cast<int>(fmaxf(fminf(ceilf(vmax), static_cast<float>(p.nv - 1)), -1.0f));
-        if (cu0 > cu1 || cv0 > cv1) continue;  // uniform
+        const int cu0 = static_cast<int>(b0 & 0xffffu), cv0 = static_cast<int>(b0 >> 16);
+        const int wu = static_cast<int>(b1 & 0xffffu), wv = static_cast<int>(b1 >> 16);
+        if (wu == 0 || wv == 0) continue;  // uniform
         const float kcell = p.tabf[view].kcell;
         // the view's FP64 ray tables, needed rows only (uniform loads)
         const ViewTab &tv = p.tab[view];
@@ -814,7 +879,6 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
         const double Ba0 = tv.B[3 * A], Ba1 = tv.B[3 * A + 1], Ba2 = tv.B[3 * A + 2] - oa;
         const double Bf0 = tv.B[3 * F], Bf1 = tv.B[3 * F + 1], Bf2 = tv.B[3 * F + 2] - of;
         const double Bs0 = tv.B[3 * S], Bs1 = tv.B[3 * S + 1], Bs2 = tv.B[3 * S + 2] - os;
-        const int wu = cu1 - cu0 + 1, wv = cv1 - cv0 + 1;
         const int wu_e = (wu + 1) >> 1, wu_o = wu >> 1, wv_e = (wv + 1) >> 1;
         const int n00 = wu_e * wv_e, n10 = wu_o * wv_e, n01 = wu_e * (wv >> 1);
         const int ncand = wu * wv;
