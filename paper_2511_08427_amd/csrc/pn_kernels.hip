@@ -619,17 +619,17 @@ struct PassAxes {
 };
 
 // Narrows the local plane range [lo, hi] to the planes m where b + m*g lies
-// in [0.5, hi_pos].  The band has half a cell of margin on both sides of the
-// positions whose taps can reach a voxel of the block, so the FP32 rounding
-// of the bounds (far below half a cell of position) neither drops a plane
-// that matters nor admits a position whose taps leave the LDS block.
+// in [lo_pos - 1e-3, hi_pos + 1e-3].  The FP32 rounding of the bounds moves
+// a position at a boundary plane by ~|b| 2^-22, far less than the 1e-3
+// widening (so no plane inside the band is dropped) and than the cell of
+// margin the LDS block has beyond the band (so no tap leaves the block).
 // Branch-free: a zero slope is replaced by a tiny positive one, which keeps
 // or empties the whole range as the exact test would.
-__device__ __forceinline__ void clip_local(float b, float g, float hi_pos, float &lo, float &hi)
+__device__ __forceinline__ void clip_local(float b, float g, float lo_pos, float hi_pos, float &lo, float &hi)
 {
     const float gg = fabsf(g) < 1e-30f ? 1e-30f : g;
     const float rg = __builtin_amdgcn_rcpf(gg);
-    const float t0 = (0.5f - b) * rg, t1 = (hi_pos - b) * rg;
+    const float t0 = (lo_pos - 1e-3f - b) * rg, t1 = (hi_pos + 1e-3f - b) * rg;
     lo = fmaxf(lo, ceilf(fminf(t0, t1)));
     hi = fminf(hi, floorf(fmaxf(t0, t1)));
 }
@@ -732,10 +732,9 @@ hipError_t launch_cbox(const AdjParams &ap, int32_t L, int32_t TS, int32_t TF, u
 //            plane range cut into segments of <= K planes;
 //   phase B  each thread takes segments and scatters the bilinear taps of
 //            their samples with ds_add_u32.  A segment's planes are those
-//            where the ray's position lies within half a cell of the block
-//            dilated by one voxel, so every tap lands in the block or its
-//            halo (no clamp); taps of positions outside the dilated block
-//            land in halo cells, which are discarded;
+//            where the ray's position lies in the block dilated by one
+//            voxel (the reach of a tap), so every tap lands in the block or
+//            its halo (no clamp); halo cells are discarded;
 //   flush    when the next batch could overflow the integers, each thread
 //            moves its voxels' integer sums into its FP32 registers and
 //            clears them (and once at the end).
@@ -790,12 +789,13 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     const int s0 = bs_ * TS, s1 = min(s0 + TS, p.n[S]);
     const int f0 = bf_ * TF, f1 = min(f0 + TF, p.n[F]);
     // block-local frame: local = global - origin, the origin being the
-    // first halo cell.  The dilated block (one voxel around it, the reach of
-    // a bilinear tap) spans local [1, f1 - f0 + 2] and [1, smax]; positions
-    // within half a cell of it, [0.5, fhi] x [0.5, shi], have both taps
-    // inside the LDS block.
-    const float fhi = static_cast<float>(f1 - f0) + 2.5f;
-    const float shi = static_cast<float>(min(s1 - s0 + 1, RP - 3)) + 1.5f;
+    // first halo cell.  The positions whose taps reach a voxel of the block
+    // lie in the block dilated by one voxel, local [1, f1 - f0 + 2] x
+    // [1, s1 - s0 + 2]; the LDS block has one more cell on every side.  2-D
+    // rays sit exactly at local row 1 (band [0.5, 1.5]).
+    const float flo = 1.0f, fhi = static_cast<float>(f1 - f0 + 2);
+    const float slo = TS == 1 ? 0.5f : 1.0f;
+    const float shi = TS == 1 ? 1.5f : static_cast<float>(s1 - s0 + 2);
     const float amaxl = static_cast<float>(a1 - a0 - 1);
     const int t = threadIdx.x, lane = t & 63;
     const double oa = a0, of = f0 - 2, os = s0 - SLO - 1;
@@ -946,8 +946,8 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
                         const float wz = static_cast<float>(A == 2 ? da : dsl) * static_cast<float>(p.s[2]);
                         dsm = __builtin_amdgcn_sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz))) * fabsf(static_cast<float>(inv));
                         float lo = 0.0f, hi = amaxl;
-                        clip_local(bfl, gf32, fhi, lo, hi);
-                        clip_local(bsl, gs32, shi, lo, hi);
+                        clip_local(bfl, gf32, flo, fhi, lo, hi);
+                        clip_local(bsl, gs32, slo, shi, lo, hi);
                         m0 = static_cast<int>(lo);
                         const int m1 = static_cast<int>(hi);
                         if (m0 <= m1 && isfinite(dsm)) {
@@ -1021,7 +1021,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
                         const float pf = fmaf(static_cast<float>(k), rp.x, pf0);
                         const float ps = fmaf(static_cast<float>(k), rp.z, ps0);
                         const float wf = __builtin_amdgcn_fractf(pf), ws = __builtin_amdgcn_fractf(ps);
-                        // positions are >= 0.5: truncation is floor
+                        // positions are >= 1 up to rounding: truncation is floor
                         uint32_t off = __umul24(static_cast<uint32_t>(ps), static_cast<uint32_t>(RW * 4)) +
                                        (base0 + static_cast<uint32_t>(k * PL * 4));
                         off += static_cast<uint32_t>(pf) << 2;

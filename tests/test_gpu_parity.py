@@ -139,7 +139,17 @@ def test_dot_product_adjoint_gpu(pn, name):
 
 
 def test_adjoint_matches_explicit_transpose_tiny(pn):
-    """GPU A^T equals the transpose of the explicit oracle matrix A."""
+    """GPU A^T equals the transpose of the explicit oracle matrix A, and GPU A
+    the matrix itself, element by element.
+
+    Bound: the kernels form in-plane positions in FP32 in a local frame whose
+    coordinates stay below 2^6, as fma(k, slope, p0) with p0 = fma(m0,
+    slope, b): two roundings of at most 2^-19 each per coordinate.  A
+    bilinear weight inherits the position error, so a contribution q ds w_f
+    w_s is off by at most ~2 x 2 x 2^-19 ~ 8e-6 of max|q ds|, plus the
+    adjoint's fixed-point rounding (<= kunits max|q ds| / 2^31 ~ 2e-7 here).
+    Observed errors are ~1e-6; the bound below is 8e-6 of max|A|.
+    """
     _say("explicit transpose, tiny cone")
     shp = (4, 5, 4)
     gp = pn.cone_geometry(shp, (1.0, 1.0, 1.0), (5, 6), (1.1, 1.0), 3, 25.0, 40.0)
@@ -149,9 +159,9 @@ def test_adjoint_matches_explicit_transpose_tiny(pn):
     nrays = A.shape[0]
     E = gpu(np.eye(nrays).reshape((nrays,) + gp.sino_shape()))
     At = cpu(pn.adjoint(E, gp)).reshape(nrays, nvox).T
-    assert np.abs(At - A.T).max() <= 1e-6 * np.abs(A).max()
+    assert np.abs(At - A.T).max() <= 8e-6 * np.abs(A).max()
     Ag = cpu(pn.forward(gpu(np.eye(nvox).reshape((nvox,) + shp)), gp)).reshape(nvox, nrays).T
-    assert np.abs(Ag - A).max() <= 1e-6 * np.abs(A).max()
+    assert np.abs(Ag - A).max() <= 8e-6 * np.abs(A).max()
 
 
 def test_edge_cases(pn):
