@@ -447,13 +447,15 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
             const int wr = bx.s_lo + PADR_LO + rrow;  // row of the work copy
             const int wc = bx.f_al + PADC + vr * VE;  // column of the work copy (multiple of VE)
             const bool in = wr >= 0 && wr < srows && wc >= 0 && wc + VE <= row;
-            const S *src = base + static_cast<int64_t>(in ? wr : 0) * row + (in ? wc : 0);
+            // a vector outside the padded copy reads the start of row 0 of
+            // its plane, a zero padding row; planes past the chunk's last
+            // re-read the last one (not staged)
+            const S *src = base + static_cast<int64_t>(bx.mc) * plane +
+                           (in ? static_cast<int64_t>(wr) * row + wc : static_cast<int64_t>(0));
+            const int kmax = bx.me - bx.mc;
 #pragma unroll
-            for (int k = 0; k < C; ++k) {
-                pre[k] = make_uint4(0u, 0u, 0u, 0u);
-                if (in && bx.mc + k <= bx.me)
-                    pre[k] = *reinterpret_cast<const uint4 *>(src + static_cast<int64_t>(bx.mc + k) * plane);
-            }
+            for (int k = 0; k < C; ++k)
+                pre[k] = *reinterpret_cast<const uint4 *>(src + static_cast<int64_t>(min(k, kmax)) * plane);
         };
 
         int wb = 0;
