@@ -310,6 +310,9 @@ struct Plan {
     // detector window that holds every ray meeting the dilated volume in
     // some view (inclusive pixel bounds; c0 > c1: no ray meets it)
     int32_t win_c0 = 0, win_c1 = -1, win_r0 = 0, win_r1 = -1;
+    // the same per view (c0, c1, r0, r1), host and device
+    std::vector<int32_t> vwin;
+    int32_t *d_vwin = nullptr;
 
     ~Plan()
     {
@@ -322,6 +325,7 @@ struct Plan {
         dev_free(d_acc);
         dev_free(d_maxabs);
         for (int a = 0; a < 3; ++a) dev_free(d_cbox[a]);
+        dev_free(d_vwin);
     }
 };
 
@@ -370,6 +374,7 @@ void build_tables(Plan &pl)
     for (int a = 0; a < 3; ++a) pl.pass_views[a].clear();
     pl.axes_union = 0;
     double umin = HUGE_VAL, umax = -HUGE_VAL, vmin = HUGE_VAL, vmax = -HUGE_VAL;
+    pl.vwin.assign((size_t)4 * g.n_views, 0);
     for (int k = 0; k < g.n_views; ++k) {
         const double *P = &g.P[(size_t)12 * k];
         ViewTab &t = pl.tab[k];
@@ -416,16 +421,27 @@ void build_tables(Plan &pl)
         pl.axes_union |= tf.axes;
         // the dilated volume [-1, n] projects into the convex hull of its
         // corners' projections (W > 0 there): rays outside it sum to zero
+        double vu0 = HUGE_VAL, vu1 = -HUGE_VAL, vv0 = HUGE_VAL, vv1 = -HUGE_VAL;
         for (int c = 0; c < 8; ++c) {
             const double x = (c & 1) ? g.n[0] : -1.0, y = (c & 2) ? g.n[1] : -1.0, z = (c & 4) ? g.n[2] : -1.0;
             const double U = t.Pi[0] * x + t.Pi[1] * y + t.Pi[2] * z + t.Pi[3];
             const double V = t.Pi[4] * x + t.Pi[5] * y + t.Pi[6] * z + t.Pi[7];
             const double W = t.Pi[8] * x + t.Pi[9] * y + t.Pi[10] * z + t.Pi[11];
-            umin = std::min(umin, U / W);
-            umax = std::max(umax, U / W);
-            vmin = std::min(vmin, V / W);
-            vmax = std::max(vmax, V / W);
+            vu0 = std::min(vu0, U / W);
+            vu1 = std::max(vu1, U / W);
+            vv0 = std::min(vv0, V / W);
+            vv1 = std::max(vv1, V / W);
         }
+        umin = std::min(umin, vu0);
+        umax = std::max(umax, vu1);
+        vmin = std::min(vmin, vv0);
+        vmax = std::max(vmax, vv1);
+        // one pixel of margin for the rounding of the bounds
+        const bool fin = std::isfinite(vu0) && std::isfinite(vu1) && std::isfinite(vv0) && std::isfinite(vv1);
+        pl.vwin[4 * k] = fin ? (int32_t)std::max(-1.0, std::min((double)g.nu, std::floor(vu0) - 1.0)) : 0;
+        pl.vwin[4 * k + 1] = fin ? (int32_t)std::max(-1.0, std::min((double)g.nu, std::ceil(vu1) + 1.0)) : g.nu;
+        pl.vwin[4 * k + 2] = fin ? (int32_t)std::max(-1.0, std::min((double)g.nv, std::floor(vv0) - 1.0)) : 0;
+        pl.vwin[4 * k + 3] = fin ? (int32_t)std::max(-1.0, std::min((double)g.nv, std::ceil(vv1) + 1.0)) : g.nv;
         for (int a = 0; a < 3; ++a)
             if (tf.axes >> a & 1) pl.pass_views[a].push_back(k);
     }
@@ -479,6 +495,7 @@ int get_plan(const pn_geometry *pg, Plan **out)
     for (int a = 0; a < 3; ++a)
         if ((rc = upload(&pl->d_views[a], pl->pass_views[a]))) return rc;
     if ((rc = upload(&pl->d_maxabs, std::vector<uint32_t>(1, 0u)))) return rc;
+    if ((rc = upload(&pl->d_vwin, pl->vwin))) return rc;
     g_plans.push_front(std::move(pl));
     while (g_plans.size() > kMaxPlans) g_plans.pop_back();
     *out = g_plans.front().get();
@@ -692,6 +709,7 @@ int forward_prepare(const pn_geometry *pg, int64_t batch, const void *vol, void 
     p.r_lo = empty ? 0 : pl->win_r0;
     p.tiles_u = empty ? 0 : (pl->win_c1 - pl->win_c0 + p.tile_u) / p.tile_u;
     p.tiles_v = empty ? 0 : (pl->win_r1 - pl->win_r0 + p.tile_v) / p.tile_v;
+    p.vwin = pl->d_vwin;
     if (forward_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
     none = forward_blocks(p) == 0;
     (void)pg;

@@ -318,6 +318,16 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
     const int c0 = p.c_lo + (tile % p.tiles_u) * TU, r0 = p.r_lo + (tile / p.tiles_u) * TV;
     const int c = c0 + t % TU, r = r0 + t / TU;
     const bool inside = c < p.nu && r < p.nv;
+    if (p.vwin) {
+        // a tile outside the view's own window sees no voxel: zeros
+        const int *w = p.vwin + 4 * view;
+        if (c0 + TU <= w[0] || c0 > w[1] || r0 + TV <= w[2] || r0 > w[3]) {  // uniform
+            if (inside)
+                static_cast<O *>(p.sino)[((static_cast<int64_t>(b) * p.n_views + view) * p.nv + r) * p.nu + c] =
+                    from_f32<O>(0.0f);
+            return;
+        }
+    }
     const ViewTab &tab = p.tab[view];
 
     RaySeg seg;
