@@ -277,7 +277,7 @@ struct Box {
 // enclose those of every ray in between) from the padded work copy into LDS
 // with 16-byte loads, and every ray then samples the chunk's planes from
 // LDS.  The loads of chunk i+1 are issued into registers before chunk i is
-// sampled, and the boxes of up to 256 chunks are computed at once, one
+// sampled, and the boxes of up to 64 chunks are computed at once, one
 // chunk per thread.  A box larger than RCAP x FCAP falls back to gathers
 // from the work copy.
 //
@@ -299,7 +299,8 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
     constexpr int PLANE = RCAP * FCAP;
     static_assert(FCAP % VE == 0 && RPI >= RCAP, "one staged row per thread and plane");
     __shared__ float box[C * PLANE];
-    __shared__ int4 s_box[256];  // boxes of a window of chunks: f_al, s_lo, nvec | ns << 16, lds
+    constexpr int WIN = 64;      // chunks per window of boxes
+    __shared__ int4 s_box[WIN];  // boxes of a window of chunks: f_al, s_lo, nvec | ns << 16, lds
     __shared__ float s_corner[4][4];
     __shared__ int s_dir[4];
     __shared__ int s_axes, s_m0, s_m1;
@@ -426,17 +427,17 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
             }
             return bx;
         };
-        // boxes of chunks wb .. wb + 255, one per thread
+        // boxes of chunks wb .. wb + WIN - 1, one per thread
         auto window = [&](int wb) {
             const int mc = M0 + (wb + t) * C;
-            if (mc <= M1) {
+            if (t < WIN && mc <= M1) {
                 const Box bx = make_box(mc);
                 s_box[t] = make_int4(bx.f_al, bx.s_lo, bx.nvec | bx.ns << 16, bx.lds ? 1 : 0);
             }
         };
         auto box_at = [&](int ci, int wb) {
             const int mc = M0 + ci * C;
-            if (ci - wb >= 256) return make_box(mc);
+            if (ci - wb >= WIN) return make_box(mc);
             const int4 v = s_box[ci - wb];
             Box bx;
             bx.mc = mc;
@@ -487,8 +488,8 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                         *reinterpret_cast<float4 *>(dst + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
                 }
             }
-            if (ci + 1 - wb == 256) {  // uniform
-                wb += 256;
+            if (ci + 1 - wb == WIN) {  // uniform
+                wb += WIN;
                 window(wb);
             }
             __syncthreads();
@@ -575,13 +576,13 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
 }
 
 template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
-__global__ __launch_bounds__(256, 4) void forward_kernel(FwdParams p)
+__global__ __launch_bounds__(256, 5) void forward_kernel(FwdParams p)
 {
     forward_block<S, O, TU, TV, C, RCAP, FCAP>(p, blockIdx.x);
 }
 
 template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
-__global__ __launch_bounds__(256, 4) void forward_batch_kernel(Batch<FwdParams> w)
+__global__ __launch_bounds__(256, 5) void forward_batch_kernel(Batch<FwdParams> w)
 {
     const int i = batch_item(w, blockIdx.x);
     forward_block<S, O, TU, TV, C, RCAP, FCAP>(w.p[i], blockIdx.x - w.start[i]);
@@ -1381,7 +1382,7 @@ static hipError_t forward_t(const Arg &a, bool two_d, uint32_t blocks, hipStream
     if (two_d)
         fwd_go<S, O, 256, 1, 8, 3, 320>(a, blocks, st);
     else
-        fwd_go<S, O, 16, 16, 8, 25, 40>(a, blocks, st);
+        fwd_go<S, O, 16, 16, 8, 24, 40>(a, blocks, st);
     return hipGetLastError();
 }
 
