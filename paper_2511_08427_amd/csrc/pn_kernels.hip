@@ -769,7 +769,7 @@ hipError_t launch_cbox(const AdjParams &ap, int32_t L, int32_t TS, int32_t TF, u
 // besides the extra row below, 1/2 in general; 0/1 for 2-D problems, whose
 // rays have z == 0 exactly (the tap at z = 0 has weight 1 and the one at
 // z = 1 weight 0).
-template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
 __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
 {
     using AX = PassAxes<A>;
@@ -779,8 +779,8 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     constexpr int RP = TS + SLO + SHI + 1;     // LDS rows per plane
     constexpr int PL = RP * RW;                // LDS plane
     constexpr int NV = L * TS * TF;            // voxels of the block
-    constexpr int NQ = (NV + 255) / 256;       // voxels per thread
-    constexpr int MAXR = 256 * CPT;            // rays per batch
+    constexpr int NQ = (NV + NT - 1) / NT;     // voxels per thread
+    constexpr int MAXR = NT * CPT;             // rays per batch
     constexpr int SPR = (L + K - 1) / K;       // segments per ray, at most
     constexpr int MAXSEG = MAXR * SPR;
     static_assert(L <= 32 && SPR <= 4, "segment record packing");
@@ -813,7 +813,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     const int t = threadIdx.x, lane = t & 63;
     const double oa = a0, of = f0 - 2, os = s0 - SLO - 1;
 
-    // the voxels this thread owns: e = t + 256 q, x fastest (coalesced output)
+    // the voxels this thread owns: e = t + NT q, x fastest (coalesced output)
     float reg[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) reg[q] = 0.0f;
@@ -829,7 +829,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
         }
     };
 
-    for (int e = t; e < L * PL; e += 256) acc[e] = 0;
+    for (int e = t; e < L * PL; e += NT) acc[e] = 0;
     if (t < 4) s_cnt[t >> 1][t & 1] = 0u;
     __syncthreads();
 
@@ -851,7 +851,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
         asm volatile("" : "+v"(tt));
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int el = tt + 256 * q;
+            const int el = tt + NT * q;
             if (el < NV) {
                 int la, ls, lf;
                 cell_of(el, la, ls, lf);
@@ -906,7 +906,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
             float qv[CPT];
 #pragma unroll
             for (int cq = 0; cq < CPT; ++cq) {
-                const int idx = cb + t + 256 * cq;
+                const int idx = cb + t + NT * cq;
                 cc[cq] = -1;
                 cr[cq] = 0;
                 qv[cq] = 0.0f;
@@ -1015,7 +1015,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
                 __syncthreads();  // cells cleared before the scatter
             }
             pending += add;
-            for (int se = t; se < nseg_all; se += 256) {
+            for (int se = t; se < nseg_all; se += NT) {
                 const uint32_t srec = s_seg[se];
                 const int slot = srec & 0xffff, la0 = (srec >> 16) & 0xff, cnt = srec >> 24;
                 const float4 rp = s_ray[slot];
@@ -1031,15 +1031,19 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     if (k == 0 || k < cnt) {
-                        const float pf = fmaf(static_cast<float>(k), rp.x, pf0);
-                        const float ps = fmaf(static_cast<float>(k), rp.z, ps0);
+                        const float pf = k == 0 ? pf0 : fmaf(static_cast<float>(k), rp.x, pf0);
+                        const float ps = k == 0 ? ps0 : fmaf(static_cast<float>(k), rp.z, ps0);
                         const float wf = __builtin_amdgcn_fractf(pf), ws = __builtin_amdgcn_fractf(ps);
-                        // positions are >= 1 up to rounding: truncation is floor
-                        uint32_t off = __umul24(static_cast<uint32_t>(ps), static_cast<uint32_t>(RW * 4)) +
-                                       (base0 + static_cast<uint32_t>(k * PL * 4));
-                        off += static_cast<uint32_t>(pf) << 2;
-                        asm volatile("" : "+v"(off));  // one base register for all four taps
-                        int *q = reinterpret_cast<int *>(reinterpret_cast<char *>(acc) + off);
+                        // positions are >= 1 up to rounding: truncation is floor.
+                        // Byte offset of the tap cell in the segment's first
+                        // plane, in two ops; the plane and the other three taps
+                        // are immediate offsets of the LDS atomics.
+                        const uint32_t is = static_cast<uint32_t>(ps), ifl = static_cast<uint32_t>(pf);
+                        uint32_t off;
+                        asm("v_mad_u32_u24 %0, %1, %2, %3\n\tv_lshl_add_u32 %0, %4, 2, %0"
+                            : "=&v"(off)
+                            : "v"(is), "s"(static_cast<uint32_t>(RW * 4)), "v"(base0), "v"(ifl));
+                        int *q = reinterpret_cast<int *>(reinterpret_cast<char *>(acc) + off) + k * PL;
                         const float t1 = qs * ws, t0 = qs - t1;
                         const float c01f = t0 * wf, c11f = t1 * wf;
                         atomicAdd(q, round_fixed(t0 - c01f));
@@ -1061,7 +1065,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     float *out = p.out + b * item;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int el = t + 256 * q;
+        const int el = t + NT * q;
         if (el >= NV) continue;
         int la, ls, lf;
         cell_of(el, la, ls, lf);
@@ -1075,17 +1079,18 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     }
 }
 
-template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
-__global__ __launch_bounds__(256, (L * TS * TF <= 4096 ? 4 : 2)) void adjoint_kernel(AdjParams p)
+// 4 waves per SIMD: 128 VGPRs at most (16 voxels per thread)
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
+__global__ __launch_bounds__(NT, 4) void adjoint_kernel(AdjParams p)
 {
-    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT>(p, blockIdx.x);
+    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT, NT>(p, blockIdx.x);
 }
 
-template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
-__global__ __launch_bounds__(256, (L * TS * TF <= 4096 ? 4 : 2)) void adjoint_batch_kernel(Batch<AdjParams> w)
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
+__global__ __launch_bounds__(NT, 4) void adjoint_batch_kernel(Batch<AdjParams> w)
 {
     const int i = batch_item(w, blockIdx.x);
-    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT>(w.p[i], blockIdx.x - w.start[i]);
+    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT, NT>(w.p[i], blockIdx.x - w.start[i]);
 }
 
 // max |x| over a buffer, as the bit pattern of a non-negative float
@@ -1423,9 +1428,9 @@ void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv)
 }
 
 // Compiled adjoint block shapes (planes x rows x columns, candidates per
-// thread per batch); index 0 is 2-D.
-static const int32_t kAdjShapes[][4] = {{32, 1, 64, 1}, {16, 16, 16, 2}, {32, 8, 16, 1}};
-constexpr int kNumAdjShapes = 3;
+// thread per batch); index 0 is 2-D; shape 3 runs 512 threads.
+static const int32_t kAdjShapes[][4] = {{32, 1, 64, 1}, {16, 16, 16, 2}, {32, 8, 16, 1}, {16, 16, 32, 1}};
+constexpr int kNumAdjShapes = 4;
 
 int adjoint_shape_count() { return kNumAdjShapes; }
 
@@ -1441,28 +1446,28 @@ int64_t adjoint_blocks(const AdjParams &p)
     return static_cast<int64_t>(p.blocks_a) * p.blocks_s * p.blocks_f * p.batch;
 }
 
-template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
 static void adj_go(const AdjParams &p, uint32_t blocks, hipStream_t st)
 {
-    adjoint_kernel<Q, A, L, TS, TF, SLO, SHI, CPT><<<dim3(blocks), 256, 0, st>>>(p);
+    adjoint_kernel<Q, A, L, TS, TF, SLO, SHI, CPT, NT><<<dim3(blocks), NT, 0, st>>>(p);
 }
-template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT>
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
 static void adj_go(const Batch<AdjParams> &w, uint32_t blocks, hipStream_t st)
 {
-    adjoint_batch_kernel<Q, A, L, TS, TF, SLO, SHI, CPT><<<dim3(blocks), 256, 0, st>>>(w);
+    adjoint_batch_kernel<Q, A, L, TS, TF, SLO, SHI, CPT, NT><<<dim3(blocks), NT, 0, st>>>(w);
 }
 
-template <typename Q, int L, int TS, int TF, int SLO, int SHI, int CPT, typename Arg>
+template <typename Q, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT, typename Arg>
 static hipError_t adjoint_axes(const Arg &a, int axis, uint32_t blocks, hipStream_t st)
 {
     switch (axis) {
-    case 0: adj_go<Q, 0, L, TS, TF, SLO, SHI, CPT>(a, blocks, st); break;
-    case 1: adj_go<Q, 1, L, TS, TF, SLO, SHI, CPT>(a, blocks, st); break;
+    case 0: adj_go<Q, 0, L, TS, TF, SLO, SHI, CPT, NT>(a, blocks, st); break;
+    case 1: adj_go<Q, 1, L, TS, TF, SLO, SHI, CPT, NT>(a, blocks, st); break;
     default:
         if constexpr (TS == 1) {
             return hipErrorInvalidValue;  // 2-D rays never have z dominant
         } else {
-            adj_go<Q, 2, L, TS, TF, SLO, SHI, CPT>(a, blocks, st);
+            adj_go<Q, 2, L, TS, TF, SLO, SHI, CPT, NT>(a, blocks, st);
         }
         break;
     }
@@ -1473,9 +1478,10 @@ template <typename Q, typename Arg>
 static hipError_t adjoint_q(const Arg &a, int axis, int shape, uint32_t blocks, hipStream_t st)
 {
     switch (shape) {
-    case 0: return adjoint_axes<Q, 32, 1, 64, 0, 1, 1>(a, axis, blocks, st);
-    case 1: return adjoint_axes<Q, 16, 16, 16, 1, 2, 2>(a, axis, blocks, st);
-    default: return adjoint_axes<Q, 32, 8, 16, 1, 2, 1>(a, axis, blocks, st);
+    case 0: return adjoint_axes<Q, 32, 1, 64, 0, 1, 1, 256>(a, axis, blocks, st);
+    case 1: return adjoint_axes<Q, 16, 16, 16, 1, 2, 2, 256>(a, axis, blocks, st);
+    case 2: return adjoint_axes<Q, 32, 8, 16, 1, 2, 1, 256>(a, axis, blocks, st);
+    default: return adjoint_axes<Q, 16, 16, 32, 1, 2, 1, 512>(a, axis, blocks, st);
     }
 }
 
