@@ -498,7 +498,9 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                 cur = box_at(ci + 1, wb);
                 issue(cur);  // in flight while this chunk is sampled
             }
-            if (!part) continue;
+            // rays whose plane range misses the chunk sample nothing (a
+            // wave whose rays all miss it skips the sampling)
+            if (!part || seg.m1 < now.mc || seg.m0 > now.me) continue;
             if (now.lds) {
                 // box-local positions (the shifts by the integer box origin
                 // are exact): every position of the tile lies more than 1e-3
@@ -1107,15 +1109,33 @@ __global__ __launch_bounds__(256) void maxabs_kernel(const Q *__restrict__ src, 
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     uint32_t m = 0u;
     const uint4 *v = reinterpret_cast<const uint4 *>(src);
-    for (int64_t e = t0; e < nvec; e += stride) {
+    // four independent 16-byte loads in flight per thread
+    int64_t e = t0;
+    for (; e + 3 * stride < nvec; e += 4 * stride) {
+        uint4 x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = v[e + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            float f[VE];
+            unpack16<Q>(x[u], f);
+#pragma unroll
+            for (int k = 0; k < VE; ++k) m = max(m, __float_as_uint(fabsf(f[k])));
+        }
+    }
+    for (; e < nvec; e += stride) {
         float f[VE];
         unpack16<Q>(v[e], f);
 #pragma unroll
         for (int k = 0; k < VE; ++k) m = max(m, __float_as_uint(fabsf(f[k])));
     }
     for (int64_t e = nvec * VE + t0; e < n; e += stride) m = max(m, __float_as_uint(fabsf(to_f32(src[e]))));
+    // one global atomic per workgroup (same-address atomics serialise)
+    __shared__ uint32_t s_m[4];
     m = wave_max_u32(m);
-    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(out, max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3])));
 }
 
 // ------------------------------------------------ back-projection --------
@@ -1567,7 +1587,7 @@ hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *ou
 {
     fill_zero_kernel<<<1, 64, 0, st>>>(out, 1);
     int64_t blocks = (n / 8 + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
     const dim3 g(static_cast<uint32_t>(blocks));
     const int32_t vec = reinterpret_cast<uintptr_t>(src) % 16 == 0;
