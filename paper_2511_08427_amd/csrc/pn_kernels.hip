@@ -1140,22 +1140,32 @@ __global__ __launch_bounds__(256) void maxabs_kernel(const Q *__restrict__ src, 
 
 // ------------------------------------------------ back-projection --------
 
-// Voxel-driven back-projection.  A workgroup owns a BX x BY x BZ block of
+// Voxel-driven back-projection.  A workgroup owns a 16 x 16 x BZ block of
 // voxels; each thread accumulates a column of BZ voxels along z in
 // registers (one writer per voxel, no atomics).  Per view, the detector
 // rectangle that the block's voxel centres project into (the projection of
 // the block's corner box, widened by one tap) is staged into LDS, zero-
 // filled outside the detector, so every bilinear tap is an unchecked LDS
 // read; the next view's rectangle is loaded into registers while the
-// current one is used.  Rectangles larger than RCAP x CCAP fall back to
-// bounds-checked gathers from the sinogram.
-template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
+// current one is used.  The rectangles of up to 256 views are computed
+// together, one view per thread, into an LDS table.  Rectangles larger than
+// RCAP x CCAP fall back to bounds-checked gathers from the sinogram.
+//
+// Views whose projection does not depend on z (Pi_02 = Pi_22 = 0: orbits
+// about z with detector columns parallel to z, such as the circular and
+// helical trajectories) take a column path: W and u are constant along a
+// column and v is linear in k, so the reciprocal of W, the distance weight
+// and the horizontal tap address and weight are computed once per column
+// and view, leaving one position, two LDS pair reads and the interpolation
+// per voxel.
+template <typename Q, typename O, int BZ, int RCAP, int CCAP>
 __device__ __forceinline__ void backproject_block(const BpParams &p, const int bid)
 {
-    static_assert(BX * BY == 256, "one voxel column per thread");
+    constexpr int BX = 16, BY = 16, CHUNK = 256;
     constexpr int NE = RCAP * CCAP;
     constexpr int PER = (NE + 255) / 256;
     __shared__ float s_det[2][NE];
+    __shared__ int4 s_rect[CHUNK];
     const int t = threadIdx.x;
     const int nbx = (p.n[0] + BX - 1) / BX, nby = (p.n[1] + BY - 1) / BY, nbz = (p.n[2] + BZ - 1) / BZ;
     int blk = bid;
@@ -1173,56 +1183,63 @@ __device__ __forceinline__ void backproject_block(const BpParams &p, const int b
     const Q *sino = static_cast<const Q *>(p.sino) + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
     const float fnu = static_cast<float>(p.nu), fnv = static_cast<float>(p.nv);
 
-    struct Rect {
-        int u0, v0, nc, nr;
-        bool lds, any;
-    };
-    // detector rectangle of the block for one view (uniform)
+    // detector rectangle of the block for one view, computed by one thread:
+    // x = first column u0, y = first row v0, z = columns | rows << 16,
+    // w = bit 0: some tap may be non-zero, bit 1: fits the LDS buffer
     auto rect_of = [&](int view) {
         const ViewTabF &tf = p.tabf[view];
-        const int lane = t & 63, corner = lane & 7;
-        const float ci = (corner & 1) ? static_cast<float>(i1) : static_cast<float>(i0);
-        const float cj = (corner & 2) ? static_cast<float>(j1) : static_cast<float>(j0);
-        const float ck = (corner & 4) ? static_cast<float>(k1) : static_cast<float>(k0);
-        const float U = fmaf(tf.Pi[0], ci, fmaf(tf.Pi[1], cj, fmaf(tf.Pi[2], ck, tf.Pi[3])));
-        const float V = fmaf(tf.Pi[4], ci, fmaf(tf.Pi[5], cj, fmaf(tf.Pi[6], ck, tf.Pi[7])));
-        const float Wc = fmaf(tf.Pi[8], ci, fmaf(tf.Pi[9], cj, fmaf(tf.Pi[10], ck, tf.Pi[11])));
-        float umin = U / Wc, vmin = V / Wc;
-        float umax = umin, vmax = vmin;
+        float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
 #pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-            umin = fminf(umin, __shfl_xor(umin, o));
-            umax = fmaxf(umax, __shfl_xor(umax, o));
-            vmin = fminf(vmin, __shfl_xor(vmin, o));
-            vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+        for (int c = 0; c < 8; ++c) {
+            const float ci = static_cast<float>((c & 1) ? i1 : i0);
+            const float cj = static_cast<float>((c & 2) ? j1 : j0);
+            const float ck = static_cast<float>((c & 4) ? k1 : k0);
+            const float U = fmaf(tf.Pi[0], ci, fmaf(tf.Pi[1], cj, fmaf(tf.Pi[2], ck, tf.Pi[3])));
+            const float V = fmaf(tf.Pi[4], ci, fmaf(tf.Pi[5], cj, fmaf(tf.Pi[6], ck, tf.Pi[7])));
+            const float Wc = fmaf(tf.Pi[8], ci, fmaf(tf.Pi[9], cj, fmaf(tf.Pi[10], ck, tf.Pi[11])));
+            const float u = U / Wc, v = V / Wc;
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
+            vmin = fminf(vmin, v);
+            vmax = fmaxf(vmax, v);
         }
         // voxel positions are clamped to [-1, n] (zero padding), so the
         // rectangle is clamped likewise; 0.01 px covers FP32 rounding
-        umin = fminf(fmaxf(__shfl(umin, 0) - 0.01f, -1.0f), fnu);
-        umax = fminf(fmaxf(__shfl(umax, 0) + 0.01f, -1.0f), fnu);
-        vmin = fminf(fmaxf(__shfl(vmin, 0) - 0.01f, -1.0f), fnv);
-        vmax = fminf(fmaxf(__shfl(vmax, 0) + 0.01f, -1.0f), fnv);
-        Rect rc;
-        rc.u0 = static_cast<int>(floorf(umin));
-        rc.v0 = static_cast<int>(floorf(vmin));
-        rc.nc = static_cast<int>(floorf(umax)) + 2 - rc.u0;
-        rc.nr = static_cast<int>(floorf(vmax)) + 2 - rc.v0;
+        umin = fminf(fmaxf(umin - 0.01f, -1.0f), fnu);
+        umax = fminf(fmaxf(umax + 0.01f, -1.0f), fnu);
+        vmin = fminf(fmaxf(vmin - 0.01f, -1.0f), fnv);
+        vmax = fminf(fmaxf(vmax + 0.01f, -1.0f), fnv);
+        const int u0 = static_cast<int>(floorf(umin)), v0 = static_cast<int>(floorf(vmin));
+        const int nc = static_cast<int>(floorf(umax)) + 2 - u0, nr = static_cast<int>(floorf(vmax)) + 2 - v0;
         // entirely outside the detector: every tap is zero
-        rc.any = !(umax <= -1.0f || umin >= fnu || vmax <= -1.0f || vmin >= fnv);
-        rc.lds = rc.nc <= CCAP && rc.nr <= RCAP;
-        return rc;
+        const bool any = !(umax <= -1.0f || umin >= fnu || vmax <= -1.0f || vmin >= fnv);
+        const bool lds = nc <= CCAP && nr <= RCAP;
+        return make_int4(u0, v0, nc | nr << 16, static_cast<int>(any) | static_cast<int>(lds) << 1);
     };
+    auto rect_at = [&](int e) {
+        const int4 r = s_rect[e];
+        return make_int4(__builtin_amdgcn_readfirstlane(r.x), __builtin_amdgcn_readfirstlane(r.y),
+                         __builtin_amdgcn_readfirstlane(r.z), __builtin_amdgcn_readfirstlane(r.w));
+    };
+    // the thread's elements of the LDS rectangle (row, column), fixed
+    int rr[PER], cc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = t + 256 * q;
+        rr[q] = e < NE ? e / CCAP : RCAP;
+        cc[q] = e % CCAP;
+    }
     float pre[PER];
-    auto issue = [&](int view, const Rect &rc) {
-        if (!rc.lds || !rc.any) return;
+    auto issue = [&](int view, const int4 &rc) {
+        if ((rc.w & 3) != 3) return;
         const Q *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
+        const int nc = rc.z & 0xffff, nr = rc.z >> 16;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = t + 256 * q;
-            const int rr = e / CCAP, cc = e % CCAP;
-            const int r = rc.v0 + rr, c = rc.u0 + cc;
+            const int r = rc.y + rr[q], c = rc.x + cc[q];
             float v = 0.0f;
-            if (rr < rc.nr && cc < rc.nc && r >= 0 && r < p.nv && c >= 0 && c < p.nu)
+            if (rr[q] < nr && cc[q] < nc && static_cast<uint32_t>(r) < static_cast<uint32_t>(p.nv) &&
+                static_cast<uint32_t>(c) < static_cast<uint32_t>(p.nu))
                 v = to_f32(img[static_cast<int64_t>(r) * p.nu + c]);
             pre[q] = v;
         }
@@ -1231,78 +1248,116 @@ __device__ __forceinline__ void backproject_block(const BpParams &p, const int b
     float acc[BZ];
 #pragma unroll
     for (int z = 0; z < BZ; ++z) acc[z] = 0.0f;
-    Rect cur = p.n_views > 0 ? rect_of(0) : Rect{0, 0, 0, 0, false, false};
-    if (p.n_views > 0) issue(0, cur);
-    for (int view = 0; view < p.n_views; ++view) {
-        const int buf = view & 1;
-        if (cur.lds && cur.any) {
+    for (int c0 = 0; c0 < p.n_views; c0 += CHUNK) {
+        const int cn = min(CHUNK, p.n_views - c0);
+        // the previous chunk's table and rectangles are no longer read
+        // (barrier at the end of its last view)
+        if (t < cn) s_rect[t] = rect_of(c0 + t);
+        __syncthreads();
+        int4 cur = rect_at(0);
+        issue(c0, cur);
+        for (int vi = 0; vi < cn; ++vi) {
+            const int view = c0 + vi, buf = vi & 1;
+            if ((cur.w & 3) == 3) {
 #pragma unroll
-            for (int q = 0; q < PER; ++q)
-                if (t + 256 * q < NE) s_det[buf][t + 256 * q] = pre[q];
-        }
-        __syncthreads();  // staged rectangle visible; the other buffer is free
-        const Rect now = cur;
-        if (view + 1 < p.n_views) {
-            cur = rect_of(view + 1);
-            issue(view + 1, cur);
-        }
-        if (own && now.any) {
-            const ViewTabF &tf = p.tabf[view];
-            const float U0 = fmaf(tf.Pi[0], fi, fmaf(tf.Pi[1], fj, fmaf(tf.Pi[2], fk0, tf.Pi[3])));
-            const float V0 = fmaf(tf.Pi[4], fi, fmaf(tf.Pi[5], fj, fmaf(tf.Pi[6], fk0, tf.Pi[7])));
-            const float Wb = fmaf(tf.Pi[8], fi, fmaf(tf.Pi[9], fj, fmaf(tf.Pi[10], fk0, tf.Pi[11])));
-            if (now.lds) {
-                const float uo = static_cast<float>(now.u0), vo = static_cast<float>(now.v0);
-                const float hu = fminf(fnu - uo, static_cast<float>(now.nc - 1) - 1e-3f);
-                const float hv = fminf(fnv - vo, static_cast<float>(now.nr - 1) - 1e-3f);
-                const float lu = fmaxf(-1.0f - uo, 0.0f), lv = fmaxf(-1.0f - vo, 0.0f);
-                const float *det = s_det[buf];
+                for (int q = 0; q < PER; ++q)
+                    if (t + 256 * q < NE) s_det[buf][t + 256 * q] = pre[q];
+            }
+            __syncthreads();  // staged rectangle visible; the other buffer is free
+            const int4 now = cur;
+            if (vi + 1 < cn) {
+                cur = rect_at(vi + 1);
+                issue(view + 1, cur);
+            }
+            if (own && (now.w & 1)) {
+                const ViewTabF &tf = p.tabf[view];
+                if (now.w & 2) {
+                    const float uo = static_cast<float>(now.x), vo = static_cast<float>(now.y);
+                    const int nc = now.z & 0xffff, nr = now.z >> 16;
+                    const float hu = fminf(fnu - uo, static_cast<float>(nc - 1) - 1e-3f);
+                    const float hv = fminf(fnv - vo, static_cast<float>(nr - 1) - 1e-3f);
+                    const float lu = fmaxf(-1.0f - uo, 0.0f), lv = fmaxf(-1.0f - vo, 0.0f);
+                    const float *det = s_det[buf];
+                    if (BZ > 1 && tf.Pi[2] == 0.0f && tf.Pi[10] == 0.0f) {
+                        // column path: u and W fixed, v linear in k
+                        const float U0 = fmaf(tf.Pi[0], fi, fmaf(tf.Pi[1], fj, tf.Pi[3]));
+                        const float V0 = fmaf(tf.Pi[4], fi, fmaf(tf.Pi[5], fj, fmaf(tf.Pi[6], fk0, tf.Pi[7])));
+                        const float Wb = fmaf(tf.Pi[8], fi, fmaf(tf.Pi[9], fj, tf.Pi[11]));
+                        const float rw = __builtin_amdgcn_rcpf(Wb);
+                        const float u = __builtin_amdgcn_fmed3f(fmaf(U0, rw, -uo), lu, hu);
+                        const float wu = __builtin_amdgcn_fractf(u);
+                        const float *col = det + static_cast<int>(u);
+                        const float dv = tf.Pi[6] * rw, v0 = fmaf(V0, rw, -vo);
+                        const float w = tf.W0 * rw, w2 = w * w;
 #pragma unroll
-                for (int z = 0; z < BZ; ++z) {
-                    const float fz = static_cast<float>(z);
-                    const float rw = __builtin_amdgcn_rcpf(fmaf(fz, tf.Pi[10], Wb));
-                    const float u = __builtin_amdgcn_fmed3f(fmaf(fmaf(fz, tf.Pi[2], U0), rw, -uo), lu, hu);
-                    const float v = __builtin_amdgcn_fmed3f(fmaf(fmaf(fz, tf.Pi[6], V0), rw, -vo), lv, hv);
-                    const float wu = __builtin_amdgcn_fractf(u), wv = __builtin_amdgcn_fractf(v);
-                    const float *q = det + __mul24(static_cast<int>(v), CCAP) + static_cast<int>(u);
-                    const float d00 = q[0], d01 = q[1], d10 = q[CCAP], d11 = q[CCAP + 1];
-                    const float lo = fmaf(wu, d01 - d00, d00);
-                    const float hi = fmaf(wu, d11 - d10, d10);
-                    const float w = tf.W0 * rw;
-                    acc[z] = fmaf(w * w, fmaf(wv, hi - lo, lo), acc[z]);
-                }
-            } else {
-                const Q *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
+                        for (int z = 0; z < BZ; ++z) {
+                            const float v = __builtin_amdgcn_fmed3f(fmaf(static_cast<float>(z), dv, v0), lv, hv);
+                            const float wv = __builtin_amdgcn_fractf(v);
+                            const float *q = col + __mul24(static_cast<int>(v), CCAP);
+                            const float d00 = q[0], d01 = q[1], d10 = q[CCAP], d11 = q[CCAP + 1];
+                            const float lo = fmaf(wu, d01 - d00, d00);
+                            const float hi = fmaf(wu, d11 - d10, d10);
+                            acc[z] = fmaf(w2, fmaf(wv, hi - lo, lo), acc[z]);
+                        }
+                    } else {
+                        const float U0 = fmaf(tf.Pi[0], fi, fmaf(tf.Pi[1], fj, fmaf(tf.Pi[2], fk0, tf.Pi[3])));
+                        const float V0 = fmaf(tf.Pi[4], fi, fmaf(tf.Pi[5], fj, fmaf(tf.Pi[6], fk0, tf.Pi[7])));
+                        const float Wb = fmaf(tf.Pi[8], fi, fmaf(tf.Pi[9], fj, fmaf(tf.Pi[10], fk0, tf.Pi[11])));
 #pragma unroll
-                for (int z = 0; z < BZ; ++z) {
-                    const float fz = static_cast<float>(z);
-                    const float Wc = fmaf(fz, tf.Pi[10], Wb);
-                    const float rw = 1.0f / Wc;
-                    const float u = fminf(fmaxf(fmaf(fz, tf.Pi[2], U0) * rw, -1.0f), fnu);
-                    const float v = fminf(fmaxf(fmaf(fz, tf.Pi[6], V0) * rw, -1.0f), fnv);
-                    const float fu = floorf(u), fv = floorf(v);
-                    const float wu = u - fu, wv = v - fv;
-                    const int iu = static_cast<int>(fu), iv = static_cast<int>(fv);
-                    float d00 = 0.f, d01 = 0.f, d10 = 0.f, d11 = 0.f;
-                    const bool c0 = iu >= 0 && iu < p.nu, c1 = iu + 1 < p.nu;
-                    if (iv >= 0 && iv < p.nv) {
-                        const Q *row = img + static_cast<int64_t>(iv) * p.nu;
-                        if (c0) d00 = to_f32(row[iu]);
-                        if (c1) d01 = to_f32(row[iu + 1]);
+                        for (int z = 0; z < BZ; ++z) {
+                            const float fz = static_cast<float>(z);
+                            const float rw = __builtin_amdgcn_rcpf(fmaf(fz, tf.Pi[10], Wb));
+                            const float u = __builtin_amdgcn_fmed3f(fmaf(fmaf(fz, tf.Pi[2], U0), rw, -uo), lu, hu);
+                            const float v = __builtin_amdgcn_fmed3f(fmaf(fmaf(fz, tf.Pi[6], V0), rw, -vo), lv, hv);
+                            const float wu = __builtin_amdgcn_fractf(u), wv = __builtin_amdgcn_fractf(v);
+                            const float *q = det + __mul24(static_cast<int>(v), CCAP) + static_cast<int>(u);
+                            const float d00 = q[0], d01 = q[1], d10 = q[CCAP], d11 = q[CCAP + 1];
+                            const float lo = fmaf(wu, d01 - d00, d00);
+                            const float hi = fmaf(wu, d11 - d10, d10);
+                            const float w = tf.W0 * rw;
+                            acc[z] = fmaf(w * w, fmaf(wv, hi - lo, lo), acc[z]);
+                        }
                     }
-                    if (iv + 1 < p.nv) {
-                        const Q *row = img + static_cast<int64_t>(iv + 1) * p.nu;
-                        if (c0) d10 = to_f32(row[iu]);
-                        if (c1) d11 = to_f32(row[iu + 1]);
+                } else {
+                    const float U0 = fmaf(tf.Pi[0], fi, fmaf(tf.Pi[1], fj, fmaf(tf.Pi[2], fk0, tf.Pi[3])));
+                    const float V0 = fmaf(tf.Pi[4], fi, fmaf(tf.Pi[5], fj, fmaf(tf.Pi[6], fk0, tf.Pi[7])));
+                    const float Wb = fmaf(tf.Pi[8], fi, fmaf(tf.Pi[9], fj, fmaf(tf.Pi[10], fk0, tf.Pi[11])));
+                    const Q *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
+                    // a rolled loop: one voxel's gathers in flight keeps the
+                    // register count of the LDS paths
+#pragma unroll 1
+                    for (int z = 0; z < BZ; ++z) {
+                        const float fz = static_cast<float>(z);
+                        const float Wc = fmaf(fz, tf.Pi[10], Wb);
+                        const float rw = 1.0f / Wc;
+                        const float u = fminf(fmaxf(fmaf(fz, tf.Pi[2], U0) * rw, -1.0f), fnu);
+                        const float v = fminf(fmaxf(fmaf(fz, tf.Pi[6], V0) * rw, -1.0f), fnv);
+                        const float fu = floorf(u), fv = floorf(v);
+                        const float wu = u - fu, wv = v - fv;
+                        const int iu = static_cast<int>(fu), iv = static_cast<int>(fv);
+                        float d00 = 0.f, d01 = 0.f, d10 = 0.f, d11 = 0.f;
+                        const bool c0 = iu >= 0 && iu < p.nu, c1 = iu + 1 < p.nu;
+                        if (iv >= 0 && iv < p.nv) {
+                            const Q *row = img + static_cast<int64_t>(iv) * p.nu;
+                            if (c0) d00 = to_f32(row[iu]);
+                            if (c1) d01 = to_f32(row[iu + 1]);
+                        }
+                        if (iv + 1 < p.nv) {
+                            const Q *row = img + static_cast<int64_t>(iv + 1) * p.nu;
+                            if (c0) d10 = to_f32(row[iu]);
+                            if (c1) d11 = to_f32(row[iu + 1]);
+                        }
+                        const float lo = fmaf(wu, d01 - d00, d00);
+                        const float hi = fmaf(wu, d11 - d10, d10);
+                        const float w = tf.W0 * rw;
+                        const float val = w * w * fmaf(wv, hi - lo, lo);
+#pragma unroll
+                        for (int zz = 0; zz < BZ; ++zz) acc[zz] += zz == z ? val : 0.0f;
                     }
-                    const float lo = fmaf(wu, d01 - d00, d00);
-                    const float hi = fmaf(wu, d11 - d10, d10);
-                    const float w = tf.W0 * rw;
-                    acc[z] = fmaf(w * w, fmaf(wv, hi - lo, lo), acc[z]);
                 }
             }
+            __syncthreads();  // every voxel is done with this view's rectangle
         }
-        __syncthreads();  // every voxel is done with this view's rectangle
     }
     if (!own) return;
     const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
@@ -1314,17 +1369,18 @@ __device__ __forceinline__ void backproject_block(const BpParams &p, const int b
     }
 }
 
-template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
-__global__ __launch_bounds__(256) void backproject_kernel(BpParams p)
+// 8 waves per SIMD: 64 VGPRs at most
+template <typename Q, typename O, int BZ, int RCAP, int CCAP>
+__global__ __launch_bounds__(256, 8) void backproject_kernel(BpParams p)
 {
-    backproject_block<Q, O, BX, BY, BZ, RCAP, CCAP>(p, blockIdx.x);
+    backproject_block<Q, O, BZ, RCAP, CCAP>(p, blockIdx.x);
 }
 
-template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
-__global__ __launch_bounds__(256) void backproject_batch_kernel(Batch<BpParams> w)
+template <typename Q, typename O, int BZ, int RCAP, int CCAP>
+__global__ __launch_bounds__(256, 8) void backproject_batch_kernel(Batch<BpParams> w)
 {
     const int i = batch_item(w, blockIdx.x);
-    backproject_block<Q, O, BX, BY, BZ, RCAP, CCAP>(w.p[i], blockIdx.x - w.start[i]);
+    backproject_block<Q, O, BZ, RCAP, CCAP>(w.p[i], blockIdx.x - w.start[i]);
 }
 
 // ------------------------------------------------------- utilities -------
@@ -1525,30 +1581,35 @@ hipError_t launch_adjoint_batch(const Batch<AdjParams> &w, int axis, int32_t in_
     return adjoint_any(w, axis, in_dt, shape, w.start[w.n], st);
 }
 
+// 3-D back-projection: voxel columns of kBpDepth along z, detector
+// rectangles of up to kBpRows x kBpCols pixels in LDS
+constexpr int kBpDepth = 16, kBpRows = 20, kBpCols = 24;
+
 int64_t backproject_blocks(const BpParams &p)
 {
     if (p.n[2] == 1) return static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * p.batch;
-    return static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * ((p.n[2] + 7) / 8) * p.batch;
+    return static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * ((p.n[2] + kBpDepth - 1) / kBpDepth) *
+           p.batch;
 }
 
-template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
+template <typename Q, typename O, int BZ, int RCAP, int CCAP>
 static void bp_go(const BpParams &p, uint32_t blocks, hipStream_t st)
 {
-    backproject_kernel<Q, O, BX, BY, BZ, RCAP, CCAP><<<dim3(blocks), 256, 0, st>>>(p);
+    backproject_kernel<Q, O, BZ, RCAP, CCAP><<<dim3(blocks), 256, 0, st>>>(p);
 }
-template <typename Q, typename O, int BX, int BY, int BZ, int RCAP, int CCAP>
+template <typename Q, typename O, int BZ, int RCAP, int CCAP>
 static void bp_go(const Batch<BpParams> &w, uint32_t blocks, hipStream_t st)
 {
-    backproject_batch_kernel<Q, O, BX, BY, BZ, RCAP, CCAP><<<dim3(blocks), 256, 0, st>>>(w);
+    backproject_batch_kernel<Q, O, BZ, RCAP, CCAP><<<dim3(blocks), 256, 0, st>>>(w);
 }
 
 template <typename Q, typename O, typename Arg>
 static hipError_t bp_t(const Arg &a, bool two_d, uint32_t blocks, hipStream_t st)
 {
     if (two_d)
-        bp_go<Q, O, 16, 16, 1, 4, 64>(a, blocks, st);
+        bp_go<Q, O, 1, 4, 64>(a, blocks, st);
     else
-        bp_go<Q, O, 16, 16, 8, 16, 32>(a, blocks, st);
+        bp_go<Q, O, kBpDepth, kBpRows, kBpCols>(a, blocks, st);
     return hipGetLastError();
 }
 
