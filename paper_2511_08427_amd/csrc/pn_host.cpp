@@ -26,7 +26,8 @@ hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hip
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
 hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st);
-hipError_t launch_cbox(const AdjParams &ap, int32_t L, int32_t TS, int32_t TF, uint32_t *out, hipStream_t st);
+hipError_t launch_cbox(const AdjParams &ap, const uint32_t *axbox, int32_t L, int32_t TS, int32_t TF, uint32_t *out,
+                       hipStream_t st);
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 int adjoint_shape_count();
@@ -250,8 +251,14 @@ void clip_poly(std::vector<double> &poly, double a, double b, double c)
 }
 
 // Which dominant axes can occur among the view's rays (conservative: near
-// ties count for both axes).  delta(u, v) = A (u, v, 1) is linear in (u, v).
-int32_t axis_mask(const double A[9], int32_t nu, int32_t nv)
+// ties count for both axes).  delta(u, v) = A (u, v, 1) is linear in (u, v),
+// so the pixels (centres in [0, nu-1] x [0, nv-1]) where axis a dominates
+// with sign sg form the detector rectangle clipped by four half-planes
+// sg delta_a +- delta_b >= 0.  box[a] receives the bounding box of those
+// pixels, widened by one pixel and clamped to the detector, as two words
+// (first column | first row << 16, last column | last row << 16); the
+// adjoint takes its candidate rays of pass a from inside it.
+int32_t axis_mask(const double A[9], int32_t nu, int32_t nv, uint32_t box[3][2])
 {
     const double U = nu - 1, V = nv - 1;
     double dmax = 0;
@@ -261,7 +268,8 @@ int32_t axis_mask(const double A[9], int32_t nu, int32_t nv)
                 dmax = std::max(dmax, std::fabs(A[3 * i] * cu * U + A[3 * i + 1] * cv * V + A[3 * i + 2]));
     const double tau = 1e-9 * dmax;
     int32_t mask = 0;
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
+        double u0 = HUGE_VAL, u1 = -HUGE_VAL, v0 = HUGE_VAL, v1 = -HUGE_VAL;
         for (int sg = -1; sg <= 1; sg += 2) {
             std::vector<double> poly = {0, 0, U, 0, U, V, 0, V};
             for (int b = 0; b < 3 && !poly.empty(); ++b) {
@@ -273,7 +281,25 @@ int32_t axis_mask(const double A[9], int32_t nu, int32_t nv)
                 }
             }
             if (!poly.empty()) mask |= 1 << a;
+            for (size_t i = 0; i + 1 < poly.size(); i += 2) {
+                u0 = std::min(u0, poly[i]);
+                u1 = std::max(u1, poly[i]);
+                v0 = std::min(v0, poly[i + 1]);
+                v1 = std::max(v1, poly[i + 1]);
+            }
         }
+        if (mask & (1 << a)) {
+            const uint32_t c0 = (uint32_t)std::min(std::max(std::floor(u0) - 1.0, 0.0), U);
+            const uint32_t c1 = (uint32_t)std::min(std::max(std::ceil(u1) + 1.0, 0.0), U);
+            const uint32_t r0 = (uint32_t)std::min(std::max(std::floor(v0) - 1.0, 0.0), V);
+            const uint32_t r1 = (uint32_t)std::min(std::max(std::ceil(v1) + 1.0, 0.0), V);
+            box[a][0] = c0 | r0 << 16;
+            box[a][1] = c1 | r1 << 16;
+        } else {
+            box[a][0] = 1u;  // empty: first column after the last
+            box[a][1] = 0u;
+        }
+    }
     return mask;
 }
 
@@ -313,6 +339,10 @@ struct Plan {
     // the same per view (c0, c1, r0, r1), host and device
     std::vector<int32_t> vwin;
     int32_t *d_vwin = nullptr;
+    // per view and axis: detector box of the pixels whose ray may have that
+    // dominant axis (axis_mask)
+    std::vector<uint32_t> axbox;
+    uint32_t *d_axbox = nullptr;
 
     ~Plan()
     {
@@ -326,6 +356,7 @@ struct Plan {
         dev_free(d_maxabs);
         for (int a = 0; a < 3; ++a) dev_free(d_cbox[a]);
         dev_free(d_vwin);
+        dev_free(d_axbox);
     }
 };
 
@@ -375,6 +406,7 @@ void build_tables(Plan &pl)
     pl.axes_union = 0;
     double umin = HUGE_VAL, umax = -HUGE_VAL, vmin = HUGE_VAL, vmax = -HUGE_VAL;
     pl.vwin.assign((size_t)4 * g.n_views, 0);
+    pl.axbox.assign((size_t)6 * g.n_views, 0u);
     for (int k = 0; k < g.n_views; ++k) {
         const double *P = &g.P[(size_t)12 * k];
         ViewTab &t = pl.tab[k];
@@ -414,7 +446,7 @@ void build_tables(Plan &pl)
         ViewTabF &tf = pl.tabf[k];
         for (int e = 0; e < 12; ++e) tf.Pi[e] = (float)t.Pi[e];
         tf.W0 = (float)P[11];
-        tf.axes = axis_mask(t.A, g.nu, g.nv);
+        tf.axes = axis_mask(t.A, g.nu, g.nv, reinterpret_cast<uint32_t(*)[2]>(&pl.axbox[(size_t)6 * k]));
         tf.kcell = (float)cell_ray_bound(t.Pi, g);
         tf.pad = 0;
         pl.kmax = std::max(pl.kmax, tf.kcell);
@@ -496,6 +528,7 @@ int get_plan(const pn_geometry *pg, Plan **out)
         if ((rc = upload(&pl->d_views[a], pl->pass_views[a]))) return rc;
     if ((rc = upload(&pl->d_maxabs, std::vector<uint32_t>(1, 0u)))) return rc;
     if ((rc = upload(&pl->d_vwin, pl->vwin))) return rc;
+    if ((rc = upload(&pl->d_axbox, pl->axbox))) return rc;
     g_plans.push_front(std::move(pl));
     while (g_plans.size() > kMaxPlans) g_plans.pop_back();
     *out = g_plans.front().get();
@@ -815,7 +848,7 @@ int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, i
                 pl->d_cbox[a] = nullptr;
                 return fail(PN_ENOMEM, "candidate box hipMalloc(%zu): %s", need, hipGetErrorString(e));
             }
-            if ((e = launch_cbox(p, L, TS, TF, pl->d_cbox[a], st)) != hipSuccess) return fail_hip(e, "cbox launch");
+            if ((e = launch_cbox(p, pl->d_axbox, L, TS, TF, pl->d_cbox[a], st)) != hipSuccess) return fail_hip(e, "cbox launch");
             pl->cbox_shape[a] = shape;
         }
         p.cbox = pl->d_cbox[a];

@@ -650,16 +650,20 @@ __device__ __forceinline__ void clip_local(float b, float g, float lo_pos, float
 }
 
 // Candidate pixel boxes of the adjoint: for every block of a pass and
-// every view of the pass, the detector bounding box of the block dilated by
-// one voxel in-plane, i.e. of the projections of its 8 corners (FP32 from
-// the rounded index-space matrix; the 0.01 pixel margin covers the
-// rounding), clamped to the detector.  The projection of a convex box in
-// front of the source is the convex hull of its corners' projections, so
-// every ray that can sample the block has its pixel in the box.  Stored as
-// 2 words: first column | first row << 16, columns | rows << 16 (0: empty).
+// every view of the pass, the pixels (integer centres) inside the detector
+// bounding box of the block dilated by one voxel in-plane, i.e. of the
+// projections of its 8 corners (FP32 from the rounded index-space matrix;
+// the 0.01 pixel margin covers the rounding), intersected with the view's
+// box of pixels whose ray may have the pass axis as dominant axis (host,
+// exact, widened by one pixel) and clamped to the detector.  The projection
+// of a convex box in front of the source is the convex hull of its corners'
+// projections, so every ray of the pass that can sample the block has its
+// pixel in the box.  Stored as 2 words: first column | first row << 16,
+// columns | rows << 16 (0: empty).
 struct CboxParams {
     const ViewTabF *tabf;
     const int32_t *views;
+    const uint32_t *axbox;  // per view and axis: first col | row << 16, last col | row << 16
     int32_t n_pass_views, axis, nu, nv;
     int32_t n[3];
     int32_t L, TS, TF;
@@ -682,7 +686,8 @@ __global__ __launch_bounds__(256) void cbox_kernel(CboxParams p)
     const int a0 = ba_ * p.L, a1 = min(a0 + p.L, p.n[a]);
     const int s0 = bs_ * p.TS, s1 = min(s0 + p.TS, p.n[sl]);
     const int f0 = bf_ * p.TF, f1 = min(f0 + p.TF, p.n[f]);
-    const ViewTabF &tf = p.tabf[p.views[pv]];
+    const int view = p.views[pv];
+    const ViewTabF &tf = p.tabf[view];
     float umin = 3e38f, umax = -3e38f, vmin = 3e38f, vmax = -3e38f;
     for (int corner = 0; corner < 8; ++corner) {
         float ijk[3];
@@ -700,10 +705,14 @@ __global__ __launch_bounds__(256) void cbox_kernel(CboxParams p)
     }
     // clamp before converting: the bounds are finite (W > 0 over the
     // dilated volume) but may lie far outside the detector
-    const int cu0 = static_cast<int>(fminf(fmaxf(floorf(umin - 0.01f), 0.0f), static_cast<float>(p.nu)));
-    const int cu1 = static_cast<int>(fmaxf(fminf(ceilf(umax + 0.01f), static_cast<float>(p.nu - 1)), -1.0f));
-    const int cv0 = static_cast<int>(fminf(fmaxf(floorf(vmin - 0.01f), 0.0f), static_cast<float>(p.nv)));
-    const int cv1 = static_cast<int>(fmaxf(fminf(ceilf(vmax + 0.01f), static_cast<float>(p.nv - 1)), -1.0f));
+    const uint32_t ab0 = p.axbox[2 * (3 * static_cast<int64_t>(view) + a)];
+    const uint32_t ab1 = p.axbox[2 * (3 * static_cast<int64_t>(view) + a) + 1];
+    const float au0 = static_cast<float>(ab0 & 0xffffu), av0 = static_cast<float>(ab0 >> 16);
+    const float au1 = static_cast<float>(ab1 & 0xffffu), av1 = static_cast<float>(ab1 >> 16);
+    const int cu0 = static_cast<int>(fminf(fmaxf(ceilf(umin - 0.01f), au0), static_cast<float>(p.nu)));
+    const int cu1 = static_cast<int>(fmaxf(fminf(floorf(umax + 0.01f), au1), -1.0f));
+    const int cv0 = static_cast<int>(fminf(fmaxf(ceilf(vmin - 0.01f), av0), static_cast<float>(p.nv)));
+    const int cv1 = static_cast<int>(fmaxf(fminf(floorf(vmax + 0.01f), av1), -1.0f));
     const bool empty = cu0 > cu1 || cv0 > cv1;
     const uint32_t w0 = empty ? 0u : static_cast<uint32_t>(cu0) | static_cast<uint32_t>(cv0) << 16;
     const uint32_t w1 = empty ? 0u : static_cast<uint32_t>(cu1 - cu0 + 1) | static_cast<uint32_t>(cv1 - cv0 + 1) << 16;
@@ -711,11 +720,13 @@ __global__ __launch_bounds__(256) void cbox_kernel(CboxParams p)
     p.out[2 * e + 1] = w1;
 }
 
-hipError_t launch_cbox(const AdjParams &ap, int32_t L, int32_t TS, int32_t TF, uint32_t *out, hipStream_t st)
+hipError_t launch_cbox(const AdjParams &ap, const uint32_t *axbox, int32_t L, int32_t TS, int32_t TF, uint32_t *out,
+                       hipStream_t st)
 {
     CboxParams p{};
     p.tabf = ap.tabf;
     p.views = ap.views;
+    p.axbox = axbox;
     p.n_pass_views = ap.n_pass_views;
     p.axis = ap.axis;
     p.nu = ap.nu;
