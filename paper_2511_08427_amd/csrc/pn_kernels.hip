@@ -824,6 +824,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     const float shi = TS == 1 ? 1.5f : static_cast<float>(s1 - s0 + 2);
     const float amaxl = static_cast<float>(a1 - a0 - 1);
     const int t = threadIdx.x, lane = t & 63;
+    const int wbase = __builtin_amdgcn_readfirstlane(t & ~63);  // first thread of the wave
     const double oa = a0, of = f0 - 2, os = s0 - SLO - 1;
 
     // the voxels this thread owns: e = t + NT q, x fastest (coalesced output)
@@ -944,6 +945,9 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
             }
 #pragma unroll
             for (int cq = 0; cq < CPT; ++cq) {
+                // a wave whose candidates all lie past the end of the box
+                // skips the set-up and the append (wave-uniform)
+                if (cb + wbase + NT * cq >= ncand) continue;
                 bool ok = false;
                 float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 float dsm = 0.0f;
