@@ -75,6 +75,7 @@ struct AdjParams {
     float *out;            // FP32 [batch][nz][ny][nx]
     int32_t accumulate;    // 0: overwrite, 1: add to existing values
     int32_t blocks_a, blocks_s, blocks_f;
+    int32_t point_source;  // 1: every ray of a view leaves one point (B has zero u and v columns)
 };
 
 struct BpParams {

@@ -818,6 +818,7 @@ int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, i
         // worth at least); the rounding error of a contribution is
         // <= kunits max|q ds| / 2^30
         p.kunits = std::max(256.0f, pl->kmax);
+        p.point_source = g.parallel ? 0 : 1;
         p.views = pl->d_views[a];
         p.n_pass_views = (int32_t)pl->pass_views[a].size();
         p.axis = a;

@@ -609,11 +609,18 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
+// Maximum over the wave: DPP exchanges within each row of 16 lanes (lane
+// xor 1, xor 2, then the half-row and row mirrors leave the row maximum in
+// every lane of the row), then the four row maxima in scalar registers.
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), o)));
-    return __builtin_amdgcn_readfirstlane(v);
+    v = max(v, static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0xb1, 0xf, 0xf, false)));
+    v = max(v, static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0x4e, 0xf, 0xf, false)));
+    v = max(v, static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0x141, 0xf, 0xf, false)));
+    v = max(v, static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0x140, 0xf, 0xf, false)));
+    const uint32_t r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const uint32_t r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return max(max(r0, r1), max(r2, r3));
 }
 
 // Axes of a pass: a is the dominant (plane) axis, f and s the in-plane fast
@@ -825,6 +832,9 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     const float amaxl = static_cast<float>(a1 - a0 - 1);
     const int t = threadIdx.x, lane = t & 63;
     const int wbase = __builtin_amdgcn_readfirstlane(t & ~63);  // first thread of the wave
+    // voxel spacing along the pass axis and the in-plane spacings relative to it
+    const float sa = static_cast<float>(p.s[A]);
+    const float sfa = static_cast<float>(p.s[F] / p.s[A]), ssa = static_cast<float>(p.s[S] / p.s[A]);
     const double oa = a0, of = f0 - 2, os = s0 - SLO - 1;
 
     // the voxels this thread owns: e = t + NT q, x fastest (coalesced output)
@@ -907,8 +917,14 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
         const double Bf0 = tv.B[3 * F], Bf1 = tv.B[3 * F + 1], Bf2 = tv.B[3 * F + 2] - of;
         const double Bs0 = tv.B[3 * S], Bs1 = tv.B[3 * S + 1], Bs2 = tv.B[3 * S + 2] - os;
         const int wu_e = (wu + 1) >> 1, wu_o = wu >> 1, wv_e = (wv + 1) >> 1;
-        const int n00 = wu_e * wv_e, n10 = wu_o * wv_e, n01 = wu_e * (wv >> 1);
+        // first candidate of the parity classes (odd column, even row),
+        // (even column, odd row) and (odd column, odd row)
+        const int T1 = wu_e * wv_e, T2 = T1 + wu_o * wv_e, T3 = T2 + wu_e * (wv >> 1);
         const int ncand = wu * wv;
+        // below 2^20 candidates the reciprocal estimate of j / w is exact:
+        // its relative error (rcp 1 ulp, product 1/2 ulp) times (j + 1/2) / w
+        // stays below the 1/(2w) distance to the nearest integer
+        const bool exact = ncand <= (1 << 20);
         const float rwe = __builtin_amdgcn_rcpf(static_cast<float>(wu_e));
         const float rwo = wu_o > 0 ? __builtin_amdgcn_rcpf(static_cast<float>(wu_o)) : 0.0f;
         const Q *sino_v = sino_b + static_cast<int64_t>(view) * p.nv * p.nu;
@@ -926,18 +942,18 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
                 qv[cq] = 0.0f;
                 if (idx < ncand) {
                     // parity classes (c - cu0, r - cv0) mod 2, each row-major
-                    int j = idx, pc, pr, w;
-                    float rwc;
-                    if (j < n00) { pc = 0; pr = 0; w = wu_e; rwc = rwe; }
-                    else if ((j -= n00) < n10) { pc = 1; pr = 0; w = wu_o; rwc = rwo; }
-                    else if ((j -= n10) < n01) { pc = 0; pr = 1; w = wu_e; rwc = rwe; }
-                    else { j -= n01; pc = 1; pr = 1; w = wu_o; rwc = rwo; }
-                    // j / w (both < 2^24): reciprocal estimate, exact correction
-                    int jq = static_cast<int>((static_cast<float>(j) + 0.5f) * rwc);
-                    jq -= (__mul24(jq, w) > j) ? 1 : 0;
-                    jq += (__mul24(jq + 1, w) <= j) ? 1 : 0;
-                    cc[cq] = cu0 + pc + 2 * (j - __mul24(jq, w));
-                    cr[cq] = cv0 + pr + 2 * jq;
+                    // (branch-free class selection)
+                    const bool k1 = idx >= T1, k2 = idx >= T2, k3 = idx >= T3;
+                    const int j = idx - (k3 ? T3 : (k2 ? T2 : (k1 ? T1 : 0)));
+                    const bool odd_c = k3 || (k1 && !k2);
+                    const int w = odd_c ? wu_o : wu_e;
+                    int jq = static_cast<int>((static_cast<float>(j) + 0.5f) * (odd_c ? rwo : rwe));
+                    if (!exact) {  // j, w < 2^24: the estimate is within one
+                        jq -= (__mul24(jq, w) > j) ? 1 : 0;
+                        jq += (__mul24(jq + 1, w) <= j) ? 1 : 0;
+                    }
+                    cc[cq] = cu0 + (odd_c ? 1 : 0) + 2 * (j - __mul24(jq, w));
+                    cr[cq] = cv0 + (k2 ? 1 : 0) + 2 * jq;
                     // r * nu + c < 2^31 (sinogram views are validated)
                     qv[cq] = to_f32(sino_v[__umul24(static_cast<uint32_t>(cr[cq]), static_cast<uint32_t>(p.nu)) +
                                            static_cast<uint32_t>(cc[cq])]);
@@ -963,18 +979,22 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
                         inv = inv * fma(-da, inv, 2.0);
                         inv = inv * fma(-da, inv, 2.0);
                         const double gf = df * inv, gs = dsl * inv;
-                        const double pa = fma(Ba0, u, fma(Ba1, v, Ba2));
-                        const double pf = fma(Bf0, u, fma(Bf1, v, Bf2));
-                        const double ps = fma(Bs0, u, fma(Bs1, v, Bs2));
+                        // a point on the ray: the source for a point source
+                        double pa = Ba2, pf = Bf2, ps = Bs2;
+                        if (!p.point_source) {  // uniform; the asm keeps it a branch
+                            asm volatile("");
+                            pa = fma(Ba0, u, fma(Ba1, v, Ba2));
+                            pf = fma(Bf0, u, fma(Bf1, v, Bf2));
+                            ps = fma(Bs0, u, fma(Bs1, v, Bs2));
+                        }
                         // in-plane position at local plane 0
                         const float bfl = static_cast<float>(fma(-pa, gf, pf));
                         const float bsl = static_cast<float>(fma(-pa, gs, ps));
                         const float gf32 = static_cast<float>(gf), gs32 = static_cast<float>(gs);
-                        // ray length per plane (mm), FP32
-                        const float wx = static_cast<float>(A == 0 ? da : df) * static_cast<float>(p.s[0]);
-                        const float wy = static_cast<float>(A == 1 ? da : (A == 0 ? df : dsl)) * static_cast<float>(p.s[1]);
-                        const float wz = static_cast<float>(A == 2 ? da : dsl) * static_cast<float>(p.s[2]);
-                        dsm = __builtin_amdgcn_sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz))) * fabsf(static_cast<float>(inv));
+                        // ray length per plane (mm), FP32: one plane step moves
+                        // (1, gf, gs) voxels along (a, f, s)
+                        const float xf = gf32 * sfa, xs = gs32 * ssa;
+                        dsm = __builtin_amdgcn_sqrtf(fmaf(xf, xf, fmaf(xs, xs, 1.0f))) * sa;
                         float lo = 0.0f, hi = amaxl;
                         clip_local(bfl, gf32, flo, fhi, lo, hi);
                         clip_local(bsl, gs32, slo, shi, lo, hi);
