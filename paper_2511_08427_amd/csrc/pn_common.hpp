@@ -56,6 +56,7 @@ struct FwdParams {
     int32_t tiles_u, tiles_v;  // tiles covering the detector window [c_lo, nu) x [r_lo, nv) that is launched
     int32_t c_lo, r_lo;        // first column and row of the window
     const int32_t *vwin;       // per view: detector window of the view (c0, c1, r0, r1), or nullptr
+    int32_t point_source;      // 1: every ray of a view leaves one point (B has zero u and v columns)
 };
 
 struct AdjParams {

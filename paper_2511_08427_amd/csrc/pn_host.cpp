@@ -743,6 +743,7 @@ int forward_prepare(const pn_geometry *pg, int64_t batch, const void *vol, void 
     p.tiles_u = empty ? 0 : (pl->win_c1 - pl->win_c0 + p.tile_u) / p.tile_u;
     p.tiles_v = empty ? 0 : (pl->win_r1 - pl->win_r0 + p.tile_v) / p.tile_v;
     p.vwin = pl->d_vwin;
+    p.point_source = g.parallel ? 0 : 1;
     if (forward_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
     none = forward_blocks(p) == 0;
     (void)pg;

@@ -63,37 +63,56 @@ __device__ __forceinline__ int fast_axis(int a) { return a == 0 ? 1 : 0; }
 __device__ __forceinline__ int slow_axis(int a) { return a == 2 ? 1 : 2; }
 
 // Narrows [lo, hi] to the planes m where b + m*g lies in [lo_pos, hi_pos].
+// The range only has to hold every plane where the ray can sample a
+// non-zero tap (the caller adds a plane of slack on each side, and planes
+// outside add exactly zero), so the crossings are formed with the hardware
+// FP64 reciprocal (relative error about 2^-23) instead of a division.  A zero
+// slope keeps or empties the whole range by the position itself.
 __device__ __forceinline__ void clip_range(double b, double g, double lo_pos, double hi_pos, double &lo, double &hi)
 {
     if (g == 0.0) {
         if (!(b >= lo_pos && b <= hi_pos)) { lo = 1.0; hi = 0.0; }
         return;
     }
-    double t0 = (lo_pos - b) / g, t1 = (hi_pos - b) / g;
-    if (t0 > t1) { double t = t0; t0 = t1; t1 = t; }
-    lo = fmax(lo, t0);
-    hi = fmin(hi, t1);
+    const double rg = __builtin_amdgcn_rcp(g);
+    const double t0 = (lo_pos - b) * rg, t1 = (hi_pos - b) * rg;
+    lo = fmax(lo, fmin(t0, t1));
+    hi = fmin(hi, fmax(t0, t1));
 }
 
+// point_source: every ray of the view leaves the same point (B has zero u
+// and v columns), so p(u, v) is the view's constant B (0, 0, 1).
 __device__ __forceinline__ void ray_setup(const ViewTab &t, double u, double v, const int32_t n[3],
-                                          const double s[3], RaySeg &r)
+                                          const double s[3], bool point_source, RaySeg &r)
 {
     double d[3], p[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         d[i] = fma(t.A[3 * i], u, fma(t.A[3 * i + 1], v, t.A[3 * i + 2]));
-        p[i] = fma(t.B[3 * i], u, fma(t.B[3 * i + 1], v, t.B[3 * i + 2]));
+        p[i] = t.B[3 * i + 2];
+    }
+    if (!point_source) {  // uniform; the asm keeps it a branch
+        asm volatile("");
+#pragma unroll
+        for (int i = 0; i < 3; ++i) p[i] = fma(t.B[3 * i], u, fma(t.B[3 * i + 1], v, t.B[3 * i + 2]));
     }
     double ax = fabs(d[0]), ay = fabs(d[1]), az = fabs(d[2]);
     // dominant index-space axis; exact ties go to the lowest axis
     int a = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
     int f = fast_axis(a), sl = slow_axis(a);
-    double inv = 1.0 / d[a];
+    // 1/d_a: hardware reciprocal refined by two Newton steps (FP64 accurate)
+    const double da = d[a];
+    double inv = __builtin_amdgcn_rcp(da);
+    inv = inv * fma(-da, inv, 2.0);
+    inv = inv * fma(-da, inv, 2.0);
     double gf = d[f] * inv, gs = d[sl] * inv;
     double bf = fma(-p[a], gf, p[f]);
     double bs = fma(-p[a], gs, p[sl]);
-    double wx = d[0] * s[0], wy = d[1] * s[1], wz = d[2] * s[2];
-    double ds = sqrt(wx * wx + wy * wy + wz * wz) * fabs(inv);
+    // ray length per plane (mm), FP32
+    const float wx = static_cast<float>(d[0]) * static_cast<float>(s[0]);
+    const float wy = static_cast<float>(d[1]) * static_cast<float>(s[1]);
+    const float wz = static_cast<float>(d[2]) * static_cast<float>(s[2]);
+    const float ds = __builtin_amdgcn_sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz))) * fabsf(static_cast<float>(inv));
     double lo = 0.0, hi = static_cast<double>(n[a] - 1);
     clip_range(bf, gf, -1.0, static_cast<double>(n[f]), lo, hi);
     clip_range(bs, gs, -1.0, static_cast<double>(n[sl]), lo, hi);
@@ -102,7 +121,7 @@ __device__ __forceinline__ void ray_setup(const ViewTab &t, double u, double v, 
     r.gs = static_cast<float>(gs);
     r.bf = static_cast<float>(bf);
     r.bs = static_cast<float>(bs);
-    r.ds = static_cast<float>(ds);
+    r.ds = ds;
     if (!(lo <= hi) || !isfinite(ds)) {
         r.m0 = 1;
         r.m1 = 0;
@@ -336,7 +355,7 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
     seg.m0 = 1;
     seg.m1 = 0;
     seg.gf = seg.gs = seg.bf = seg.bs = seg.ds = 0.0f;
-    if (inside) ray_setup(tab, static_cast<double>(c), static_cast<double>(r), p.n, p.s, seg);
+    if (inside) ray_setup(tab, static_cast<double>(c), static_cast<double>(r), p.n, p.s, p.point_source != 0, seg);
     const bool live = inside && seg.m0 <= seg.m1;
     if (t == 0) s_axes = 0;
     __syncthreads();
