@@ -53,6 +53,7 @@ struct FwdParams {
     const void *vol;       // caller's volume [batch][nz][ny][nx] (fallback path)
     void *sino;            // [batch][n_views][nv][nu]
     int32_t tile_u, tile_v;  // ray tile (tile_u * tile_v == block size)
+    int32_t view_group;      // consecutive views per workgroup
     int32_t tiles_u, tiles_v;  // tiles covering the detector window [c_lo, nu) x [r_lo, nv) that is launched
     int32_t c_lo, r_lo;        // first column and row of the window
     const int32_t *vwin;       // per view: detector window of the view (c0, c1, r0, r1), or nullptr

@@ -32,7 +32,7 @@ hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 int adjoint_shape_count();
 void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF);
-void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv);
+void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv, int32_t &views);
 int64_t forward_blocks(const FwdParams &p);
 int64_t adjoint_blocks(const AdjParams &p);
 int64_t backproject_blocks(const BpParams &p);
@@ -729,7 +729,7 @@ int forward_prepare(const pn_geometry *pg, int64_t batch, const void *vol, void 
     }
     p.vol = vol;
     p.sino = sino;
-    forward_tile_shape(g.ndim == 2, p.tile_u, p.tile_v);
+    forward_tile_shape(g.ndim == 2, p.tile_u, p.tile_v, p.view_group);
     // only the tiles of the detector window that can see the volume are
     // launched; the rest of the sinogram is zero
     const bool full = pl->win_c0 == 0 && pl->win_r0 == 0 && pl->win_c1 == g.nu - 1 && pl->win_r1 == g.nv - 1;

@@ -289,86 +289,122 @@ struct Box {
 };
 
 // Ray-driven forward projection.  A workgroup owns a TU x TV tile of
-// detector pixels of one view (one ray per thread).  For each dominant axis
-// present in the tile it walks the union of the rays' plane ranges in chunks
-// of C planes; per chunk it stages the box of volume that the tile's rays can
-// touch (bounded by the four corner rays, whose crossings with a plane
-// enclose those of every ray in between) from the padded work copy into LDS
-// with 16-byte loads, and every ray then samples the chunk's planes from
-// LDS.  The loads of chunk i+1 are issued into registers before chunk i is
-// sampled, and the boxes of up to 64 chunks are computed at once, one
-// chunk per thread.  A box larger than RCAP x FCAP falls back to gathers
+// detector pixels and NVW consecutive views (one pixel per thread, its ray
+// in each of the views).  For each dominant axis present among the rays it
+// walks the union of their plane ranges in chunks of C planes; per chunk it
+// stages the box of volume that the rays can touch (bounded by the four
+// corner rays of each view, whose crossings with a plane enclose those of
+// every ray of the tile in between) from the padded work copy into LDS with
+// 16-byte loads, and every ray then samples the chunk's planes from LDS.
+// Rays of neighbouring views cross nearly the same voxels, so one staged box
+// serves NVW views.  The loads of chunk i+1 are issued into registers before
+// chunk i is sampled, and the boxes of up to 64 chunks are computed at once,
+// one chunk per thread.  A box larger than RCAP x FCAP falls back to gathers
 // from the work copy.
 //
 // A ray samples every plane of a chunk, also planes outside its own range:
 // there its position lies outside [-1, n] in some in-plane axis and the
-// clamp puts all weight on a zero padding cell, so the sample is exactly 0.
+// box's zero padding makes the sample exactly 0.
 //
 // Workgroup order: consecutive workgroup ids go round-robin to the 8 XCDs;
-// each XCD gets every 8th tile and runs the views of a tile back to back, so
-// the workgroups resident on one XCD sample nearly the same beam of the
-// volume and share its L2.
-template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
+// each XCD gets every 8th tile and runs the view groups of a tile back to
+// back, so the workgroups resident on one XCD sample nearly the same beam of
+// the volume and share its L2.
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP, int NVW>
 __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
 {
-    static_assert(TU * TV == 256, "one ray per thread");
+    static_assert(TU * TV == 256, "one pixel per thread");
+    static_assert(4 * NVW <= 64, "corner rays of a view group");
     constexpr int VE = Vec<S>::N;
     constexpr int VPR = FCAP / VE;
     constexpr int RPI = 256 / VPR;
     constexpr int PLANE = RCAP * FCAP;
+    constexpr int NCR = 4 * NVW;  // corner rays
     static_assert(FCAP % VE == 0 && RPI >= RCAP, "one staged row per thread and plane");
     __shared__ float box[C * PLANE];
     constexpr int WIN = 64;      // chunks per window of boxes
     __shared__ int4 s_box[WIN];  // boxes of a window of chunks: f_al, s_lo, nvec | ns << 16, lds
-    __shared__ float s_corner[4][4];
-    __shared__ int s_dir[4];
+    __shared__ float s_corner[NCR][4];
+    __shared__ int s_dir[NCR];
     __shared__ int s_axes, s_m0, s_m1;
 
     const int t = threadIdx.x;
     const int tiles = p.tiles_u * p.tiles_v;
     const int tpx = (tiles + 7) >> 3;
+    const int n_vg = (p.n_views + NVW - 1) / NVW;
     const int xcd = bid & 7;
     const int slot = bid >> 3;
-    const int per_b = tpx * p.n_views;
+    const int per_b = tpx * n_vg;
     const int b = slot / per_b;
     const int rem = slot - b * per_b;
-    const int tile = (rem / p.n_views) * 8 + xcd;
-    const int view = rem % p.n_views;
+    const int tile = (rem / n_vg) * 8 + xcd;
+    const int view0 = (rem % n_vg) * NVW;
     if (tile >= tiles || b >= p.batch) return;  // padding workgroups (uniform exit)
     const int c0 = p.c_lo + (tile % p.tiles_u) * TU, r0 = p.r_lo + (tile / p.tiles_u) * TV;
     const int c = c0 + t % TU, r = r0 + t / TU;
     const bool inside = c < p.nu && r < p.nv;
-    if (p.vwin) {
-        // a tile outside the view's own window sees no voxel: zeros
-        const int *w = p.vwin + 4 * view;
-        if (c0 + TU <= w[0] || c0 > w[1] || r0 + TV <= w[2] || r0 > w[3]) {  // uniform
-            if (inside)
-                static_cast<O *>(p.sino)[((static_cast<int64_t>(b) * p.n_views + view) * p.nv + r) * p.nu + c] =
-                    from_f32<O>(0.0f);
-            return;
+    O *out = static_cast<O *>(p.sino);
+    // views of the group that exist and whose window the tile meets (a
+    // tile outside a view's own window sees no voxel: zeros); uniform
+    bool vin[NVW];
+    int wfirst = -1;
+#pragma unroll
+    for (int w = 0; w < NVW; ++w) {
+        const int view = view0 + w;
+        vin[w] = view < p.n_views;
+        if (vin[w] && p.vwin) {
+            const int *wn = p.vwin + 4 * view;
+            if (c0 + TU <= wn[0] || c0 > wn[1] || r0 + TV <= wn[2] || r0 > wn[3]) vin[w] = false;
         }
+        if (vin[w] && wfirst < 0) wfirst = w;
     }
-    const ViewTab &tab = p.tab[view];
+    if (wfirst < 0) {
+        if (inside)
+#pragma unroll
+            for (int w = 0; w < NVW; ++w)
+                if (view0 + w < p.n_views)
+                    out[((static_cast<int64_t>(b) * p.n_views + view0 + w) * p.nv + r) * p.nu + c] = from_f32<O>(0.0f);
+        return;
+    }
 
-    RaySeg seg;
-    seg.axis = 0;
-    seg.m0 = 1;
-    seg.m1 = 0;
-    seg.gf = seg.gs = seg.bf = seg.bs = seg.ds = 0.0f;
-    if (inside) ray_setup(tab, static_cast<double>(c), static_cast<double>(r), p.n, p.s, p.point_source != 0, seg);
-    const bool live = inside && seg.m0 <= seg.m1;
+    RaySeg seg[NVW];
+    bool live[NVW];
+    int amask = 0;
+#pragma unroll
+    for (int w = 0; w < NVW; ++w) {
+        seg[w].axis = 0;
+        seg[w].m0 = 1;
+        seg[w].m1 = 0;
+        seg[w].gf = seg[w].gs = seg[w].bf = seg[w].bs = seg[w].ds = 0.0f;
+        if (inside && vin[w])
+            ray_setup(p.tab[view0 + w], static_cast<double>(c), static_cast<double>(r), p.n, p.s, p.point_source != 0,
+                      seg[w]);
+        live[w] = inside && vin[w] && seg[w].m0 <= seg[w].m1;
+        if (live[w]) amask |= 1 << seg[w].axis;
+    }
     if (t == 0) s_axes = 0;
     __syncthreads();
-    if (live) atomicOr(&s_axes, 1 << seg.axis);
+    if (amask) atomicOr(&s_axes, amask);
     __syncthreads();
     const int axes = s_axes;
 
     const int c1 = min(c0 + TU, p.nu) - 1, r1 = min(r0 + TV, p.nv) - 1;
     const int vr = t % VPR, rrow = t / VPR;  // this thread's vector and row of a staged plane
-    float acc = 0.0f;
+    float acc[NVW];
+#pragma unroll
+    for (int w = 0; w < NVW; ++w) acc[w] = 0.0f;
     for (int a = 0; a < 3; ++a) {
         if (!((axes >> a) & 1)) continue;
-        const bool part = live && seg.axis == a;
+        bool part[NVW];
+        int pm0 = 0x7fffffff, pm1 = -1;
+#pragma unroll
+        for (int w = 0; w < NVW; ++w) {
+            part[w] = live[w] && seg[w].axis == a;
+            if (part[w]) {
+                pm0 = min(pm0, seg[w].m0);
+                pm1 = max(pm1, seg[w].m1);
+            }
+        }
         const int f = fast_axis(a), sl = slow_axis(a);
         const float nf = static_cast<float>(p.n[f]), ns = static_cast<float>(p.n[sl]);
         __syncthreads();
@@ -377,13 +413,16 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
             s_m1 = -1;
         }
         __syncthreads();
-        if (part) {
-            atomicMin(&s_m0, seg.m0);
-            atomicMax(&s_m1, seg.m1);
+        if (pm0 <= pm1) {
+            atomicMin(&s_m0, pm0);
+            atomicMax(&s_m1, pm1);
         }
-        if (t < 4) {
-            // corner ray t of the tile, parametrised along axis a
-            const double u = (t & 1) ? c1 : c0, v = (t & 2) ? r1 : r0;
+        if (t < NCR) {
+            // corner ray t & 3 of view t >> 2, parametrised along axis a (a
+            // view outside the tile's reach repeats the first one in reach)
+            const int w = vin[t >> 2] ? t >> 2 : wfirst;
+            const ViewTab &tab = p.tab[view0 + w];
+            const double u = (t & 1) ? c1 : c0, v = ((t >> 1) & 1) ? r1 : r0;
             double d[3], q[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -402,8 +441,9 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
         const int M0 = s_m0, M1 = s_m1;
         // the corner crossings bound the tile's crossings when no ray of the
         // tile is parallel to the planes (same non-zero sign at the corners)
-        const bool box_ok = p.lay[a] != nullptr && s_dir[0] != 0 && s_dir[0] == s_dir[1] && s_dir[0] == s_dir[2] &&
-                            s_dir[0] == s_dir[3];
+        bool box_ok = p.lay[a] != nullptr && s_dir[0] != 0;
+#pragma unroll
+        for (int k = 1; k < NCR; ++k) box_ok = box_ok && s_dir[k] == s_dir[0];
         const S *base = box_ok ? static_cast<const S *>(p.lay[a]) + b * p.lay_item[a] : nullptr;
         const int32_t row = p.lay_row[a];
         const int64_t plane = p.lay_plane[a];
@@ -418,7 +458,7 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
             if (box_ok) {
                 float fmn = 3e38f, fmx = -3e38f, smn = 3e38f, smx = -3e38f;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < NCR; ++k) {
                     const float4 cr = *reinterpret_cast<const float4 *>(s_corner[k]);
                     const float pf0 = fmaf(static_cast<float>(bx.mc), cr.x, cr.y);
                     const float pf1 = fmaf(static_cast<float>(bx.me), cr.x, cr.y);
@@ -517,96 +557,106 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                 cur = box_at(ci + 1, wb);
                 issue(cur);  // in flight while this chunk is sampled
             }
-            // rays whose plane range misses the chunk sample nothing (a
-            // wave whose rays all miss it skips the sampling)
-            if (!part || seg.m1 < now.mc || seg.m0 > now.me) continue;
-            if (now.lds) {
-                // box-local positions (the shifts by the integer box origin
-                // are exact): every position of the tile lies more than 1e-3
-                // inside the box, which holds zeros outside the padded grid,
-                // so no clamp is needed; positions are >= 0, so truncation
-                // is floor.  The offset is capped to keep the reads inside
-                // the box array whatever the positions.
-                const float fo = static_cast<float>(now.f_al), so = static_cast<float>(now.s_lo);
-                const float fmc = static_cast<float>(now.mc);
-                const float pf0 = fmaf(fmc, seg.gf, seg.bf - fo);
-                const float ps0 = fmaf(fmc, seg.gs, seg.bs - so);
-                const int kn = now.me - now.mc;
-                // taps of plane k: the reads of plane k + 1 are issued
-                // before plane k is interpolated (planes past the chunk's
-                // last read stale in-bounds LDS and are not used)
-                float tv[2][4], twf[2], tws[2];
-                auto fetch = [&](int k, int slot) {
-                    const float pf = fmaf(static_cast<float>(k), seg.gf, pf0);
-                    const float ps = fmaf(static_cast<float>(k), seg.gs, ps0);
-                    twf[slot] = __builtin_amdgcn_fractf(pf);
-                    tws[slot] = __builtin_amdgcn_fractf(ps);
-                    uint32_t off = __mul24(static_cast<uint32_t>(ps), static_cast<uint32_t>(FCAP * 4)) +
-                                   static_cast<uint32_t>(k * PLANE * 4);
-                    off = min(off + (static_cast<uint32_t>(pf) << 2), static_cast<uint32_t>((C * PLANE - FCAP - 2) * 4));
-                    asm volatile("" : "+v"(off));  // one base register for all four taps
-                    const float *q = reinterpret_cast<const float *>(reinterpret_cast<const char *>(box) + off);
-                    tv[slot][0] = q[0];
-                    tv[slot][1] = q[1];
-                    tv[slot][2] = q[FCAP];
-                    tv[slot][3] = q[FCAP + 1];
-                };
-                auto interp = [&](int slot) {
-                    const float lo = fmaf(twf[slot], tv[slot][1] - tv[slot][0], tv[slot][0]);
-                    const float hi = fmaf(twf[slot], tv[slot][3] - tv[slot][2], tv[slot][2]);
-                    acc += fmaf(tws[slot], hi - lo, lo);
-                };
-                fetch(0, 0);
-                if (kn == C - 1) {  // whole chunk (uniform): straight-line code
 #pragma unroll
-                    for (int k = 0; k < C; ++k) {
-                        if (k + 1 < C) fetch(k + 1, (k + 1) & 1);
-                        interp(k & 1);
-                    }
-                } else {
+            for (int w = 0; w < NVW; ++w) {
+                // rays whose plane range misses the chunk sample nothing (a
+                // wave whose rays all miss it skips the sampling)
+                if (!part[w] || seg[w].m1 < now.mc || seg[w].m0 > now.me) continue;
+                const RaySeg &sg = seg[w];
+                if (now.lds) {
+                    // box-local positions (the shifts by the integer box
+                    // origin are exact): every position of the tile lies more
+                    // than 1e-3 inside the box, which holds zeros outside the
+                    // padded grid, so no clamp is needed; positions are >= 0,
+                    // so truncation is floor.  The offset is capped to keep
+                    // the reads inside the box array whatever the positions.
+                    const float fo = static_cast<float>(now.f_al), so = static_cast<float>(now.s_lo);
+                    const float fmc = static_cast<float>(now.mc);
+                    const float pf0 = fmaf(fmc, sg.gf, sg.bf - fo);
+                    const float ps0 = fmaf(fmc, sg.gs, sg.bs - so);
+                    const int kn = now.me - now.mc;
+                    // taps of plane k: the reads of plane k + 1 are issued
+                    // before plane k is interpolated (planes past the chunk's
+                    // last read stale in-bounds LDS and are not used)
+                    float tv[2][4], twf[2], tws[2];
+                    float sum = 0.0f;
+                    auto fetch = [&](int k, int sl_) {
+                        const float pf = fmaf(static_cast<float>(k), sg.gf, pf0);
+                        const float ps = fmaf(static_cast<float>(k), sg.gs, ps0);
+                        twf[sl_] = __builtin_amdgcn_fractf(pf);
+                        tws[sl_] = __builtin_amdgcn_fractf(ps);
+                        uint32_t off = __mul24(static_cast<uint32_t>(ps), static_cast<uint32_t>(FCAP * 4)) +
+                                       static_cast<uint32_t>(k * PLANE * 4);
+                        off = min(off + (static_cast<uint32_t>(pf) << 2),
+                                  static_cast<uint32_t>((C * PLANE - FCAP - 2) * 4));
+                        asm volatile("" : "+v"(off));  // one base register for all four taps
+                        const float *q = reinterpret_cast<const float *>(reinterpret_cast<const char *>(box) + off);
+                        tv[sl_][0] = q[0];
+                        tv[sl_][1] = q[1];
+                        tv[sl_][2] = q[FCAP];
+                        tv[sl_][3] = q[FCAP + 1];
+                    };
+                    auto interp = [&](int sl_) {
+                        const float lo = fmaf(twf[sl_], tv[sl_][1] - tv[sl_][0], tv[sl_][0]);
+                        const float hi = fmaf(twf[sl_], tv[sl_][3] - tv[sl_][2], tv[sl_][2]);
+                        sum += fmaf(tws[sl_], hi - lo, lo);
+                    };
+                    fetch(0, 0);
+                    if (kn == C - 1) {  // whole chunk (uniform): straight-line code
 #pragma unroll
-                    for (int k = 0; k < C; ++k) {
-                        if (k > kn) break;  // uniform
-                        if (k + 1 < C) fetch(k + 1, (k + 1) & 1);
-                        interp(k & 1);
+                        for (int k = 0; k < C; ++k) {
+                            if (k + 1 < C) fetch(k + 1, (k + 1) & 1);
+                            interp(k & 1);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < C; ++k) {
+                            if (k > kn) break;  // uniform
+                            if (k + 1 < C) fetch(k + 1, (k + 1) & 1);
+                            interp(k & 1);
+                        }
                     }
-                }
-            } else {
-                const int ma = max(now.mc, seg.m0), mb = min(now.me, seg.m1);
-                if (p.lay[a] != nullptr) {
-                    const S *lay = static_cast<const S *>(p.lay[a]) + b * p.lay_item[a];
-                    for (int m = ma; m <= mb; ++m) {
-                        const float fm = static_cast<float>(m);
-                        acc += sample_padded(lay + m * plane, row, fmaf(fm, seg.gf, seg.bf),
-                                             fmaf(fm, seg.gs, seg.bs), nf, ns);
-                    }
+                    acc[w] += sum;
                 } else {
-                    const S *vol = static_cast<const S *>(p.vol) +
-                                   static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
-                    for (int m = ma; m <= mb; ++m) {
-                        const float fm = static_cast<float>(m);
-                        acc += sample_raw(vol, p.n, a, m, fmaf(fm, seg.gf, seg.bf), fmaf(fm, seg.gs, seg.bs));
+                    const int ma = max(now.mc, sg.m0), mb = min(now.me, sg.m1);
+                    if (p.lay[a] != nullptr) {
+                        const S *lay = static_cast<const S *>(p.lay[a]) + b * p.lay_item[a];
+                        for (int m = ma; m <= mb; ++m) {
+                            const float fm = static_cast<float>(m);
+                            acc[w] += sample_padded(lay + m * plane, row, fmaf(fm, sg.gf, sg.bf),
+                                                    fmaf(fm, sg.gs, sg.bs), nf, ns);
+                        }
+                    } else {
+                        const S *vol = static_cast<const S *>(p.vol) +
+                                       static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
+                        for (int m = ma; m <= mb; ++m) {
+                            const float fm = static_cast<float>(m);
+                            acc[w] += sample_raw(vol, p.n, a, m, fmaf(fm, sg.gf, sg.bf), fmaf(fm, sg.gs, sg.bs));
+                        }
                     }
                 }
             }
         }
     }
     if (!inside) return;
-    O *out = static_cast<O *>(p.sino);
-    out[((static_cast<int64_t>(b) * p.n_views + view) * p.nv + r) * p.nu + c] = from_f32<O>(live ? acc * seg.ds : 0.0f);
+#pragma unroll
+    for (int w = 0; w < NVW; ++w)
+        if (view0 + w < p.n_views)
+            out[((static_cast<int64_t>(b) * p.n_views + view0 + w) * p.nv + r) * p.nu + c] =
+                from_f32<O>(live[w] ? acc[w] * seg[w].ds : 0.0f);
 }
 
-template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP, int NVW>
 __global__ __launch_bounds__(256, 5) void forward_kernel(FwdParams p)
 {
-    forward_block<S, O, TU, TV, C, RCAP, FCAP>(p, blockIdx.x);
+    forward_block<S, O, TU, TV, C, RCAP, FCAP, NVW>(p, blockIdx.x);
 }
 
-template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP, int NVW>
 __global__ __launch_bounds__(256, 5) void forward_batch_kernel(Batch<FwdParams> w)
 {
     const int i = batch_item(w, blockIdx.x);
-    forward_block<S, O, TU, TV, C, RCAP, FCAP>(w.p[i], blockIdx.x - w.start[i]);
+    forward_block<S, O, TU, TV, C, RCAP, FCAP, NVW>(w.p[i], blockIdx.x - w.start[i]);
 }
 
 // ------------------------------------------------------- adjoint A^T -----
@@ -1492,32 +1542,37 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
     }
 }
 
+// 3-D forward: 16 x 16 pixel tiles of kFwdViews consecutive views, chunks of
+// 4 planes; 2-D: 256-pixel rows of one view, chunks of 8 planes
+constexpr int kFwdViews = 2;
+
 int64_t forward_blocks(const FwdParams &p)
 {
     const int64_t tiles = static_cast<int64_t>(p.tiles_u) * p.tiles_v;
-    return 8 * ((tiles + 7) / 8) * p.n_views * p.batch;
+    const int64_t groups = (p.n_views + p.view_group - 1) / p.view_group;
+    return 8 * ((tiles + 7) / 8) * groups * p.batch;
 }
 
 // Launch dispatch: a single problem passes its parameters, a batch its work
 // list; the kernel templates are the same.
-template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP, int NVW>
 static void fwd_go(const FwdParams &p, uint32_t blocks, hipStream_t st)
 {
-    forward_kernel<S, O, TU, TV, C, RCAP, FCAP><<<dim3(blocks), 256, 0, st>>>(p);
+    forward_kernel<S, O, TU, TV, C, RCAP, FCAP, NVW><<<dim3(blocks), 256, 0, st>>>(p);
 }
-template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP>
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP, int NVW>
 static void fwd_go(const Batch<FwdParams> &w, uint32_t blocks, hipStream_t st)
 {
-    forward_batch_kernel<S, O, TU, TV, C, RCAP, FCAP><<<dim3(blocks), 256, 0, st>>>(w);
+    forward_batch_kernel<S, O, TU, TV, C, RCAP, FCAP, NVW><<<dim3(blocks), 256, 0, st>>>(w);
 }
 
 template <typename S, typename O, typename Arg>
 static hipError_t forward_t(const Arg &a, bool two_d, uint32_t blocks, hipStream_t st)
 {
     if (two_d)
-        fwd_go<S, O, 256, 1, 8, 3, 320>(a, blocks, st);
+        fwd_go<S, O, 256, 1, 8, 3, 320, 1>(a, blocks, st);
     else
-        fwd_go<S, O, 16, 16, 8, 24, 40>(a, blocks, st);
+        fwd_go<S, O, 16, 16, 4, 24, 40, kFwdViews>(a, blocks, st);
     return hipGetLastError();
 }
 
@@ -1551,10 +1606,10 @@ hipError_t launch_forward_batch(const Batch<FwdParams> &w, bool two_d, int32_t i
     return forward_any(w, two_d, w.start[w.n], in_dt, out_dt, st);
 }
 
-void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv)
+void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv, int32_t &views)
 {
-    if (two_d) { tu = 256; tv = 1; }
-    else { tu = 16; tv = 16; }
+    if (two_d) { tu = 256; tv = 1; views = 1; }
+    else { tu = 16; tv = 16; views = kFwdViews; }
 }
 
 // Compiled adjoint block shapes (planes x rows x columns, candidates per
