@@ -367,20 +367,35 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
         return;
     }
 
-    RaySeg seg[NVW];
+    // the rays' lines in registers: slopes, positions at plane 0, plane
+    // range packed as m0 | m1 << 16 (empty: m0 > m1); the length per plane
+    // is recomputed from the slopes at the end
+    struct Line {
+        float gf, gs, bf, bs;
+        uint32_t rng;
+        int axis;
+    };
+    Line seg[NVW];
     bool live[NVW];
     int amask = 0;
 #pragma unroll
     for (int w = 0; w < NVW; ++w) {
-        seg[w].axis = 0;
-        seg[w].m0 = 1;
-        seg[w].m1 = 0;
-        seg[w].gf = seg[w].gs = seg[w].bf = seg[w].bs = seg[w].ds = 0.0f;
+        RaySeg rs;
+        rs.axis = 0;
+        rs.m0 = 1;
+        rs.m1 = 0;
+        rs.gf = rs.gs = rs.bf = rs.bs = rs.ds = 0.0f;
         if (inside && vin[w])
             ray_setup(p.tab[view0 + w], static_cast<double>(c), static_cast<double>(r), p.n, p.s, p.point_source != 0,
-                      seg[w]);
-        live[w] = inside && vin[w] && seg[w].m0 <= seg[w].m1;
-        if (live[w]) amask |= 1 << seg[w].axis;
+                      rs);
+        live[w] = inside && vin[w] && rs.m0 <= rs.m1;
+        seg[w].gf = rs.gf;
+        seg[w].gs = rs.gs;
+        seg[w].bf = rs.bf;
+        seg[w].bs = rs.bs;
+        seg[w].axis = rs.axis;
+        seg[w].rng = live[w] ? static_cast<uint32_t>(rs.m0) | static_cast<uint32_t>(rs.m1) << 16 : 1u;
+        if (live[w]) amask |= 1 << rs.axis;
     }
     if (t == 0) s_axes = 0;
     __syncthreads();
@@ -401,8 +416,8 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
         for (int w = 0; w < NVW; ++w) {
             part[w] = live[w] && seg[w].axis == a;
             if (part[w]) {
-                pm0 = min(pm0, seg[w].m0);
-                pm1 = max(pm1, seg[w].m1);
+                pm0 = min(pm0, static_cast<int>(seg[w].rng & 0xffffu));
+                pm1 = max(pm1, static_cast<int>(seg[w].rng >> 16));
             }
         }
         const int f = fast_axis(a), sl = slow_axis(a);
@@ -561,8 +576,9 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
             for (int w = 0; w < NVW; ++w) {
                 // rays whose plane range misses the chunk sample nothing (a
                 // wave whose rays all miss it skips the sampling)
-                if (!part[w] || seg[w].m1 < now.mc || seg[w].m0 > now.me) continue;
-                const RaySeg &sg = seg[w];
+                const Line &sg = seg[w];
+                const int sm0 = static_cast<int>(sg.rng & 0xffffu), sm1 = static_cast<int>(sg.rng >> 16);
+                if (!part[w] || sm1 < now.mc || sm0 > now.me) continue;
                 if (now.lds) {
                     // box-local positions (the shifts by the integer box
                     // origin are exact): every position of the tile lies more
@@ -618,7 +634,7 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                     }
                     acc[w] += sum;
                 } else {
-                    const int ma = max(now.mc, sg.m0), mb = min(now.me, sg.m1);
+                    const int ma = max(now.mc, sm0), mb = min(now.me, sm1);
                     if (p.lay[a] != nullptr) {
                         const S *lay = static_cast<const S *>(p.lay[a]) + b * p.lay_item[a];
                         for (int m = ma; m <= mb; ++m) {
@@ -640,10 +656,18 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
     }
     if (!inside) return;
 #pragma unroll
-    for (int w = 0; w < NVW; ++w)
-        if (view0 + w < p.n_views)
-            out[((static_cast<int64_t>(b) * p.n_views + view0 + w) * p.nv + r) * p.nu + c] =
-                from_f32<O>(live[w] ? acc[w] * seg[w].ds : 0.0f);
+    for (int w = 0; w < NVW; ++w) {
+        if (view0 + w >= p.n_views) continue;
+        // ray length per plane (mm): one plane step moves (1, gf, gs) voxels
+        // along (a, f, s)
+        const int ax = seg[w].axis;
+        const float sa = static_cast<float>(p.s[ax]);
+        const float xf = seg[w].gf * static_cast<float>(p.s[fast_axis(ax)]);
+        const float xs = seg[w].gs * static_cast<float>(p.s[slow_axis(ax)]);
+        const float ds = __builtin_amdgcn_sqrtf(fmaf(xf, xf, fmaf(xs, xs, sa * sa)));
+        out[((static_cast<int64_t>(b) * p.n_views + view0 + w) * p.nv + r) * p.nu + c] =
+            from_f32<O>(live[w] ? acc[w] * ds : 0.0f);
+    }
 }
 
 template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP, int NVW>
@@ -1544,7 +1568,7 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
 
 // 3-D forward: 16 x 16 pixel tiles of kFwdViews consecutive views, chunks of
 // 4 planes; 2-D: 256-pixel rows of one view, chunks of 8 planes
-constexpr int kFwdViews = 2;
+constexpr int kFwdViews = 3;
 
 int64_t forward_blocks(const FwdParams &p)
 {
