@@ -321,7 +321,16 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
     constexpr int PLANE = RCAP * FCAP;
     constexpr int NCR = 4 * NVW;  // corner rays
     static_assert(FCAP % VE == 0 && RPI >= RCAP, "one staged row per thread and plane");
-    __shared__ float box[C * PLANE];
+    // FP32 storage is staged with direct global-to-LDS loads (16 bytes per
+    // lane, lane i of a wave at the wave's base + 16 i: thread t's vector
+    // lands at float 4 t of the plane, its row-major place since a row holds
+    // exactly VPR vectors) into two buffers, chunk i + 1 arriving while chunk
+    // i is sampled; 16-bit storage goes through registers (widened to FP32)
+    // into one buffer.
+    constexpr bool DMA = std::is_same<S, float>::value;
+    constexpr int NBUF = DMA ? 2 : 1;
+    static_assert(!DMA || VPR * VE == FCAP, "direct staging needs rows of exactly VPR vectors");
+    __shared__ float box[NBUF][C * PLANE];
     constexpr int WIN = 64;      // chunks per window of boxes
     __shared__ int4 s_box[WIN];  // boxes of a window of chunks: f_al, s_lo, nvec | ns << 16, lds
     __shared__ float s_corner[NCR][4];
@@ -543,34 +552,70 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                 pre[k] = *reinterpret_cast<const uint4 *>(src + static_cast<int64_t>(min(k, kmax)) * plane);
         };
 
+        // direct loads of this thread's share of a box into buffer `buf`
+        auto issue_direct = [&](const Box &bx, int buf) {
+            if (!bx.lds) return;  // uniform
+            const bool mine = rrow < bx.ns && vr < bx.nvec;
+            const int wr = bx.s_lo + PADR_LO + rrow;
+            const int wc = bx.f_al + PADC + vr * VE;
+            const bool in = wr >= 0 && wr < srows && wc >= 0 && wc + VE <= row;
+            const S *src = base + static_cast<int64_t>(bx.mc) * plane +
+                           (in ? static_cast<int64_t>(wr) * row + wc : static_cast<int64_t>(0));
+            float *wave_dst = box[buf] + (t & ~63) * VE;  // the wave's first vector
+            const int kmax = bx.me - bx.mc;
+#if defined(__HIP_DEVICE_COMPILE__)  // a gfx950 builtin: the host pass never runs this
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+                if (k <= kmax && mine)
+                    __builtin_amdgcn_global_load_lds(src + static_cast<int64_t>(k) * plane, wave_dst + k * PLANE, 16,
+                                                     0, 0);
+#else
+            (void)src, (void)wave_dst, (void)kmax, (void)mine;
+#endif
+        };
+
         int wb = 0;
         window(0);
         __syncthreads();
         Box cur = box_at(0, 0);
-        issue(cur);
-        for (int ci = 0, mc = M0; mc <= M1; ++ci, mc += C) {
-            __syncthreads();  // every ray is done with the previous box and window
-            if (cur.lds && rrow < cur.ns && vr < cur.nvec) {
-#pragma unroll
-                for (int k = 0; k < C; ++k) {
-                    if (cur.mc + k > cur.me) break;
-                    float v[VE];
-                    unpack16<S>(pre[k], v);
-                    float *dst = box + (k * RCAP + rrow) * FCAP + vr * VE;
-#pragma unroll
-                    for (int e = 0; e < VE; e += 4)
-                        *reinterpret_cast<float4 *>(dst + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
-                }
-            }
-            if (ci + 1 - wb == WIN) {  // uniform
-                wb += WIN;
-                window(wb);
-            }
+        if constexpr (DMA) {
+            issue_direct(cur, 0);
+            __builtin_amdgcn_s_waitcnt(0);  // this thread's loads have reached LDS
             __syncthreads();
+        } else {
+            issue(cur);
+        }
+        for (int ci = 0, mc = M0; mc <= M1; ++ci, mc += C) {
+            int buf = 0;
+            if constexpr (DMA) {
+                buf = ci & 1;
+            } else {
+                __syncthreads();  // every ray is done with the previous box and window
+                if (cur.lds && rrow < cur.ns && vr < cur.nvec) {
+#pragma unroll
+                    for (int k = 0; k < C; ++k) {
+                        if (cur.mc + k > cur.me) break;
+                        float v[VE];
+                        unpack16<S>(pre[k], v);
+                        float *dst = box[0] + (k * RCAP + rrow) * FCAP + vr * VE;
+#pragma unroll
+                        for (int e = 0; e < VE; e += 4)
+                            *reinterpret_cast<float4 *>(dst + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+                    }
+                }
+                if (ci + 1 - wb == WIN) {  // uniform
+                    wb += WIN;
+                    window(wb);
+                }
+                __syncthreads();
+            }
             const Box now = cur;
             if (mc + C <= M1) {
                 cur = box_at(ci + 1, wb);
-                issue(cur);  // in flight while this chunk is sampled
+                // in flight while this chunk is sampled; the direct loads go to
+                // the other buffer, last read for chunk i - 1
+                if constexpr (DMA) issue_direct(cur, buf ^ 1);
+                else issue(cur);
             }
 #pragma unroll
             for (int w = 0; w < NVW; ++w) {
@@ -606,7 +651,7 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                         off = min(off + (static_cast<uint32_t>(pf) << 2),
                                   static_cast<uint32_t>((C * PLANE - FCAP - 2) * 4));
                         asm volatile("" : "+v"(off));  // one base register for all four taps
-                        const float *q = reinterpret_cast<const float *>(reinterpret_cast<const char *>(box) + off);
+                        const float *q = reinterpret_cast<const float *>(reinterpret_cast<const char *>(box[buf]) + off);
                         tv[sl_][0] = q[0];
                         tv[sl_][1] = q[1];
                         tv[sl_][2] = q[FCAP];
@@ -651,6 +696,15 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                         }
                     }
                 }
+            }
+            if constexpr (DMA) {
+                if (ci + 2 - wb == WIN) {  // uniform: the next box lies past the window
+                    __syncthreads();       // every box_at of this chunk has read the window
+                    wb += WIN;
+                    window(wb);
+                }
+                __builtin_amdgcn_s_waitcnt(0);  // chunk i + 1 has reached LDS
+                __syncthreads();                // ... for every thread; chunk i is done
             }
         }
     }
@@ -1567,7 +1621,7 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
 }
 
 // 3-D forward: 16 x 16 pixel tiles of kFwdViews consecutive views, chunks of
-// 4 planes; 2-D: 256-pixel rows of one view, chunks of 8 planes
+// 4 planes; 2-D: 256-pixel rows of one view, chunks of 4 planes
 constexpr int kFwdViews = 3;
 
 int64_t forward_blocks(const FwdParams &p)
@@ -1594,7 +1648,7 @@ template <typename S, typename O, typename Arg>
 static hipError_t forward_t(const Arg &a, bool two_d, uint32_t blocks, hipStream_t st)
 {
     if (two_d)
-        fwd_go<S, O, 256, 1, 8, 3, 320, 1>(a, blocks, st);
+        fwd_go<S, O, 256, 1, 4, 3, 320, 1>(a, blocks, st);
     else
         fwd_go<S, O, 16, 16, 4, 24, 40, kFwdViews>(a, blocks, st);
     return hipGetLastError();
