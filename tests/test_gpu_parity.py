@@ -80,6 +80,17 @@ def make_case(pn, name):
         Po = np.stack([O.cone_matrix(So[k], Co[k], euo[k], evo[k], det) for k in range(nv)])
         go = O.cone_geometry(shp, sp, det, ds, Po)
         vols = [W.ellipsoid_phantom_3d(404, shp, sp)[0]]
+    elif name == "cone3d_long_x":
+        # source near +x: rays run along x through 300 planes, more chunks
+        # than one window of forward boxes holds
+        shp, sp, det, ds = (20, 36, 300), (0.5, 0.5, 0.5), (24, 40), (1.0, 1.0)
+        gp = pn.cone_geometry(shp, sp, det, ds, 5, 750.0, 1200.0, angular_range=0.2)
+        go = O.circular_cone(shp, sp, det, ds, 5, 0.2, 750.0, 1200.0)
+        vols = [W.ellipsoid_phantom_3d(21, shp, sp)[0]]
+    elif name == "parallel2d_long_x":
+        gp = pn.parallel_geometry((30, 520), (1.0, 1.0), 40, 1.0, 4, angular_range=0.1)
+        go = O.parallel_2d((30, 520), (1.0, 1.0), 40, 1.0, 4, 0.1)
+        vols = [W.ellipse_phantom_2d(6, (30, 520), (1.0, 1.0))[0]]
     elif name == "cone3d_parallel_beam":
         shp, sp, det = (18, 21, 23), (1.0, 0.9, 1.1), (20, 26)
         ts = np.linspace(0.1, 3.0, 11)
@@ -97,7 +108,7 @@ def make_case(pn, name):
 
 
 CASES = ["parallel2d_64", "fan2d_ragged", "cone3d_ragged", "cone3d_anisotropic", "cone3d_perturbed",
-         "cone3d_helical", "cone3d_sinusoidal", "cone3d_parallel_beam"]
+         "cone3d_helical", "cone3d_sinusoidal", "cone3d_parallel_beam", "cone3d_long_x", "parallel2d_long_x"]
 
 
 @pytest.mark.parametrize("name", CASES)
