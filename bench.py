@@ -29,6 +29,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_08427_amd", "csrc", "pn_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cone3d_256_hbm_traffic.md")
+VALU_FILE = os.path.join(ROOT, "profiles", "cone3d_256_valu.md")
+# VALU issue ceiling: one wave64 instruction per CU per clock (each of the 4
+# SIMDs takes 4 cycles per wave instruction), 256 CUs at 2.4 GHz
+VALU_PEAK_PER_S = 256 * 2.4e9
 
 
 def log(msg):
@@ -53,13 +57,13 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(op):
-    """HBM bytes per call of `op` from the committed FETCH_SIZE/WRITE_SIZE
-    summary, or None when the kernels have changed since it was taken."""
+def profiled_value(path, key):
+    """A per-call figure from a committed rocprofv3 summary, or None when the
+    kernels have changed since it was taken (source sha256 recorded there)."""
     import hashlib
 
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
         src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -67,9 +71,15 @@ def measured_traffic(op):
     for line in text.splitlines():
         if line.startswith("kernel_source_sha256:"):
             sha = line.split(":", 1)[1].strip()
-        if line.startswith(f"traffic_bytes_per_call {op}:"):
+        if line.startswith(key + ":"):
             val = float(line.split(":", 1)[1])
     return val if sha == src else None
+
+
+def measured_traffic(op):
+    """HBM bytes per call of `op` from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernels have changed since it was taken."""
+    return profiled_value(TRAFFIC_FILE, f"traffic_bytes_per_call {op}")
 
 
 def timed(fn, reps, stream):
@@ -276,6 +286,17 @@ def main():
         "algorithmic_bytes_per_call": bytes_per_upd * upd,
         "call_ms": round(dom_ms, 4),
     }
+    # the bound the kernels actually meet: VALU issue (wave instructions per
+    # call from the committed SQ_INSTS_VALU summary, over the measured time)
+    n_valu = profiled_value(VALU_FILE, f"valu_instructions_per_call {dom_name}")
+    if n_valu is not None:
+        roofline["valu"] = {
+            "instructions_per_call": n_valu,
+            "achieved": n_valu / (dom_ms * 1e-3),
+            "peak": VALU_PEAK_PER_S,
+            "unit": "wave instructions/s",
+            "frac": round(n_valu / (dom_ms * 1e-3) / VALU_PEAK_PER_S, 4),
+        }
 
     cpu = None
     if not args.no_cpu_baseline:
