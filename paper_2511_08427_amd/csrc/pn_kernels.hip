@@ -297,10 +297,11 @@ struct Box {
 // every ray of the tile in between) from the padded work copy into LDS with
 // 16-byte loads, and every ray then samples the chunk's planes from LDS.
 // Rays of neighbouring views cross nearly the same voxels, so one staged box
-// serves NVW views.  The loads of chunk i+1 are issued into registers before
-// chunk i is sampled, and the boxes of up to 64 chunks are computed at once,
-// one chunk per thread.  A box larger than RCAP x FCAP falls back to gathers
-// from the work copy.
+// serves NVW views.  The loads of chunk i+1 are issued before chunk i is
+// sampled (straight into the other LDS buffer for FP32 storage, into
+// registers for 16-bit storage), and the boxes of up to 64 chunks are
+// computed at once, one chunk per thread.  A box larger than RCAP x FCAP
+// falls back to gathers from the work copy.
 //
 // A ray samples every plane of a chunk, also planes outside its own range:
 // there its position lies outside [-1, n] in some in-plane axis and the
