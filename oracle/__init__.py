@@ -357,3 +357,81 @@ def ray_taps(g, view, row, col):
         ctypes.c_int(g["dims"]), ctypes.c_int(int(g["parallel"])), pn, ps, po, Pv.ctypes.data_as(_F64P),
         ctypes.c_int64(row), ctypes.c_int64(col), idx.ctypes.data_as(_I64P), w.ctypes.data_as(_F64P))
     return idx[:cnt].copy(), w[:cnt].copy()
+
+
+# ------------------------------------------------------------------ FBP ----
+#
+# Filtered back-projection (PYRO-NN update, Sec. 2.4: the reconstruction is
+# the back-projection of the sinogram filtered along detector rows by a
+# diagonal Fourier-domain filter between an FFT and its inverse).  Readings
+# where the paper is silent: the filter K is the DFT of the discrete
+# Ram-Lak kernel g (g[0] = 1/4, g[k] = -1/(pi^2 k^2) for odd k, 0 for even
+# k != 0; Shepp-Logan: g[k] = -2 / (pi^2 (4 k^2 - 1))) on rows zero-padded
+# to at least twice their length, so the product is the linear convolution
+# of each row with g; divergent beams weight each pixel by the cosine of
+# its ray's angle to the detector normal before filtering (Feldkamp); the
+# kernel is in units of the pixel pitch at the rotation axis (du * SID / SDD
+# for divergent beams); the back-projection is the voxel-driven (W0/W)^2
+# weighted one; the result is scaled by pi / N (full 2 pi orbit, or pi for
+# parallel beams).
+
+
+def ramp_kernel(n, kind="ram-lak"):
+    """Discrete filter kernel g[k] for k = 0 .. n-1 (even: g[-k] = g[k])."""
+    k = np.arange(n, dtype=np.float64)
+    if kind == "ram-lak":
+        g = np.where(k % 2 == 1, -1.0 / (math.pi ** 2 * np.maximum(k, 1.0) ** 2), 0.0)
+        g[0] = 0.25
+    elif kind == "shepp-logan":
+        g = -2.0 / (math.pi ** 2 * (4.0 * k * k - 1.0))
+    else:
+        raise ValueError(kind)
+    return g
+
+
+def cosine_weights(g):
+    """Per view, row and column: the cosine of the ray's angle to the
+    detector normal, 1 / (|q3| |d|) with q3 the last row of the 3x3 (2-D:
+    2x2) part of P and d = (that part)^-1 (u, v, 1) the ray from the source
+    to the pixel (q3 . d = 1); ones for parallel beams."""
+    nv, nu = g["det"]
+    nviews = g["P"].shape[0]
+    if g["parallel"]:
+        return np.ones((nviews, nv, nu))
+    out = np.empty((nviews, nv, nu))
+    for k in range(nviews):
+        if g["dims"] == 3:
+            Q = g["P"][k][:, :3]
+            u, v = np.meshgrid(np.arange(nu, dtype=np.float64), np.arange(nv, dtype=np.float64))
+            pix = np.stack([u.ravel(), v.ravel(), np.ones(u.size)])
+        else:
+            Q = g["P"][k][:, :2]
+            pix = np.stack([np.arange(nu, dtype=np.float64), np.ones(nu)])
+        d = np.linalg.solve(Q, pix)
+        out[k] = (1.0 / (np.linalg.norm(Q[-1]) * np.linalg.norm(d, axis=0))).reshape(nv, nu)
+    return out
+
+
+def fbp_filter(sino, g, du_axis, kind="ram-lak"):
+    """The filtered sinogram q = (pi / N) (1 / du_axis) F^-1 K F (c p) along
+    detector rows, FP64; sino has shape [n_views][rows][cols]."""
+    nviews = g["P"].shape[0]
+    nv, nu = g["det"]
+    p = np.asarray(sino, dtype=np.float64).reshape(nviews, nv, nu) * cosine_weights(g)
+    L = 1
+    while L < 2 * nu:
+        L *= 2
+    gk = ramp_kernel(nu, kind)
+    circ = np.zeros(L)
+    circ[:nu] = gk
+    circ[L - nu + 1:] = gk[1:][::-1]
+    K = np.fft.fft(circ)
+    F = np.fft.fft(p, n=L, axis=-1)
+    q = np.real(np.fft.ifft(F * K, axis=-1))[..., :nu]
+    return q * (math.pi / nviews) / du_axis
+
+
+def fbp(sino, g, du_axis, kind="ram-lak", nthreads=0):
+    """Filtered back-projection: the voxel-driven back-projection of
+    fbp_filter(sino)."""
+    return backproject(fbp_filter(sino, g, du_axis, kind), g, nthreads)

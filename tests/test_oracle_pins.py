@@ -447,3 +447,72 @@ def test_oracle_reproduces_stored_fixture(O):
     g = O.parallel_2d((64, 64), (1.0, 1.0), 95, 1.0, 90, math.pi)
     p = O.forward(img, g)[::15, 0, :]
     assert np.abs(p - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ FBP ----
+
+
+@pytest.mark.parametrize("kind", ["ram-lak", "shepp-logan"])
+def test_filter_kernel_frequency_response(O, kind):
+    """The discrete kernels' frequency responses: |f| (Ram-Lak) and
+    sin(pi |f|) / pi (Shepp-Logan), f in cycles per sample (closed forms of
+    the infinite sums; the truncation at 4096 taps leaves < 1e-4)."""
+    g = O.ramp_kernel(4096, kind)
+    full = np.concatenate([g[::-1][:-1], g])
+    k = np.arange(-4095, 4096)
+    for f in (0.0, 0.05, 0.13, 0.25, 0.37, 0.5):
+        h = float(np.sum(full * np.cos(2 * math.pi * f * k)))
+        want = abs(f) if kind == "ram-lak" else math.sin(math.pi * abs(f)) / math.pi
+        assert abs(h - want) < 1e-4, (kind, f, h, want)
+
+
+def _disk_interior_exterior(rec, spacing, R):
+    n = rec.shape[0]
+    c = (np.arange(n) - (n - 1) / 2) * spacing
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    r = np.hypot(xx, yy)
+    return rec[r < R - 2].mean(), np.abs(rec[(r > R + 2) & (r < c[-1])]).mean()
+
+
+def test_fbp_parallel_reconstructs_disk(O):
+    """FBP of the exact parallel-beam line integrals of a unit disk
+    (2 sqrt(R^2 - s^2)) is 1 inside and 0 outside, up to discretization."""
+    R, n, ncol, nv = 20.0, 96, 129, 180
+    go = O.parallel_2d((n, n), (0.5, 0.5), ncol, 0.5, nv, math.pi)
+    s = (np.arange(ncol) - (ncol - 1) / 2) * 0.5
+    p = np.where(np.abs(s) < R, 2 * np.sqrt(np.maximum(R * R - s * s, 0.0)), 0.0)
+    inside, outside = _disk_interior_exterior(O.fbp(np.tile(p, (nv, 1, 1)), go, 0.5)[0], 0.5, R)
+    assert abs(inside - 1.0) < 0.01 and outside < 0.01, (inside, outside)
+
+
+def test_fbp_fan_reconstructs_disk(O):
+    """Fan-beam FBP (cosine weights, kernel at the axis pitch du SID/SDD,
+    (W0/W)^2 back-projection) of a centred unit disk: the ray at detector
+    coordinate u passes SID sin(atan(u / SDD)) from the centre."""
+    R, n, ncol, nv, sid, sdd, du = 20.0, 96, 181, 240, 400.0, 600.0, 0.5
+    go = O.circular_fan((n, n), (0.5, 0.5), ncol, du, nv, 2 * math.pi, sid, sdd)
+    u = (np.arange(ncol) - (ncol - 1) / 2) * du
+    dist = sid * np.sin(np.abs(np.arctan(u / sdd)))
+    p = np.where(dist < R, 2 * np.sqrt(np.maximum(R * R - dist * dist, 0.0)), 0.0)
+    inside, outside = _disk_interior_exterior(O.fbp(np.tile(p, (nv, 1, 1)), go, du * sid / sdd)[0], 0.5, R)
+    assert abs(inside - 1.0) < 0.01 and outside < 0.01, (inside, outside)
+
+
+def test_fdk_reconstructs_ball_central_slice(O):
+    """Cone-beam FDK of a centred unit ball: exact line integrals from the
+    ray-to-centre distance |S x d| / |d|; the central slice is 1 inside and
+    0 outside, up to discretization."""
+    nz, n, R, nvr, nuc, dd, sid, sdd, nviews = 48, 64, 10.0, 64, 96, 0.75, 400.0, 600.0, 120
+    go = O.circular_cone((nz, n, n), (0.5, 0.5, 0.5), (nvr, nuc), (dd, dd), nviews, 2 * math.pi, sid, sdd)
+    sino = np.zeros((nviews, nvr, nuc))
+    uu, vv = np.meshgrid(np.arange(nuc, dtype=np.float64), np.arange(nvr, dtype=np.float64))
+    pix = np.stack([uu.ravel(), vv.ravel(), np.ones(uu.size)])
+    for k in range(nviews):
+        Q = go["P"][k][:, :3]
+        S = -np.linalg.solve(Q, go["P"][k][:, 3])
+        d = np.linalg.solve(Q, pix)
+        dist = np.linalg.norm(np.cross(S[None, :], d.T), axis=1) / np.linalg.norm(d, axis=0)
+        sino[k] = np.where(dist < R, 2 * np.sqrt(np.maximum(R * R - dist ** 2, 0.0)), 0.0).reshape(nvr, nuc)
+    rec = O.fbp(sino, go, dd * sid / sdd)
+    inside, outside = _disk_interior_exterior(rec[nz // 2 - 1:nz // 2 + 1].mean(axis=0), 0.5, R)
+    assert abs(inside - 1.0) < 0.01 and outside < 0.01, (inside, outside)
