@@ -241,6 +241,14 @@ def main():
     t_adj, t_adj_mean = timed(lambda: pn.adjoint(y, geom), reps, stream)
     t_bp, _ = timed(lambda: pn.backproject(y, geom), reps, stream)
     log(f"A {t_fwd:.3f} ms, AT {t_adj:.3f} ms, BP {t_bp:.3f} ms")
+    # FDK: the row filter (a direct linear convolution, nu^2 multiply-adds
+    # per detector row) followed by the back-projection
+    t_filt, _ = timed(lambda: pn.fbp_filter(y, geom), reps, stream)
+    t_filt_sl, _ = timed(lambda: pn.fbp_filter(y, geom, "shepp-logan"), reps, stream)
+    t_fdk, _ = timed(lambda: pn.fbp(y, geom), reps, stream)
+    filt_flop = 2.0 * geom.n_views * geom.det_shape[0] * geom.det_shape[1] ** 2
+    log(f"FDK: Ram-Lak filter {t_filt:.3f} ms, Shepp-Logan filter {t_filt_sl:.3f} ms "
+        f"({filt_flop / (t_filt_sl * 1e-3) / 1e12:.1f} TFLOP/s), filter + BP {t_fdk:.3f} ms")
 
     variants = {
         "forward_gups": upd / (t_fwd * 1e-3) / 1e9,
@@ -249,6 +257,10 @@ def main():
         "forward_ms": t_fwd,
         "adjoint_ms": t_adj,
         "backproject_ms": t_bp,
+        "fdk_filter_ms": t_filt,
+        "fdk_filter_shepp_logan_ms": t_filt_sl,
+        "fdk_filter_shepp_logan_tflops": filt_flop / (t_filt_sl * 1e-3) / 1e12,
+        "fdk_ms": t_fdk,
     }
     if not args.no_variants:
         xb = x.to(torch.bfloat16)

@@ -124,6 +124,25 @@ int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol
 int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
                    int32_t in_dtype, int32_t out_dtype, void *hip_stream);
 
+/* Row filter of the filtered back-projection (Sec. 2.4: the reconstruction
+ * is the back-projection of the sinogram filtered along detector rows by a
+ * diagonal Fourier-domain filter).  out = (pi / N) (1 / a) g * (c p) along
+ * every detector row, where N = n_views, a is the pixel pitch at the
+ * rotation axis (det_spacing[1], times sid / sdd for fan and cone beams),
+ * c the cosine of each pixel's ray to the detector normal (1 for parallel
+ * beams) and g the discrete kernel: PN_FILTER_RAM_LAK (g[0] = 1/4,
+ * g[k] = -1/(pi^2 k^2) for odd k, 0 otherwise) or PN_FILTER_SHEPP_LOGAN
+ * (g[k] = -2/(pi^2 (4 k^2 - 1))); the convolution is linear (zero outside
+ * the row), i.e. F^-1 K F with K the kernel's DFT on rows padded to twice
+ * their length.  pn_backproject of the result is the FBP (parallel) or FDK
+ * (fan, cone; full 2 pi orbit) reconstruction.
+ * sino and out: [batch][n_views][rows][cols], device pointers, distinct
+ * buffers; cols <= 1024.  Fan and cone beams need sid > 0 and sdd > 0 in the
+ * geometry.  Errors: PN_EINVAL (kind, sizes, spacing, sid/sdd), PN_EGEOM. */
+enum { PN_FILTER_RAM_LAK = 0, PN_FILTER_SHEPP_LOGAN = 1 };
+int pn_filter(const pn_geometry *pg, int64_t batch, const void *sino, void *out, int32_t in_dtype,
+              int32_t out_dtype, int32_t kind, void *hip_stream);
+
 /* The same operators over n independent problems of uneven sizes in one
  * persistent launch per operator, replayed from a captured HIP graph when the
  * same problem set (geometries and pointers) is seen again.  Each problem's

@@ -31,6 +31,8 @@ from .ops import (
     adjoint_batched,
     backproject,
     backproject_batched,
+    fbp,
+    fbp_filter,
     forward,
     forward_batched,
     unrolled_gd,

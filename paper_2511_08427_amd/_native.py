@@ -33,6 +33,7 @@ EXPORTS = (
     "pn_forward_batched",
     "pn_adjoint_batched",
     "pn_backproject_batched",
+    "pn_filter",
     "pn_check_geometry",
     "pn_cone_matrices",
     "pn_fan_matrices",
@@ -88,6 +89,8 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [ctypes.POINTER(PnProblem), i32, i32, i32, vp]
         f.restype = ctypes.c_int
+    lib.pn_filter.argtypes = [gp, i64, vp, vp, i32, i32, i32, vp]
+    lib.pn_filter.restype = ctypes.c_int
     lib.pn_check_geometry.argtypes = [gp]
     lib.pn_check_geometry.restype = ctypes.c_int
     lib.pn_cone_matrices.argtypes = [i64, dp, dp, dp, dp, i64, i64, dp]

@@ -88,6 +88,17 @@ struct BpParams {
     void *vol;
 };
 
+struct FiltParams {
+    const ViewTab *tab;
+    int32_t n_views, nu, nv, batch;
+    double s[3];           // voxel spacing (index-space tables to world)
+    int32_t parallel;      // 1: no cosine weights
+    int32_t kind;          // 0: Ram-Lak, 1: Shepp-Logan
+    float scale;           // pi / N / (pixel pitch at the rotation axis)
+    const void *in;        // [batch][n_views][nv][nu]
+    void *out;             // same shape
+};
+
 // Work list of a batched launch, passed by value as the kernel argument
 // (no device allocation or copy, so a batched call can be captured in a
 // graph): workgroups [start[i], start[i+1]) run problem i.

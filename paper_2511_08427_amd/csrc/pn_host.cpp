@@ -29,6 +29,8 @@ hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *ou
 hipError_t launch_cbox(const AdjParams &ap, const uint32_t *axbox, int32_t L, int32_t TS, int32_t TF, uint32_t *out,
                        hipStream_t st);
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
+hipError_t launch_filter(const FiltParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
+int32_t filter_max_cols();
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 int adjoint_shape_count();
 void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF);
@@ -997,6 +999,48 @@ int backproject_impl(const pn_geometry *pg, int64_t batch, const void *sino, voi
     return PN_OK;
 }
 
+int filter_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *out, int32_t in_dt, int32_t out_dt,
+                int32_t kind, hipStream_t st)
+{
+    if (kind != PN_FILTER_RAM_LAK && kind != PN_FILTER_SHEPP_LOGAN)
+        return fail(PN_EINVAL, "filter kind %d is neither PN_FILTER_RAM_LAK nor PN_FILTER_SHEPP_LOGAN", kind);
+    Geo pre;
+    int rc = preflight(pg, batch, sino, out, in_dt, out_dt, true, pre);
+    if (rc || batch == 0) return rc;
+    if (pre.n_views == 0) return PN_OK;
+    if (!out) return fail(PN_EINVAL, "output pointer is NULL");
+    if (pre.nu > filter_max_cols())
+        return fail(PN_EINVAL, "detector rows of %d columns: the filter handles at most %d", pre.nu, filter_max_cols());
+    const double du = pg->det_spacing[1];
+    if (!(du > 0.0) || !std::isfinite(du)) return fail(PN_EINVAL, "det_spacing[1] must be positive (got %g)", du);
+    double pitch = du;  // pixel pitch at the rotation axis
+    if (!pre.parallel) {
+        if (!(pg->sid > 0.0 && pg->sdd > 0.0) || !std::isfinite(pg->sid) || !std::isfinite(pg->sdd))
+            return fail(PN_EINVAL, "divergent beams need sid > 0 and sdd > 0 for the filter (got %g, %g)", pg->sid,
+                        pg->sdd);
+        pitch = du * pg->sid / pg->sdd;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *pl;
+    if ((rc = get_plan(pg, &pl))) return rc;
+    const Geo &g = pl->g;
+    FiltParams p{};
+    p.tab = pl->d_tab;
+    p.n_views = g.n_views;
+    p.nu = g.nu;
+    p.nv = g.nv;
+    p.batch = (int32_t)batch;
+    for (int i = 0; i < 3; ++i) p.s[i] = g.s[i];
+    p.parallel = g.parallel ? 1 : 0;
+    p.kind = kind == PN_FILTER_RAM_LAK ? 0 : 1;
+    p.scale = (float)(M_PI / g.n_views / pitch);
+    p.in = sino;
+    p.out = out;
+    hipError_t e = launch_filter(p, in_dt, out_dt, st);
+    if (e != hipSuccess) return fail_hip(e, "filter launch");
+    return PN_OK;
+}
+
 // ---------------------------------------------------------- batched calls
 
 // Validates every problem (nothing is launched on a failure) and orders
@@ -1220,6 +1264,13 @@ int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void 
 {
     t_err.clear();
     return backproject_impl(pg, batch, sino, vol, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_filter(const pn_geometry *pg, int64_t batch, const void *sino, void *out, int32_t in_dtype,
+              int32_t out_dtype, int32_t kind, void *hip_stream)
+{
+    t_err.clear();
+    return filter_impl(pg, batch, sino, out, in_dtype, out_dtype, kind, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_forward_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype, void *hip_stream)

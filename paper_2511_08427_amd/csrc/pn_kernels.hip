@@ -1566,6 +1566,162 @@ __global__ __launch_bounds__(256, 8) void backproject_batch_kernel(Batch<BpParam
     backproject_block<Q, O, BZ, RCAP, CCAP>(w.p[i], blockIdx.x - w.start[i]);
 }
 
+// ------------------------------------------------------- FBP filter ------
+
+// Row filter of the filtered back-projection: per detector row, the cosine
+// weight of each pixel's ray (divergent beams: 1 / (|q3| |d|), q3 the last
+// row of the view's 3x3 matrix, d the ray from the source to the pixel,
+// q3 . d = 1) and the linear convolution with the discrete kernel g
+// (Ram-Lak: g[0] = 1/4, g[k] = -1/(pi^2 k^2) for odd k, 0 for even k;
+// Shepp-Logan: g[k] = -2 / (pi^2 (4 k^2 - 1))), times `scale`.  One wave
+// per row, the row and the kernel in LDS.  Each lane computes FR adjacent
+// outputs; per step of FR inputs it reads the inputs once (broadcast) and a
+// window of 2 FR - 1 kernel values, then does FR^2 FMAs, so the loop is
+// bound by the FMAs.
+constexpr int kFiltMaxCols = 1024;
+constexpr int kFiltR = 8;
+constexpr int kFiltGOff = kFiltMaxCols + 2 * kFiltR - 1;        // g[k] at table entry k + kFiltGOff
+constexpr int kFiltGN = 2 * kFiltGOff + 1 + kFiltR;             // table entries
+constexpr int kFiltXW = kFiltMaxCols + kFiltR;                  // row buffer (zero tail)
+
+// Table position of entry e: one spare word after every eight, so the
+// reads of a wave (lane l at 8 l + c for a common c) fall on distinct banks.
+__device__ __forceinline__ int filt_pad(int e) { return e + (e >> 3); }
+
+// One wave per detector row; lane l computes outputs n0 .. n0 + 7 with
+// n0 = 8 l (+ 512 for a second pass when the row is longer than 512).  The
+// row, cosine-weighted, sits in LDS; out[n] = scale * sum_m g[n - m] x[m]
+// in 8 x 8 register blocks that share a window of 15 kernel taps, summed in
+// the order of m.  For the Ram-Lak kernel every even tap but g[0] is zero:
+// only the 32 odd-distance pairs of a block and its 8 same-index pairs (the
+// g[0] term when the block is the lane's own, zero otherwise) are formed.
+// The sum nearly cancels (the odd taps add up to -g[0]), so g[0] x[n] is
+// added where m reaches n, not first: that keeps the partial sums of the far
+// taps small and the FP32 error about ten times lower.  Workgroups stride
+// over the rows (four per pass).
+template <typename Q, typename O, int KIND>
+__global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
+{
+    constexpr int R = kFiltR, GOFF = kFiltGOff, GN = kFiltGN, XW = kFiltXW;
+    __shared__ float gtab[GN + GN / 8 + 1];
+    __shared__ __align__(16) float xs[4][XW];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int nu = p.nu;
+    for (int e = t; e < GN; e += 256) {
+        const int k = e - GOFF, ak = k < 0 ? -k : k;
+        float g = 0.0f;
+        if (ak < nu) {
+            const double dk = static_cast<double>(ak);
+            if (KIND == 0) {
+                if (ak == 0) g = 0.25f;
+                else if (ak & 1) g = static_cast<float>(-1.0 / (M_PI * M_PI * dk * dk));
+            } else {
+                g = static_cast<float>(-2.0 / (M_PI * M_PI * (4.0 * dk * dk - 1.0)));
+            }
+        }
+        gtab[filt_pad(e)] = g;
+    }
+    const int64_t rows = static_cast<int64_t>(p.batch) * p.n_views * p.nv;
+    float *x = xs[wave];
+    for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * 4; r0 < rows; r0 += static_cast<int64_t>(gridDim.x) * 4) {
+        const int64_t row = r0 + wave;
+        const bool have = row < rows;
+        __syncthreads();  // the table is written; the previous rows are read
+        if (have) {
+            const int r = static_cast<int>(row % p.nv);
+            const int view = static_cast<int>((row / p.nv) % p.n_views);
+            const Q *src = static_cast<const Q *>(p.in) + row * nu;
+            float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, rq = 1.0f;
+            if (!p.parallel) {
+                // ray from the source to pixel (u, r) in world units: s (A (u, r, 1))
+                const ViewTab &tv = p.tab[view];
+                const double rr = static_cast<double>(r);
+                a0 = static_cast<float>(tv.A[0] * p.s[0]);
+                a1 = static_cast<float>(tv.A[3] * p.s[1]);
+                a2 = static_cast<float>(tv.A[6] * p.s[2]);
+                b0 = static_cast<float>((tv.A[1] * rr + tv.A[2]) * p.s[0]);
+                b1 = static_cast<float>((tv.A[4] * rr + tv.A[5]) * p.s[1]);
+                b2 = static_cast<float>((tv.A[7] * rr + tv.A[8]) * p.s[2]);
+                const double q0 = tv.Pi[8] / p.s[0], q1 = tv.Pi[9] / p.s[1], q2 = tv.Pi[10] / p.s[2];
+                rq = static_cast<float>(1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2));
+            }
+            for (int c = lane; c < XW; c += 64) {
+                float v = 0.0f;
+                if (c < nu) {
+                    v = to_f32(src[c]);
+                    if (!p.parallel) {
+                        const float fc = static_cast<float>(c);
+                        const float d0 = fmaf(fc, a0, b0), d1 = fmaf(fc, a1, b1), d2 = fmaf(fc, a2, b2);
+                        v *= __builtin_amdgcn_rsqf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2))) * rq;
+                    }
+                }
+                x[c] = v;
+            }
+        }
+        __syncthreads();
+        if (!have) continue;
+        O *dst = static_cast<O *>(p.out) + row * nu;
+        for (int n0 = lane * R; n0 < nu; n0 += 64 * R) {
+            float acc[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) acc[j] = 0.0f;
+            for (int m0 = 0; m0 < nu; m0 += R) {
+                const float4 xa = *reinterpret_cast<const float4 *>(x + m0);
+                const float4 xb = *reinterpret_cast<const float4 *>(x + m0 + 4);
+                const float xv[R] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+                // gv[w] = g[n0 - m0 - (R - 1) + w]; the window start is a multiple of 8
+                const int base = GOFF + n0 - m0 - (R - 1);
+                const float *gp = gtab + filt_pad(base);
+                float gv[2 * R - 1];
+#pragma unroll
+                for (int w = 0; w < 2 * R - 1; ++w)
+                    gv[w] = (KIND == 0 && (w & 1) && w != R - 1) ? 0.0f : gp[w + (w >> 3)];
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+#pragma unroll
+                    for (int j = 0; j < R; ++j)
+                        if (KIND != 0 || ((j - i) & 1) || i == j) acc[j] = fmaf(gv[j - i + R - 1], xv[i], acc[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (n0 + j < nu) dst[n0 + j] = from_f32<O>(acc[j] * p.scale);
+        }
+    }
+}
+
+template <typename Q, int KIND>
+static hipError_t filter_q(const FiltParams &p, uint32_t blocks, int32_t out_dt, hipStream_t st)
+{
+    switch (out_dt) {
+    case DT_F32: filter_kernel<Q, float, KIND><<<dim3(blocks), 256, 0, st>>>(p); break;
+    case DT_BF16: filter_kernel<Q, bf16, KIND><<<dim3(blocks), 256, 0, st>>>(p); break;
+    default: filter_kernel<Q, f16, KIND><<<dim3(blocks), 256, 0, st>>>(p); break;
+    }
+    return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t filter_k(const FiltParams &p, uint32_t blocks, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    switch (in_dt) {
+    case DT_F32: return filter_q<float, KIND>(p, blocks, out_dt, st);
+    case DT_BF16: return filter_q<bf16, KIND>(p, blocks, out_dt, st);
+    default: return filter_q<f16, KIND>(p, blocks, out_dt, st);
+    }
+}
+
+int32_t filter_max_cols() { return kFiltMaxCols; }
+
+hipError_t launch_filter(const FiltParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st)
+{
+    const int64_t rows = static_cast<int64_t>(p.batch) * p.n_views * p.nv;
+    // six workgroups fit a CU (26 KB of LDS each); the rest stride
+    const int64_t blocks = std::min<int64_t>((rows + 3) / 4, 256 * 6);
+    if (blocks == 0) return hipSuccess;
+    return p.kind == 0 ? filter_k<0>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st)
+                       : filter_k<1>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st);
+}
+
 // ------------------------------------------------------- utilities -------
 
 __global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t *__restrict__ dst, int64_t n_words)

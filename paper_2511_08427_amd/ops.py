@@ -72,6 +72,29 @@ def backproject(sino, geom: Geometry, out_dtype=None):
     return _run(N.lib.pn_backproject, "pn_backproject", geom, sino, geom.sino_shape(), geom.vol_shape, out_dtype)
 
 
+_FILTERS = {"ram-lak": 0, "shepp-logan": 1}
+
+
+def fbp_filter(sino, geom: Geometry, kind="ram-lak", out_dtype=None):
+    """Row filter of the filtered back-projection (pn_filter): cosine weights
+    (fan, cone), the discrete Ram-Lak or Shepp-Logan kernel along detector
+    rows, scaled by pi / n_views / (pixel pitch at the rotation axis)."""
+    if kind not in _FILTERS:
+        raise ValueError(f"filter kind must be one of {sorted(_FILTERS)}")
+    k = _FILTERS[kind]
+
+    def fn(g, b, x, o, dti, dto, st):
+        return N.lib.pn_filter(g, b, x, o, dti, dto, k, st)
+
+    return _run(fn, "pn_filter", geom, sino, geom.sino_shape(), geom.sino_shape(), out_dtype)
+
+
+def fbp(sino, geom: Geometry, kind="ram-lak", out_dtype=None):
+    """Filtered back-projection (FBP for parallel beams, FDK for fan and cone
+    beams on a full orbit): the back-projection of fbp_filter(sino)."""
+    return backproject(fbp_filter(sino, geom, kind, torch.float32), geom, out_dtype or sino.dtype)
+
+
 def _batched(fn, where, pairs, src_tail_of, dst_tail_of, out_dtype):
     """pairs: list of (tensor, geometry), one problem each (no batch axis)."""
     if not pairs:

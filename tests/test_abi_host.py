@@ -113,6 +113,21 @@ def test_entry_points_validate_before_device_work(pn, N):
         mis = ctypes.c_void_p(ctypes.cast(buf, vp).value + 2)
         assert fn(g, 1, mis, q, 0, 0, None) == N.PN_EINVAL
         assert fn(g, 0, None, None, 0, 0, None) == 0  # empty batch: nothing to do
+    # the row filter: kind, dtypes, pointers, then its own limits
+    f = N.lib.pn_filter
+    assert f(g, 1, p, q, 0, 0, 2, None) == N.PN_EINVAL
+    assert "kind" in N.last_error()
+    assert f(g, 1, p, q, 9, 0, 0, None) == N.PN_EDTYPE
+    assert f(g, 1, None, q, 0, 0, 1, None) == N.PN_EINVAL
+    assert f(g, 1, p, p, 0, 0, 0, None) == N.PN_EINVAL
+    assert f(g, 0, None, None, 0, 0, 0, None) == 0
+    wide = pn.parallel_geometry((8, 8), (1.0, 1.0), 1025, 1.0, 2).c_struct()
+    assert f(wide, 1, p, q, 0, 0, 0, None) == N.PN_EINVAL
+    assert "at most 1024" in N.last_error()
+    gf = pn.fan_geometry((8, 8), (1.0, 1.0), 9, 1.0, 3, 100.0, 200.0)
+    nosid = pn.Geometry(2, "fan", gf.vol_shape, gf.vol_spacing, gf.det_shape, gf.matrices, gf.det_spacing)
+    assert f(nosid.c_struct(), 1, p, q, 0, 0, 0, None) == N.PN_EINVAL
+    assert "sid > 0" in N.last_error()
     probs = (N.PnProblem * 1)()
     assert N.lib.pn_forward_batched(probs, -1, 0, 0, None) == N.PN_EINVAL
     assert N.lib.pn_forward_batched(None, 3, 0, 0, None) == N.PN_EINVAL
