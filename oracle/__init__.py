@@ -435,3 +435,84 @@ def fbp(sino, g, du_axis, kind="ram-lak", nthreads=0):
     """Filtered back-projection: the voxel-driven back-projection of
     fbp_filter(sino)."""
     return backproject(fbp_filter(sino, g, du_axis, kind), g, nthreads)
+
+
+# --------------------------------------------------- artifact simulation --
+#
+# Sinogram-domain artifacts (PYRO-NN update, Sec. 3 "Advanced Simulation
+# Tool"): additive Gaussian noise with a given mean and standard deviation,
+# and ring artifacts (chosen detector columns scaled, e.g. set to zero, over
+# a range of views).  Random numbers come from the counter-based generator
+# Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11), written out here from
+# its published definition; a standard normal pair comes from two uniforms
+# by the Box-Muller transform.  Readings where the paper is silent: element
+# i of the flat sinogram takes word i mod 4 of the Philox block at counter
+# (i div 4, 0, 0, 0) under key (seed, 0); uniforms are ((w >> 11) + 1/2)
+# 2^-53, so never 0 or 1; words (0, 1) and (2, 3) of a block form the
+# Box-Muller pairs, the first of a pair taking the cosine and the second the
+# sine.
+
+_PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)
+_PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
+_LO32 = np.uint64(0xFFFFFFFF)
+_S32 = np.uint64(32)
+
+
+def _mulhilo64(a, b):
+    """(high, low) 64-bit halves of the 128-bit products a * b (uint64)."""
+    a = np.asarray(a, np.uint64)
+    b = np.asarray(b, np.uint64)
+    a0, a1 = a & _LO32, a >> _S32
+    b0, b1 = b & _LO32, b >> _S32
+    p00, p01, p10, p11 = a0 * b0, a0 * b1, a1 * b0, a1 * b1
+    mid = (p00 >> _S32) + (p01 & _LO32) + (p10 & _LO32)
+    hi = p11 + (p01 >> _S32) + (p10 >> _S32) + (mid >> _S32)
+    return hi, a * b
+
+
+def philox4x64(counter, key, rounds=10):
+    """Philox4x64 blocks: counter is 4 uint64 arrays (broadcastable), key 2;
+    returns the 4 output words.  Each round multiplies words 0 and 2 by the
+    two round constants, swaps and xors the high halves with words 1, 3 and
+    the key; the key grows by the two Weyl constants between rounds."""
+    c = [np.asarray(x, np.uint64) for x in counter]
+    k0, k1 = (np.asarray(x, np.uint64) for x in key)
+    with np.errstate(over="ignore"):
+        for r in range(rounds):
+            if r:
+                k0 = k0 + np.uint64(_PHILOX_W[0])
+                k1 = k1 + np.uint64(_PHILOX_W[1])
+            h0, l0 = _mulhilo64(np.uint64(_PHILOX_M[0]), c[0])
+            h1, l1 = _mulhilo64(np.uint64(_PHILOX_M[1]), c[2])
+            c = [h1 ^ c[1] ^ k0, l1, h0 ^ c[3] ^ k1, l0]
+    return c
+
+
+def standard_normal_at(index, seed):
+    """The standard normal draw z_i for flat element indices i (int64)."""
+    i = np.asarray(index, dtype=np.int64).astype(np.uint64)
+    z = np.zeros(i.shape, dtype=np.uint64)
+    w = philox4x64([i >> np.uint64(2), z, z, z], [np.uint64(seed), np.uint64(0)])
+    u = [((x >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53 for x in w]
+    q = (i & np.uint64(3)).astype(np.int64)
+    pair = q >> 1
+    ua = np.where(pair == 0, u[0], u[2])
+    ub = np.where(pair == 0, u[1], u[3])
+    r = np.sqrt(-2.0 * np.log(ua))
+    return np.where(q & 1 == 0, r * np.cos(2.0 * math.pi * ub), r * np.sin(2.0 * math.pi * ub))
+
+
+def gaussian_noise(x, mean, sigma, seed):
+    """x + mean + sigma z over the flat elements of x, FP64."""
+    x = np.asarray(x, dtype=np.float64)
+    return x + mean + sigma * standard_normal_at(np.arange(x.size), seed).reshape(x.shape)
+
+
+def ring_artifacts(sino, columns, gain, v0, v1):
+    """sino[..., v, :, c] times gain for views v0 <= v < v1 and the given
+    detector columns; sino is [batch][views][rows][cols].  The product is
+    taken in FP32 (the storage precision), so the result is exact."""
+    out = np.array(sino, dtype=np.float32, copy=True)
+    cols = np.unique(np.asarray(columns, dtype=np.int64))
+    out[:, v0:v1, :, cols] = out[:, v0:v1, :, cols] * np.float32(gain)
+    return out

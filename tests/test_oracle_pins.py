@@ -516,3 +516,57 @@ def test_fdk_reconstructs_ball_central_slice(O):
     rec = O.fbp(sino, go, dd * sid / sdd)
     inside, outside = _disk_interior_exterior(rec[nz // 2 - 1:nz // 2 + 1].mean(axis=0), 0.5, R)
     assert abs(inside - 1.0) < 0.01 and outside < 0.01, (inside, outside)
+
+
+# ------------------------------------------------- artifact simulation ----
+
+
+def test_philox_matches_numpy_bit_generator(O):
+    """numpy's Philox bit generator is Philox4x64-10; it steps its counter
+    before each block, so its first four raw words are the block at
+    counter + 1.  Cases include a carry out of the low counter word."""
+    for key, ctr in [((0, 0), (0, 0, 0, 0)), ((123, 456), (7, 0, 0, 0)),
+                     ((2 ** 64 - 1, 5), (2 ** 64 - 1, 3, 0, 9)), ((0xDEADBEEF, 0), (41, 0, 0, 0))]:
+        raw = np.random.Philox(key=np.array(key, np.uint64), counter=np.array(ctr, np.uint64)).random_raw(4)
+        c0 = (ctr[0] + 1) % 2 ** 64
+        c1 = (ctr[1] + (ctr[0] + 1) // 2 ** 64) % 2 ** 64
+        out = O.philox4x64([np.uint64(c0), np.uint64(c1), np.uint64(ctr[2]), np.uint64(ctr[3])],
+                           [np.uint64(key[0]), np.uint64(key[1])])
+        assert [int(v) for v in out] == [int(v) for v in raw]
+
+
+def test_mulhilo64_matches_python_integers(O):
+    rng = np.random.default_rng(3)
+    a = rng.integers(0, 2 ** 63, 200, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    b = rng.integers(0, 2 ** 63, 200, dtype=np.uint64) * np.uint64(2)
+    hi, lo = O._mulhilo64(a, b)
+    for x, y, h, l in zip(a, b, hi, lo):
+        p = int(x) * int(y)
+        assert int(h) == p >> 64 and int(l) == p & (2 ** 64 - 1)
+
+
+def test_gaussian_noise_is_standard_normal(O):
+    """10^6 draws: Kolmogorov-Smirnov against N(0, 1), and each of the four
+    words of a block (cosine and sine halves of both pairs) separately."""
+    from scipy import stats
+
+    z = O.standard_normal_at(np.arange(1_000_000), seed=2024)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    for q in range(4):
+        assert stats.kstest(z[q::4], "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 5e-3 and abs(z.std() - 1.0) < 5e-3
+    # pairs from one block are uncorrelated, and other seeds differ
+    assert abs(np.corrcoef(z[0::4], z[1::4])[0, 1]) < 5e-3
+    assert not np.array_equal(z[:100], O.standard_normal_at(np.arange(100), seed=2025))
+    x = np.full((3, 5, 7), 2.0)
+    y = O.gaussian_noise(x, 0.5, 3.0, seed=9)
+    assert np.allclose((y - 2.5) / 3.0, O.standard_normal_at(np.arange(105), 9).reshape(3, 5, 7))
+
+
+def test_ring_artifacts_touch_only_the_chosen_columns(O):
+    rng = np.random.default_rng(1)
+    s = rng.random((2, 6, 3, 10)).astype(np.float32)
+    r = O.ring_artifacts(s, [7, 2, 7], 0.0, 1, 4)
+    changed = np.argwhere(r != s)
+    assert set(map(tuple, changed[:, [1, 3]])) == {(v, c) for v in (1, 2, 3) for c in (2, 7)}
+    assert np.all(r[:, 1:4, :, [2, 7]] == 0.0)
