@@ -247,6 +247,12 @@ def main():
     t_filt_sl, _ = timed(lambda: pn.fbp_filter(y, geom, "shepp-logan"), reps, stream)
     t_fdk, _ = timed(lambda: pn.fbp(y, geom), reps, stream)
     filt_flop = 2.0 * geom.n_views * geom.det_shape[0] * geom.det_shape[1] ** 2
+    # artifact simulation on the sinogram: Gaussian noise (read + write of
+    # every element)
+    yn = y.clone()
+    t_noise, _ = timed(lambda: pn.gaussian_noise_(yn, 0.0, 0.01, seed=1), reps, stream)
+    noise_gbs = 2 * yn.numel() * 4 / (t_noise * 1e-3) / 1e9
+    log(f"Gaussian noise on the sinogram: {t_noise:.3f} ms ({noise_gbs:.0f} GB/s)")
     log(f"FDK: Ram-Lak filter {t_filt:.3f} ms, Shepp-Logan filter {t_filt_sl:.3f} ms "
         f"({filt_flop / (t_filt_sl * 1e-3) / 1e12:.1f} TFLOP/s), filter + BP {t_fdk:.3f} ms")
 
@@ -261,6 +267,8 @@ def main():
         "fdk_filter_shepp_logan_ms": t_filt_sl,
         "fdk_filter_shepp_logan_tflops": filt_flop / (t_filt_sl * 1e-3) / 1e12,
         "fdk_ms": t_fdk,
+        "noise_ms": t_noise,
+        "noise_gbps": noise_gbs,
     }
     if not args.no_variants:
         xb = x.to(torch.bfloat16)

@@ -143,6 +143,31 @@ enum { PN_FILTER_RAM_LAK = 0, PN_FILTER_SHEPP_LOGAN = 1 };
 int pn_filter(const pn_geometry *pg, int64_t batch, const void *sino, void *out, int32_t in_dtype,
               int32_t out_dtype, int32_t kind, void *hip_stream);
 
+/* Additive Gaussian noise (Sec. 3, artifact simulation: electronic and
+ * thermal read-out noise): data[i] += mean + sigma * z_i for 0 <= i < n, in
+ * place on a device buffer of n elements of dtype.  z_i is standard normal:
+ * the counter-based generator Philox4x64-10 (Salmon et al., SC'11) under
+ * key (seed, 0) gives at counter (i / 4, 0, 0, 0) four words w0..w3;
+ * uniforms u = ((w >> 11) + 1/2) 2^-53; Box-Muller on (u0, u1) gives z for
+ * i % 4 = 0 (cosine) and 1 (sine), on (u2, u3) for 2 and 3.  The draw is
+ * formed in FP64 and added in FP32; the result is a pure function of
+ * (seed, i, input), so calls are reproducible and any slice of a buffer can
+ * be regenerated.  Errors: PN_EINVAL (n < 0, NULL or misaligned data,
+ * sigma < 0 or non-finite mean/sigma), PN_EDTYPE. */
+int pn_gaussian_noise(int64_t n, void *data, int32_t dtype, double mean, double sigma, uint64_t seed,
+                      void *hip_stream);
+
+/* Ring artifacts (Sec. 3: defective or miscalibrated detector elements):
+ * in place on sino [batch][n_views][rows][cols] (device, dtype), every row
+ * of detector columns columns[0 .. n_columns) (host array; duplicates count
+ * once; n_columns <= 256) in views v0 <= v < v1 is multiplied by gain
+ * (0 gives dead columns); the product is taken in FP32.  Errors: PN_EINVAL
+ * (shape, view range, column out of range, too many columns, NULL pointers,
+ * non-finite gain), PN_EDTYPE. */
+int pn_ring_artifacts(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, void *sino, int32_t dtype,
+                      const int32_t *columns, int32_t n_columns, double gain, int32_t v0, int32_t v1,
+                      void *hip_stream);
+
 /* The same operators over n independent problems of uneven sizes in one
  * persistent launch per operator, replayed from a captured HIP graph when the
  * same problem set (geometries and pointers) is seen again.  Each problem's

@@ -35,6 +35,8 @@ from .ops import (
     fbp_filter,
     forward,
     forward_batched,
+    gaussian_noise_,
+    ring_artifacts_,
     unrolled_gd,
 )
 

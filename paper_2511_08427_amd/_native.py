@@ -34,6 +34,8 @@ EXPORTS = (
     "pn_adjoint_batched",
     "pn_backproject_batched",
     "pn_filter",
+    "pn_gaussian_noise",
+    "pn_ring_artifacts",
     "pn_check_geometry",
     "pn_cone_matrices",
     "pn_fan_matrices",
@@ -91,6 +93,11 @@ def _load():
         f.restype = ctypes.c_int
     lib.pn_filter.argtypes = [gp, i64, vp, vp, i32, i32, i32, vp]
     lib.pn_filter.restype = ctypes.c_int
+    lib.pn_gaussian_noise.argtypes = [i64, vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, vp]
+    lib.pn_gaussian_noise.restype = ctypes.c_int
+    lib.pn_ring_artifacts.argtypes = [i64, i32, i32, i32, vp, i32, ctypes.POINTER(ctypes.c_int32), i32,
+                                      ctypes.c_double, i32, i32, vp]
+    lib.pn_ring_artifacts.restype = ctypes.c_int
     lib.pn_check_geometry.argtypes = [gp]
     lib.pn_check_geometry.restype = ctypes.c_int
     lib.pn_cone_matrices.argtypes = [i64, dp, dp, dp, dp, i64, i64, dp]

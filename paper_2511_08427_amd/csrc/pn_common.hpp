@@ -88,6 +88,25 @@ struct BpParams {
     void *vol;
 };
 
+constexpr int kRingMaxCols = 256;
+
+struct NoiseParams {
+    void *data;            // n elements, updated in place
+    int64_t n;
+    double mean, sigma;
+    uint64_t seed;         // Philox key word 0
+};
+
+struct RingParams {
+    void *data;            // [batch][n_views][rows][cols], updated in place
+    int64_t batch;
+    int32_t n_views, rows, cols;
+    int32_t v0, v1;        // views v0 <= v < v1
+    int32_t n_sel;         // distinct columns in sel
+    float gain;
+    int32_t sel[kRingMaxCols];
+};
+
 struct FiltParams {
     const ViewTab *tab;
     int32_t n_views, nu, nv, batch;

@@ -31,6 +31,8 @@ hipError_t launch_cbox(const AdjParams &ap, const uint32_t *axbox, int32_t L, in
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
 hipError_t launch_filter(const FiltParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 int32_t filter_max_cols();
+hipError_t launch_noise(const NoiseParams &p, int32_t dt, hipStream_t st);
+hipError_t launch_ring(const RingParams &p, int32_t dt, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 int adjoint_shape_count();
 void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF);
@@ -1041,6 +1043,64 @@ int filter_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *ou
     return PN_OK;
 }
 
+// ---------------------------------------------------- artifact simulation
+
+int noise_impl(int64_t n, void *data, int32_t dt, double mean, double sigma, uint64_t seed, hipStream_t st)
+{
+    int rc;
+    if (!dtype_ok(dt)) return fail(PN_EDTYPE, "unknown dtype %d", dt);
+    if (n < 0) return fail(PN_EINVAL, "element count %lld is negative", (long long)n);
+    if (!std::isfinite(mean) || !std::isfinite(sigma) || sigma < 0.0)
+        return fail(PN_EINVAL, "mean must be finite and sigma finite and >= 0 (got %g, %g)", mean, sigma);
+    if (n == 0) return PN_OK;
+    if ((rc = check_ptr(data, dt, "data"))) return rc;
+    NoiseParams p{};
+    p.data = data;
+    p.n = n;
+    p.mean = mean;
+    p.sigma = sigma;
+    p.seed = seed;
+    hipError_t e = launch_noise(p, dt, st);
+    if (e != hipSuccess) return fail_hip(e, "noise launch");
+    return PN_OK;
+}
+
+int ring_impl(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, void *sino, int32_t dt,
+              const int32_t *columns, int32_t n_columns, double gain, int32_t v0, int32_t v1, hipStream_t st)
+{
+    int rc = common_checks(batch, dt, dt);
+    if (rc) return rc;
+    if (n_views < 0 || rows <= 0 || cols <= 0)
+        return fail(PN_EINVAL, "sinogram shape views=%d rows=%d cols=%d", n_views, rows, cols);
+    if (v0 < 0 || v1 < v0 || v1 > n_views)
+        return fail(PN_EINVAL, "view range [%d, %d) outside [0, %d)", v0, v1, n_views);
+    if (n_columns < 0 || n_columns > kRingMaxCols)
+        return fail(PN_EINVAL, "%d columns: between 0 and %d may be chosen", n_columns, kRingMaxCols);
+    if (n_columns > 0 && !columns) return fail(PN_EINVAL, "column list is NULL");
+    if (!std::isfinite(gain)) return fail(PN_EINVAL, "gain must be finite (got %g)", gain);
+    std::vector<int32_t> sel(columns, columns + n_columns);
+    for (int32_t c : sel)
+        if (c < 0 || c >= cols) return fail(PN_EINVAL, "column %d outside [0, %d)", c, cols);
+    std::sort(sel.begin(), sel.end());
+    sel.erase(std::unique(sel.begin(), sel.end()), sel.end());
+    if (batch == 0 || v1 == v0 || sel.empty()) return PN_OK;
+    if ((rc = check_ptr(sino, dt, "sinogram"))) return rc;
+    RingParams p{};
+    p.data = sino;
+    p.batch = batch;
+    p.n_views = n_views;
+    p.rows = rows;
+    p.cols = cols;
+    p.v0 = v0;
+    p.v1 = v1;
+    p.n_sel = static_cast<int32_t>(sel.size());
+    p.gain = static_cast<float>(gain);
+    std::copy(sel.begin(), sel.end(), p.sel);
+    hipError_t e = launch_ring(p, dt, st);
+    if (e != hipSuccess) return fail_hip(e, "ring launch");
+    return PN_OK;
+}
+
 // ---------------------------------------------------------- batched calls
 
 // Validates every problem (nothing is launched on a failure) and orders
@@ -1271,6 +1331,22 @@ int pn_filter(const pn_geometry *pg, int64_t batch, const void *sino, void *out,
 {
     t_err.clear();
     return filter_impl(pg, batch, sino, out, in_dtype, out_dtype, kind, static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_gaussian_noise(int64_t n, void *data, int32_t dtype, double mean, double sigma, uint64_t seed,
+                      void *hip_stream)
+{
+    t_err.clear();
+    return noise_impl(n, data, dtype, mean, sigma, seed, static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_ring_artifacts(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, void *sino, int32_t dtype,
+                      const int32_t *columns, int32_t n_columns, double gain, int32_t v0, int32_t v1,
+                      void *hip_stream)
+{
+    t_err.clear();
+    return ring_impl(batch, n_views, rows, cols, sino, dtype, columns, n_columns, gain, v0, v1,
+                     static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_forward_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype, void *hip_stream)

@@ -1722,6 +1722,110 @@ hipError_t launch_filter(const FiltParams &p, int32_t in_dt, int32_t out_dt, hip
                        : filter_k<1>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st);
 }
 
+// ------------------------------------------------ artifact simulation -----
+
+// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
+// 64 x 64 -> 128-bit multiplies; the key grows by the Weyl constants
+// between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t h0 = __umul64hi(M0, c[0]), l0 = M0 * c[0];
+        const uint64_t h1 = __umul64hi(M1, c[2]), l1 = M1 * c[2];
+        const uint64_t n0 = h1 ^ c[1] ^ k0, n2 = h0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = l1;
+        c[2] = n2;
+        c[3] = l0;
+    }
+}
+
+// Additive Gaussian noise: one thread per four consecutive elements, which
+// share the Philox block at counter (i / 4, 0, 0, 0) under key (seed, 0).
+// Words (0, 1) and (2, 3) become Box-Muller pairs (uniforms
+// ((w >> 11) + 1/2) 2^-53; the first of a pair takes the cosine).  The
+// normal draws are formed in FP64, the sum in FP32.
+template <typename T>
+__global__ __launch_bounds__(256) void noise_kernel(NoiseParams p)
+{
+    const int64_t nb = (p.n + 3) / 4;
+    T *d = static_cast<T *>(p.data);
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; b < nb;
+         b += static_cast<int64_t>(gridDim.x) * 256) {
+        uint64_t c[4] = {static_cast<uint64_t>(b), 0, 0, 0};
+        philox4x64_10(c, p.seed, 0);
+        double z[4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double ua = (static_cast<double>(c[2 * h] >> 11) + 0.5) * 0x1p-53;
+            const double ub = (static_cast<double>(c[2 * h + 1] >> 11) + 0.5) * 0x1p-53;
+            const double r = sqrt(-2.0 * log(ua));
+            double sn, cs;
+            sincospi(2.0 * ub, &sn, &cs);
+            z[2 * h] = r * cs;
+            z[2 * h + 1] = r * sn;
+        }
+        const int64_t e0 = b * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (e0 + q < p.n)
+                d[e0 + q] = from_f32<T>(to_f32(d[e0 + q]) + static_cast<float>(p.mean + p.sigma * z[q]));
+    }
+}
+
+// Ring artifacts: the chosen detector columns of views v0 .. v1 - 1 scaled
+// by gain (FP32 product), one thread per touched element.
+template <typename T>
+__global__ __launch_bounds__(256) void ring_kernel(RingParams p)
+{
+    const int64_t nvs = p.v1 - p.v0;
+    const int64_t total = p.batch * nvs * p.rows * p.n_sel;
+    T *d = static_cast<T *>(p.data);
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * 256) {
+        const int j = static_cast<int>(e % p.n_sel);
+        int64_t t = e / p.n_sel;
+        const int r = static_cast<int>(t % p.rows);
+        t /= p.rows;
+        const int v = p.v0 + static_cast<int>(t % nvs);
+        const int64_t bb = t / nvs;
+        const int64_t at = ((bb * p.n_views + v) * p.rows + r) * p.cols + p.sel[j];
+        d[at] = from_f32<T>(to_f32(d[at]) * p.gain);
+    }
+}
+
+template <typename P, typename F32K, typename B16K, typename F16K>
+static hipError_t launch_elementwise(const P &p, int64_t items, int32_t dt, F32K kf, B16K kb, F16K kh, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>((items + 255) / 256, 256 * 32);
+    if (blocks <= 0) return hipSuccess;
+    const dim3 grid(static_cast<uint32_t>(blocks));
+    switch (dt) {
+    case DT_F32: kf<<<grid, 256, 0, st>>>(p); break;
+    case DT_BF16: kb<<<grid, 256, 0, st>>>(p); break;
+    default: kh<<<grid, 256, 0, st>>>(p); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_noise(const NoiseParams &p, int32_t dt, hipStream_t st)
+{
+    return launch_elementwise(p, (p.n + 3) / 4, dt, noise_kernel<float>, noise_kernel<bf16>, noise_kernel<f16>, st);
+}
+
+hipError_t launch_ring(const RingParams &p, int32_t dt, hipStream_t st)
+{
+    const int64_t items = p.batch * (p.v1 - p.v0) * p.rows * p.n_sel;
+    return launch_elementwise(p, items, dt, ring_kernel<float>, ring_kernel<bf16>, ring_kernel<f16>, st);
+}
+
 // ------------------------------------------------------- utilities -------
 
 __global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t *__restrict__ dst, int64_t n_words)

@@ -95,6 +95,35 @@ def fbp(sino, geom: Geometry, kind="ram-lak", out_dtype=None):
     return backproject(fbp_filter(sino, geom, kind, torch.float32), geom, out_dtype or sino.dtype)
 
 
+def gaussian_noise_(x, mean=0.0, sigma=1.0, seed=0):
+    """In place: x += mean + sigma * z, z standard normal from Philox4x64-10
+    (pn_gaussian_noise); a pure function of (seed, flat index, x)."""
+    if not x.is_cuda or not x.is_contiguous() or x.dtype not in _DT:
+        raise ValueError("gaussian_noise_ needs a contiguous CUDA tensor of float32, bfloat16 or float16")
+    with torch.cuda.device(x.device):
+        rc = N.lib.pn_gaussian_noise(x.numel(), ctypes.c_void_p(x.data_ptr()), _DT[x.dtype], float(mean),
+                                     float(sigma), int(seed) & (2 ** 64 - 1), _stream(x.device))
+    N.check(rc, "pn_gaussian_noise")
+    return x
+
+
+def ring_artifacts_(sino, columns, gain=0.0, views=None):
+    """In place: detector columns `columns` of sino [B,]views,rows,cols
+    scaled by gain over the view range `views` (a (start, stop) pair, default
+    all) (pn_ring_artifacts)."""
+    if not sino.is_cuda or not sino.is_contiguous() or sino.dtype not in _DT or sino.dim() not in (3, 4):
+        raise ValueError("ring_artifacts_ needs a contiguous CUDA [B,]views,rows,cols tensor")
+    s4 = sino if sino.dim() == 4 else sino.unsqueeze(0)
+    b, nv, rows, cols = s4.shape
+    v0, v1 = (0, nv) if views is None else (int(views[0]), int(views[1]))
+    col = (ctypes.c_int32 * max(len(columns), 1))(*[int(c) for c in columns])
+    with torch.cuda.device(sino.device):
+        rc = N.lib.pn_ring_artifacts(b, nv, rows, cols, ctypes.c_void_p(sino.data_ptr()), _DT[sino.dtype], col,
+                                     len(columns), float(gain), v0, v1, _stream(sino.device))
+    N.check(rc, "pn_ring_artifacts")
+    return sino
+
+
 def _batched(fn, where, pairs, src_tail_of, dst_tail_of, out_dtype):
     """pairs: list of (tensor, geometry), one problem each (no batch axis)."""
     if not pairs:

@@ -175,3 +175,21 @@ def test_no_cpu_fallback(pn):
     g = pn.parallel_geometry((8, 8), (1.0, 1.0), 11, 1.0, 4)
     with pytest.raises(ValueError, match="GPU"):
         pn.forward(torch.zeros(1, 8, 8), g)
+
+
+def test_artifact_entry_points_validate_before_device_work(N):
+    L = N.lib
+    assert L.pn_gaussian_noise(-1, None, 0, 0.0, 1.0, 0, None) == N.PN_EINVAL
+    assert L.pn_gaussian_noise(4, None, 5, 0.0, 1.0, 0, None) == N.PN_EDTYPE
+    assert L.pn_gaussian_noise(4, None, 0, 0.0, -1.0, 0, None) == N.PN_EINVAL
+    assert L.pn_gaussian_noise(4, None, 0, float("nan"), 1.0, 0, None) == N.PN_EINVAL
+    assert L.pn_gaussian_noise(0, None, 0, 0.0, 1.0, 0, None) == 0
+    assert L.pn_gaussian_noise(4, None, 0, 0.0, 1.0, 0, None) == N.PN_EINVAL
+    c = (ctypes.c_int32 * 2)(1, 40)
+    assert L.pn_ring_artifacts(1, 4, 2, 32, None, 0, c, 2, 0.0, 0, 4, None) == N.PN_EINVAL
+    assert "column 40" in N.last_error()
+    assert L.pn_ring_artifacts(1, 4, 2, 32, None, 0, c, 1, 0.0, 3, 5, None) == N.PN_EINVAL
+    assert L.pn_ring_artifacts(1, 4, 2, 32, None, 0, c, 300, 0.0, 0, 4, None) == N.PN_EINVAL
+    assert L.pn_ring_artifacts(1, 4, 2, 32, None, 0, None, 1, 0.0, 0, 4, None) == N.PN_EINVAL
+    assert L.pn_ring_artifacts(1, 4, 2, 32, None, 9, c, 1, 0.0, 0, 4, None) == N.PN_EDTYPE
+    assert L.pn_ring_artifacts(1, 4, 2, 32, None, 0, c, 1, 0.0, 2, 2, None) == 0  # empty view range

@@ -1,0 +1,113 @@
+"""GPU parity of the sinogram artifact simulation (pn_gaussian_noise,
+pn_ring_artifacts) against the FP64 oracle.
+
+Noise: the GPU adds an FP64 normal draw, rounded to FP32, to the FP32 value,
+so each element may differ from the FP64 oracle by the two roundings:
+|g - o| <= 2^-23 (|x| + |mean + sigma z|) + 2^-40 sigma.  The underlying
+Philox words are integers: any wrong bit changes a draw by far more than
+that bound, so the element bound also checks the generator bit for bit in
+practice.  Ring artifacts are bit-exact in FP32.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-artifacts] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pn():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2511_08427_amd as pn
+
+    return pn
+
+
+def _bound(x, mean, sigma, z):
+    return 2.0 ** -23 * (np.abs(x) + np.abs(mean + sigma * z)) + 2.0 ** -40 * sigma
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 1023, 100_003])
+def test_gaussian_noise_matches_oracle(pn, n):
+    _say(f"noise n={n}")
+    rng = np.random.default_rng(n)
+    x = rng.random(n).astype(np.float32)
+    g = torch.from_numpy(x).cuda()
+    pn.gaussian_noise_(g, 0.25, 1.5, seed=77)
+    got = g.cpu().numpy().astype(np.float64)
+    z = O.standard_normal_at(np.arange(n), 77)
+    ref = x.astype(np.float64) + 0.25 + 1.5 * z
+    assert np.all(np.abs(got - ref) <= _bound(x, 0.25, 1.5, z)), np.abs(got - ref).max()
+
+
+def test_gaussian_noise_properties(pn):
+    # reproducible, seed-dependent, sigma = 0 adds only the mean
+    a = torch.zeros(4096, device="cuda")
+    b = torch.zeros(4096, device="cuda")
+    pn.gaussian_noise_(a, 0.0, 1.0, seed=5)
+    pn.gaussian_noise_(b, 0.0, 1.0, seed=5)
+    assert torch.equal(a, b)
+    pn.gaussian_noise_(b, 0.0, 1.0, seed=6)
+    assert not torch.equal(a, b - a)
+    c = torch.full((10,), 2.0, device="cuda")
+    pn.gaussian_noise_(c, 0.5, 0.0, seed=1)
+    assert torch.equal(c, torch.full_like(c, 2.5))
+    pn.gaussian_noise_(torch.zeros(0, device="cuda"), 0.0, 1.0)
+    with pytest.raises(RuntimeError):
+        pn.gaussian_noise_(torch.zeros(8, device="cuda"), 0.0, -1.0)
+
+
+@pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16])
+def test_gaussian_noise_16bit_storage(pn, dt):
+    x = torch.linspace(-3, 3, 999, device="cuda").to(dt)
+    x0 = x.float().cpu().numpy().astype(np.float64)
+    pn.gaussian_noise_(x, 0.0, 0.1, seed=3)
+    ref = x0 + 0.1 * O.standard_normal_at(np.arange(999), 3)
+    eps = 2.0 ** -8 if dt == torch.bfloat16 else 2.0 ** -11
+    assert np.all(np.abs(x.float().cpu().numpy() - ref) <= eps * np.abs(ref) + 1e-6)
+
+
+def test_full_size_noise_sampled(pn):
+    """The 360 x 512 x 512 sinogram of the cone workload, in the launch shape
+    the benchmark times; 20000 sampled elements against the oracle."""
+    _say("noise on 360 x 512 x 512")
+    y = torch.rand(360, 512, 512, device="cuda")
+    x = y.cpu().numpy()
+    pn.gaussian_noise_(y, 0.0, 0.05, seed=2026)
+    got = y.cpu().numpy().ravel()
+    idx = np.random.default_rng(0).integers(0, got.size, 20000)
+    idx = np.concatenate([idx, [0, 1, 2, 3, got.size - 1]])
+    z = O.standard_normal_at(idx, 2026)
+    ref = x.ravel()[idx].astype(np.float64) + 0.05 * z
+    assert np.all(np.abs(got[idx] - ref) <= _bound(x.ravel()[idx], 0.0, 0.05, z))
+
+
+def test_ring_artifacts_match_oracle(pn):
+    rng = np.random.default_rng(11)
+    s = rng.random((2, 9, 5, 31)).astype(np.float32)
+    g = torch.from_numpy(s).cuda()
+    cols = [30, 0, 7, 7, 15]
+    pn.ring_artifacts_(g, cols, 0.37, views=(2, 7))
+    assert np.array_equal(g.cpu().numpy(), O.ring_artifacts(s, cols, 0.37, 2, 7))
+    # 3-D input, all views, dead columns
+    s3 = torch.from_numpy(s[0].copy()).cuda()
+    pn.ring_artifacts_(s3, [3], 0.0)
+    assert np.array_equal(s3.cpu().numpy(), O.ring_artifacts(s[:1], [3], 0.0, 0, 9)[0])
+    # empty view range and no columns change nothing; bad arguments raise
+    t = torch.from_numpy(s).cuda()
+    pn.ring_artifacts_(t, [1, 2], 0.0, views=(4, 4))
+    pn.ring_artifacts_(t, [], 0.0)
+    assert np.array_equal(t.cpu().numpy(), s)
+    with pytest.raises(RuntimeError):
+        pn.ring_artifacts_(t, [31], 0.0)
+    with pytest.raises(RuntimeError):
+        pn.ring_artifacts_(t, [1], 0.0, views=(5, 10))
