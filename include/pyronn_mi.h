@@ -12,7 +12,7 @@
  *                   padding, and the sum is scaled by the ray length per plane.
  *   pn_adjoint      the exact adjoint A^T of pn_forward (Sec. 2.2 pairs the
  *                   forward operator A with its adjoint A^T; it is the
- *                   analytic gradient of A, Sec. 2 and Sec. 2.3 "PyTorch
+ *                   analytic gradient of A, Sec. 2 and Sec. 2.4 "PyTorch
  *                   Integration").
  *   pn_backproject  the voxel-driven back-projection (Sec. 2.1: each voxel is
  *                   projected onto the detector and the measured values are
@@ -26,7 +26,7 @@
  * projection matrix per view for arbitrary trajectories (calibrated matrices
  * from real systems are accepted as they are).  The pn_*_matrices helpers
  * compose matrices from source/detector positions and detector directions
- * (Sec. 2.3 "Flexible Trajectory Modeling", after Graetz).
+ * (Sec. 2.4 "Flexible Trajectory Modeling", after Graetz).
  *
  * Conventions
  *   volume    C-contiguous [batch][nz][ny][nx]; voxel (i,j,k) centre at world
@@ -124,7 +124,7 @@ int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol
 int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
                    int32_t in_dtype, int32_t out_dtype, void *hip_stream);
 
-/* Row filter of the filtered back-projection (Sec. 2.4: the reconstruction
+/* Row filter of the filtered back-projection (Sec. 2.2: the reconstruction
  * is the back-projection of the sinogram filtered along detector rows by a
  * diagonal Fourier-domain filter).  out = (pi / N) (1 / a) g * (c p) along
  * every detector row, where N = n_views, a is the pixel pitch at the
@@ -143,7 +143,7 @@ enum { PN_FILTER_RAM_LAK = 0, PN_FILTER_SHEPP_LOGAN = 1 };
 int pn_filter(const pn_geometry *pg, int64_t batch, const void *sino, void *out, int32_t in_dtype,
               int32_t out_dtype, int32_t kind, void *hip_stream);
 
-/* Additive Gaussian noise (Sec. 3, artifact simulation: electronic and
+/* Additive Gaussian noise (Sec. 2.4, artifact simulation: electronic and
  * thermal read-out noise): data[i] += mean + sigma * z_i for 0 <= i < n, in
  * place on a device buffer of n elements of dtype.  z_i is standard normal:
  * the counter-based generator Philox4x64-10 (Salmon et al., SC'11) under
@@ -157,7 +157,7 @@ int pn_filter(const pn_geometry *pg, int64_t batch, const void *sino, void *out,
 int pn_gaussian_noise(int64_t n, void *data, int32_t dtype, double mean, double sigma, uint64_t seed,
                       void *hip_stream);
 
-/* Ring artifacts (Sec. 3: defective or miscalibrated detector elements):
+/* Ring artifacts (Sec. 2.4: defective or miscalibrated detector elements):
  * in place on sino [batch][n_views][rows][cols] (device, dtype), every row
  * of detector columns columns[0 .. n_columns) (host array; duplicates count
  * once; n_columns <= 256) in views v0 <= v < v1 is multiplied by gain
@@ -182,7 +182,7 @@ int pn_backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dtype,
 /* Host-only validation of a geometry (no device work): 0 or a PN_E* code. */
 int pn_check_geometry(const pn_geometry *pg);
 
-/* Projection-matrix composition (Sec. 2.3, after Graetz), host only, FP64.
+/* Projection-matrix composition (Sec. 2.4, after Graetz), host only, FP64.
  * Vectors are arrays of n_views rows, world mm.  S: source, C: detector
  * centre (the point halfway between the outermost pixel centres), eu/ev:
  * world step from one pixel centre to the next along a row / a column.

@@ -5,7 +5,7 @@ import this package.  It shares no code with the GPU library: geometry is
 composed here with numpy, and the ray loops live in ``oracle.c`` (loaded with
 ctypes).
 
-Geometry (PYRO-NN update, Sec. 2.3 "Flexible Trajectory Modeling"): a
+Geometry (PYRO-NN update, Sec. 2.4 "Flexible Trajectory Modeling"): a
 projection matrix is built from the source position, the detector position
 and the detector's two (scaled) pixel directions, after Graetz's method
 cited there.  With pixel (0, 0) at world position d00,
@@ -361,7 +361,7 @@ def ray_taps(g, view, row, col):
 
 # ------------------------------------------------------------------ FBP ----
 #
-# Filtered back-projection (PYRO-NN update, Sec. 2.4: the reconstruction is
+# Filtered back-projection (PYRO-NN update, Sec. 2.2: the reconstruction is
 # the back-projection of the sinogram filtered along detector rows by a
 # diagonal Fourier-domain filter between an FFT and its inverse).  Readings
 # where the paper is silent: the filter K is the DFT of the discrete
@@ -439,7 +439,7 @@ def fbp(sino, g, du_axis, kind="ram-lak", nthreads=0):
 
 # --------------------------------------------------- artifact simulation --
 #
-# Sinogram-domain artifacts (PYRO-NN update, Sec. 3 "Advanced Simulation
+# Sinogram-domain artifacts (PYRO-NN update, Sec. 2.4 "Advanced Simulation
 # Tool"): additive Gaussian noise with a given mean and standard deviation,
 # and ring artifacts (chosen detector columns scaled, e.g. set to zero, over
 # a range of views).  Random numbers come from the counter-based generator

@@ -1,5 +1,5 @@
 """Acquisition geometry: volume/detector description plus one projection
-matrix per view (PYRO-NN update, Listing 1 parameters and Sec. 2.3
+matrix per view (PYRO-NN update, Listing 1 parameters and Sec. 2.4
 "Flexible Trajectory Modeling").
 
 Trajectories are described by per-view vectors -- source position S (or ray

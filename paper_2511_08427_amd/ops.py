@@ -1,4 +1,4 @@
-"""PyTorch-facing operators (PYRO-NN update, Sec. 2.3 "PyTorch Integration").
+"""PyTorch-facing operators (PYRO-NN update, Sec. 2.4 "PyTorch Integration").
 
 Torch supplies device memory and the current stream; every operator is one
 call into the native library, which runs the gfx950 kernels:
