@@ -516,3 +516,30 @@ def ring_artifacts(sino, columns, gain, v0, v1):
     cols = np.unique(np.asarray(columns, dtype=np.int64))
     out[:, v0:v1, :, cols] = out[:, v0:v1, :, cols] * np.float32(gain)
     return out
+
+
+def jitter_shifts(n_rows, max_shift, seed):
+    """Detector jitter (Sec. 2.4, artifact simulation): the integer shift of
+    each detector row (flat index g over batch, view and row), uniform in
+    -max_shift .. max_shift, from word 0 of the Philox4x64-10 block at counter
+    (g, 0, 0, 0) under key (seed, 1): (w0 mod (2 max_shift + 1)) - max_shift."""
+    g = np.arange(n_rows, dtype=np.uint64)
+    z = np.zeros_like(g)
+    w = philox4x64([g, z, z, z], [np.uint64(seed), np.uint64(1)])
+    return (w[0] % np.uint64(2 * max_shift + 1)).astype(np.int64) - max_shift
+
+
+def detector_jitter(sino, max_shift, seed):
+    """Each detector row of sino [..., rows, cols] moved by its shift s along
+    the columns: out[c] = in[c - s], zero where c - s leaves the row."""
+    a = np.asarray(sino)
+    cols = a.shape[-1]
+    flat = a.reshape(-1, cols)
+    s = jitter_shifts(flat.shape[0], max_shift, seed)
+    out = np.zeros_like(flat)
+    for g in range(flat.shape[0]):
+        for c in range(cols):
+            src = c - s[g]
+            if 0 <= src < cols:
+                out[g, c] = flat[g, src]
+    return out.reshape(a.shape)

@@ -570,3 +570,25 @@ def test_ring_artifacts_touch_only_the_chosen_columns(O):
     changed = np.argwhere(r != s)
     assert set(map(tuple, changed[:, [1, 3]])) == {(v, c) for v in (1, 2, 3) for c in (2, 7)}
     assert np.all(r[:, 1:4, :, [2, 7]] == 0.0)
+
+
+def test_detector_jitter_shifts_rows(O):
+    """Shifts are uniform over -m .. m (chi-square on 60000 rows) and each
+    row equals np.roll of the input with the wrapped part zeroed."""
+    from scipy import stats
+
+    s = O.jitter_shifts(60000, 3, seed=8)
+    counts = np.bincount(s + 3, minlength=7)
+    assert s.min() == -3 and s.max() == 3
+    assert stats.chisquare(counts).pvalue > 1e-3
+    x = np.random.default_rng(2).random((2, 3, 4, 9))
+    y = O.detector_jitter(x, 2, seed=4)
+    sh = O.jitter_shifts(24, 2, seed=4)
+    for g, row in enumerate(x.reshape(-1, 9)):
+        ref = np.roll(row, sh[g])
+        if sh[g] > 0:
+            ref[:sh[g]] = 0.0
+        elif sh[g] < 0:
+            ref[sh[g]:] = 0.0
+        assert np.array_equal(y.reshape(-1, 9)[g], ref)
+    assert np.array_equal(O.detector_jitter(x, 0, seed=4), x)
