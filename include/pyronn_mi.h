@@ -157,6 +157,18 @@ int pn_filter(const pn_geometry *pg, int64_t batch, const void *sino, void *out,
 int pn_gaussian_noise(int64_t n, void *data, int32_t dtype, double mean, double sigma, uint64_t seed,
                       void *hip_stream);
 
+/* Detector jitter (Sec. 2.4, artifact simulation: random pixel shifts of
+ * detector rows): out row g = in row g moved by an integer shift s_g along
+ * the columns, out[c] = in[c - s_g], 0 where c - s_g leaves the row.
+ * in and out: [n_rows][cols] device buffers of dtype that do not overlap
+ * (n_rows = batch x views x detector rows).  s_g is uniform in
+ * -max_shift .. max_shift: word w0 of the Philox4x64-10 block at counter
+ * (g, 0, 0, 0) under key (seed, 1), s_g = (w0 mod (2 max_shift + 1)) -
+ * max_shift.  Errors: PN_EINVAL (shape, 0 <= max_shift <= 2^20, NULL,
+ * misaligned or overlapping buffers), PN_EDTYPE. */
+int pn_detector_jitter(int64_t n_rows, int32_t cols, const void *in, void *out, int32_t dtype, int32_t max_shift,
+                       uint64_t seed, void *hip_stream);
+
 /* Ring artifacts (Sec. 2.4: defective or miscalibrated detector elements):
  * in place on sino [batch][n_views][rows][cols] (device, dtype), every row
  * of detector columns columns[0 .. n_columns) (host array; duplicates count

@@ -31,6 +31,7 @@ from .ops import (
     adjoint_batched,
     backproject,
     backproject_batched,
+    detector_jitter,
     fbp,
     fbp_filter,
     forward,

@@ -107,6 +107,15 @@ struct RingParams {
     int32_t sel[kRingMaxCols];
 };
 
+struct JitterParams {
+    const void *in;        // [n_rows][cols]
+    void *out;             // same shape, distinct buffer
+    int64_t n_rows;
+    int32_t cols;
+    int32_t max_shift;
+    uint64_t seed;         // Philox key word 0 (word 1 is 1)
+};
+
 struct FiltParams {
     const ViewTab *tab;
     int32_t n_views, nu, nv, batch;

@@ -33,6 +33,7 @@ hipError_t launch_filter(const FiltParams &p, int32_t in_dt, int32_t out_dt, hip
 int32_t filter_max_cols();
 hipError_t launch_noise(const NoiseParams &p, int32_t dt, hipStream_t st);
 hipError_t launch_ring(const RingParams &p, int32_t dt, hipStream_t st);
+hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 int adjoint_shape_count();
 void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF);
@@ -1101,6 +1102,31 @@ int ring_impl(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, void *
     return PN_OK;
 }
 
+int jitter_impl(int64_t n_rows, int32_t cols, const void *in, void *out, int32_t dt, int32_t max_shift,
+                uint64_t seed, hipStream_t st)
+{
+    int rc;
+    if (!dtype_ok(dt)) return fail(PN_EDTYPE, "unknown dtype %d", dt);
+    if (n_rows < 0 || cols <= 0) return fail(PN_EINVAL, "shape rows=%lld cols=%d", (long long)n_rows, cols);
+    if (max_shift < 0 || max_shift > 1 << 20) return fail(PN_EINVAL, "max_shift %d outside 0 .. 2^20", max_shift);
+    if (n_rows > INT64_MAX / cols) return fail(PN_EINVAL, "rows x cols overflows");
+    if (n_rows == 0) return PN_OK;
+    if ((rc = check_ptr(in, dt, "input")) || (rc = check_ptr(out, dt, "output"))) return rc;
+    const size_t bytes = (size_t)(n_rows * cols) * esize(dt);
+    const char *a = static_cast<const char *>(in), *b = static_cast<const char *>(out);
+    if (a < b + bytes && b < a + bytes) return fail(PN_EINVAL, "input and output overlap");
+    JitterParams p{};
+    p.in = in;
+    p.out = out;
+    p.n_rows = n_rows;
+    p.cols = cols;
+    p.max_shift = max_shift;
+    p.seed = seed;
+    hipError_t e = launch_jitter(p, dt, st);
+    if (e != hipSuccess) return fail_hip(e, "jitter launch");
+    return PN_OK;
+}
+
 // ---------------------------------------------------------- batched calls
 
 // Validates every problem (nothing is launched on a failure) and orders
@@ -1338,6 +1364,13 @@ int pn_gaussian_noise(int64_t n, void *data, int32_t dtype, double mean, double 
 {
     t_err.clear();
     return noise_impl(n, data, dtype, mean, sigma, seed, static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_detector_jitter(int64_t n_rows, int32_t cols, const void *in, void *out, int32_t dtype, int32_t max_shift,
+                       uint64_t seed, void *hip_stream)
+{
+    t_err.clear();
+    return jitter_impl(n_rows, cols, in, out, dtype, max_shift, seed, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_ring_artifacts(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, void *sino, int32_t dtype,

@@ -1801,6 +1801,31 @@ __global__ __launch_bounds__(256) void ring_kernel(RingParams p)
     }
 }
 
+// Detector jitter: every detector row moved by its own integer shift s in
+// -m .. m along the columns (zero where the source leaves the row).  s is
+// word 0 of the Philox block at counter (row, 0, 0, 0) under key (seed, 1),
+// reduced mod 2m + 1; each thread recomputes it for its row.
+template <typename T>
+__global__ __launch_bounds__(256) void jitter_kernel(JitterParams p)
+{
+    const int64_t total = p.n_rows * p.cols;
+    const T *src = static_cast<const T *>(p.in);
+    T *dst = static_cast<T *>(p.out);
+    const uint64_t span = static_cast<uint64_t>(2 * p.max_shift + 1);
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * 256) {
+        const int64_t g = e / p.cols;
+        const int c = static_cast<int>(e - g * p.cols);
+        uint64_t w[4] = {static_cast<uint64_t>(g), 0, 0, 0};
+        philox4x64_10(w, p.seed, 1);
+        const int s = static_cast<int>(w[0] % span) - p.max_shift;
+        const int from = c - s;
+        dst[e] = (from >= 0 && from < p.cols) ? src[g * p.cols + from] : from_f32<T>(0.0f);
+    }
+}
+
+hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st);
+
 template <typename P, typename F32K, typename B16K, typename F16K>
 static hipError_t launch_elementwise(const P &p, int64_t items, int32_t dt, F32K kf, B16K kb, F16K kh, hipStream_t st)
 {
@@ -1818,6 +1843,12 @@ static hipError_t launch_elementwise(const P &p, int64_t items, int32_t dt, F32K
 hipError_t launch_noise(const NoiseParams &p, int32_t dt, hipStream_t st)
 {
     return launch_elementwise(p, (p.n + 3) / 4, dt, noise_kernel<float>, noise_kernel<bf16>, noise_kernel<f16>, st);
+}
+
+hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st)
+{
+    return launch_elementwise(p, p.n_rows * p.cols, dt, jitter_kernel<float>, jitter_kernel<bf16>,
+                              jitter_kernel<f16>, st);
 }
 
 hipError_t launch_ring(const RingParams &p, int32_t dt, hipStream_t st)

@@ -107,6 +107,21 @@ def gaussian_noise_(x, mean=0.0, sigma=1.0, seed=0):
     return x
 
 
+def detector_jitter(sino, max_shift=1, seed=0):
+    """A copy of sino with every detector row moved by its own random integer
+    shift in -max_shift .. max_shift along the columns (pn_detector_jitter)."""
+    if not sino.is_cuda or not sino.is_contiguous() or sino.dtype not in _DT or sino.dim() < 1:
+        raise ValueError("detector_jitter needs a contiguous CUDA tensor of float32, bfloat16 or float16")
+    out = torch.empty_like(sino)
+    cols = sino.shape[-1]
+    with torch.cuda.device(sino.device):
+        rc = N.lib.pn_detector_jitter(sino.numel() // max(cols, 1), cols, ctypes.c_void_p(sino.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _DT[sino.dtype], int(max_shift),
+                                      int(seed) & (2 ** 64 - 1), _stream(sino.device))
+    N.check(rc, "pn_detector_jitter")
+    return out
+
+
 def ring_artifacts_(sino, columns, gain=0.0, views=None):
     """In place: detector columns `columns` of sino [B,]views,rows,cols
     scaled by gain over the view range `views` (a (start, stop) pair, default

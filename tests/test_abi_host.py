@@ -193,3 +193,17 @@ def test_artifact_entry_points_validate_before_device_work(N):
     assert L.pn_ring_artifacts(1, 4, 2, 32, None, 0, None, 1, 0.0, 0, 4, None) == N.PN_EINVAL
     assert L.pn_ring_artifacts(1, 4, 2, 32, None, 9, c, 1, 0.0, 0, 4, None) == N.PN_EDTYPE
     assert L.pn_ring_artifacts(1, 4, 2, 32, None, 0, c, 1, 0.0, 2, 2, None) == 0  # empty view range
+
+
+def test_jitter_entry_point_validates(N):
+    L = N.lib
+    buf = ctypes.create_string_buffer(256)
+    a = ctypes.cast(buf, ctypes.c_void_p)
+    b = ctypes.c_void_p(a.value + 64)
+    assert L.pn_detector_jitter(2, 8, a, a, 0, 1, 0, None) == N.PN_EINVAL  # overlap
+    assert "overlap" in N.last_error()
+    assert L.pn_detector_jitter(2, 8, a, b, 0, -1, 0, None) == N.PN_EINVAL
+    assert L.pn_detector_jitter(2, 0, a, b, 0, 1, 0, None) == N.PN_EINVAL
+    assert L.pn_detector_jitter(2, 8, a, b, 7, 1, 0, None) == N.PN_EDTYPE
+    assert L.pn_detector_jitter(2, 8, None, b, 0, 1, 0, None) == N.PN_EINVAL
+    assert L.pn_detector_jitter(0, 8, None, None, 0, 1, 0, None) == 0

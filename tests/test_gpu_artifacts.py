@@ -111,3 +111,25 @@ def test_ring_artifacts_match_oracle(pn):
         pn.ring_artifacts_(t, [31], 0.0)
     with pytest.raises(RuntimeError):
         pn.ring_artifacts_(t, [1], 0.0, views=(5, 10))
+
+
+@pytest.mark.parametrize("shape,m", [((2, 5, 3, 37), 3), ((7, 1, 200), 0), ((4, 6, 1), 2), ((3, 2, 64), 70)])
+def test_detector_jitter_matches_oracle(pn, shape, m):
+    _say(f"jitter {shape} m={m}")
+    x = np.random.default_rng(len(shape)).random(shape).astype(np.float32)
+    y = pn.detector_jitter(torch.from_numpy(x).cuda(), m, seed=31)
+    assert np.array_equal(y.cpu().numpy(), O.detector_jitter(x, m, 31))
+
+
+def test_detector_jitter_full_size_sampled(pn):
+    """The 360 x 512 x 512 sinogram: the shift of 3000 sampled rows, read
+    off the output of a column ramp, equals the oracle's."""
+    cols = torch.arange(1, 513, device="cuda", dtype=torch.float32)
+    y = cols.expand(360 * 512, 512).contiguous()
+    out = pn.detector_jitter(y, 4, seed=99).cpu().numpy()
+    rows = np.random.default_rng(1).integers(0, 360 * 512, 3000)
+    s = O.jitter_shifts(360 * 512, 4, 99)[rows]
+    # column 256 reads column 256 - s, whose value is 257 - s
+    assert np.array_equal(out[rows, 256], 257.0 - s)
+    with pytest.raises(RuntimeError):
+        pn.detector_jitter(y, -1)
