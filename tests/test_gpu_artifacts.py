@@ -133,3 +133,45 @@ def test_detector_jitter_full_size_sampled(pn):
     assert np.array_equal(out[rows, 256], 257.0 - s)
     with pytest.raises(RuntimeError):
         pn.detector_jitter(y, -1)
+
+
+def test_graph_capture_filter_and_artifacts(pn):
+    """pn_filter, pn_gaussian_noise, pn_ring_artifacts and pn_detector_jitter
+    enqueue kernels only, so they can be captured; every replay (with eager
+    work on the same geometry plan between replays) equals the eager result."""
+    import math
+
+    _say("graph capture: filter, noise, ring, jitter")
+    g = pn.cone_geometry((20, 24, 22), (0.8, 0.8, 0.8), (26, 30), (1.2, 1.2), 16, 400.0, 650.0)
+    y0 = torch.rand(g.sino_shape(), device="cuda")
+
+    def work(y):
+        q = pn.fbp_filter(y, g, "shepp-logan")
+        r = pn.backproject(q, g)
+        yn = y.clone()
+        pn.gaussian_noise_(yn, 0.1, 0.5, seed=12)
+        pn.ring_artifacts_(yn, [3, 17], 0.5, views=(2, 9))
+        j = pn.detector_jitter(yn, 2, seed=5)
+        return q, r, yn, j
+
+    ref = work(y0)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up on the capture stream
+        work(y0)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out = work(y0)
+    for rep in range(3):
+        pn.fbp(2.0 * y0, g)
+        torch.cuda.synchronize()
+        for o in out:
+            o.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        for name, o, r in zip(("filter", "fbp", "noise+ring", "jitter"), out, ref):
+            assert torch.equal(o, r), f"replay {rep}: {name}"
+    assert math.isfinite(float(out[1].abs().sum()))
