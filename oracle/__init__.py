@@ -543,3 +543,36 @@ def detector_jitter(sino, max_shift, seed):
             if 0 <= src < cols:
                 out[g, c] = flat[g, src]
     return out.reshape(a.shape)
+
+
+def gantry_blur(sino, angle_start, angle_step, taps):
+    """Gantry motion blur (Sec. 2.4, artifact simulation): each projection
+    convolved with a line kernel turned to its acquisition angle.  Reading:
+    view k has angle a_k = angle_start + k angle_step; the kernel is the mean
+    of `taps` (odd) samples at unit spacing t = -h .. h, h = (taps - 1) / 2,
+    along (cos a_k, sin a_k) in detector (column, row) pixel units; samples
+    are bilinear with zeros outside the detector.  sino is
+    [batch][views][rows][cols]; FP64."""
+    a = np.asarray(sino, dtype=np.float64)
+    nb, nv, nr, nc = a.shape
+    h = (taps - 1) // 2
+    rr, cc = np.meshgrid(np.arange(nr, dtype=np.float64), np.arange(nc, dtype=np.float64), indexing="ij")
+    pad = np.zeros((nb, nv, nr + 2, nc + 2))
+    pad[:, :, 1:-1, 1:-1] = a                      # pixel (r, c) at pad[r + 1, c + 1]
+    out = np.zeros_like(a)
+    for k in range(nv):
+        ang = angle_start + k * angle_step
+        du, dv = math.cos(ang), math.sin(ang)
+        for t in range(-h, h + 1):
+            x, y = cc + t * du, rr + t * dv
+            x0, y0 = np.floor(x), np.floor(y)
+            fx, fy = x - x0, y - y0
+            acc = np.zeros((nb, nr, nc))
+            for oy, wy in ((0, 1.0 - fy), (1, fy)):
+                for ox, wx in ((0, 1.0 - fx), (1, fx)):
+                    yi, xi = (y0 + oy).astype(np.int64), (x0 + ox).astype(np.int64)
+                    inside = (yi >= 0) & (yi < nr) & (xi >= 0) & (xi < nc)
+                    v = pad[:, k, np.clip(yi, -1, nr) + 1, np.clip(xi, -1, nc) + 1] * inside
+                    acc += wy * wx * v
+            out[:, k] += acc
+    return out / taps

@@ -592,3 +592,23 @@ def test_detector_jitter_shifts_rows(O):
             ref[sh[g]:] = 0.0
         assert np.array_equal(y.reshape(-1, 9)[g], ref)
     assert np.array_equal(O.detector_jitter(x, 0, seed=4), x)
+
+
+def test_gantry_blur_matches_map_coordinates(O):
+    """Each tap equals scipy's order-1 map_coordinates with zero padding
+    (grid-constant); one tap is the identity; a view at angle 0 blurs along
+    the columns only, so a constant row stays constant away from its ends."""
+    rng = np.random.default_rng(4)
+    s = rng.random((2, 3, 7, 9))
+    got = O.gantry_blur(s, 0.3, 0.9, 5)
+    rr, cc = np.meshgrid(np.arange(7.0), np.arange(9.0), indexing="ij")
+    for b in range(2):
+        for k in range(3):
+            a = 0.3 + 0.9 * k
+            ref = sum(map_coordinates(s[b, k], [rr + t * math.sin(a), cc + t * math.cos(a)], order=1,
+                                      mode="grid-constant", cval=0.0) for t in range(-2, 3)) / 5
+            assert np.abs(got[b, k] - ref).max() < 1e-12
+    assert np.abs(O.gantry_blur(s, 0.3, 0.9, 1) - s).max() < 1e-15
+    flat = np.ones((1, 1, 4, 12))
+    g0 = O.gantry_blur(flat, 0.0, 0.0, 3)
+    assert np.abs(g0[..., 1:-1] - 1.0).max() < 1e-15 and np.abs(g0[..., 0] - 2.0 / 3.0).max() < 1e-15
