@@ -169,6 +169,17 @@ int pn_gaussian_noise(int64_t n, void *data, int32_t dtype, double mean, double 
 int pn_detector_jitter(int64_t n_rows, int32_t cols, const void *in, void *out, int32_t dtype, int32_t max_shift,
                        uint64_t seed, void *hip_stream);
 
+/* Gantry motion blur (Sec. 2.4, artifact simulation: a kernel turned to
+ * each projection's acquisition angle): out = in convolved, per view k, with
+ * a line kernel at angle a_k = angle_start + k angle_step: the mean of
+ * `taps` (odd, 1 .. 255) samples at unit spacing t = -h .. h along
+ * (cos a_k, sin a_k) in (column, row) pixel units, bilinear, zeros outside
+ * the detector.  in and out: [batch][n_views][rows][cols] device buffers of
+ * dtype that do not overlap.  Errors: PN_EINVAL (shape, taps, non-finite
+ * angles, NULL, misaligned or overlapping buffers), PN_EDTYPE. */
+int pn_gantry_blur(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, const void *in, void *out,
+                   int32_t dtype, double angle_start, double angle_step, int32_t taps, void *hip_stream);
+
 /* Ring artifacts (Sec. 2.4: defective or miscalibrated detector elements):
  * in place on sino [batch][n_views][rows][cols] (device, dtype), every row
  * of detector columns columns[0 .. n_columns) (host array; duplicates count

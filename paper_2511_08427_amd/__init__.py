@@ -36,6 +36,7 @@ from .ops import (
     fbp_filter,
     forward,
     forward_batched,
+    gantry_blur,
     gaussian_noise_,
     ring_artifacts_,
     unrolled_gd,

@@ -36,6 +36,7 @@ EXPORTS = (
     "pn_filter",
     "pn_gaussian_noise",
     "pn_detector_jitter",
+    "pn_gantry_blur",
     "pn_ring_artifacts",
     "pn_check_geometry",
     "pn_cone_matrices",
@@ -98,6 +99,8 @@ def _load():
     lib.pn_gaussian_noise.restype = ctypes.c_int
     lib.pn_detector_jitter.argtypes = [i64, i32, vp, vp, i32, i32, ctypes.c_uint64, vp]
     lib.pn_detector_jitter.restype = ctypes.c_int
+    lib.pn_gantry_blur.argtypes = [i64, i32, i32, i32, vp, vp, i32, ctypes.c_double, ctypes.c_double, i32, vp]
+    lib.pn_gantry_blur.restype = ctypes.c_int
     lib.pn_ring_artifacts.argtypes = [i64, i32, i32, i32, vp, i32, ctypes.POINTER(ctypes.c_int32), i32,
                                       ctypes.c_double, i32, i32, vp]
     lib.pn_ring_artifacts.restype = ctypes.c_int

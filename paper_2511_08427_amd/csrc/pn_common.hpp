@@ -116,6 +116,15 @@ struct JitterParams {
     uint64_t seed;         // Philox key word 0 (word 1 is 1)
 };
 
+struct BlurParams {
+    const void *in;        // [batch][n_views][rows][cols]
+    void *out;             // same shape, distinct buffer
+    int64_t batch;
+    int32_t n_views, rows, cols;
+    int32_t taps;          // odd
+    double angle_start, angle_step;
+};
+
 struct FiltParams {
     const ViewTab *tab;
     int32_t n_views, nu, nv, batch;

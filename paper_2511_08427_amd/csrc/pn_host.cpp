@@ -34,6 +34,7 @@ int32_t filter_max_cols();
 hipError_t launch_noise(const NoiseParams &p, int32_t dt, hipStream_t st);
 hipError_t launch_ring(const RingParams &p, int32_t dt, hipStream_t st);
 hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st);
+hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
 int adjoint_shape_count();
 void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF);
@@ -1127,6 +1128,36 @@ int jitter_impl(int64_t n_rows, int32_t cols, const void *in, void *out, int32_t
     return PN_OK;
 }
 
+int blur_impl(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, const void *in, void *out, int32_t dt,
+              double angle_start, double angle_step, int32_t taps, hipStream_t st)
+{
+    int rc = common_checks(batch, dt, dt);
+    if (rc) return rc;
+    if (n_views < 0 || rows <= 0 || cols <= 0)
+        return fail(PN_EINVAL, "sinogram shape views=%d rows=%d cols=%d", n_views, rows, cols);
+    if (taps < 1 || taps > 255 || taps % 2 == 0) return fail(PN_EINVAL, "taps = %d: odd, 1 .. 255", taps);
+    if (!std::isfinite(angle_start) || !std::isfinite(angle_step))
+        return fail(PN_EINVAL, "angles must be finite (got %g, %g)", angle_start, angle_step);
+    if (batch == 0 || n_views == 0) return PN_OK;
+    if ((rc = check_ptr(in, dt, "input")) || (rc = check_ptr(out, dt, "output"))) return rc;
+    const size_t bytes = (size_t)(batch * n_views) * rows * cols * esize(dt);
+    const char *a = static_cast<const char *>(in), *b = static_cast<const char *>(out);
+    if (a < b + bytes && b < a + bytes) return fail(PN_EINVAL, "input and output overlap");
+    BlurParams p{};
+    p.in = in;
+    p.out = out;
+    p.batch = batch;
+    p.n_views = n_views;
+    p.rows = rows;
+    p.cols = cols;
+    p.taps = taps;
+    p.angle_start = angle_start;
+    p.angle_step = angle_step;
+    hipError_t e = launch_blur(p, dt, st);
+    if (e != hipSuccess) return fail_hip(e, "gantry blur launch");
+    return PN_OK;
+}
+
 // ---------------------------------------------------------- batched calls
 
 // Validates every problem (nothing is launched on a failure) and orders
@@ -1364,6 +1395,14 @@ int pn_gaussian_noise(int64_t n, void *data, int32_t dtype, double mean, double 
 {
     t_err.clear();
     return noise_impl(n, data, dtype, mean, sigma, seed, static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_gantry_blur(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, const void *in, void *out,
+                   int32_t dtype, double angle_start, double angle_step, int32_t taps, void *hip_stream)
+{
+    t_err.clear();
+    return blur_impl(batch, n_views, rows, cols, in, out, dtype, angle_start, angle_step, taps,
+                     static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_detector_jitter(int64_t n_rows, int32_t cols, const void *in, void *out, int32_t dtype, int32_t max_shift,

@@ -1826,6 +1826,55 @@ __global__ __launch_bounds__(256) void jitter_kernel(JitterParams p)
 
 hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st);
 
+// Gantry motion blur: every output pixel is the mean of `taps` bilinear
+// samples at unit spacing along the view's acquisition direction
+// (cos a, sin a) in (column, row) pixel units, zeros outside the detector.
+template <typename T>
+__global__ __launch_bounds__(256) void blur_kernel(BlurParams p)
+{
+    const int64_t total = p.batch * p.n_views * p.rows * p.cols;
+    const T *src = static_cast<const T *>(p.in);
+    T *dst = static_cast<T *>(p.out);
+    const int h = (p.taps - 1) / 2;
+    const float inv = 1.0f / static_cast<float>(p.taps);
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * 256) {
+        const int c = static_cast<int>(e % p.cols);
+        const int64_t rowi = e / p.cols;
+        const int r = static_cast<int>(rowi % p.rows);
+        const int64_t img = rowi / p.rows;
+        const int v = static_cast<int>(img % p.n_views);
+        double sd, cd;
+        sincos(p.angle_start + v * p.angle_step, &sd, &cd);
+        const float du = static_cast<float>(cd), dv = static_cast<float>(sd);
+        const T *im = src + img * p.rows * p.cols;
+        float acc = 0.0f;
+        for (int t = -h; t <= h; ++t) {
+            // offsets from the pixel, split into whole and fractional parts
+            // before the pixel index is added, so the fractions keep full
+            // FP32 precision whatever the detector size
+            const float tu = static_cast<float>(t) * du, tv = static_cast<float>(t) * dv;
+            const float iu = floorf(tu), iv = floorf(tv);
+            const float fx = tu - iu, fy = tv - iv;
+            const int x0 = c + static_cast<int>(iu), y0 = r + static_cast<int>(iv);
+            float s = 0.0f;
+#pragma unroll
+            for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+                for (int ox = 0; ox < 2; ++ox) {
+                    const int xi = x0 + ox, yi = y0 + oy;
+                    const float w = (oy ? fy : 1.0f - fy) * (ox ? fx : 1.0f - fx);
+                    if (xi >= 0 && xi < p.cols && yi >= 0 && yi < p.rows)
+                        s = fmaf(w, to_f32(im[static_cast<int64_t>(yi) * p.cols + xi]), s);
+                }
+            acc += s;
+        }
+        dst[e] = from_f32<T>(acc * inv);
+    }
+}
+
+hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st);
+
 template <typename P, typename F32K, typename B16K, typename F16K>
 static hipError_t launch_elementwise(const P &p, int64_t items, int32_t dt, F32K kf, B16K kb, F16K kh, hipStream_t st)
 {
@@ -1849,6 +1898,12 @@ hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st)
 {
     return launch_elementwise(p, p.n_rows * p.cols, dt, jitter_kernel<float>, jitter_kernel<bf16>,
                               jitter_kernel<f16>, st);
+}
+
+hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st)
+{
+    return launch_elementwise(p, p.batch * p.n_views * p.rows * p.cols, dt, blur_kernel<float>, blur_kernel<bf16>,
+                              blur_kernel<f16>, st);
 }
 
 hipError_t launch_ring(const RingParams &p, int32_t dt, hipStream_t st)

@@ -122,6 +122,23 @@ def detector_jitter(sino, max_shift=1, seed=0):
     return out
 
 
+def gantry_blur(sino, angle_start, angle_step, taps=3):
+    """A copy of sino [B,]views,rows,cols with each projection blurred by a
+    `taps`-sample line kernel turned to its acquisition angle
+    angle_start + k angle_step (pn_gantry_blur)."""
+    if not sino.is_cuda or not sino.is_contiguous() or sino.dtype not in _DT or sino.dim() not in (3, 4):
+        raise ValueError("gantry_blur needs a contiguous CUDA [B,]views,rows,cols tensor")
+    s4 = sino if sino.dim() == 4 else sino.unsqueeze(0)
+    b, nv, rows, cols = s4.shape
+    out = torch.empty_like(sino)
+    with torch.cuda.device(sino.device):
+        rc = N.lib.pn_gantry_blur(b, nv, rows, cols, ctypes.c_void_p(sino.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  _DT[sino.dtype], float(angle_start), float(angle_step), int(taps),
+                                  _stream(sino.device))
+    N.check(rc, "pn_gantry_blur")
+    return out
+
+
 def ring_artifacts_(sino, columns, gain=0.0, views=None):
     """In place: detector columns `columns` of sino [B,]views,rows,cols
     scaled by gain over the view range `views` (a (start, stop) pair, default

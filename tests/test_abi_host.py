@@ -207,3 +207,17 @@ def test_jitter_entry_point_validates(N):
     assert L.pn_detector_jitter(2, 8, a, b, 7, 1, 0, None) == N.PN_EDTYPE
     assert L.pn_detector_jitter(2, 8, None, b, 0, 1, 0, None) == N.PN_EINVAL
     assert L.pn_detector_jitter(0, 8, None, None, 0, 1, 0, None) == 0
+
+
+def test_gantry_blur_entry_point_validates(N):
+    L = N.lib
+    buf = ctypes.create_string_buffer(1024)
+    a = ctypes.cast(buf, ctypes.c_void_p)
+    b = ctypes.c_void_p(a.value + 512)
+    assert L.pn_gantry_blur(1, 2, 4, 8, a, b, 0, 0.0, 0.1, 4, None) == N.PN_EINVAL  # even taps
+    assert L.pn_gantry_blur(1, 2, 4, 8, a, b, 0, 0.0, 0.1, 257, None) == N.PN_EINVAL
+    assert L.pn_gantry_blur(1, 2, 4, 8, a, a, 0, 0.0, 0.1, 3, None) == N.PN_EINVAL  # overlap
+    assert L.pn_gantry_blur(1, 2, 4, 8, a, b, 0, float("inf"), 0.1, 3, None) == N.PN_EINVAL
+    assert L.pn_gantry_blur(1, 2, 0, 8, a, b, 0, 0.0, 0.1, 3, None) == N.PN_EINVAL
+    assert L.pn_gantry_blur(1, 2, 4, 8, a, b, 3, 0.0, 0.1, 3, None) == N.PN_EDTYPE
+    assert L.pn_gantry_blur(0, 2, 4, 8, None, None, 0, 0.0, 0.1, 3, None) == 0

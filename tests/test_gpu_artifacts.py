@@ -8,6 +8,7 @@ Philox words are integers: any wrong bit changes a draw by far more than
 that bound, so the element bound also checks the generator bit for bit in
 practice.  Ring artifacts are bit-exact in FP32.
 """
+import math
 import sys
 
 import numpy as np
@@ -175,3 +176,29 @@ def test_graph_capture_filter_and_artifacts(pn):
         for name, o, r in zip(("filter", "fbp", "noise+ring", "jitter"), out, ref):
             assert torch.equal(o, r), f"replay {rep}: {name}"
     assert math.isfinite(float(out[1].abs().sum()))
+
+
+@pytest.mark.parametrize("shape,taps,a0,da", [((2, 6, 9, 13), 5, 0.2, 0.7), ((1, 4, 1, 50), 7, 0.0, math.pi / 2),
+                                              ((1, 3, 5, 5), 1, 1.0, 1.0), ((1, 8, 16, 40), 31, -0.4, 0.9)])
+def test_gantry_blur_matches_oracle(pn, shape, taps, a0, da):
+    _say(f"gantry blur {shape} taps={taps}")
+    x = np.random.default_rng(taps).random(shape).astype(np.float32)
+    y = pn.gantry_blur(torch.from_numpy(x).cuda(), a0, da, taps)
+    ref = O.gantry_blur(x.astype(np.float64), a0, da, taps)
+    err = np.linalg.norm((y.cpu().numpy() - ref).ravel()) / np.linalg.norm(ref.ravel())
+    assert err <= 1e-6, err
+
+
+def test_gantry_blur_full_size_sampled(pn):
+    """The 360 x 512 x 512 cone sinogram shape: 6 whole views against the
+    oracle, run on those views alone with their own angles."""
+    x = torch.rand(1, 360, 512, 512, device="cuda")
+    step = 2 * math.pi / 360
+    y = pn.gantry_blur(x, 0.0, step, 9).cpu().numpy()
+    xs = x.cpu().numpy()
+    for k in (0, 45, 90, 133, 270, 359):
+        ref = O.gantry_blur(xs[:, k:k + 1].astype(np.float64), k * step, step, 9)
+        err = np.linalg.norm((y[:, k:k + 1] - ref).ravel()) / np.linalg.norm(ref.ravel())
+        assert err <= 1e-6, (k, err)
+    with pytest.raises(RuntimeError):
+        pn.gantry_blur(x, 0.0, step, 4)
