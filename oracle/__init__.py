@@ -30,7 +30,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-# Mutation checks of the pins load a deliberately broken build from elsewhere.
+# The mutation test of the pins (tests/test_oracle_mutations.py) loads a
+# deliberately broken build from a temporary directory through this variable.
 _LIB_LOAD = os.environ.get("ORACLE_LIB_OVERRIDE") or _LIB_PATH
 _lib = None
 

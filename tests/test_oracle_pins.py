@@ -518,6 +518,171 @@ def test_fdk_reconstructs_ball_central_slice(O):
     assert abs(inside - 1.0) < 0.01 and outside < 0.01, (inside, outside)
 
 
+def _unit(v):
+    v = np.asarray(v, float)
+    return v / np.linalg.norm(v)
+
+
+def test_cosine_weights_are_cosines_to_the_detector_normal(O):
+    """FDK's pre-weight is the cosine of the angle between a pixel's ray
+    and the detector normal.  Computed here straight from the trajectory
+    vectors -- pixel X = C + (c - (cols-1)/2) e_u + (r - (rows-1)/2) e_v,
+    ray X - S, normal e_u x e_v -- and, for the circular orbit, from the
+    closed form SDD / sqrt(SDD^2 + u^2 + v^2) in centred detector mm.  A
+    wide fan (half-angle 39 deg) and a tilted, rotated, off-centre panel make
+    a weight of 1, cos^2 or 1/cos differ by far more than the tolerance."""
+    rows, cols, dv, du, sid, sdd, nviews = 24, 401, 0.7, 1.6, 300.0, 400.0, 5
+    g = O.circular_cone((8, 8, 8), (1.0, 1.0, 1.0), (rows, cols), (dv, du), nviews, 2 * math.pi, sid, sdd)
+    w = O.cosine_weights(g)
+    uc = (np.arange(cols) - (cols - 1) / 2) * du
+    vc = (np.arange(rows) - (rows - 1) / 2) * dv
+    ref = sdd / np.sqrt(sdd ** 2 + uc[None, :] ** 2 + vc[:, None] ** 2)
+    assert ref.min() < 0.83  # the weight matters at the panel's edge
+    for k in range(nviews):
+        assert np.abs(w[k] - ref).max() < 1e-13
+    # a panel tilted out of its plane, rotated in it and shifted off-centre
+    rng = np.random.default_rng(11)
+    for k in range(4):
+        S = np.array([sid, 0.0, 0.0]) + rng.normal(0, 5, 3)
+        C = np.array([sid - sdd, 0.0, 0.0]) + rng.normal(0, 20, 3)
+        a, b = rng.uniform(-0.4, 0.4, 2)
+        eu = du * _unit([math.sin(a), math.cos(a), 0.3 * b])
+        ev = dv * _unit(np.cross(_unit([math.cos(a) * math.cos(b), -math.sin(a), math.sin(b)]), eu / du))
+        P = O.cone_matrix(S, C, eu, ev, (rows, cols))
+        gk = O.cone_geometry((8, 8, 8), (1.0, 1.0, 1.0), (rows, cols), (dv, du), P[None])
+        cc, rr = np.meshgrid(np.arange(cols, dtype=float), np.arange(rows, dtype=float))
+        X = C + (cc[..., None] - (cols - 1) / 2) * eu + (rr[..., None] - (rows - 1) / 2) * ev
+        d = X - S
+        n = np.cross(eu, ev)
+        cosv = np.abs(d @ n) / (np.linalg.norm(d, axis=-1) * np.linalg.norm(n))
+        assert np.abs(O.cosine_weights(gk)[0] - cosv).max() < 1e-12
+    # fan: SDD / sqrt(SDD^2 + u^2); parallel: ones
+    gf = O.circular_fan((8, 8), (1.0, 1.0), cols, du, nviews, 2 * math.pi, sid, sdd)
+    wf = O.cosine_weights(gf)
+    assert np.abs(wf[:, 0, :] - sdd / np.sqrt(sdd ** 2 + uc ** 2)[None, :]).max() < 1e-13
+    gp = O.parallel_2d((8, 8), (1.0, 1.0), cols, du, nviews, math.pi)
+    assert np.array_equal(O.cosine_weights(gp), np.ones((nviews, 1, cols)))
+
+
+def _radial_max_dev(rec, spacing, R):
+    n = rec.shape[-1]
+    c = (np.arange(n) - (n - 1) / 2) * spacing
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    return float(np.abs(rec[np.hypot(xx, yy) < R - 3] - 1.0).max())
+
+
+def test_fan_fdk_short_source_distance_reconstructs_disk(O):
+    """A short-SDD fan (SID 100, SDD 150) around a centred unit disk of
+    radius 45 mm: the disk's edge rays leave the central ray at 26.7 deg,
+    where the cosine pre-weight is 0.89.  The FBP is 1 to within 1% on the
+    whole interior; without the weight (or squared, or inverted) it misses by
+    more than 8% somewhere inside.  Exact line integrals: the ray at detector
+    coordinate u passes SID sin(atan(u / SDD)) from the centre."""
+    R, n, ncol, nv, sid, sdd, du = 45.0, 200, 401, 360, 100.0, 150.0, 0.5
+    go = O.circular_fan((n, n), (0.5, 0.5), ncol, du, nv, 2 * math.pi, sid, sdd)
+    u = (np.arange(ncol) - (ncol - 1) / 2) * du
+    dist = sid * np.sin(np.abs(np.arctan(u / sdd)))
+    p = np.where(dist < R, 2 * np.sqrt(np.maximum(R * R - dist * dist, 0.0)), 0.0)
+    rec = O.fbp(np.tile(p, (nv, 1, 1)), go, du * sid / sdd)[0]
+    assert _radial_max_dev(rec, 0.5, R) < 0.01
+
+
+def test_cone_fdk_short_source_distance_reconstructs_ball(O):
+    """Cone-beam FDK with SID 100, SDD 150 of a centred unit ball of radius
+    42 mm (edge rays 24.8 deg off the central ray): its central slices are 1
+    to within 1%.  The line integrals are exact chords, from each ray's
+    distance to the centre |S x d| / |d| with S and d from the matrices."""
+    nz, n, R, nvr, nuc, dd, sid, sdd, nviews = 4, 184, 42.0, 9, 361, 0.5, 100.0, 150.0, 360
+    go = O.circular_cone((nz, n, n), (0.5, 0.5, 0.5), (nvr, nuc), (dd, dd), nviews, 2 * math.pi, sid, sdd)
+    sino = np.zeros((nviews, nvr, nuc))
+    uu, vv = np.meshgrid(np.arange(nuc, dtype=np.float64), np.arange(nvr, dtype=np.float64))
+    pix = np.stack([uu.ravel(), vv.ravel(), np.ones(uu.size)])
+    for k in range(nviews):
+        Q = go["P"][k][:, :3]
+        S = -np.linalg.solve(Q, go["P"][k][:, 3])
+        d = np.linalg.solve(Q, pix)
+        dist = np.linalg.norm(np.cross(S[None, :], d.T), axis=1) / np.linalg.norm(d, axis=0)
+        sino[k] = np.where(dist < R, 2 * np.sqrt(np.maximum(R * R - dist ** 2, 0.0)), 0.0).reshape(nvr, nuc)
+    rec = O.fbp(sino, go, dd * sid / sdd)
+    assert _radial_max_dev(rec[1:3].mean(axis=0), 0.5, R) < 0.01
+
+
+# ---------------------------------------------- trajectory generators ----
+
+
+def _sources(P):
+    return np.stack([-np.linalg.solve(p[:, :3], p[:, 3]) for p in P])
+
+
+def test_helical_trajectory_has_the_requested_pitch(O):
+    """Helical pitch = table feed per turn / collimation at the isocentre.
+    The feed comes from the sources of the composed matrices; the
+    collimation is the length of the rotation axis whose points project
+    between the outer edges of the first and last detector rows
+    (v = -1/2 and v = rows - 1/2), solved from the matrix of one view."""
+    rows, cols, dv, du, sid, sdd, N = 64, 48, 1.5, 1.0, 750.0, 1200.0, 90
+    for pitch in (0.5, 1.25):
+        S, C, eu, ev = O.trajectory_vectors("helical", N, 2 * math.pi, sid, sdd, (rows, cols), (dv, du),
+                                            (32, 32, 32), (1.0, 1.0, 1.0), pitch=pitch)
+        P = np.stack([O.cone_matrix(S[k], C[k], eu[k], ev[k], (rows, cols)) for k in range(N)])
+        Sz = _sources(P)[:, 2]
+        feed = (Sz[-1] - Sz[0]) * N / (N - 1)
+        assert np.allclose(np.diff(Sz), feed / N, rtol=0, atol=1e-9)
+
+        def z_at(p, v):  # axis point (0, 0, z) with V / W = v
+            return -(p[1, 3] - v * p[2, 3]) / (p[1, 2] - v * p[2, 2])
+
+        col = abs(z_at(P[7], rows - 0.5) - z_at(P[7], -0.5))
+        assert abs(feed / col - pitch) < 1e-9
+        assert abs(0.5 * (Sz[0] + Sz[-1] + feed / N)) < 1e-9  # one turn centred on z = 0
+
+
+def test_sinusoidal_trajectory_amplitude_and_frequency(O):
+    """The sinusoidal orbit's source height is a pure sinusoid of two
+    periods per turn and amplitude nz sz / 4 (read from the matrices'
+    sources, N divisible by 8 so the samples reach the peaks); the detector
+    follows the source: its centre pixel stays at the source's height."""
+    N, rows, cols, nz, sz = 96, 32, 40, 40, 0.8
+    S, C, eu, ev = O.trajectory_vectors("sinusoidal", N, 2 * math.pi, 750.0, 1200.0, (rows, cols), (1.0, 1.0),
+                                        (nz, 16, 16), (sz, 1.0, 1.0))
+    P = np.stack([O.cone_matrix(S[k], C[k], eu[k], ev[k], (rows, cols)) for k in range(N)])
+    Sz = _sources(P)[:, 2]
+    assert abs(0.5 * (Sz.max() - Sz.min()) - nz * sz / 4) < 1e-9
+    spec = np.abs(np.fft.rfft(Sz))
+    assert np.argmax(spec) == 2 and np.delete(spec, 2).max() < 1e-9 * spec[2]
+    for k in range(N):
+        # the ray of the centre pixel runs level: the panel's centre sits at
+        # the source's height
+        d = np.linalg.solve(P[k][:, :3], [(cols - 1) / 2, (rows - 1) / 2, 1.0])
+        assert abs(d[2]) < 1e-9 * np.linalg.norm(d)
+
+
+def test_perturbed_trajectory_statistics(O):
+    """The perturbed orbit differs from the circular one by i.i.d. N(0, 0.5 mm)
+    source shifts and an N(0, 0.5 deg) in-panel detector rotation; both are
+    read back from the composed matrices (sources, and the angle of the
+    column direction e_u = first column of the inverse 3x3 block)."""
+    import workloads as W
+
+    N, rows, cols = 2000, 16, 16
+    args = (N, 2 * math.pi, 750.0, 1200.0, (rows, cols), (1.0, 1.0), (16, 16, 16), (1.0, 1.0, 1.0))
+    P0 = [O.cone_matrix(*v, (rows, cols)) for v in zip(*O.trajectory_vectors("circular", *args))]
+    Pp = [O.cone_matrix(*v, (rows, cols)) for v in zip(*O.trajectory_vectors("perturbed", *args,
+                                                                            draws=W.perturbation_draws(7, N)))]
+    dS = _sources(Pp) - _sources(P0)
+    assert abs(dS.std() - 0.5) < 0.02 and abs(dS.mean()) < 0.02
+    ang = []
+    for p0, p1 in zip(P0, Pp):
+        e0 = np.linalg.inv(p0[:, :3])[:, 0]
+        e1 = np.linalg.inv(p1[:, :3])[:, 0]
+        ang.append(math.atan2(np.linalg.norm(np.cross(e0, e1)), e0 @ e1))
+    assert abs(math.degrees(np.sqrt(np.mean(np.square(ang)))) - 0.5) < 0.03
+    # the rotation keeps the panel's pixel grid square: e_u stays normal to e_v
+    for p1 in Pp:
+        M = np.linalg.inv(p1[:, :3])
+        assert abs(M[:, 0] @ M[:, 1]) < 1e-12 * np.linalg.norm(M[:, 0]) * np.linalg.norm(M[:, 1])
+
+
 # ------------------------------------------------- artifact simulation ----
 
 
