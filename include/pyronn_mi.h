@@ -50,11 +50,29 @@
  *   the call only.  Work is enqueued asynchronously on `hip_stream` (a
  *   hipStream_t; NULL = the default stream).  Outputs are overwritten, never
  *   accumulated into.  The library keeps a cache of per-geometry plans
- *   (per-view tables and work buffers in device memory); the first call with
- *   a new geometry allocates and uploads synchronously, later calls with an
- *   equal geometry allocate nothing.  Two calls that use the same geometry
- *   and operator on different streams at the same time race on that plan's
- *   work buffers: order them on one stream.
+ *   (per-view tables and work buffers in device memory, at most 32 plans
+ *   besides pinned ones, least recently used evicted first); the first call
+ *   with a new geometry allocates and uploads synchronously, later calls
+ *   with an equal geometry, batch and types allocate nothing.  Two calls
+ *   that use the same geometry and operator on different streams at the
+ *   same time race on that plan's work buffers: order them on one stream.
+ *
+ * Graph capture
+ *   The operator calls enqueue kernels only (no memset, copy or allocation
+ *   once their plan and buffers exist), so they can be captured into a HIP
+ *   graph.  Rules:
+ *   - a captured call must follow an eager call with the same geometry,
+ *     batch and types; a call that would allocate while its stream is
+ *     capturing returns PN_EINVAL and enqueues nothing;
+ *   - a plan used by a captured call is pinned: it is never evicted, and its
+ *     buffers are never freed or re-purposed.  A later call on the same
+ *     geometry that needs a larger buffer (a larger batch) or one laid out
+ *     for another storage type gets a new buffer; the old one stays
+ *     allocated for the graph until pn_release_caches;
+ *   - pn_release_caches frees everything, pinned plans included: graphs that
+ *     captured calls of this library must not be replayed after it;
+ *   - a replay shares the plan's buffers with eager calls of the same
+ *     geometry: order them on one stream.
  *
  * Errors
  *   Every function returns 0 on success or a negative PN_E* code; the text of
@@ -114,7 +132,13 @@ int pn_forward(const pn_geometry *pg, int64_t batch, const void *vol, void *sino
                int32_t in_dtype, int32_t out_dtype, void *hip_stream);
 
 /* A^T: sino [batch][n_views][rows][cols] (in_dtype) -> vol [batch][nz][ny][nx]
- * (out_dtype).  Exact transpose of pn_forward up to FP32 rounding. */
+ * (out_dtype).  Exact transpose of pn_forward up to rounding: each block of
+ * output voxels sums its rays' contributions in 32-bit fixed point whose
+ * power-of-two scale follows the magnitude of those rays (the error of a
+ * contribution is at most 2^-20 of the largest |q ds| among the few hundred
+ * rays processed with it), then in FP32; the result is bitwise
+ * reproducible.  A non-finite sinogram value turns the output blocks its
+ * ray reaches into NaN (other blocks and batch items are unaffected). */
 int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
                int32_t in_dtype, int32_t out_dtype, void *hip_stream);
 
@@ -191,10 +215,13 @@ int pn_ring_artifacts(int64_t batch, int32_t n_views, int32_t rows, int32_t cols
                       const int32_t *columns, int32_t n_columns, double gain, int32_t v0, int32_t v1,
                       void *hip_stream);
 
-/* The same operators over n independent problems of uneven sizes in one
- * persistent launch per operator, replayed from a captured HIP graph when the
- * same problem set (geometries and pointers) is seen again.  Each problem's
- * result equals its single-problem call. */
+/* The same operators over n independent problems of uneven sizes (each a
+ * batch of one, all of the same in and out types).  Every problem is
+ * validated before anything is enqueued; the problems are ordered by
+ * estimated cost, largest first, and run as work lists of up to 12 problems
+ * per kernel launch (per dominant axis for the adjoint).  Each problem's
+ * result equals its single-problem call bit for bit.  Graph capture follows
+ * the rules above. */
 int pn_forward_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
                        void *hip_stream);
 int pn_adjoint_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
@@ -225,7 +252,9 @@ int pn_parallel3d_matrices(int64_t n_views, const double *dir, const double *C, 
 /* Text of the calling thread's last error ("" if none). */
 const char *pn_last_error(void);
 
-/* Frees every cached plan, work buffer and graph; the next call rebuilds. */
+/* Frees every cached plan and work buffer, pinned ones included (graphs
+ * that captured calls of this library become invalid); the next call
+ * rebuilds. */
 int pn_release_caches(void);
 
 /* Library version string. */

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libpyronn_mi.so")
-SOURCES = ["pn_kernels.hip", "pn_host.cpp"]
+SOURCES = ["pn_kernels.hip", "pn_host.cpp", "pn_geometry.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -63,9 +63,7 @@ struct FwdParams {
 struct AdjParams {
     const ViewTab *tab;
     const ViewTabF *tabf;
-    const uint32_t *maxabs;  // bit pattern of max |sino| (fixed-point scale)
-    float ds_bound;          // upper bound of the ray length per plane (mm)
-    float kunits;            // rays x max|q ds| units a flush period holds (>= every kcell)
+    float kunits;            // power of two >= every kcell: max|q ds| units a flush period holds
     const uint32_t *cbox;  // per (block, pass view) 2 words: candidate pixel box (cbox_kernel)
     const int32_t *views;  // views processed by this pass
     int32_t n_pass_views;

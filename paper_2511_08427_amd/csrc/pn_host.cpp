@@ -1,23 +1,22 @@
-// Host side of the CT projector library: argument and geometry validation,
-// FP64 per-view tables, the plan cache, work buffers, and the extern "C"
-// entry points declared in include/pyronn_mi.h.
+// Device side of the CT projector library's host code: the plan cache and
+// work buffers, kernel launches, and the extern "C" operator entry points
+// declared in include/pyronn_mi.h.  Validation and the per-view tables are
+// in pn_geometry.cpp; the rules for cached device memory under graph
+// capture in pn_cache.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
-#include <limits>
-#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <list>
 #include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
 
-#include "../../include/pyronn_mi.h"
-#include "pn_common.hpp"
+#include "pn_cache.hpp"
+#include "pn_internal.hpp"
 
 namespace pn {
 hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32_t n[3], int axis, int32_t batch,
@@ -25,7 +24,6 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
 hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
-hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st);
 hipError_t launch_cbox(const AdjParams &ap, const uint32_t *axbox, int32_t L, int32_t TS, int32_t TF, uint32_t *out,
                        hipStream_t st);
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
@@ -54,447 +52,99 @@ using namespace pn;
 
 // ---------------------------------------------------------------- errors --
 
-thread_local std::string t_err;
-
-int fail(int code, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    t_err = buf;
-    return code;
-}
-
 int fail_hip(hipError_t e, const char *what)
 {
     return fail(PN_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-int64_t esize(int32_t dt) { return dt == PN_F32 ? 4 : 2; }
-
 void dev_free(void *p)
 {
     if (p) (void)hipFree(p);
 }
-bool dtype_ok(int32_t dt) { return dt == PN_F32 || dt == PN_BF16 || dt == PN_F16; }
-
-// --------------------------------------------------------- small algebra --
-
-bool inv3(const double m[9], double r[9])
-{
-    double c0 = m[4] * m[8] - m[5] * m[7];
-    double c1 = m[5] * m[6] - m[3] * m[8];
-    double c2 = m[3] * m[7] - m[4] * m[6];
-    double det = m[0] * c0 + m[1] * c1 + m[2] * c2;
-    double n0 = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
-    double n1 = std::sqrt(m[3] * m[3] + m[4] * m[4] + m[5] * m[5]);
-    double n2 = std::sqrt(m[6] * m[6] + m[7] * m[7] + m[8] * m[8]);
-    if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * n0 * n1 * n2) return false;
-    double id = 1.0 / det;
-    r[0] = c0 * id;
-    r[1] = (m[2] * m[7] - m[1] * m[8]) * id;
-    r[2] = (m[1] * m[5] - m[2] * m[4]) * id;
-    r[3] = c1 * id;
-    r[4] = (m[0] * m[8] - m[2] * m[6]) * id;
-    r[5] = (m[2] * m[3] - m[0] * m[5]) * id;
-    r[6] = c2 * id;
-    r[7] = (m[1] * m[6] - m[0] * m[7]) * id;
-    r[8] = (m[0] * m[4] - m[1] * m[3]) * id;
-    return true;
-}
-
-// --------------------------------------------------------- geometry -------
-
-// Normalised geometry: 2-D problems embedded as 3-D with nz = 1, every
-// matrix 3x4, sign chosen so that W > 0 over the volume.
-struct Geo {
-    int32_t ndim = 3, beam = PN_CONE;
-    bool parallel = false;
-    int32_t n[3] = {0, 0, 0};  // nx, ny, nz
-    double s[3] = {1, 1, 1};   // sx, sy, sz
-    double o[3] = {0, 0, 0};   // ox, oy, oz
-    int32_t nv = 0, nu = 0;
-    int32_t n_views = 0;
-    std::vector<double> P;     // n_views x 12 (world matrices)
-    std::vector<double> raw;   // caller's matrices, for exact cache matching
-    double raw_scalars[16] = {};
-
-    bool same(const Geo &g) const
-    {
-        return ndim == g.ndim && beam == g.beam && nv == g.nv && nu == g.nu && n_views == g.n_views &&
-               std::memcmp(n, g.n, sizeof n) == 0 && std::memcmp(raw_scalars, g.raw_scalars, sizeof raw_scalars) == 0 &&
-               raw == g.raw;
-    }
-};
-
-int normalise_geometry(const pn_geometry *pg, Geo &g)
-{
-    if (!pg) return fail(PN_EINVAL, "geometry pointer is NULL");
-    if (pg->ndim != 2 && pg->ndim != 3) return fail(PN_EINVAL, "ndim must be 2 or 3 (got %d)", pg->ndim);
-    if (pg->ndim == 2 && pg->beam != PN_PARALLEL && pg->beam != PN_FAN)
-        return fail(PN_EINVAL, "2-D geometry needs beam PN_PARALLEL or PN_FAN (got %d)", pg->beam);
-    if (pg->ndim == 3 && pg->beam != PN_PARALLEL && pg->beam != PN_CONE)
-        return fail(PN_EINVAL, "3-D geometry needs beam PN_PARALLEL or PN_CONE (got %d)", pg->beam);
-    const int64_t lim = 65535;
-    for (int a = 0; a < 3; ++a)
-        if (pg->vol_shape[a] < 1 || pg->vol_shape[a] > lim)
-            return fail(PN_EINVAL, "vol_shape[%d] = %lld outside [1, %lld]", a, (long long)pg->vol_shape[a],
-                        (long long)lim);
-    for (int a = 0; a < 2; ++a)
-        if (pg->det_shape[a] < 1 || pg->det_shape[a] > lim)
-            return fail(PN_EINVAL, "det_shape[%d] = %lld outside [1, %lld]", a, (long long)pg->det_shape[a],
-                        (long long)lim);
-    if (pg->ndim == 2 && pg->vol_shape[0] != 1) return fail(PN_EINVAL, "2-D geometry needs vol_shape[0] == 1");
-    if (pg->ndim == 2 && pg->det_shape[0] != 1) return fail(PN_EINVAL, "2-D geometry needs det_shape[0] == 1");
-    const int64_t item = pg->vol_shape[0] * pg->vol_shape[1] * pg->vol_shape[2];
-    if (item > INT32_MAX) return fail(PN_EINVAL, "volume has more than 2^31-1 voxels");
-    if (pg->n_views < 0 || pg->n_views > 1000000) return fail(PN_EINVAL, "n_views = %lld out of range",
-                                                              (long long)pg->n_views);
-    if (pg->n_views * pg->det_shape[0] * pg->det_shape[1] > INT32_MAX)
-        return fail(PN_EINVAL, "sinogram has more than 2^31-1 pixels");
-    for (int a = (pg->ndim == 2 ? 1 : 0); a < 3; ++a)
-        if (!std::isfinite(pg->vol_spacing[a]) || !(pg->vol_spacing[a] > 0))
-            return fail(PN_EINVAL, "vol_spacing[%d] must be finite and > 0", a);
-    for (int a = 0; a < 3; ++a)
-        if (std::isinf(pg->vol_origin[a])) return fail(PN_EINVAL, "vol_origin[%d] is infinite", a);
-    if (pg->n_views > 0 && !pg->proj) return fail(PN_EINVAL, "proj is NULL");
-
-    g.ndim = pg->ndim;
-    g.beam = pg->beam;
-    g.parallel = pg->beam == PN_PARALLEL;
-    g.n[0] = (int32_t)pg->vol_shape[2];
-    g.n[1] = (int32_t)pg->vol_shape[1];
-    g.n[2] = (int32_t)pg->vol_shape[0];
-    g.s[0] = pg->vol_spacing[2];
-    g.s[1] = pg->vol_spacing[1];
-    g.s[2] = pg->ndim == 2 ? 1.0 : pg->vol_spacing[0];
-    for (int a = 0; a < 3; ++a) {
-        double org = pg->vol_origin[2 - a];
-        g.o[a] = std::isnan(org) ? -0.5 * (g.n[a] - 1) * g.s[a] : org;
-    }
-    if (pg->ndim == 2) g.o[2] = 0.0;
-    g.nv = (int32_t)pg->det_shape[0];
-    g.nu = (int32_t)pg->det_shape[1];
-    g.n_views = (int32_t)pg->n_views;
-    const int psz = pg->ndim == 2 ? 6 : 12;
-    g.raw.assign(pg->proj, pg->proj + (size_t)psz * g.n_views);
-    double sc[16] = {g.s[0], g.s[1], g.s[2], g.o[0], g.o[1], g.o[2]};
-    std::memcpy(g.raw_scalars, sc, sizeof sc);
-    g.P.resize((size_t)12 * g.n_views);
-    for (int k = 0; k < g.n_views; ++k) {
-        const double *q = pg->proj + (size_t)psz * k;
-        double *P = &g.P[(size_t)12 * k];
-        for (int e = 0; e < psz; ++e)
-            if (!std::isfinite(q[e])) return fail(PN_EGEOM, "view %d: non-finite matrix entry", k);
-        if (pg->ndim == 2) {
-            // (U, W) = P2 (x, y, 1) embedded as rows (U, V = z, W)
-            double e3[12] = {q[0], q[1], 0.0, q[2], 0.0, 0.0, 1.0, 0.0, q[3], q[4], 0.0, q[5]};
-            std::memcpy(P, e3, sizeof e3);
-        } else {
-            std::memcpy(P, q, sizeof(double) * 12);
-        }
-        double scale = 0;
-        for (int e = 0; e < 12; ++e) scale = std::max(scale, std::fabs(P[e]));
-        if (!(scale > 0)) return fail(PN_EGEOM, "view %d: zero matrix", k);
-        if (g.parallel) {
-            if (std::fabs(P[8]) > 1e-12 * scale || std::fabs(P[9]) > 1e-12 * scale || std::fabs(P[10]) > 1e-12 * scale ||
-                P[11] == 0.0)
-                return fail(PN_EGEOM, "view %d: a parallel-beam matrix needs last row (0, 0, 0, w), w != 0", k);
-            P[8] = P[9] = P[10] = 0.0;
-            if (P[11] < 0)
-                for (int e = 0; e < 12; ++e) P[e] = -P[e];
-            double a[3] = {P[0], P[1], P[2]}, b[3] = {P[4], P[5], P[6]};
-            double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2], cz = a[0] * b[1] - a[1] * b[0];
-            double na = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
-            double nb = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-            if (!(std::sqrt(cx * cx + cy * cy + cz * cz) > 1e-12 * na * nb))
-                return fail(PN_EGEOM, "view %d: parallel-beam matrix rows are dependent", k);
-        } else {
-            double M[9] = {P[0], P[1], P[2], P[4], P[5], P[6], P[8], P[9], P[10]}, Mi[9];
-            if (!inv3(M, Mi)) return fail(PN_EGEOM, "view %d: singular 3x3 block", k);
-            // sign: W > 0 at the volume centre
-            double c[3];
-            for (int a = 0; a < 3; ++a) c[a] = g.o[a] + 0.5 * (g.n[a] - 1) * g.s[a];
-            double Wc = P[8] * c[0] + P[9] * c[1] + P[10] * c[2] + P[11];
-            if (Wc < 0)
-                for (int e = 0; e < 12; ++e) P[e] = -P[e];
-            // the whole volume, dilated by one voxel, must be in front of the source
-            for (int corner = 0; corner < 8; ++corner) {
-                double X[3];
-                for (int a = 0; a < 3; ++a) {
-                    double idx = (corner >> a & 1) ? (double)g.n[a] : -1.0;
-                    X[a] = g.o[a] + idx * g.s[a];
-                }
-                if (pg->ndim == 2) X[2] = 0.0;
-                double W = P[8] * X[0] + P[9] * X[1] + P[10] * X[2] + P[11];
-                if (!(W > 1e-12 * scale))
-                    return fail(PN_EGEOM, "view %d: the volume (dilated by one voxel) is not entirely in front of the source", k);
-            }
-        }
-    }
-    return PN_OK;
-}
-
-// Sutherland-Hodgman: keep the part of a convex polygon with a*u + b*v + c >= 0.
-void clip_poly(std::vector<double> &poly, double a, double b, double c)
-{
-    std::vector<double> out;
-    const size_t n = poly.size() / 2;
-    for (size_t i = 0; i < n; ++i) {
-        double u0 = poly[2 * i], v0 = poly[2 * i + 1];
-        double u1 = poly[2 * ((i + 1) % n)], v1 = poly[2 * ((i + 1) % n) + 1];
-        double f0 = a * u0 + b * v0 + c, f1 = a * u1 + b * v1 + c;
-        if (f0 >= 0) { out.push_back(u0); out.push_back(v0); }
-        if ((f0 >= 0) != (f1 >= 0)) {
-            double t = f0 / (f0 - f1);
-            out.push_back(u0 + t * (u1 - u0));
-            out.push_back(v0 + t * (v1 - v0));
-        }
-    }
-    poly.swap(out);
-}
-
-// Which dominant axes can occur among the view's rays (conservative: near
-// ties count for both axes).  delta(u, v) = A (u, v, 1) is linear in (u, v),
-// so the pixels (centres in [0, nu-1] x [0, nv-1]) where axis a dominates
-// with sign sg form the detector rectangle clipped by four half-planes
-// sg delta_a +- delta_b >= 0.  box[a] receives the bounding box of those
-// pixels, widened by one pixel and clamped to the detector, as two words
-// (first column | first row << 16, last column | last row << 16); the
-// adjoint takes its candidate rays of pass a from inside it.
-int32_t axis_mask(const double A[9], int32_t nu, int32_t nv, uint32_t box[3][2])
-{
-    const double U = nu - 1, V = nv - 1;
-    double dmax = 0;
-    for (int cu = 0; cu < 2; ++cu)
-        for (int cv = 0; cv < 2; ++cv)
-            for (int i = 0; i < 3; ++i)
-                dmax = std::max(dmax, std::fabs(A[3 * i] * cu * U + A[3 * i + 1] * cv * V + A[3 * i + 2]));
-    const double tau = 1e-9 * dmax;
-    int32_t mask = 0;
-    for (int a = 0; a < 3; ++a) {
-        double u0 = HUGE_VAL, u1 = -HUGE_VAL, v0 = HUGE_VAL, v1 = -HUGE_VAL;
-        for (int sg = -1; sg <= 1; sg += 2) {
-            std::vector<double> poly = {0, 0, U, 0, U, V, 0, V};
-            for (int b = 0; b < 3 && !poly.empty(); ++b) {
-                if (b == a) continue;
-                for (int pm = -1; pm <= 1 && !poly.empty(); pm += 2) {
-                    // sg*delta_a + pm*delta_b >= -tau
-                    clip_poly(poly, sg * A[3 * a] + pm * A[3 * b], sg * A[3 * a + 1] + pm * A[3 * b + 1],
-                              sg * A[3 * a + 2] + pm * A[3 * b + 2] + tau);
-                }
-            }
-            if (!poly.empty()) mask |= 1 << a;
-            for (size_t i = 0; i + 1 < poly.size(); i += 2) {
-                u0 = std::min(u0, poly[i]);
-                u1 = std::max(u1, poly[i]);
-                v0 = std::min(v0, poly[i + 1]);
-                v1 = std::max(v1, poly[i + 1]);
-            }
-        }
-        if (mask & (1 << a)) {
-            const uint32_t c0 = (uint32_t)std::min(std::max(std::floor(u0) - 1.0, 0.0), U);
-            const uint32_t c1 = (uint32_t)std::min(std::max(std::ceil(u1) + 1.0, 0.0), U);
-            const uint32_t r0 = (uint32_t)std::min(std::max(std::floor(v0) - 1.0, 0.0), V);
-            const uint32_t r1 = (uint32_t)std::min(std::max(std::ceil(v1) + 1.0, 0.0), V);
-            box[a][0] = c0 | r0 << 16;
-            box[a][1] = c1 | r1 << 16;
-        } else {
-            box[a][0] = 1u;  // empty: first column after the last
-            box[a][1] = 0u;
-        }
-    }
-    return mask;
-}
 
 // ------------------------------------------------------------- plans ------
 
-struct Plan {
+struct HipMem {
+    static bool alloc(void **p, size_t n) { return hipMalloc(p, n) == hipSuccess; }
+    static void release(void *p) { (void)hipFree(p); }
+};
+
+// Retired buffers of pinned plans (pn_cache.hpp); guarded by g_mu.
+BufferKeeper<HipMem> g_keeper;
+
+struct Plan : HostTables {
     Geo g;
     int device = 0;
-    std::vector<ViewTab> tab;
-    std::vector<ViewTabF> tabf;
-    int32_t axes_union = 0;
-    std::vector<int32_t> pass_views[3];
+    // used by a call under stream capture: never evicted, buffers never
+    // freed or re-purposed before pn_release_caches
+    bool pinned = false;
     ViewTab *d_tab = nullptr;
     ViewTabF *d_tabf = nullptr;
     int32_t *d_views[3] = {nullptr, nullptr, nullptr};
-    // forward work copies, one allocation per dominant axis
-    void *d_lay[3] = {nullptr, nullptr, nullptr};
-    size_t lay_cap[3] = {0, 0, 0};
-    int32_t lay_dtype[3] = {-1, -1, -1};
+    int32_t *d_vwin = nullptr;
+    uint32_t *d_axbox = nullptr;
+    // forward work copies, one per dominant axis (tag: storage type)
+    DevBuf lay[3];
     int64_t lay_item[3] = {0, 0, 0}, lay_plane[3] = {0, 0, 0};
     int32_t lay_row[3] = {0, 0, 0};
     // FP32 accumulation buffer of the adjoint for 16-bit outputs
-    float *d_acc = nullptr;
-    size_t acc_cap = 0;
-    // max |sinogram| of the current adjoint call (fixed-point scale)
-    uint32_t *d_maxabs = nullptr;
-    // largest per-view bound on the rays that sample one voxel's neighbourhood
-    float kmax = 1.0f;
+    DevBuf acc;
     // 3-D adjoint block shape chosen by the autotuner (0: not tuned)
     int adj_shape = 0;
-    // adjoint candidate pixel boxes per pass axis, for block shape cbox_shape
-    uint32_t *d_cbox[3] = {nullptr, nullptr, nullptr};
-    int cbox_shape[3] = {-1, -1, -1};
-    // detector window that holds every ray meeting the dilated volume in
-    // some view (inclusive pixel bounds; c0 > c1: no ray meets it)
-    int32_t win_c0 = 0, win_c1 = -1, win_r0 = 0, win_r1 = -1;
-    // the same per view (c0, c1, r0, r1), host and device
-    std::vector<int32_t> vwin;
-    int32_t *d_vwin = nullptr;
-    // per view and axis: detector box of the pixels whose ray may have that
-    // dominant axis (axis_mask)
-    std::vector<uint32_t> axbox;
-    uint32_t *d_axbox = nullptr;
+    // adjoint candidate pixel boxes per pass axis (tag: block shape)
+    DevBuf cbox[3];
 
     ~Plan()
     {
         dev_free(d_tab);
         dev_free(d_tabf);
-        for (int a = 0; a < 3; ++a) {
-            dev_free(d_views[a]);
-            dev_free(d_lay[a]);
-        }
-        dev_free(d_acc);
-        dev_free(d_maxabs);
-        for (int a = 0; a < 3; ++a) dev_free(d_cbox[a]);
+        for (int a = 0; a < 3; ++a) dev_free(d_views[a]);
         dev_free(d_vwin);
         dev_free(d_axbox);
+        for (int a = 0; a < 3; ++a) {
+            g_keeper.free(lay[a]);
+            g_keeper.free(cbox[a]);
+        }
+        g_keeper.free(acc);
     }
 };
 
 std::mutex g_mu;
-std::list<std::unique_ptr<Plan>> g_plans;  // most recently used first
+PlanLru<Plan> g_plans;
 const size_t kMaxPlans = 32;
 
-// Upper bound on the number of rays of one view whose sample in some plane
-// lies within one voxel, in both in-plane axes, of a given voxel (the rays
-// that can add to that voxel in the adjoint).  Such a sample lies in a 2 x 2
-// square of the plane around the voxel; the ray's pixel is the projection
-// of the sample, so it lies in the projection of the square, which fits in
-// a detector box of 2 Du x 2 Dv pixels, Du bounding |du/df| + |du/ds| over
-// the dilated volume (mean value theorem).  With u = U/W,
-// du/dx_c = (Pi_0c - u Pi_2c) / W, and over the box W >= Wmin > 0 and
-// |u| <= max |u| at the corners (u is linear-fractional).  The box holds at
-// most (floor(2 Du) + 1) (floor(2 Dv) + 1) pixel centres.  The sum over all
-// three axes covers every pass.
-double cell_ray_bound(const double *Pi, const Geo &g)
+// True when work enqueued on `st` is being captured into a graph.
+bool capturing(hipStream_t st)
 {
-    double wmin = std::numeric_limits<double>::infinity(), umax = 0.0, vmax = 0.0;
-    for (int c = 0; c < 8; ++c) {
-        const double x = (c & 1) ? g.n[0] : -1.0, y = (c & 2) ? g.n[1] : -1.0, z = (c & 4) ? g.n[2] : -1.0;
-        const double U = Pi[0] * x + Pi[1] * y + Pi[2] * z + Pi[3];
-        const double V = Pi[4] * x + Pi[5] * y + Pi[6] * z + Pi[7];
-        const double W = Pi[8] * x + Pi[9] * y + Pi[10] * z + Pi[11];
-        wmin = std::min(wmin, W);
-        umax = std::max(umax, std::fabs(U / W));
-        vmax = std::max(vmax, std::fabs(V / W));
-    }
-    double du = 0.0, dv = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        du += (std::fabs(Pi[c]) + umax * std::fabs(Pi[8 + c])) / wmin;
-        dv += (std::fabs(Pi[4 + c]) + vmax * std::fabs(Pi[8 + c])) / wmin;
-    }
-    const double cu = std::min(std::ceil(2.0 * du * (1.0 + 1e-9)) + 1.0, (double)g.nu);
-    const double cv = std::min(std::ceil(2.0 * dv * (1.0 + 1e-9)) + 1.0, (double)g.nv);
-    return std::max(cu * cv, 1.0);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
 }
 
-void build_tables(Plan &pl)
+int capture_error(const char *what)
 {
-    const Geo &g = pl.g;
-    pl.tab.resize(g.n_views);
-    pl.tabf.resize(g.n_views);
-    for (int a = 0; a < 3; ++a) pl.pass_views[a].clear();
-    pl.axes_union = 0;
-    double umin = HUGE_VAL, umax = -HUGE_VAL, vmin = HUGE_VAL, vmax = -HUGE_VAL;
-    pl.vwin.assign((size_t)4 * g.n_views, 0);
-    pl.axbox.assign((size_t)6 * g.n_views, 0u);
-    for (int k = 0; k < g.n_views; ++k) {
-        const double *P = &g.P[(size_t)12 * k];
-        ViewTab &t = pl.tab[k];
-        // index-space matrix: Pi = P [diag(s) o; 0 1]
-        for (int r = 0; r < 3; ++r) {
-            for (int a = 0; a < 3; ++a) t.Pi[4 * r + a] = P[4 * r + a] * g.s[a];
-            t.Pi[4 * r + 3] = P[4 * r + 3] + P[4 * r] * g.o[0] + P[4 * r + 1] * g.o[1] + P[4 * r + 2] * g.o[2];
-        }
-        std::memset(t.A, 0, sizeof t.A);
-        std::memset(t.B, 0, sizeof t.B);
-        if (!g.parallel) {
-            double M[9] = {t.Pi[0], t.Pi[1], t.Pi[2], t.Pi[4], t.Pi[5], t.Pi[6], t.Pi[8], t.Pi[9], t.Pi[10]};
-            inv3(M, t.A);  // validated non-singular (scaling by s keeps it so)
-            for (int i = 0; i < 3; ++i)
-                t.B[3 * i + 2] = -(t.A[3 * i] * t.Pi[3] + t.A[3 * i + 1] * t.Pi[7] + t.A[3 * i + 2] * t.Pi[11]);
-        } else {
-            const double w = t.Pi[11];
-            double a[3] = {t.Pi[0] / w, t.Pi[1] / w, t.Pi[2] / w};
-            double b[3] = {t.Pi[4] / w, t.Pi[5] / w, t.Pi[6] / w};
-            double cu = t.Pi[3] / w, cv = t.Pi[7] / w;
-            t.A[2] = a[1] * b[2] - a[2] * b[1];
-            t.A[5] = a[2] * b[0] - a[0] * b[2];
-            t.A[8] = a[0] * b[1] - a[1] * b[0];
-            double g00 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
-            double g01 = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-            double g11 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-            double det = g00 * g11 - g01 * g01;
-            double h00 = g11 / det, h01 = -g01 / det, h11 = g00 / det;
-            for (int i = 0; i < 3; ++i) {
-                double ku = a[i] * h00 + b[i] * h01;  // coefficient of (u - cu)
-                double kv = a[i] * h01 + b[i] * h11;  // coefficient of (v - cv)
-                t.B[3 * i] = ku;
-                t.B[3 * i + 1] = kv;
-                t.B[3 * i + 2] = -(ku * cu + kv * cv);
-            }
-        }
-        ViewTabF &tf = pl.tabf[k];
-        for (int e = 0; e < 12; ++e) tf.Pi[e] = (float)t.Pi[e];
-        tf.W0 = (float)P[11];
-        tf.axes = axis_mask(t.A, g.nu, g.nv, reinterpret_cast<uint32_t(*)[2]>(&pl.axbox[(size_t)6 * k]));
-        tf.kcell = (float)cell_ray_bound(t.Pi, g);
-        tf.pad = 0;
-        pl.kmax = std::max(pl.kmax, tf.kcell);
-        pl.axes_union |= tf.axes;
-        // the dilated volume [-1, n] projects into the convex hull of its
-        // corners' projections (W > 0 there): rays outside it sum to zero
-        double vu0 = HUGE_VAL, vu1 = -HUGE_VAL, vv0 = HUGE_VAL, vv1 = -HUGE_VAL;
-        for (int c = 0; c < 8; ++c) {
-            const double x = (c & 1) ? g.n[0] : -1.0, y = (c & 2) ? g.n[1] : -1.0, z = (c & 4) ? g.n[2] : -1.0;
-            const double U = t.Pi[0] * x + t.Pi[1] * y + t.Pi[2] * z + t.Pi[3];
-            const double V = t.Pi[4] * x + t.Pi[5] * y + t.Pi[6] * z + t.Pi[7];
-            const double W = t.Pi[8] * x + t.Pi[9] * y + t.Pi[10] * z + t.Pi[11];
-            vu0 = std::min(vu0, U / W);
-            vu1 = std::max(vu1, U / W);
-            vv0 = std::min(vv0, V / W);
-            vv1 = std::max(vv1, V / W);
-        }
-        umin = std::min(umin, vu0);
-        umax = std::max(umax, vu1);
-        vmin = std::min(vmin, vv0);
-        vmax = std::max(vmax, vv1);
-        // one pixel of margin for the rounding of the bounds
-        const bool fin = std::isfinite(vu0) && std::isfinite(vu1) && std::isfinite(vv0) && std::isfinite(vv1);
-        pl.vwin[4 * k] = fin ? (int32_t)std::max(-1.0, std::min((double)g.nu, std::floor(vu0) - 1.0)) : 0;
-        pl.vwin[4 * k + 1] = fin ? (int32_t)std::max(-1.0, std::min((double)g.nu, std::ceil(vu1) + 1.0)) : g.nu;
-        pl.vwin[4 * k + 2] = fin ? (int32_t)std::max(-1.0, std::min((double)g.nv, std::floor(vv0) - 1.0)) : 0;
-        pl.vwin[4 * k + 3] = fin ? (int32_t)std::max(-1.0, std::min((double)g.nv, std::ceil(vv1) + 1.0)) : g.nv;
-        for (int a = 0; a < 3; ++a)
-            if (tf.axes >> a & 1) pl.pass_views[a].push_back(k);
+    return fail(PN_EINVAL,
+                "%s would allocate or re-purpose device memory while the stream is capturing: run the same call "
+                "(geometry, batch, types) eagerly once before capturing it",
+                what);
+}
+
+// Makes a plan buffer fit; a fresh buffer is zero-filled when `zero`.
+int ensure_buf(Plan &pl, DevBuf &b, size_t need, int32_t tag, bool zero, hipStream_t st, const char *what,
+               bool &fresh)
+{
+    fresh = false;
+    switch (g_keeper.ensure(b, need, tag, pl.pinned, capturing(st))) {
+    case Ensure::kReady: return PN_OK;
+    case Ensure::kCapturing: return capture_error(what);
+    case Ensure::kNoMem: return fail(PN_ENOMEM, "%s: hipMalloc(%zu) failed", what, need);
+    case Ensure::kFresh: break;
     }
-    // one pixel of margin for the rounding of the bounds
-    if (g.n_views > 0 && std::isfinite(umin) && std::isfinite(umax) && std::isfinite(vmin) && std::isfinite(vmax)) {
-        pl.win_c0 = (int32_t)std::max(0.0, std::min((double)g.nu, std::floor(umin) - 1.0));
-        pl.win_c1 = (int32_t)std::min((double)g.nu - 1.0, std::max(-1.0, std::ceil(umax) + 1.0));
-        pl.win_r0 = (int32_t)std::max(0.0, std::min((double)g.nv, std::floor(vmin) - 1.0));
-        pl.win_r1 = (int32_t)std::min((double)g.nv - 1.0, std::max(-1.0, std::ceil(vmax) + 1.0));
-    } else {
-        pl.win_c0 = 0;
-        pl.win_c1 = g.nu - 1;
-        pl.win_r0 = 0;
-        pl.win_r1 = g.nv - 1;
+    fresh = true;
+    if (zero) {
+        hipError_t e = launch_fill_zero(b.ptr, (int64_t)b.cap, st);
+        if (e != hipSuccess) return fail_hip(e, "fill");
     }
+    return PN_OK;
 }
 
 template <typename T>
@@ -509,7 +159,10 @@ int upload(T **dst, const std::vector<T> &src)
 }
 
 // Looks up or builds the plan of a geometry.  Caller holds g_mu.
-int get_plan(const pn_geometry *pg, Plan **out)
+// Looks up or builds the plan of a geometry for calls on stream `st`; a
+// call under capture pins the plan it uses and cannot build one.  Caller
+// holds g_mu.
+int get_plan(const pn_geometry *pg, hipStream_t st, Plan **out)
 {
     Geo g;
     int rc = normalise_geometry(pg, g);
@@ -517,68 +170,26 @@ int get_plan(const pn_geometry *pg, Plan **out)
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
-    for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
-        if ((*it)->device == dev && (*it)->g.same(g)) {
-            if (it != g_plans.begin()) g_plans.splice(g_plans.begin(), g_plans, it);
-            *out = g_plans.front().get();
-            return PN_OK;
-        }
+    const bool cap = capturing(st);
+    Plan *found = g_plans.find([&](const Plan &p) { return p.device == dev && p.g.same(g); });
+    if (found) {
+        if (cap) found->pinned = true;
+        *out = found;
+        return PN_OK;
     }
+    if (cap) return capture_error("the first call with this geometry");
     auto pl = std::make_unique<Plan>();
     pl->g = std::move(g);
     pl->device = dev;
-    build_tables(*pl);
+    build_host_tables(pl->g, *pl);
     if ((rc = upload(&pl->d_tab, pl->tab))) return rc;
     if ((rc = upload(&pl->d_tabf, pl->tabf))) return rc;
     for (int a = 0; a < 3; ++a)
         if ((rc = upload(&pl->d_views[a], pl->pass_views[a]))) return rc;
-    if ((rc = upload(&pl->d_maxabs, std::vector<uint32_t>(1, 0u)))) return rc;
     if ((rc = upload(&pl->d_vwin, pl->vwin))) return rc;
     if ((rc = upload(&pl->d_axbox, pl->axbox))) return rc;
-    g_plans.push_front(std::move(pl));
-    while (g_plans.size() > kMaxPlans) g_plans.pop_back();
-    *out = g_plans.front().get();
+    *out = g_plans.insert(std::move(pl), kMaxPlans);
     return PN_OK;
-}
-
-int check_ptr(const void *p, int32_t dt, const char *name)
-{
-    if (!p) return fail(PN_EINVAL, "%s is NULL", name);
-    if ((uintptr_t)p % (uintptr_t)esize(dt)) return fail(PN_EINVAL, "%s is not %lld-byte aligned", name,
-                                                         (long long)esize(dt));
-    return PN_OK;
-}
-
-int common_checks(int64_t batch, int32_t in_dt, int32_t out_dt)
-{
-    if (!dtype_ok(in_dt)) return fail(PN_EDTYPE, "unknown input dtype %d", in_dt);
-    if (!dtype_ok(out_dt)) return fail(PN_EDTYPE, "unknown output dtype %d", out_dt);
-    if (batch < 0 || batch > 65535) return fail(PN_EINVAL, "batch = %lld out of range", (long long)batch);
-    return PN_OK;
-}
-
-// Pointer checks; a buffer with no elements may be NULL (as torch passes it).
-int buffer_checks(const void *in, bool in_empty, const void *out, bool out_empty, int32_t in_dt, int32_t out_dt)
-{
-    int rc;
-    if (!in_empty && (rc = check_ptr(in, in_dt, "input"))) return rc;
-    if (!out_empty && (rc = check_ptr(out, out_dt, "output"))) return rc;
-    if (!in_empty && in == out) return fail(PN_EINVAL, "input and output alias");
-    return PN_OK;
-}
-
-// Argument checks that need no device: dtypes, batch, then (after the
-// geometry) the pointers.  Runs before anything is allocated or enqueued.
-int preflight(const pn_geometry *pg, int64_t batch, const void *in, const void *out, int32_t in_dt, int32_t out_dt,
-              bool sino_is_input, Geo &g)
-{
-    int rc = common_checks(batch, in_dt, out_dt);
-    if (rc) return rc;
-    if (batch == 0) return PN_OK;
-    if ((rc = normalise_geometry(pg, g))) return rc;
-    const bool sino_empty = g.n_views == 0;
-    return sino_is_input ? buffer_checks(in, sino_empty, out, false, in_dt, out_dt)
-                         : buffer_checks(in, false, out, sino_empty, in_dt, out_dt);
 }
 
 int ensure_work_copy(Plan &pl, int a, int32_t dt, int64_t batch, hipStream_t st)
@@ -589,25 +200,11 @@ int ensure_work_copy(Plan &pl, int a, int32_t dt, int64_t batch, hipStream_t st)
     const int64_t plane = (int64_t)row * (g.n[sl] + PADR_LO + PADR_HI);
     const int64_t item = plane * g.n[a];
     const size_t need = (size_t)(item * batch * esize(dt));
-    bool zero = pl.lay_dtype[a] != dt;
-    if (need > pl.lay_cap[a]) {
-        dev_free(pl.d_lay[a]);
-        pl.d_lay[a] = nullptr;
-        pl.lay_cap[a] = 0;
-        hipError_t e = hipMalloc(&pl.d_lay[a], need);
-        if (e != hipSuccess) {
-            pl.d_lay[a] = nullptr;
-            return fail(PN_ENOMEM, "work copy hipMalloc(%zu): %s", need, hipGetErrorString(e));
-        }
-        pl.lay_cap[a] = need;
-        zero = true;
-    }
-    if (zero) {
-        // padding must read as zero; the interior is rewritten on every call
-        hipError_t e = launch_fill_zero(pl.d_lay[a], (int64_t)pl.lay_cap[a], st);
-        if (e != hipSuccess) return fail_hip(e, "fill");
-        pl.lay_dtype[a] = dt;
-    }
+    // padding must read as zero: a fresh copy (new, or laid out for another
+    // storage type) is cleared; the interior is rewritten on every call
+    bool fresh;
+    int rc = ensure_buf(pl, pl.lay[a], need, dt, true, st, "work copy", fresh);
+    if (rc) return rc;
     pl.lay_item[a] = item;
     pl.lay_plane[a] = plane;
     pl.lay_row[a] = row;
@@ -718,16 +315,19 @@ int forward_prepare(const pn_geometry *pg, int64_t batch, const void *vol, void 
     p.nv = g.nv;
     p.batch = (int32_t)batch;
     int rc;
+    // every work copy is made ready before anything is launched, so a call
+    // refused under capture enqueues nothing
+    for (int a = 0; a < 3; ++a)
+        if ((pl->axes_union >> a & 1) && (rc = ensure_work_copy(*pl, a, in_dt, batch, st))) return rc;
     for (int a = 0; a < 3; ++a) {
         p.n[a] = g.n[a];
         p.s[a] = g.s[a];
         p.lay[a] = nullptr;
         if (pl->axes_union >> a & 1) {
-            if ((rc = ensure_work_copy(*pl, a, in_dt, batch, st))) return rc;
-            hipError_t e = launch_relayout(in_dt, vol, pl->d_lay[a], g.n, a, (int32_t)batch, pl->lay_item[a],
+            hipError_t e = launch_relayout(in_dt, vol, pl->lay[a].ptr, g.n, a, (int32_t)batch, pl->lay_item[a],
                                            pl->lay_row[a], pl->lay_plane[a], st);
             if (e != hipSuccess) return fail_hip(e, "relayout launch");
-            p.lay[a] = pl->d_lay[a];
+            p.lay[a] = pl->lay[a].ptr;
             p.lay_item[a] = pl->lay_item[a];
             p.lay_plane[a] = pl->lay_plane[a];
             p.lay_row[a] = pl->lay_row[a];
@@ -788,29 +388,19 @@ int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, i
         target = static_cast<float *>(vol);
     } else {
         const size_t need = (size_t)total * 4;
-        if (need > pl->acc_cap) {
-            dev_free(pl->d_acc);
-            pl->d_acc = nullptr;
-            pl->acc_cap = 0;
-            hipError_t e = hipMalloc((void **)&pl->d_acc, need);
-            if (e != hipSuccess) {
-                pl->d_acc = nullptr;
-                return fail(PN_ENOMEM, "adjoint accumulator hipMalloc(%zu): %s", need, hipGetErrorString(e));
-            }
-            pl->acc_cap = need;
-        }
-        target = pl->d_acc;
+        bool fresh;
+        int rc = ensure_buf(*pl, pl->acc, need, 0, false, st, "adjoint accumulator", fresh);
+        if (rc) return rc;
+        target = static_cast<float *>(pl->acc.ptr);
     }
     const bool two_d = g.ndim == 2;
     const int shape = two_d ? 0 : (force_shape ? force_shape : plan_adjoint_shape(pl));
     int32_t L, TS, TF;
     adjoint_shape(shape, L, TS, TF);
-    {
-        hipError_t e = launch_maxabs(in_dt, sino, (int64_t)g.n_views * g.nv * g.nu * batch, pl->d_maxabs, st);
-        if (e != hipSuccess) return fail_hip(e, "maxabs launch");
-    }
-    // |s (.) delta| / |delta_a| <= |s| because delta_a is the largest component
-    const float ds_bound = (float)(std::sqrt(g.s[0] * g.s[0] + g.s[1] * g.s[1] + g.s[2] * g.s[2]) * 1.0001);
+    // a flush period of the adjoint holds >= 256 units of its first batch's
+    // max|q ds| (and one view's worth at least), a power of two
+    float kunits = 256.0f;
+    while (kunits < pl->kmax) kunits *= 2.0f;
     int done = 0;
     for (int a = 0; a < 3; ++a) {
         AdjParams &p = job.pass[a];
@@ -819,12 +409,7 @@ int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, i
         const int f = a == 0 ? 1 : 0, sl = a == 2 ? 1 : 2;
         p.tab = pl->d_tab;
         p.tabf = pl->d_tabf;
-        p.maxabs = pl->d_maxabs;
-        p.ds_bound = ds_bound;
-        // a flush period holds >= 256 units of max|q ds| (and one view's
-        // worth at least); the rounding error of a contribution is
-        // <= kunits max|q ds| / 2^30
-        p.kunits = std::max(256.0f, pl->kmax);
+        p.kunits = kunits;
         p.point_source = g.parallel ? 0 : 1;
         p.views = pl->d_views[a];
         p.n_pass_views = (int32_t)pl->pass_views[a].size();
@@ -846,20 +431,17 @@ int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, i
         if (adjoint_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
         // candidate boxes depend on the geometry and the block shape only:
         // built once per plan and shape (a kernel on the caller's stream)
-        if (pl->cbox_shape[a] != shape) {
-            dev_free(pl->d_cbox[a]);
-            pl->d_cbox[a] = nullptr;
-            pl->cbox_shape[a] = -1;
+        {
             const size_t need = (size_t)p.blocks_a * p.blocks_s * p.blocks_f * p.n_pass_views * 8;
-            hipError_t e = hipMalloc((void **)&pl->d_cbox[a], need);
-            if (e != hipSuccess) {
-                pl->d_cbox[a] = nullptr;
-                return fail(PN_ENOMEM, "candidate box hipMalloc(%zu): %s", need, hipGetErrorString(e));
+            bool fresh;
+            int rc = ensure_buf(*pl, pl->cbox[a], need, shape, false, st, "candidate boxes", fresh);
+            if (rc) return rc;
+            if (fresh) {
+                hipError_t e = launch_cbox(p, pl->d_axbox, L, TS, TF, static_cast<uint32_t *>(pl->cbox[a].ptr), st);
+                if (e != hipSuccess) return fail_hip(e, "cbox launch");
             }
-            if ((e = launch_cbox(p, pl->d_axbox, L, TS, TF, pl->d_cbox[a], st)) != hipSuccess) return fail_hip(e, "cbox launch");
-            pl->cbox_shape[a] = shape;
         }
-        p.cbox = pl->d_cbox[a];
+        p.cbox = static_cast<const uint32_t *>(pl->cbox[a].ptr);
         ++done;
     }
     job.two_d = two_d;
@@ -912,7 +494,7 @@ int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *si
     if (rc || batch == 0) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *pl;
-    if ((rc = get_plan(pg, &pl))) return rc;
+    if ((rc = get_plan(pg, st, &pl))) return rc;
     FwdJob job;
     bool none;
     if ((rc = forward_prepare(pg, batch, vol, sino, in_dt, out_dt, st, pl, job, none)) || none) return rc;
@@ -929,7 +511,7 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
     if (rc || batch == 0) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *pl;
-    if ((rc = get_plan(pg, &pl))) return rc;
+    if ((rc = get_plan(pg, st, &pl))) return rc;
     AdjJob job;
     bool none;
     auto run = [&](int force) -> int {
@@ -995,7 +577,7 @@ int backproject_impl(const pn_geometry *pg, int64_t batch, const void *sino, voi
     if (rc || batch == 0) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *pl;
-    if ((rc = get_plan(pg, &pl))) return rc;
+    if ((rc = get_plan(pg, st, &pl))) return rc;
     BpJob job;
     backproject_prepare(batch, sino, vol, pl, job);
     hipError_t e = launch_backproject(job.p, in_dt, out_dt, st);
@@ -1026,7 +608,7 @@ int filter_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *ou
     }
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *pl;
-    if ((rc = get_plan(pg, &pl))) return rc;
+    if ((rc = get_plan(pg, st, &pl))) return rc;
     const Geo &g = pl->g;
     FiltParams p{};
     p.tab = pl->d_tab;
@@ -1173,7 +755,7 @@ int batch_order(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t out_d
         Geo g;
         int rc = preflight(&probs[i].geom, 1, probs[i].in, probs[i].out, in_dt, out_dt, sino_is_input, g);
         if (rc) {
-            std::string msg = t_err;
+            std::string msg = pn_last_error();
             return fail(rc, "problem %d: %s", i, msg.c_str());
         }
         cost[i] = (double)g.n_views * g.nu * g.nv * std::max(g.n[0], std::max(g.n[1], g.n[2]));
@@ -1206,15 +788,16 @@ int make_batch(const std::vector<Job> &jobs, const std::vector<int> &idx, Blocks
 // problem i, and `launch(pending)` runs a list of prepared problems, at
 // most kMaxBatch and no plan twice.
 template <typename Prepare, typename Launch>
-int run_batched(const pn_problem *probs, const std::vector<int32_t> &order, Prepare prepare, Launch launch)
+int run_batched(const pn_problem *probs, const std::vector<int32_t> &order, hipStream_t st, Prepare prepare,
+                Launch launch)
 {
     std::vector<int32_t> pending;
     std::vector<Plan *> plans;
     for (int32_t i : order) {
         Plan *pl;
-        int rc = get_plan(&probs[i].geom, &pl);
+        int rc = get_plan(&probs[i].geom, st, &pl);
         if (rc) {
-            std::string msg = t_err;
+            std::string msg = pn_last_error();
             return fail(rc, "problem %d: %s", i, msg.c_str());
         }
         const bool seen = std::find(plans.begin(), plans.end(), pl) != plans.end();
@@ -1224,7 +807,7 @@ int run_batched(const pn_problem *probs, const std::vector<int32_t> &order, Prep
             plans.clear();
         }
         if ((rc = prepare(i, pl))) {
-            std::string msg = t_err;
+            std::string msg = pn_last_error();
             return fail(rc, "problem %d: %s", i, msg.c_str());
         }
         pending.push_back(i);
@@ -1264,7 +847,7 @@ int forward_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t o
         }
         return (int)PN_OK;
     };
-    return run_batched(probs, order, prepare, launch);
+    return run_batched(probs, order, st, prepare, launch);
 }
 
 int adjoint_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t out_dt, hipStream_t st)
@@ -1304,7 +887,7 @@ int adjoint_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t o
         }
         return (int)PN_OK;
     };
-    return run_batched(probs, order, prepare, launch);
+    return run_batched(probs, order, st, prepare, launch);
 }
 
 int backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32_t out_dt, hipStream_t st)
@@ -1333,27 +916,7 @@ int backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32
         }
         return (int)PN_OK;
     };
-    return run_batched(probs, order, prepare, launch);
-}
-
-// ------------------------------------------------ matrix composition -----
-
-int cone_one(const double *S, const double *C, const double *eu, const double *ev, int64_t rows, int64_t cols,
-             double *P)
-{
-    double d00[3], M[9], Mi[9];
-    for (int i = 0; i < 3; ++i) d00[i] = C[i] - 0.5 * (cols - 1) * eu[i] - 0.5 * (rows - 1) * ev[i];
-    for (int i = 0; i < 3; ++i) {
-        M[3 * i] = eu[i];
-        M[3 * i + 1] = ev[i];
-        M[3 * i + 2] = d00[i] - S[i];
-    }
-    if (!inv3(M, Mi)) return -1;
-    for (int r = 0; r < 3; ++r) {
-        for (int c = 0; c < 3; ++c) P[4 * r + c] = Mi[3 * r + c];
-        P[4 * r + 3] = -(Mi[3 * r] * S[0] + Mi[3 * r + 1] * S[1] + Mi[3 * r + 2] * S[2]);
-    }
-    return 0;
+    return run_batched(probs, order, st, prepare, launch);
 }
 
 }  // namespace
@@ -1365,42 +928,42 @@ extern "C" {
 int pn_forward(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dtype,
                int32_t out_dtype, void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return forward_impl(pg, batch, vol, sino, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dtype,
                int32_t out_dtype, void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return adjoint_impl(pg, batch, sino, vol, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dtype,
                    int32_t out_dtype, void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return backproject_impl(pg, batch, sino, vol, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_filter(const pn_geometry *pg, int64_t batch, const void *sino, void *out, int32_t in_dtype,
               int32_t out_dtype, int32_t kind, void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return filter_impl(pg, batch, sino, out, in_dtype, out_dtype, kind, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_gaussian_noise(int64_t n, void *data, int32_t dtype, double mean, double sigma, uint64_t seed,
                       void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return noise_impl(n, data, dtype, mean, sigma, seed, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_gantry_blur(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, const void *in, void *out,
                    int32_t dtype, double angle_start, double angle_step, int32_t taps, void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return blur_impl(batch, n_views, rows, cols, in, out, dtype, angle_start, angle_step, taps,
                      static_cast<hipStream_t>(hip_stream));
 }
@@ -1408,7 +971,7 @@ int pn_gantry_blur(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, c
 int pn_detector_jitter(int64_t n_rows, int32_t cols, const void *in, void *out, int32_t dtype, int32_t max_shift,
                        uint64_t seed, void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return jitter_impl(n_rows, cols, in, out, dtype, max_shift, seed, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -1416,133 +979,39 @@ int pn_ring_artifacts(int64_t batch, int32_t n_views, int32_t rows, int32_t cols
                       const int32_t *columns, int32_t n_columns, double gain, int32_t v0, int32_t v1,
                       void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return ring_impl(batch, n_views, rows, cols, sino, dtype, columns, n_columns, gain, v0, v1,
                      static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_forward_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype, void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return forward_batched(probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_adjoint_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype, void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return adjoint_batched(probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
                            void *hip_stream)
 {
-    t_err.clear();
+    clear_error();
     return backproject_batched(probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
-int pn_check_geometry(const pn_geometry *pg)
-{
-    t_err.clear();
-    Geo g;
-    return normalise_geometry(pg, g);
-}
-
-int pn_cone_matrices(int64_t n_views, const double *S, const double *C, const double *eu, const double *ev,
-                     int64_t rows, int64_t cols, double *P_out)
-{
-    t_err.clear();
-    if (n_views < 0 || rows < 1 || cols < 1) return fail(PN_EINVAL, "bad sizes");
-    if (n_views > 0 && (!S || !C || !eu || !ev || !P_out)) return fail(PN_EINVAL, "NULL vector");
-    for (int64_t k = 0; k < n_views; ++k)
-        if (cone_one(S + 3 * k, C + 3 * k, eu + 3 * k, ev + 3 * k, rows, cols, P_out + 12 * k))
-            return fail(PN_EGEOM, "view %lld: degenerate source/detector vectors", (long long)k);
-    return PN_OK;
-}
-
-int pn_fan_matrices(int64_t n_views, const double *S, const double *C, const double *eu, int64_t cols,
-                    double *P_out)
-{
-    t_err.clear();
-    if (n_views < 0 || cols < 1) return fail(PN_EINVAL, "bad sizes");
-    if (n_views > 0 && (!S || !C || !eu || !P_out)) return fail(PN_EINVAL, "NULL vector");
-    for (int64_t k = 0; k < n_views; ++k) {
-        const double *s = S + 2 * k, *c = C + 2 * k, *e = eu + 2 * k;
-        double d0[2] = {c[0] - 0.5 * (cols - 1) * e[0], c[1] - 0.5 * (cols - 1) * e[1]};
-        // M = [eu | d0 - S], P = M^-1 [I | -S]
-        double m00 = e[0], m01 = d0[0] - s[0], m10 = e[1], m11 = d0[1] - s[1];
-        double det = m00 * m11 - m01 * m10;
-        double sc = std::sqrt(m00 * m00 + m10 * m10) * std::sqrt(m01 * m01 + m11 * m11);
-        if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * sc)
-            return fail(PN_EGEOM, "view %lld: degenerate source/detector vectors", (long long)k);
-        double i00 = m11 / det, i01 = -m01 / det, i10 = -m10 / det, i11 = m00 / det;
-        double *P = P_out + 6 * k;
-        P[0] = i00;
-        P[1] = i01;
-        P[2] = -(i00 * s[0] + i01 * s[1]);
-        P[3] = i10;
-        P[4] = i11;
-        P[5] = -(i10 * s[0] + i11 * s[1]);
-    }
-    return PN_OK;
-}
-
-int pn_parallel2d_matrices(int64_t n_views, const double *dir, const double *C, const double *eu, int64_t cols,
-                           double *P_out)
-{
-    t_err.clear();
-    if (n_views < 0 || cols < 1) return fail(PN_EINVAL, "bad sizes");
-    if (n_views > 0 && (!dir || !C || !eu || !P_out)) return fail(PN_EINVAL, "NULL vector");
-    for (int64_t k = 0; k < n_views; ++k) {
-        const double *d = dir + 2 * k, *c = C + 2 * k, *e = eu + 2 * k;
-        // [eu | dir]^-1 (X - C) = (u - (cols-1)/2, t)
-        double det = e[0] * d[1] - d[0] * e[1];
-        double sc = std::sqrt(e[0] * e[0] + e[1] * e[1]) * std::sqrt(d[0] * d[0] + d[1] * d[1]);
-        if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * sc)
-            return fail(PN_EGEOM, "view %lld: detector axis parallel to the rays", (long long)k);
-        double r0 = d[1] / det, r1 = -d[0] / det;
-        double *P = P_out + 6 * k;
-        P[0] = r0;
-        P[1] = r1;
-        P[2] = -(r0 * c[0] + r1 * c[1]) + 0.5 * (cols - 1);
-        P[3] = 0.0;
-        P[4] = 0.0;
-        P[5] = 1.0;
-    }
-    return PN_OK;
-}
-
-int pn_parallel3d_matrices(int64_t n_views, const double *dir, const double *C, const double *eu, const double *ev,
-                           int64_t rows, int64_t cols, double *P_out)
-{
-    t_err.clear();
-    if (n_views < 0 || rows < 1 || cols < 1) return fail(PN_EINVAL, "bad sizes");
-    if (n_views > 0 && (!dir || !C || !eu || !ev || !P_out)) return fail(PN_EINVAL, "NULL vector");
-    for (int64_t k = 0; k < n_views; ++k) {
-        const double *d = dir + 3 * k, *c = C + 3 * k, *e = eu + 3 * k, *f = ev + 3 * k;
-        double M[9] = {e[0], f[0], d[0], e[1], f[1], d[1], e[2], f[2], d[2]}, Mi[9];
-        if (!inv3(M, Mi)) return fail(PN_EGEOM, "view %lld: degenerate direction/detector vectors", (long long)k);
-        double *P = P_out + 12 * k;
-        const double off[2] = {0.5 * (cols - 1), 0.5 * (rows - 1)};
-        for (int r = 0; r < 2; ++r) {
-            for (int j = 0; j < 3; ++j) P[4 * r + j] = Mi[3 * r + j];
-            P[4 * r + 3] = -(Mi[3 * r] * c[0] + Mi[3 * r + 1] * c[1] + Mi[3 * r + 2] * c[2]) + off[r];
-        }
-        P[8] = P[9] = P[10] = 0.0;
-        P[11] = 1.0;
-    }
-    return PN_OK;
-}
-
-const char *pn_last_error(void) { return t_err.c_str(); }
-
 int pn_release_caches(void)
 {
-    t_err.clear();
+    clear_error();
     std::lock_guard<std::mutex> lk(g_mu);
     g_plans.clear();
+    g_keeper.release_retired();
     return PN_OK;
 }
 
-const char *pn_version(void) { return "pyronn_mi 0.1.0 (gfx950)"; }
+const char *pn_version(void) { return "pyronn_mi 0.2.0 (gfx950)"; }
 
 }  // extern "C"

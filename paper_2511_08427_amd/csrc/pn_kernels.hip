@@ -900,6 +900,10 @@ hipError_t launch_cbox(const AdjParams &ap, const uint32_t *axbox, int32_t L, in
     return hipGetLastError();
 }
 
+// A flush period of the adjoint ends early when a batch's rays are more than
+// 2^kQuietBits times quieter than the period's scale is made for.
+constexpr int kQuietBits = 2;
+
 // Each workgroup owns a block of L planes (dominant axis A) x TS rows x TF
 // columns of the output.  Its FP32 sums live in registers (each thread owns
 // L*TS*TF/256 voxels); per batch of candidate rays they are gathered in LDS
@@ -921,17 +925,21 @@ hipError_t launch_cbox(const AdjParams &ap, const uint32_t *axbox, int32_t L, in
 //            clears them (and once at the end).
 // A ray samples a voxel's plane once with weight <= 1, and at most kcell
 // rays of a view sample within one voxel of a given voxel (a per-view bound
-// from the geometry), so a batch adds at most min(rays, kcell) x max|q*ds|
-// to any voxel; the flush keeps the sum of these bounds since the last
-// flush, times the fixed-point scale, below 2^30.  The scale is one power
-// of two for the launch: it maps kunits (>= 256, >= every kcell) times the
-// largest possible |q*ds| (max|q| over the sinogram times the ray length
-// bound |s|) into [2^29, 2^30), so the rounding error of a contribution is
-// at most kunits max|q*ds| / 2^30 (2.4e-7 max|q*ds| for kunits = 256;
-// round to nearest, so the errors of a voxel's contributions partly
-// cancel).  Integer addition is exact and order-independent and the
-// flushes happen at the same points in every run, so the result is
-// deterministic.
+// from the geometry), so a batch adds at most min(rays, kcell) x qmax to any
+// voxel, qmax being the batch's largest |q*ds| (gathered in phase A).  The
+// fixed-point scale is a power of two per flush period of the workgroup:
+// the first batch of a period sets it so that kunits (a power of two,
+// >= 256 and >= every kcell) times its qmax lies in [2^29, 2^30).  A batch
+// whose bound would take the period's running sum past 2^30, or whose qmax
+// needs a scale more than 2^kQuietBits larger (a much quieter batch), flushes
+// and starts a new period at its own scale.  The rounding error of a
+// contribution is therefore at most kunits 2^(kQuietBits+1) 2^-31 times the
+// qmax of its own batch (round to nearest, so errors partly cancel): the
+// accuracy follows the magnitude of the rays that reach the block, not the
+// sinogram's global maximum, and each batch item has its own scales.
+// Integer addition is exact and order-independent and the flushes happen
+// at the same points in every run, so the result is deterministic.  A
+// non-finite q*ds among a batch's rays turns the block's output into NaN.
 //
 // SLO/SHI: halo rows below/above the block in the slow in-plane direction
 // besides the extra row below, 1/2 in general; 0/1 for 2-D problems, whose
@@ -1005,17 +1013,14 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     if (t < 4) s_cnt[t >> 1][t & 1] = 0u;
     __syncthreads();
 
-    // fixed-point scale of the launch: 2^e with kunits qlim 2^e in [2^29, 2^30)
-    const float qlim = __uint_as_float(*p.maxabs) * p.ds_bound;
-    const float ulim = qlim * p.kunits;
-    float e = 0.0f;
-    if (ulim > 0.0f)
-        e = isfinite(ulim) ? fminf(fmaxf(static_cast<float>(30 - __builtin_amdgcn_frexp_expf(ulim)), -126.0f), 126.0f)
-                           : 200.0f;
-    const float scale = e > 150.0f ? 0.0f : exp2f(e);
-    // a non-finite sinogram value (no scale) turns every voxel into NaN
-    const float inv_scale = e > 150.0f ? __int_as_float(0x7fc00000) : exp2f(-e);
-    float pending = 0.0f;  // bound of |integer sum| since the last flush
+    // fixed-point scale of the current flush period, 2^ecur; `pending`
+    // bounds the period's integer sums (no period open before the first
+    // batch with a non-zero contribution)
+    int ecur = 0;
+    bool open = false, poisoned = false;
+    float scale = 1.0f, inv_scale = 1.0f;
+    float pending = 0.0f;
+    const int ku = __builtin_amdgcn_frexp_expf(p.kunits) - 1;  // kunits = 2^ku
     auto flush = [&]() {
         // flushes are rare: recompute the cell addresses rather than keep
         // them in registers across the whole kernel
@@ -1190,17 +1195,33 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
             const uint32_t cnts = s_cnt[parity][0];
             const int nray = static_cast<int>(cnts & 0xffff);
             const int nseg_all = static_cast<int>(cnts >> 16);
-            const float qmax = __uint_as_float(s_cnt[parity][1]);
+            const uint32_t qbits = s_cnt[parity][1];
+            const float qmax = __uint_as_float(qbits);
             if (t < 2) s_cnt[parity ^ 1][t] = 0u;
-            // the batch adds at most min(nray, kcell) x qmax to a voxel
-            const float add = fminf(static_cast<float>(nray), kcell) * qmax * scale;
-            if (pending + add > 1073741824.0f) {
-                flush();
-                pending = 0.0f;
-                __syncthreads();  // cells cleared before the scatter
+            // a batch whose rays all carry q*ds = 0 adds nothing; a non-finite
+            // q*ds poisons the block (uniform decisions: LDS values)
+            if (qbits >= 0x7f800000u) poisoned = true;
+            const bool live = nray > 0 && qbits != 0u && qbits < 0x7f800000u;
+            if (live) {
+                // the scale this batch alone would take: kunits qmax 2^eb in
+                // [2^29, 2^30); the batch adds at most min(nray, kcell) x qmax
+                // to a voxel
+                const int eb = min(126, max(-126, 30 - ku - __builtin_amdgcn_frexp_expf(qmax)));
+                const float nb = fminf(static_cast<float>(nray), kcell) * qmax;
+                if (!open || pending + nb * scale > 1073741824.0f || eb > ecur + kQuietBits) {
+                    if (open) {
+                        flush();
+                        __syncthreads();  // cells cleared before the scatter
+                    }
+                    ecur = eb;
+                    scale = exp2f(static_cast<float>(eb));
+                    inv_scale = exp2f(static_cast<float>(-eb));
+                    pending = 0.0f;
+                    open = true;
+                }
+                pending += nb * scale;
             }
-            pending += add;
-            for (int se = t; se < nseg_all; se += NT) {
+            for (int se = t; se < (live ? nseg_all : 0); se += NT) {
                 const uint32_t srec = s_seg[se];
                 const int slot = srec & 0xffff, la0 = (srec >> 16) & 0xff, cnt = srec >> 24;
                 const float4 rp = s_ray[slot];
@@ -1243,7 +1264,10 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
             parity ^= 1;
         }
     }
-    flush();
+    if (open) flush();
+    if (poisoned)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) reg[q] = __int_as_float(0x7fc00000);
 
     // write the block; the memory-contiguous axis x runs fastest
     const int64_t item = static_cast<int64_t>(p.n[0]) * p.n[1] * p.n[2];
@@ -1276,49 +1300,6 @@ __global__ __launch_bounds__(NT, 4) void adjoint_batch_kernel(Batch<AdjParams> w
 {
     const int i = batch_item(w, blockIdx.x);
     adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT, NT>(w.p[i], blockIdx.x - w.start[i]);
-}
-
-// max |x| over a buffer, as the bit pattern of a non-negative float
-// (integer order = float order; NaN compares above +inf), combined with a
-// global atomic max.  A 16-byte aligned buffer is read as 16-byte vectors
-// (`vec`), the tail and unaligned buffers element by element.
-template <typename Q>
-__global__ __launch_bounds__(256) void maxabs_kernel(const Q *__restrict__ src, int64_t n, int32_t vec,
-                                                     uint32_t *__restrict__ out)
-{
-    constexpr int VE = Vec<Q>::N;
-    const int64_t nvec = vec ? n / VE : 0;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    uint32_t m = 0u;
-    const uint4 *v = reinterpret_cast<const uint4 *>(src);
-    // four independent 16-byte loads in flight per thread
-    int64_t e = t0;
-    for (; e + 3 * stride < nvec; e += 4 * stride) {
-        uint4 x[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = v[e + u * stride];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            float f[VE];
-            unpack16<Q>(x[u], f);
-#pragma unroll
-            for (int k = 0; k < VE; ++k) m = max(m, __float_as_uint(fabsf(f[k])));
-        }
-    }
-    for (; e < nvec; e += stride) {
-        float f[VE];
-        unpack16<Q>(v[e], f);
-#pragma unroll
-        for (int k = 0; k < VE; ++k) m = max(m, __float_as_uint(fabsf(f[k])));
-    }
-    for (int64_t e = nvec * VE + t0; e < n; e += stride) m = max(m, __float_as_uint(fabsf(to_f32(src[e]))));
-    // one global atomic per workgroup (same-address atomics serialise)
-    __shared__ uint32_t s_m[4];
-    m = wave_max_u32(m);
-    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) atomicMax(out, max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3])));
 }
 
 // ------------------------------------------------ back-projection --------
@@ -2176,22 +2157,6 @@ hipError_t launch_backproject_batch(const Batch<BpParams> &w, bool two_d, int32_
                                     hipStream_t st)
 {
     return bp_any(w, two_d, w.start[w.n], in_dt, out_dt, st);
-}
-
-hipError_t launch_maxabs(int32_t in_dt, const void *src, int64_t n, uint32_t *out, hipStream_t st)
-{
-    fill_zero_kernel<<<1, 64, 0, st>>>(out, 1);
-    int64_t blocks = (n / 8 + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    if (blocks < 1) blocks = 1;
-    const dim3 g(static_cast<uint32_t>(blocks));
-    const int32_t vec = reinterpret_cast<uintptr_t>(src) % 16 == 0;
-    switch (in_dt) {
-    case DT_F32: maxabs_kernel<float><<<g, 256, 0, st>>>(static_cast<const float *>(src), n, vec, out); break;
-    case DT_BF16: maxabs_kernel<bf16><<<g, 256, 0, st>>>(static_cast<const bf16 *>(src), n, vec, out); break;
-    default: maxabs_kernel<f16><<<g, 256, 0, st>>>(static_cast<const f16 *>(src), n, vec, out); break;
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st)

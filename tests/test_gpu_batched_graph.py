@@ -120,3 +120,86 @@ def test_graph_capture_replays_match_eager(pn):
         assert torch.equal(a, a_ref), f"replay {rep}: adjoint"
         for o, r in zip(b, b_ref):
             assert torch.equal(o, r), f"replay {rep}: batched forward"
+
+
+def test_graph_replays_after_evictions_larger_batch_and_new_type(pn):
+    """A plan used under capture is pinned: 40 other geometries (more than
+    the 32 plans the cache keeps), a batch of 2 (the work copies grow) and
+    BF16 storage on the same geometry (new layouts, an accumulator) leave
+    the graph's memory alone, and every replay equals the eager result."""
+    _say("graph lifetime: capture, then evictions, a larger batch, another type")
+    shp, sp, det, ds = (20, 22, 18), (0.8, 0.8, 0.8), (26, 28), (1.2, 1.2)
+    g = pn.cone_geometry(shp, sp, det, ds, 16, 400.0, 650.0)
+    x = torch.from_numpy(W.ellipsoid_phantom_3d(32, shp, sp, 6)[0]).float().cuda()
+    y_ref = pn.forward(x, g)
+    a_ref = pn.adjoint(y_ref, g)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pn.adjoint(pn.forward(x, g), g)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        y = pn.forward(x, g)
+        a = pn.adjoint(y, g)
+    torch.cuda.synchronize()
+    others = [pn.cone_geometry((10 + i % 5, 12, 11), (1.0, 1.0, 1.0), (14, 16), (1.5, 1.5), 5 + i, 400.0, 650.0)
+              for i in range(40)]
+    for go in others:
+        pn.forward(torch.ones(go.vol_shape, device="cuda"), go)
+    x2 = torch.stack([x, 0.5 * x])
+    y2 = pn.forward(x2, g)
+    a2 = pn.adjoint(y2, g)
+    xb = x.to(torch.bfloat16)
+    yb = pn.forward(xb, g)
+    ab = pn.adjoint(yb, g)
+    torch.cuda.synchronize()
+    assert torch.equal(y2[0], y_ref) and torch.equal(a2[0], a_ref)
+    assert yb.dtype == torch.bfloat16 and ab.dtype == torch.bfloat16
+    for rep in range(3):
+        pn.forward(x2, g)
+        pn.adjoint(yb, g)
+        torch.cuda.synchronize()
+        y.zero_()
+        a.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_ref), f"replay {rep}: forward"
+        assert torch.equal(a, a_ref), f"replay {rep}: adjoint"
+
+
+def test_capture_refuses_calls_that_would_allocate(pn):
+    """Under capture a call with a geometry never run eagerly, or a batch
+    larger than the eager one, returns PN_EINVAL and enqueues nothing; the
+    rest of the capture replays correctly."""
+    _say("graph capture: refused calls")
+    shp, sp, det, ds = (16, 18, 14), (0.9, 0.9, 0.9), (22, 24), (1.3, 1.3)
+    g = pn.cone_geometry(shp, sp, det, ds, 12, 420.0, 700.0)
+    g_new = pn.cone_geometry(shp, sp, det, ds, 13, 420.0, 700.0)
+    x = torch.from_numpy(W.ellipsoid_phantom_3d(33, shp, sp, 5)[0]).float().cuda()
+    y_ref = pn.forward(x, g)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pn.forward(x, g)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    x3 = torch.stack([x, x, x])
+    graph = torch.cuda.CUDAGraph()
+    errors = []
+    with torch.cuda.graph(graph):
+        for args in ((x, g_new), (x3, g)):
+            try:
+                pn.forward(*args)
+            except pn.PnError as e:
+                errors.append(str(e))
+        y = pn.forward(x, g)
+    assert len(errors) == 2 and all("capturing" in e for e in errors), errors
+    for rep in range(2):
+        y.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_ref), f"replay {rep}"
