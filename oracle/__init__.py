@@ -345,6 +345,23 @@ def backproject_voxels(sino, g, i, j, k, nthreads=0):
     return out
 
 
+def splat(vol, g, nthreads=0):
+    """Transpose of ``backproject``: each voxel's (W0/W)^2-weighted value
+    spread over the bilinear taps of its projection; returns
+    [n_views][rows][cols]."""
+    lib = _load()
+    keep, pn, ps, po, pP = _geo_args(g)
+    nv, nu = g["det"]
+    nviews = g["P"].shape[0]
+    v, pv = _f64(vol)
+    assert v.size == g["n"][0] * g["n"][1] * g["n"][2]
+    out = np.zeros((nviews, nv, nu), dtype=np.float64)
+    lib.oracle_splat(
+        ctypes.c_int(g["dims"]), pn, ps, po, ctypes.c_int64(nviews), pP, ctypes.c_int64(nv), ctypes.c_int64(nu),
+        pv, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads))
+    return out
+
+
 def ray_taps(g, view, row, col):
     """(voxel linear indices, weights*ds) of one ray: a row of the matrix A."""
     lib = _load()

@@ -26,6 +26,10 @@
  *                  padding, weighted by (W0/W)^2 and summed over views
  *                  (Sec. 2.1; the distance weight is the FDK weight, with
  *                  W0 the W coordinate of the world origin).
+ *   splat          the transpose of back-project, its analytic gradient
+ *                  (Sec. 2: gradients for all operators): each voxel's
+ *                  weighted value is spread over the interpolation taps of
+ *                  its projection.
  *
  * Conventions (all readings of the paper, which fixes none of them):
  *   volume     array [nz][ny][nx], voxel (i,j,k) centre at
@@ -467,6 +471,63 @@ int oracle_backproject_voxels(int dims, const int64_t n[3], const double s[3], c
 #pragma omp parallel for schedule(static)
     for (int64_t t = 0; t < n_vox; ++t)
         out[t] = bp_voxel(&g, dims, n_views, P, nv, nu, sino, vi[t], vj[t], vk[t]);
+    return 0;
+}
+
+/* Transpose of the voxel-driven back-projection (the splat projector):
+ * every voxel centre is projected onto each view's detector and its value,
+ * times the distance weight (W0/W)^2, is spread over the (bi)linear
+ * interpolation taps of its projection (zero padding: taps off the detector
+ * are dropped), so that <backproject(q), x> = <q, splat(x)>.  sino:
+ * [n_views][nv][nu], overwritten.  Parallel over views. */
+int oracle_splat(int dims, const int64_t n[3], const double s[3], const double o[3], int64_t n_views,
+                 const double *P, int64_t nv, int64_t nu, const double *vol, double *sino, int nthreads)
+{
+    grid_t g;
+    make_grid(&g, n, s, o);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t view = 0; view < n_views; ++view) {
+        double *img = sino + view * nv * nu;
+        for (int64_t e = 0; e < nv * nu; ++e) img[e] = 0.0;
+        for (int64_t k = 0; k < g.n[2]; ++k)
+            for (int64_t j = 0; j < g.n[1]; ++j)
+                for (int64_t i = 0; i < g.n[0]; ++i) {
+                    const double val = vol[(k * g.n[1] + j) * g.n[0] + i];
+                    const double x = g.o[0] + (double)i * g.s[0];
+                    const double y = g.o[1] + (double)j * g.s[1];
+                    const double z = g.o[2] + (double)k * g.s[2];
+                    double u, v = 0.0, W, W0;
+                    if (dims == 2) {
+                        const double *p = P + view * 6;
+                        W = p[3] * x + p[4] * y + p[5];
+                        u = (p[0] * x + p[1] * y + p[2]) / W;
+                        W0 = p[5];
+                    } else {
+                        const double *p = P + view * 12;
+                        W = p[8] * x + p[9] * y + p[10] * z + p[11];
+                        u = (p[0] * x + p[1] * y + p[2] * z + p[3]) / W;
+                        v = (p[4] * x + p[5] * y + p[6] * z + p[7]) / W;
+                        W0 = p[11];
+                    }
+                    const double wt = (W0 / W) * (W0 / W) * val;
+                    const double fu = floor(u), wu = u - fu;
+                    const double fv = floor(v), wv = v - fv;
+                    const int64_t iu = (int64_t)fu, iv = (int64_t)fv;
+                    for (int tv = 0; tv < (dims == 2 ? 1 : 2); ++tv) {
+                        const int64_t r = iv + tv;
+                        if (r < 0 || r >= nv) continue;
+                        const double fvw = dims == 2 ? 1.0 : (tv ? wv : 1.0 - wv);
+                        for (int tu = 0; tu < 2; ++tu) {
+                            const int64_t c = iu + tu;
+                            if (c < 0 || c >= nu) continue;
+                            img[r * nu + c] += wt * fvw * (tu ? wu : 1.0 - wu);
+                        }
+                    }
+                }
+    }
     return 0;
 }
 

@@ -35,6 +35,9 @@ C_MUTANTS = [
      "double q = sino[(k * nv + r) * nu + (nu - 1 - c)];"),
     ("3-D parallel base point sign", "ray->x0[i] = ca * a[i] + cb * b[i];", "ray->x0[i] = ca * a[i] - cb * b[i];"),
     ("2-D parallel base point sign", "ray->x0[0] = a * t;", "ray->x0[0] = -a * t;"),
+    ("splat distance weight dropped", "const double wt = (W0 / W) * (W0 / W) * val;", "const double wt = val;"),
+    ("splat column taps swapped", "img[r * nu + c] += wt * fvw * (tu ? wu : 1.0 - wu);",
+     "img[r * nu + c] += wt * fvw * (tu ? 1.0 - wu : wu);"),
 ]
 
 

@@ -449,6 +449,81 @@ def test_oracle_reproduces_stored_fixture(O):
     assert np.abs(p - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+# -------------------------------------------- splat (transpose of BP) ----
+
+
+def _splat_cases(O):
+    yield "fan2d", (1, 5, 6), O.circular_fan((5, 6), (1.0, 0.8), 9, 0.7, 4, 2 * math.pi, 20.0, 35.0)
+    yield "parallel2d", (1, 5, 5), O.parallel_2d((5, 5), (1.0, 1.0), 7, 0.9, 5, math.pi)
+    yield "cone3d", (4, 4, 5), O.circular_cone((4, 4, 5), (1.0, 1.0, 0.8), (5, 5), (1.1, 1.0), 3, 2 * math.pi,
+                                               25.0, 40.0)
+    import workloads as W
+
+    draws = W.perturbation_draws(5, 3)
+    args = (3, 2 * math.pi, 25.0, 40.0, (6, 7), (1.0, 1.2), (4, 5, 4), (0.9, 1.0, 1.1))
+    P = np.stack([O.cone_matrix(*v, (6, 7)) for v in zip(*O.trajectory_vectors("perturbed", *args, draws=draws))])
+    yield "cone3d_perturbed", (4, 5, 4), O.cone_geometry((4, 5, 4), (0.9, 1.0, 1.1), (6, 7), (1.0, 1.2), P)
+
+
+def test_splat_is_the_transpose_of_backprojection(O):
+    """Column i of the explicit back-projection matrix is the back-projection
+    of unit sinogram i; column j of its transpose is the splat of unit
+    voxel j.  They agree entry by entry (4 geometries)."""
+    for name, shape, g in _splat_cases(O):
+        nviews = g["P"].shape[0]
+        nv, nu = g["det"]
+        npix, nvox = nviews * nv * nu, int(np.prod(shape))
+        B = np.zeros((nvox, npix))
+        for i in range(npix):
+            e = np.zeros(npix)
+            e[i] = 1.0
+            B[:, i] = O.backproject(e.reshape(nviews, nv, nu), g).ravel()
+        Bt = np.zeros((npix, nvox))
+        for j in range(nvox):
+            e = np.zeros(nvox)
+            e[j] = 1.0
+            Bt[:, j] = O.splat(e.reshape(shape), g).ravel()
+        assert np.abs(B).max() > 0.1, name
+        assert np.abs(Bt - B.T).max() <= 1e-14 * np.abs(B).max(), name
+
+
+def test_splat_dot_product(O):
+    rng = np.random.default_rng(21)
+    g = O.circular_cone((9, 11, 10), (0.7, 0.8, 0.9), (13, 15), (1.0, 1.1), 7, 2 * math.pi, 60.0, 100.0)
+    x = rng.standard_normal((9, 11, 10))
+    q = rng.standard_normal((7, 13, 15))
+    lhs = float(np.sum(O.backproject(q, g) * x))
+    rhs = float(np.sum(q * O.splat(x, g)))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
+
+
+def test_splat_deposits_weight_at_the_pinhole_projection(O):
+    """A single voxel projecting inside the detector deposits, per view, the
+    total weight (W0/W)^2 with its centroid at the projected (u, v): bilinear
+    weights sum to one and reproduce linear functions.  (u, v, W) come from
+    an independent pinhole camera K [R | t] with focal length SDD / pitch."""
+    shape, sp, det, dd, sid, sdd, nviews = (5, 6, 7), (1.0, 1.0, 1.0), (15, 17), (0.9, 0.8), 50.0, 80.0, 6
+    g = O.circular_cone(shape, sp, det, dd, nviews, 2 * math.pi, sid, sdd)
+    for (k, j, i) in [(2, 3, 3), (0, 0, 6), (4, 5, 1)]:
+        e = np.zeros(shape)
+        e[k, j, i] = 1.0
+        out = O.splat(e, g)
+        X = np.array([(i - 3) * sp[2], (j - 2.5) * sp[1], (k - 2) * sp[0]])
+        for view in range(nviews):
+            b = 2 * math.pi * view / nviews
+            # camera frame: depth along -(cos b, sin b, 0) from the source,
+            # image axes e_u = (-sin b, cos b, 0), e_v = +z
+            Xc = X - sid * np.array([math.cos(b), math.sin(b), 0.0])
+            depth = -Xc @ np.array([math.cos(b), math.sin(b), 0.0])
+            u = sdd * (Xc @ np.array([-math.sin(b), math.cos(b), 0.0])) / depth / dd[1] + (det[1] - 1) / 2
+            v = sdd * Xc[2] / depth / dd[0] + (det[0] - 1) / 2
+            w = (sid / depth) ** 2
+            img = out[view]
+            rr, cc = np.meshgrid(np.arange(det[0]), np.arange(det[1]), indexing="ij")
+            assert abs(img.sum() - w) < 1e-12
+            assert abs((img * cc).sum() / w - u) < 1e-10 and abs((img * rr).sum() / w - v) < 1e-10
+
+
 # ------------------------------------------------------------------ FBP ----
 
 
