@@ -148,6 +148,19 @@ int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol
 int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
                    int32_t in_dtype, int32_t out_dtype, void *hip_stream);
 
+/* Transpose of pn_backproject (the splat projector), the analytic gradient
+ * of the back-projection with respect to its sinogram (Sec. 2: gradients
+ * for all operators): vol [batch][nz][ny][nx] (in_dtype) -> sino
+ * [batch][n_views][rows][cols] (out_dtype), where every voxel's value times
+ * (W0/W)^2 is spread over the bilinear taps of its projection (taps off the
+ * detector are dropped), so that <pn_backproject(q), x> = <q, pn_splat(x)>.
+ * Deposits gather per block of voxels in fixed point and are added to the
+ * sinogram with float atomics: the result is not bitwise reproducible
+ * (differences are FP32 rounding).  A 16-bit output is accumulated in an
+ * FP32 buffer of the plan and rounded at the end. */
+int pn_splat(const pn_geometry *pg, int64_t batch, const void *vol, void *sino,
+             int32_t in_dtype, int32_t out_dtype, void *hip_stream);
+
 /* Row filter of the filtered back-projection (Sec. 2.2: the reconstruction
  * is the back-projection of the sinogram filtered along detector rows by a
  * diagonal Fourier-domain filter).  out = (pi / N) (1 / a) g * (c p) along

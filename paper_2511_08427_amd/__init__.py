@@ -20,6 +20,7 @@ from .geometry import (
 )
 from .ops import (
     AdjointProjection,
+    BackProjection,
     ConeBackProjection3D,
     ConeProjection3D,
     FanBackProjection2D,
@@ -39,6 +40,8 @@ from .ops import (
     gantry_blur,
     gaussian_noise_,
     ring_artifacts_,
+    splat,
+    SplatProjection,
     unrolled_gd,
 )
 

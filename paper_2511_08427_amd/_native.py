@@ -30,6 +30,7 @@ EXPORTS = (
     "pn_forward",
     "pn_adjoint",
     "pn_backproject",
+    "pn_splat",
     "pn_forward_batched",
     "pn_adjoint_batched",
     "pn_backproject_batched",
@@ -85,7 +86,7 @@ def _load():
     gp = ctypes.POINTER(PnGeometry)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     dp = ctypes.POINTER(ctypes.c_double)
-    for name in ("pn_forward", "pn_adjoint", "pn_backproject"):
+    for name in ("pn_forward", "pn_adjoint", "pn_backproject", "pn_splat"):
         f = getattr(lib, name)
         f.argtypes = [gp, i64, vp, vp, i32, i32, vp]
         f.restype = ctypes.c_int

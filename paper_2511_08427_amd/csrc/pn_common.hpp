@@ -86,6 +86,15 @@ struct BpParams {
     void *vol;
 };
 
+// Splat projector (transpose of the voxel-driven back-projection).
+struct SplatParams {
+    const ViewTabF *tabf;
+    int32_t n_views, nu, nv, batch;
+    int32_t n[3];
+    const void *vol;       // [batch][nz][ny][nx]
+    float *sino;           // FP32 [batch][n_views][nv][nu], zeroed, accumulated into
+};
+
 constexpr int kRingMaxCols = 256;
 
 struct NoiseParams {

@@ -24,6 +24,8 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
 hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
+hipError_t launch_splat(const SplatParams &p, int32_t in_dt, hipStream_t st);
+int64_t splat_blocks(const SplatParams &p);
 hipError_t launch_cbox(const AdjParams &ap, const uint32_t *axbox, int32_t L, int32_t TS, int32_t TF, uint32_t *out,
                        hipStream_t st);
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st);
@@ -87,8 +89,9 @@ struct Plan : HostTables {
     DevBuf lay[3];
     int64_t lay_item[3] = {0, 0, 0}, lay_plane[3] = {0, 0, 0};
     int32_t lay_row[3] = {0, 0, 0};
-    // FP32 accumulation buffer of the adjoint for 16-bit outputs
-    DevBuf acc;
+    // FP32 accumulation buffers for 16-bit outputs: the adjoint's volume,
+    // the splat projector's sinogram
+    DevBuf acc, sacc;
     // 3-D adjoint block shape chosen by the autotuner (0: not tuned)
     int adj_shape = 0;
     // adjoint candidate pixel boxes per pass axis (tag: block shape)
@@ -106,6 +109,7 @@ struct Plan : HostTables {
             g_keeper.free(cbox[a]);
         }
         g_keeper.free(acc);
+        g_keeper.free(sacc);
     }
 };
 
@@ -585,6 +589,42 @@ int backproject_impl(const pn_geometry *pg, int64_t batch, const void *sino, voi
     return PN_OK;
 }
 
+int splat_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt, int32_t out_dt,
+               hipStream_t st)
+{
+    Geo pre;
+    int rc = preflight(pg, batch, vol, sino, in_dt, out_dt, false, pre);
+    if (rc || batch == 0) return rc;
+    if (pre.n_views == 0) return PN_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *pl;
+    if ((rc = get_plan(pg, st, &pl))) return rc;
+    const Geo &g = pl->g;
+    const int64_t total = (int64_t)g.n_views * g.nv * g.nu * batch;
+    float *target = static_cast<float *>(sino);
+    if (out_dt != PN_F32) {
+        bool fresh;
+        if ((rc = ensure_buf(*pl, pl->sacc, (size_t)total * 4, 0, false, st, "splat accumulator", fresh))) return rc;
+        target = static_cast<float *>(pl->sacc.ptr);
+    }
+    SplatParams p{};
+    p.tabf = pl->d_tabf;
+    p.n_views = g.n_views;
+    p.nu = g.nu;
+    p.nv = g.nv;
+    p.batch = (int32_t)batch;
+    for (int a = 0; a < 3; ++a) p.n[a] = g.n[a];
+    p.vol = vol;
+    p.sino = target;
+    if (splat_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
+    hipError_t e = launch_fill_zero(target, total * 4, st);
+    if (e != hipSuccess) return fail_hip(e, "fill");
+    if ((e = launch_splat(p, in_dt, st)) != hipSuccess) return fail_hip(e, "splat launch");
+    if (out_dt != PN_F32 && (e = launch_convert(target, sino, out_dt, total, st)) != hipSuccess)
+        return fail_hip(e, "convert launch");
+    return PN_OK;
+}
+
 int filter_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *out, int32_t in_dt, int32_t out_dt,
                 int32_t kind, hipStream_t st)
 {
@@ -944,6 +984,13 @@ int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void 
 {
     clear_error();
     return backproject_impl(pg, batch, sino, vol, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_splat(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dtype, int32_t out_dtype,
+             void *hip_stream)
+{
+    clear_error();
+    return splat_impl(pg, batch, vol, sino, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_filter(const pn_geometry *pg, int64_t batch, const void *sino, void *out, int32_t in_dtype,

@@ -1547,6 +1547,226 @@ __global__ __launch_bounds__(256, 8) void backproject_batch_kernel(Batch<BpParam
     backproject_block<Q, O, BZ, RCAP, CCAP>(w.p[i], blockIdx.x - w.start[i]);
 }
 
+// ------------------------------------------------------ splat (BP^T) ----
+
+// Transpose of the voxel-driven back-projection: every voxel's value times
+// the distance weight (W0/W)^2 is spread over the bilinear taps of its
+// projection in each view; taps off the detector are dropped.  A workgroup
+// owns the same 16 x 16 x BZ block as the back-projection, its values in
+// registers (a z-column of BZ voxels per thread).  Per view, the block's
+// deposits collect in an LDS copy of the detector rectangle the block
+// projects into (the back-projection's rectangle), as 32-bit fixed point
+// with one power-of-two scale per view: the block's max |x| times the view's
+// largest weight (W0 / min W over the block's corners)^2 times the number of
+// voxels of the block stays below 2^30, so no sum can overflow; the error of
+// a deposit is at most 2^-31 of that bound.  Integer adds are exact, so the
+// rectangle is independent of the order of the deposits.  The rectangle is
+// then added to the FP32 sinogram with one hardware float atomic per non-zero
+// pixel, which a pixel receives from every block along its ray: the result
+// is not bitwise reproducible (the order of those adds varies).  Two LDS
+// rectangles alternate between views, one barrier per view.  Rectangles
+// larger than RCAP x CCAP, and blocks holding a non-finite value, deposit
+// straight into the sinogram with one float atomic per tap.
+template <typename S, int BZ, int RCAP, int CCAP>
+__device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
+{
+    constexpr int BX = 16, BY = 16, CHUNK = 256;
+    constexpr int NE = RCAP * CCAP;
+    constexpr int PER = (NE + 255) / 256;
+    __shared__ int s_acc[2][NE];
+    __shared__ int4 s_rect[CHUNK];
+    __shared__ float s_scale[CHUNK];
+    __shared__ uint32_t s_max[4];
+    const int t = threadIdx.x;
+    const int nbx = (p.n[0] + BX - 1) / BX, nby = (p.n[1] + BY - 1) / BY, nbz = (p.n[2] + BZ - 1) / BZ;
+    int blk = bid;
+    const int bx = blk % nbx;
+    blk /= nbx;
+    const int by = blk % nby;
+    blk /= nby;
+    const int bz = blk % nbz;
+    const int b = blk / nbz;
+    const int i0 = bx * BX, j0 = by * BY, k0 = bz * BZ;
+    const int i1 = min(i0 + BX, p.n[0]) - 1, j1 = min(j0 + BY, p.n[1]) - 1, k1 = min(k0 + BZ, p.n[2]) - 1;
+    const int i = i0 + t % BX, j = j0 + t / BX;
+    const bool own = i <= i1 && j <= j1;
+    const float fi = static_cast<float>(i), fj = static_cast<float>(j), fk0 = static_cast<float>(k0);
+    const float fnu = static_cast<float>(p.nu), fnv = static_cast<float>(p.nv);
+    float *sino = p.sino + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
+
+    // the thread's voxel values and the block's max |x|
+    float x[BZ];
+    uint32_t mbits = 0u;
+    const S *vol = static_cast<const S *>(p.vol) + static_cast<int64_t>(b) * p.n[0] * p.n[1] * static_cast<int64_t>(p.n[2]);
+#pragma unroll
+    for (int z = 0; z < BZ; ++z) {
+        const int k = k0 + z;
+        x[z] = (own && k <= k1) ? to_f32(vol[(static_cast<int64_t>(k) * p.n[1] + j) * p.n[0] + i]) : 0.0f;
+        mbits = max(mbits, __float_as_uint(fabsf(x[z])));
+    }
+    mbits = wave_max_u32(mbits);
+    if ((t & 63) == 0) s_max[t >> 6] = mbits;
+    for (int e = t; e < 2 * NE; e += 256) s_acc[e / NE][e % NE] = 0;
+    __syncthreads();
+    mbits = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+    if (mbits == 0u) return;                       // nothing to deposit (uniform)
+    const bool finite = mbits < 0x7f800000u;       // else: straight float atomics
+    const float xmax = __uint_as_float(mbits);
+    constexpr float kVox = static_cast<float>(BX * BY * BZ);
+
+    // detector rectangle and fixed-point scale of the block for one view
+    auto rect_of = [&](int view, float &scale) {
+        const ViewTabF &tf = p.tabf[view];
+        float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, wmin = INFINITY;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float ci = static_cast<float>((c & 1) ? i1 : i0);
+            const float cj = static_cast<float>((c & 2) ? j1 : j0);
+            const float ck = static_cast<float>((c & 4) ? k1 : k0);
+            const float U = fmaf(tf.Pi[0], ci, fmaf(tf.Pi[1], cj, fmaf(tf.Pi[2], ck, tf.Pi[3])));
+            const float V = fmaf(tf.Pi[4], ci, fmaf(tf.Pi[5], cj, fmaf(tf.Pi[6], ck, tf.Pi[7])));
+            const float Wc = fmaf(tf.Pi[8], ci, fmaf(tf.Pi[9], cj, fmaf(tf.Pi[10], ck, tf.Pi[11])));
+            const float u = U / Wc, v = V / Wc;
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
+            vmin = fminf(vmin, v);
+            vmax = fmaxf(vmax, v);
+            wmin = fminf(wmin, Wc);
+        }
+        umin = fminf(fmaxf(umin - 0.01f, -1.0f), fnu);
+        umax = fminf(fmaxf(umax + 0.01f, -1.0f), fnu);
+        vmin = fminf(fmaxf(vmin - 0.01f, -1.0f), fnv);
+        vmax = fminf(fmaxf(vmax + 0.01f, -1.0f), fnv);
+        const int u0 = static_cast<int>(floorf(umin)), v0 = static_cast<int>(floorf(vmin));
+        const int nc = static_cast<int>(floorf(umax)) + 2 - u0, nr = static_cast<int>(floorf(vmax)) + 2 - v0;
+        const bool any = !(umax <= -1.0f || umin >= fnu || vmax <= -1.0f || vmin >= fnv);
+        const bool lds = finite && nc <= CCAP && nr <= RCAP;
+        // bound of a rectangle cell's sum: every voxel's |x| (W0/W)^2 (a
+        // corner's W is the smallest over the convex block; 1% slack)
+        const float w0 = tf.W0 / wmin;
+        const float bound = xmax * w0 * w0 * 1.01f * kVox;
+        const int e = min(126, max(-126, 30 - __builtin_amdgcn_frexp_expf(bound)));
+        scale = exp2f(static_cast<float>(e));
+        return make_int4(u0, v0, nc | nr << 16, static_cast<int>(any) | static_cast<int>(lds) << 1);
+    };
+    auto rect_at = [&](int e) {
+        const int4 r = s_rect[e];
+        return make_int4(__builtin_amdgcn_readfirstlane(r.x), __builtin_amdgcn_readfirstlane(r.y),
+                         __builtin_amdgcn_readfirstlane(r.z), __builtin_amdgcn_readfirstlane(r.w));
+    };
+    // deposits the rectangle of view `view` (buffer buf) into the sinogram
+    // and clears it
+    auto flush = [&](int view, const int4 &rc, float inv, int buf) {
+        if ((rc.w & 3) != 3) return;
+        const int nc = rc.z & 0xffff, nr = rc.z >> 16;
+        float *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q;
+            if (e >= NE) break;
+            const int v = s_acc[buf][e];
+            if (v == 0) continue;
+            s_acc[buf][e] = 0;
+            const int rr = e / CCAP, cc = e - rr * CCAP;
+            const int r = rc.y + rr, c = rc.x + cc;
+            if (rr < nr && cc < nc && static_cast<uint32_t>(r) < static_cast<uint32_t>(p.nv) &&
+                static_cast<uint32_t>(c) < static_cast<uint32_t>(p.nu))
+                unsafeAtomicAdd(img + static_cast<int64_t>(r) * p.nu + c, static_cast<float>(v) * inv);
+        }
+    };
+
+    for (int c0 = 0; c0 < p.n_views; c0 += CHUNK) {
+        const int cn = min(CHUNK, p.n_views - c0);
+        __syncthreads();  // the previous chunk's table is no longer read
+        if (t < cn) {
+            float sc;
+            s_rect[t] = rect_of(c0 + t, sc);
+            s_scale[t] = sc;
+        }
+        __syncthreads();
+        for (int vi = 0; vi < cn; ++vi) {
+            const int view = c0 + vi, buf = view & 1;
+            const int4 now = rect_at(vi);
+            const float scale = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(s_scale[vi])));
+            if (own && (now.w & 1)) {
+                const ViewTabF &tf = p.tabf[view];
+                const float uo = static_cast<float>(now.x), vo = static_cast<float>(now.y);
+                const int nc = now.z & 0xffff, nr = now.z >> 16;
+                float *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
+                const bool column = BZ > 1 && tf.Pi[2] == 0.0f && tf.Pi[10] == 0.0f;
+                const float U0 = fmaf(tf.Pi[0], fi, fmaf(tf.Pi[1], fj, fmaf(tf.Pi[2], fk0, tf.Pi[3])));
+                const float V0 = fmaf(tf.Pi[4], fi, fmaf(tf.Pi[5], fj, fmaf(tf.Pi[6], fk0, tf.Pi[7])));
+                const float Wb = fmaf(tf.Pi[8], fi, fmaf(tf.Pi[9], fj, fmaf(tf.Pi[10], fk0, tf.Pi[11])));
+                if (now.w & 2) {
+                    // positions relative to the rectangle, clamped to it as in
+                    // the back-projection (a clamped position deposits only
+                    // off the detector, which the flush drops)
+                    const float hu = fminf(fnu - uo, static_cast<float>(nc - 1) - 1e-3f);
+                    const float hv = fminf(fnv - vo, static_cast<float>(nr - 1) - 1e-3f);
+                    const float lu = fmaxf(-1.0f - uo, 0.0f), lv = fmaxf(-1.0f - vo, 0.0f);
+                    int *acc = s_acc[buf];
+#pragma unroll
+                    for (int z = 0; z < BZ; ++z) {
+                        if (x[z] == 0.0f) continue;
+                        const float fz = static_cast<float>(z);
+                        const float rw = __builtin_amdgcn_rcpf(column ? Wb : fmaf(fz, tf.Pi[10], Wb));
+                        const float u = __builtin_amdgcn_fmed3f(fmaf(column ? U0 : fmaf(fz, tf.Pi[2], U0), rw, -uo), lu, hu);
+                        const float v = __builtin_amdgcn_fmed3f(fmaf(fmaf(fz, tf.Pi[6], V0), rw, -vo), lv, hv);
+                        const float wu = __builtin_amdgcn_fractf(u), wv = __builtin_amdgcn_fractf(v);
+                        const float w = tf.W0 * rw;
+                        const float qs = x[z] * (w * w) * scale;
+                        const float t1 = qs * wv, t0 = qs - t1;
+                        const float c01 = t0 * wu, c11 = t1 * wu;
+                        int *q = acc + __mul24(static_cast<int>(v), CCAP) + static_cast<int>(u);
+                        atomicAdd(q, round_fixed(t0 - c01));
+                        atomicAdd(q + 1, round_fixed(c01));
+                        atomicAdd(q + CCAP, round_fixed(t1 - c11));
+                        atomicAdd(q + CCAP + 1, round_fixed(c11));
+                    }
+                } else {
+                    // straight to the sinogram, bounds-checked, one atomic per tap
+#pragma unroll 1
+                    for (int z = 0; z < BZ; ++z) {
+                        if (x[z] == 0.0f) continue;
+                        const float fz = static_cast<float>(z);
+                        const float Wc = fmaf(fz, tf.Pi[10], Wb);
+                        const float rw = 1.0f / Wc;
+                        const float u = fminf(fmaxf(fmaf(fz, tf.Pi[2], U0) * rw, -2.0f), fnu + 1.0f);
+                        const float v = fminf(fmaxf(fmaf(fz, tf.Pi[6], V0) * rw, -2.0f), fnv + 1.0f);
+                        const float fu = floorf(u), fv = floorf(v);
+                        const float wu = u - fu, wv = v - fv;
+                        const int iu = static_cast<int>(fu), iv = static_cast<int>(fv);
+                        const float w = tf.W0 * rw;
+                        const float val = x[z] * w * w;
+#pragma unroll
+                        for (int tv = 0; tv < 2; ++tv) {
+                            const int r = iv + tv;
+                            if (r < 0 || r >= p.nv) continue;
+                            const float a = (tv ? wv : 1.0f - wv) * val;
+#pragma unroll
+                            for (int tu = 0; tu < 2; ++tu) {
+                                const int c = iu + tu;
+                                if (c < 0 || c >= p.nu) continue;
+                                unsafeAtomicAdd(img + static_cast<int64_t>(r) * p.nu + c, (tu ? wu : 1.0f - wu) * a);
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();  // this view's deposits are complete
+            // flush this view's rectangle now; the next view deposits into the
+            // other buffer, flushed and cleared one view ago
+            flush(view, now, 1.0f / scale, buf);
+        }
+    }
+}
+
+template <typename S, int BZ, int RCAP, int CCAP>
+__global__ __launch_bounds__(256, 6) void splat_kernel(SplatParams p)
+{
+    splat_block<S, BZ, RCAP, CCAP>(p, blockIdx.x);
+}
+
 // ------------------------------------------------------- FBP filter ------
 
 // Row filter of the filtered back-projection: per detector row, the cosine
@@ -2157,6 +2377,33 @@ hipError_t launch_backproject_batch(const Batch<BpParams> &w, bool two_d, int32_
                                     hipStream_t st)
 {
     return bp_any(w, two_d, w.start[w.n], in_dt, out_dt, st);
+}
+
+int64_t splat_blocks(const SplatParams &p)
+{
+    const int64_t bz = p.n[2] == 1 ? 1 : (p.n[2] + kBpDepth - 1) / kBpDepth;
+    return static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * bz * p.batch;
+}
+
+template <typename S>
+static hipError_t splat_s(const SplatParams &p, uint32_t blocks, hipStream_t st)
+{
+    if (p.n[2] == 1)
+        splat_kernel<S, 1, 4, 64><<<dim3(blocks), 256, 0, st>>>(p);
+    else
+        splat_kernel<S, kBpDepth, kBpRows, kBpCols><<<dim3(blocks), 256, 0, st>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_splat(const SplatParams &p, int32_t in_dt, hipStream_t st)
+{
+    const int64_t blocks = splat_blocks(p);
+    if (blocks == 0) return hipSuccess;
+    switch (in_dt) {
+    case DT_F32: return splat_s<float>(p, static_cast<uint32_t>(blocks), st);
+    case DT_BF16: return splat_s<bf16>(p, static_cast<uint32_t>(blocks), st);
+    default: return splat_s<f16>(p, static_cast<uint32_t>(blocks), st);
+    }
 }
 
 hipError_t launch_fill_zero(void *dst, int64_t bytes, hipStream_t st)

@@ -6,9 +6,12 @@ call into the native library, which runs the gfx950 kernels:
   forward(vol, geom)      A     -> pn_forward
   adjoint(sino, geom)     A^T   -> pn_adjoint
   backproject(sino, geom)       -> pn_backproject (voxel-driven, (W0/W)^2)
+  splat(vol, geom)        B^T   -> pn_splat (transpose of the back-projection)
 
 ``Projection`` is the autograd pair: its backward is the exact adjoint
-kernel, so gradients of any loss of A x are analytic (Sec. 2).  The layer
+kernel, so gradients of any loss of A x are analytic (Sec. 2);
+``BackProjection``'s backward is the splat projector, the exact transpose
+of the voxel-driven back-projection.  The layer
 classes mirror the paper's naming (Listing 1).
 """
 from __future__ import annotations
@@ -70,6 +73,12 @@ def adjoint(sino, geom: Geometry, out_dtype=None):
 def backproject(sino, geom: Geometry, out_dtype=None):
     """Voxel-driven (W0/W)^2-weighted back-projection: sino -> volume."""
     return _run(N.lib.pn_backproject, "pn_backproject", geom, sino, geom.sino_shape(), geom.vol_shape, out_dtype)
+
+
+def splat(vol, geom: Geometry, out_dtype=None):
+    """Transpose of ``backproject`` (pn_splat): every voxel's (W0/W)^2-weighted
+    value spread over the bilinear taps of its projection; volume -> sino."""
+    return _run(N.lib.pn_splat, "pn_splat", geom, vol, geom.vol_shape, geom.sino_shape(), out_dtype)
 
 
 _FILTERS = {"ram-lak": 0, "shepp-logan": 1}
@@ -231,16 +240,33 @@ class AdjointProjection(torch.autograd.Function):
         return forward(grad.contiguous(), ctx.geom, out_dtype=ctx.sino_dtype), None
 
 
-class _BackProjection(torch.autograd.Function):
+class BackProjection(torch.autograd.Function):
+    """x = B q (voxel-driven back-projection); dL/dq = B^T dL/dx (the splat
+    projector)."""
+
     @staticmethod
     def forward(ctx, sino, geom):
+        ctx.geom = geom
+        ctx.sino_dtype = sino.dtype
         return backproject(sino, geom)
 
     @staticmethod
     def backward(ctx, grad):
-        raise NotImplementedError(
-            "the gradient of the voxel-driven back-projection (a voxel-driven splat projector) is not "
-            "implemented; use AdjointProjection for a differentiable A^T")
+        return splat(grad.contiguous(), ctx.geom, out_dtype=ctx.sino_dtype), None
+
+
+class SplatProjection(torch.autograd.Function):
+    """y = B^T x (splat projector); dL/dx = B dL/dy (the back-projection)."""
+
+    @staticmethod
+    def forward(ctx, vol, geom):
+        ctx.geom = geom
+        ctx.vol_dtype = vol.dtype
+        return splat(vol, geom)
+
+    @staticmethod
+    def backward(ctx, grad):
+        return backproject(grad.contiguous(), ctx.geom, out_dtype=ctx.vol_dtype), None
 
 
 class _Layer(torch.nn.Module):
@@ -266,17 +292,17 @@ class ConeProjection3D(_Layer):
 
 class ParallelBackProjection2D(_Layer):
     def forward(self, y):
-        return _BackProjection.apply(y, self.geom)
+        return BackProjection.apply(y, self.geom)
 
 
 class FanBackProjection2D(_Layer):
     def forward(self, y):
-        return _BackProjection.apply(y, self.geom)
+        return BackProjection.apply(y, self.geom)
 
 
 class ConeBackProjection3D(_Layer):
     def forward(self, y):
-        return _BackProjection.apply(y, self.geom)
+        return BackProjection.apply(y, self.geom)
 
 
 def unrolled_gd(x0, y, geom: Geometry, alpha: float, steps: int, checkpoint: bool = True):
