@@ -83,6 +83,7 @@
 #ifndef PYRONN_MI_H
 #define PYRONN_MI_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -141,6 +142,33 @@ int pn_forward(const pn_geometry *pg, int64_t batch, const void *vol, void *sino
  * ray reaches into NaN (other blocks and batch items are unaffected). */
 int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
                int32_t in_dtype, int32_t out_dtype, void *hip_stream);
+
+/* pn_adjoint for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, kernels and results as pn_adjoint (bitwise equal to it
+ * with the default adjoint block shape, i.e. without PN_AUTOTUNE or
+ * PN_ADJ_SHAPE).  It calls no hipMalloc/hipFree: its view tables, candidate
+ * boxes and, for a 16-bit output, its FP32 accumulator live in one fixed
+ * device array of PN_NOALLOC_SCRATCH_BYTES per GPU, created with the
+ * library's code object and held until the process ends.
+ *   - A call that needs more than that (large volumes, many views, a large
+ *     batch with a 16-bit output) returns PN_EINVAL, says how much it needs
+ *     in pn_last_error(), and enqueues nothing.  The 256^3 x 360-view cone
+ *     problem fits for every output type.
+ *   - The array keeps the last call's tables and boxes.  A call with the
+ *     same geometry as the previous call on this GPU enqueues only the
+ *     adjoint kernels; any other geometry first copies its tables from
+ *     pageable host memory (the copy blocks the calling thread) and builds
+ *     the boxes with a kernel.
+ *   - Under stream capture only the first kind of call is accepted (else
+ *     PN_EINVAL); a captured graph replays correctly only while no call
+ *     with another geometry has gone through this entry point on that GPU.
+ *   - Every call on one GPU uses the same array: calls that overlap in
+ *     time on one GPU (other streams, other threads) race, and the caller
+ *     must serialise them. */
+#define PN_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+int pn_adjoint_noalloc(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
+                       int32_t in_dtype, int32_t out_dtype, void *hip_stream);
 
 /* Voxel-driven (W0/W)^2-weighted back-projection: sino -> vol, shapes as
  * pn_adjoint.  A 16-bit output may overflow (F16 max 65504) for many views;

@@ -30,6 +30,7 @@ from .ops import (
     Projection,
     adjoint,
     adjoint_batched,
+    adjoint_noalloc,
     backproject,
     backproject_batched,
     detector_jitter,

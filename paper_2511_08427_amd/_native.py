@@ -29,6 +29,7 @@ ERROR_NAMES = {
 EXPORTS = (
     "pn_forward",
     "pn_adjoint",
+    "pn_adjoint_noalloc",
     "pn_backproject",
     "pn_splat",
     "pn_forward_batched",
@@ -86,7 +87,7 @@ def _load():
     gp = ctypes.POINTER(PnGeometry)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     dp = ctypes.POINTER(ctypes.c_double)
-    for name in ("pn_forward", "pn_adjoint", "pn_backproject", "pn_splat"):
+    for name in ("pn_forward", "pn_adjoint", "pn_adjoint_noalloc", "pn_backproject", "pn_splat"):
         f = getattr(lib, name)
         f.argtypes = [gp, i64, vp, vp, i32, i32, vp]
         f.restype = ctypes.c_int

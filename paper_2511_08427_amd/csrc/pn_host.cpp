@@ -36,6 +36,8 @@ hipError_t launch_ring(const RingParams &p, int32_t dt, hipStream_t st);
 hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st);
 hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st);
 hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n, hipStream_t st);
+size_t scratch_bytes();
+hipError_t scratch_address(void **out);
 int adjoint_shape_count();
 void adjoint_shape(int id, int32_t &L, int32_t &TS, int32_t &TF);
 void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv, int32_t &views);
@@ -374,6 +376,53 @@ struct AdjJob {
     int64_t total;
 };
 
+// kunits of the adjoint: a flush period holds >= 256 units of its first
+// batch's max|q ds| (and one view's worth at least), a power of two
+float adjoint_kunits(const HostTables &t)
+{
+    float kunits = 256.0f;
+    while (kunits < t.kmax) kunits *= 2.0f;
+    return kunits;
+}
+
+// Parameters of the adjoint pass over dominant axis a (block shape L x TS x
+// TF) of geometry g, with the device tables tab/tabf/views; cbox is set by
+// the caller.
+void adjoint_pass_params(const Geo &g, const HostTables &t, int a, int32_t L, int32_t TS, int32_t TF,
+                         const ViewTab *tab, const ViewTabF *tabf, const int32_t *views, int64_t batch,
+                         const void *sino, float *target, bool accumulate, AdjParams &p)
+{
+    const int f = a == 0 ? 1 : 0, sl = a == 2 ? 1 : 2;
+    p = AdjParams{};
+    p.tab = tab;
+    p.tabf = tabf;
+    p.kunits = adjoint_kunits(t);
+    p.point_source = g.parallel ? 0 : 1;
+    p.views = views;
+    p.n_pass_views = (int32_t)t.pass_views[a].size();
+    p.axis = a;
+    p.nu = g.nu;
+    p.nv = g.nv;
+    p.n_views = g.n_views;
+    p.batch = (int32_t)batch;
+    for (int i = 0; i < 3; ++i) {
+        p.n[i] = g.n[i];
+        p.s[i] = g.s[i];
+    }
+    p.sino = sino;
+    p.out = target;
+    p.accumulate = accumulate ? 1 : 0;
+    p.blocks_a = (g.n[a] + L - 1) / L;
+    p.blocks_s = (g.n[sl] + TS - 1) / TS;
+    p.blocks_f = (g.n[f] + TF - 1) / TF;
+}
+
+// Bytes of the candidate-box table of an adjoint pass.
+size_t cbox_bytes(const AdjParams &p)
+{
+    return (size_t)p.blocks_a * p.blocks_s * p.blocks_f * p.n_pass_views * 8;
+}
+
 int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, int32_t out_dt, hipStream_t st,
                     Plan *pl, AdjJob &job, bool &none, int force_shape = 0)
 {
@@ -401,44 +450,19 @@ int adjoint_prepare(int64_t batch, const void *sino, void *vol, int32_t in_dt, i
     const int shape = two_d ? 0 : (force_shape ? force_shape : plan_adjoint_shape(pl));
     int32_t L, TS, TF;
     adjoint_shape(shape, L, TS, TF);
-    // a flush period of the adjoint holds >= 256 units of its first batch's
-    // max|q ds| (and one view's worth at least), a power of two
-    float kunits = 256.0f;
-    while (kunits < pl->kmax) kunits *= 2.0f;
     int done = 0;
     for (int a = 0; a < 3; ++a) {
         AdjParams &p = job.pass[a];
         p = AdjParams{};
         if (pl->pass_views[a].empty()) continue;
-        const int f = a == 0 ? 1 : 0, sl = a == 2 ? 1 : 2;
-        p.tab = pl->d_tab;
-        p.tabf = pl->d_tabf;
-        p.kunits = kunits;
-        p.point_source = g.parallel ? 0 : 1;
-        p.views = pl->d_views[a];
-        p.n_pass_views = (int32_t)pl->pass_views[a].size();
-        p.axis = a;
-        p.nu = g.nu;
-        p.nv = g.nv;
-        p.n_views = g.n_views;
-        p.batch = (int32_t)batch;
-        for (int i = 0; i < 3; ++i) {
-            p.n[i] = g.n[i];
-            p.s[i] = g.s[i];
-        }
-        p.sino = sino;
-        p.out = target;
-        p.accumulate = done > 0;
-        p.blocks_a = (g.n[a] + L - 1) / L;
-        p.blocks_s = (g.n[sl] + TS - 1) / TS;
-        p.blocks_f = (g.n[f] + TF - 1) / TF;
+        adjoint_pass_params(g, *pl, a, L, TS, TF, pl->d_tab, pl->d_tabf, pl->d_views[a], batch, sino, target,
+                            done > 0, p);
         if (adjoint_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
         // candidate boxes depend on the geometry and the block shape only:
         // built once per plan and shape (a kernel on the caller's stream)
         {
-            const size_t need = (size_t)p.blocks_a * p.blocks_s * p.blocks_f * p.n_pass_views * 8;
             bool fresh;
-            int rc = ensure_buf(*pl, pl->cbox[a], need, shape, false, st, "candidate boxes", fresh);
+            int rc = ensure_buf(*pl, pl->cbox[a], cbox_bytes(p), shape, false, st, "candidate boxes", fresh);
             if (rc) return rc;
             if (fresh) {
                 hipError_t e = launch_cbox(p, pl->d_axbox, L, TS, TF, static_cast<uint32_t *>(pl->cbox[a].ptr), st);
@@ -571,6 +595,146 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
     }
     if ((rc = run(0)) || none) return rc;
     return adjoint_finish(job, st);
+}
+
+// ------------------------------------------- allocation-free adjoint ----
+//
+// pn_adjoint_noalloc keeps its device data in the library's fixed scratch
+// array (scratch_address(), one per GPU) instead of a plan: the FP64 and
+// FP32 view tables, the pass view lists, the axis boxes and the candidate
+// boxes of each pass, then the FP32 accumulator of a 16-bit output.  The
+// array keeps the last call's contents; the host remembers which geometry
+// they belong to, per device, and re-uses them for the same geometry.
+
+struct ScratchLayout {
+    size_t tab = 0, tabf = 0, views[3] = {0, 0, 0}, axbox = 0, cbox[3] = {0, 0, 0}, acc = 0, end = 0;
+};
+
+struct NoallocState {
+    bool valid = false;  // the array holds the tables and boxes of `g`
+    Geo g;
+    HostTables t;
+    ScratchLayout lay;
+};
+
+std::mutex g_na_mu;
+std::vector<NoallocState> g_na;  // per device
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int adjoint_noalloc_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt,
+                         int32_t out_dt, hipStream_t st)
+{
+    Geo pre;
+    int rc = preflight(pg, batch, sino, vol, in_dt, out_dt, true, pre);
+    if (rc || batch == 0) return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if ((size_t)dev >= g_na.size()) g_na.resize((size_t)dev + 1);
+    NoallocState &ns = g_na[(size_t)dev];
+    const bool two_d = pre.ndim == 2;
+    const int shape = two_d ? 0 : adjoint_shape_3d();
+    int32_t L, TS, TF;
+    adjoint_shape(shape, L, TS, TF);
+    const int64_t total = (int64_t)pre.n[0] * pre.n[1] * pre.n[2] * batch;
+    const bool reuse = ns.valid && ns.g.same(pre);
+    // host tables and the layout of the array (nothing is enqueued yet)
+    HostTables fresh_t;
+    ScratchLayout lay;
+    const HostTables &t = reuse ? ns.t : fresh_t;
+    if (reuse) {
+        lay = ns.lay;
+    } else {
+        build_host_tables(pre, fresh_t);
+        size_t off = 0;
+        lay.tab = off;
+        off = align256(off + sizeof(ViewTab) * t.tab.size());
+        lay.tabf = off;
+        off = align256(off + sizeof(ViewTabF) * t.tabf.size());
+        for (int a = 0; a < 3; ++a) {
+            lay.views[a] = off;
+            off = align256(off + sizeof(int32_t) * t.pass_views[a].size());
+        }
+        lay.axbox = off;
+        off = align256(off + sizeof(uint32_t) * t.axbox.size());
+        for (int a = 0; a < 3; ++a) {
+            lay.cbox[a] = off;
+            if (t.pass_views[a].empty()) continue;
+            AdjParams p;
+            adjoint_pass_params(pre, t, a, L, TS, TF, nullptr, nullptr, nullptr, batch, sino, nullptr, false, p);
+            off = align256(off + cbox_bytes(p));
+        }
+        lay.acc = off;
+    }
+    lay.end = lay.acc + (out_dt == PN_F32 ? 0 : (size_t)total * 4);
+    if (lay.end > scratch_bytes())
+        return fail(PN_EINVAL,
+                    "pn_adjoint_noalloc: this geometry, batch and output type need %zu bytes of scratch; the "
+                    "allocation-free entry point has %zu (use pn_adjoint)",
+                    lay.end, scratch_bytes());
+    if (!reuse && capturing(st))
+        return fail(PN_EINVAL,
+                    "pn_adjoint_noalloc: the stream is capturing and the scratch array does not hold this "
+                    "geometry's tables: call it once eagerly with the same geometry first");
+    void *base_v = nullptr;
+    if ((e = scratch_address(&base_v)) != hipSuccess) return fail_hip(e, "scratch address");
+    char *base = static_cast<char *>(base_v);
+    const ViewTab *d_tab = reinterpret_cast<const ViewTab *>(base + lay.tab);
+    const ViewTabF *d_tabf = reinterpret_cast<const ViewTabF *>(base + lay.tabf);
+    if (!reuse) {
+        // the host tables are pageable: HIP copies pageable host memory
+        // synchronously, so they may go out of scope after the call
+        ns.valid = false;
+        auto put = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+            if (bytes == 0) return hipSuccess;
+            return hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, st);
+        };
+        if ((e = put(lay.tab, t.tab.data(), sizeof(ViewTab) * t.tab.size())) != hipSuccess ||
+            (e = put(lay.tabf, t.tabf.data(), sizeof(ViewTabF) * t.tabf.size())) != hipSuccess ||
+            (e = put(lay.axbox, t.axbox.data(), sizeof(uint32_t) * t.axbox.size())) != hipSuccess)
+            return fail_hip(e, "table copy");
+        for (int a = 0; a < 3; ++a)
+            if ((e = put(lay.views[a], t.pass_views[a].data(), sizeof(int32_t) * t.pass_views[a].size())) !=
+                hipSuccess)
+                return fail_hip(e, "table copy");
+        for (int a = 0; a < 3; ++a) {
+            if (t.pass_views[a].empty()) continue;
+            AdjParams p;
+            adjoint_pass_params(pre, t, a, L, TS, TF, d_tab, d_tabf,
+                                reinterpret_cast<const int32_t *>(base + lay.views[a]), batch, sino, nullptr, false, p);
+            e = launch_cbox(p, reinterpret_cast<const uint32_t *>(base + lay.axbox), L, TS, TF,
+                            reinterpret_cast<uint32_t *>(base + lay.cbox[a]), st);
+            if (e != hipSuccess) return fail_hip(e, "cbox launch");
+        }
+        ns.g = pre;
+        ns.t = std::move(fresh_t);
+        ns.lay = lay;
+        ns.valid = true;
+    }
+    const HostTables &tt = ns.t;
+    int npass = 0;
+    for (int a = 0; a < 3; ++a) npass += tt.pass_views[a].empty() ? 0 : 1;
+    if (npass == 0) {
+        e = launch_fill_zero(vol, total * esize(out_dt), st);
+        return e == hipSuccess ? PN_OK : fail_hip(e, "fill");
+    }
+    float *target = out_dt == PN_F32 ? static_cast<float *>(vol) : reinterpret_cast<float *>(base + lay.acc);
+    int done = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (tt.pass_views[a].empty()) continue;
+        AdjParams p;
+        adjoint_pass_params(pre, tt, a, L, TS, TF, d_tab, d_tabf,
+                            reinterpret_cast<const int32_t *>(base + lay.views[a]), batch, sino, target, done > 0, p);
+        if (adjoint_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
+        p.cbox = reinterpret_cast<const uint32_t *>(base + lay.cbox[a]);
+        if ((e = launch_adjoint(p, in_dt, shape, st)) != hipSuccess) return fail_hip(e, "adjoint launch");
+        ++done;
+    }
+    if (out_dt != PN_F32 && (e = launch_convert(target, vol, out_dt, total, st)) != hipSuccess)
+        return fail_hip(e, "convert launch");
+    return PN_OK;
 }
 
 int backproject_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt,
@@ -977,6 +1141,13 @@ int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol
 {
     clear_error();
     return adjoint_impl(pg, batch, sino, vol, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_adjoint_noalloc(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dtype,
+                       int32_t out_dtype, void *hip_stream)
+{
+    clear_error();
+    return adjoint_noalloc_impl(pg, batch, sino, vol, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dtype,

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "pn_common.hpp"
 
@@ -2432,6 +2433,40 @@ hipError_t launch_convert(const float *src, void *dst, int32_t out_dt, int64_t n
     else
         convert_kernel<float><<<dim3(static_cast<uint32_t>(blocks)), 256, 0, st>>>(src, static_cast<float *>(dst), n);
     return hipGetLastError();
+}
+
+// ------------------------------------------------ allocation-free scratch --
+
+// Device memory of the allocation-free adjoint (pn_adjoint_noalloc): one
+// array per GPU, created with the code object and held until the process
+// ends.  In host code `scratch` names a host-side stand-in, not the device
+// array: host code uses only the address that scratch_address() looks up.
+constexpr size_t kScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+size_t scratch_bytes() { return kScratchBytes; }
+
+// Device address of this GPU's scratch array, looked up once per device
+// (with that device current) and kept.
+hipError_t scratch_address(void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace pn

@@ -70,6 +70,14 @@ def adjoint(sino, geom: Geometry, out_dtype=None):
     return _run(N.lib.pn_adjoint, "pn_adjoint", geom, sino, geom.sino_shape(), geom.vol_shape, out_dtype)
 
 
+def adjoint_noalloc(sino, geom: Geometry, out_dtype=None):
+    """A^T sino through pn_adjoint_noalloc: the same result as ``adjoint``
+    with no device allocation inside the library (its tables live in a
+    fixed per-GPU scratch array; calls on one GPU must not overlap)."""
+    return _run(N.lib.pn_adjoint_noalloc, "pn_adjoint_noalloc", geom, sino, geom.sino_shape(), geom.vol_shape,
+                out_dtype)
+
+
 def backproject(sino, geom: Geometry, out_dtype=None):
     """Voxel-driven (W0/W)^2-weighted back-projection: sino -> volume."""
     return _run(N.lib.pn_backproject, "pn_backproject", geom, sino, geom.sino_shape(), geom.vol_shape, out_dtype)
