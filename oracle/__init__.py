@@ -569,7 +569,9 @@ def gantry_blur(sino, angle_start, angle_step, taps):
     view k has angle a_k = angle_start + k angle_step; the kernel is the mean
     of `taps` (odd) samples at unit spacing t = -h .. h, h = (taps - 1) / 2,
     along (cos a_k, sin a_k) in detector (column, row) pixel units; samples
-    are bilinear with zeros outside the detector.  sino is
+    are bilinear with zeros outside the detector.  A single-row projection
+    (2-D sinograms) has no row direction: the turned kernel acts through its
+    column component, taps at t cos a_k along the row.  sino is
     [batch][views][rows][cols]; FP64."""
     a = np.asarray(sino, dtype=np.float64)
     nb, nv, nr, nc = a.shape
@@ -580,7 +582,7 @@ def gantry_blur(sino, angle_start, angle_step, taps):
     out = np.zeros_like(a)
     for k in range(nv):
         ang = angle_start + k * angle_step
-        du, dv = math.cos(ang), math.sin(ang)
+        du, dv = math.cos(ang), (math.sin(ang) if nr > 1 else 0.0)
         for t in range(-h, h + 1):
             x, y = cc + t * du, rr + t * dv
             x0, y0 = np.floor(x), np.floor(y)

@@ -852,3 +852,24 @@ def test_gantry_blur_matches_map_coordinates(O):
     flat = np.ones((1, 1, 4, 12))
     g0 = O.gantry_blur(flat, 0.0, 0.0, 3)
     assert np.abs(g0[..., 1:-1] - 1.0).max() < 1e-15 and np.abs(g0[..., 0] - 2.0 / 3.0).max() < 1e-15
+
+
+def test_gantry_blur_single_row_uses_the_column_component(O):
+    """A single-row projection has no row direction: the turned kernel acts
+    along the row through its column component, so a view at pi/2 is
+    unchanged, a constant row stays constant away from its ends at every
+    angle (no darkening by taps leaving the row), and a view at angle a
+    equals zero-padded np.interp samples at c + t cos a."""
+    rng = np.random.default_rng(6)
+    s = rng.random((2, 4, 1, 30))
+    got = O.gantry_blur(s, 0.0, math.pi / 2, 5)
+    assert np.abs(got[:, 1] - s[:, 1]).max() < 1e-15 and np.abs(got[:, 3] - s[:, 3]).max() < 1e-12
+    flat = O.gantry_blur(np.ones((1, 5, 1, 40)), 0.1, 0.6, 7)
+    assert np.abs(flat[..., 4:-4] - 1.0).max() < 1e-12
+    a = 0.7
+    one = O.gantry_blur(s[:, :1], a, 0.0, 5)
+    c, cp = np.arange(30.0), np.arange(-1.0, 31.0)
+    for b in range(2):
+        row = np.pad(s[b, 0, 0], 1)
+        ref = sum(np.interp(c + t * math.cos(a), cp, row, left=0.0, right=0.0) for t in range(-2, 3)) / 5
+        assert np.abs(one[b, 0, 0] - ref).max() < 1e-12
