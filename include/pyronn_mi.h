@@ -239,7 +239,8 @@ int pn_detector_jitter(int64_t n_rows, int32_t cols, const void *in, void *out, 
  * a line kernel at angle a_k = angle_start + k angle_step: the mean of
  * `taps` (odd, 1 .. 255) samples at unit spacing t = -h .. h along
  * (cos a_k, sin a_k) in (column, row) pixel units, bilinear, zeros outside
- * the detector.  in and out: [batch][n_views][rows][cols] device buffers of
+ * the detector; a single-row detector (rows == 1, 2-D sinograms) has no
+ * row direction and uses (cos a_k, 0).  in and out: [batch][n_views][rows][cols] device buffers of
  * dtype that do not overlap.  Errors: PN_EINVAL (shape, taps, non-finite
  * angles, NULL, misaligned or overlapping buffers), PN_EDTYPE. */
 int pn_gantry_blur(int64_t batch, int32_t n_views, int32_t rows, int32_t cols, const void *in, void *out,

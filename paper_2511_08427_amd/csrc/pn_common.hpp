@@ -50,7 +50,6 @@ struct FwdParams {
     int64_t lay_item[3];   // elements per batch item of each copy
     int64_t lay_plane[3];  // elements per plane
     int32_t lay_row[3];    // elements per row
-    const void *vol;       // caller's volume [batch][nz][ny][nx] (fallback path)
     void *sino;            // [batch][n_views][nv][nu]
     int32_t tile_u, tile_v;  // ray tile (tile_u * tile_v == block size)
     int32_t view_group;      // consecutive views per workgroup

@@ -339,7 +339,6 @@ int forward_prepare(const pn_geometry *pg, int64_t batch, const void *vol, void 
             p.lay_row[a] = pl->lay_row[a];
         }
     }
-    p.vol = vol;
     p.sino = sino;
     forward_tile_shape(g.ndim == 2, p.tile_u, p.tile_v, p.view_group);
     // only the tiles of the detector window that can see the volume are

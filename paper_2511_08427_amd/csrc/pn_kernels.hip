@@ -194,48 +194,39 @@ __global__ __launch_bounds__(256) void relayout_rows_kernel(const S *__restrict_
 // ------------------------------------------------------- forward A -------
 
 // 16-byte vector of storage elements, widened to FP32.
+// A staged vector holds 4 storage elements: 16 bytes (a uint4) for FP32,
+// 8 bytes (a uint2) for the 16-bit types.
 template <typename S>
-struct Vec;
-template <>
-struct Vec<float> {
-    static constexpr int N = 4;
+struct Stage {
+    using T = uint2;
 };
 template <>
-struct Vec<bf16> {
-    static constexpr int N = 8;
-};
-template <>
-struct Vec<f16> {
-    static constexpr int N = 8;
+struct Stage<float> {
+    using T = uint4;
 };
 
-// Widens 16 bytes of storage elements (held in a uint4) to FP32.
-template <typename S>
-__device__ __forceinline__ void unpack16(const uint4 v, float *o);
-template <>
-__device__ __forceinline__ void unpack16<float>(const uint4 v, float *o)
+// Widens one staged vector to 4 FP32 values.
+__device__ __forceinline__ void unpack4(const uint4 v, float *o, float)
 {
     o[0] = __uint_as_float(v.x);
     o[1] = __uint_as_float(v.y);
     o[2] = __uint_as_float(v.z);
     o[3] = __uint_as_float(v.w);
 }
-template <>
-__device__ __forceinline__ void unpack16<bf16>(const uint4 v, float *o)
+__device__ __forceinline__ void unpack4(const uint2 v, float *o, bf16)
 {
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    const uint32_t w[2] = {v.x, v.y};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i) {
         o[2 * i] = __uint_as_float(w[i] << 16);
         o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
     }
 }
-template <>
-__device__ __forceinline__ void unpack16<f16>(const uint4 v, float *o)
+__device__ __forceinline__ void unpack4(const uint2 v, float *o, f16)
 {
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    const uint32_t w[2] = {v.x, v.y};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i) {
         o[2 * i] = static_cast<float>(__builtin_bit_cast(f16, static_cast<uint16_t>(w[i] & 0xffffu)));
         o[2 * i + 1] = static_cast<float>(__builtin_bit_cast(f16, static_cast<uint16_t>(w[i] >> 16)));
     }
@@ -255,31 +246,6 @@ __device__ __forceinline__ float sample_padded(const S *__restrict__ plane, int3
     float lo = fmaf(wf, v01 - v00, v00);
     float hi = fmaf(wf, v11 - v10, v10);
     return fmaf(ws, hi - lo, lo);
-}
-
-// Gather from the caller's [nz][ny][nx] volume with bounds checks; used only
-// for a dominant axis whose work copy was not built.
-template <typename S>
-__device__ float sample_raw(const S *__restrict__ vol, const int32_t n[3], int a, int m, float pf, float ps)
-{
-    const int f = fast_axis(a), sl = slow_axis(a);
-    const float ff = floorf(pf), fs = floorf(ps);
-    const float wf = pf - ff, ws = ps - fs;
-    const int i_f = static_cast<int>(fminf(fmaxf(ff, -2.0f), 70000.0f));
-    const int i_s = static_cast<int>(fminf(fmaxf(fs, -2.0f), 70000.0f));
-    float acc = 0.0f;
-    for (int ts = 0; ts < 2; ++ts)
-        for (int tf = 0; tf < 2; ++tf) {
-            const int cf = i_f + tf, cs = i_s + ts;
-            if (cf < 0 || cf >= n[f] || cs < 0 || cs >= n[sl]) continue;
-            int idx[3];
-            idx[a] = m;
-            idx[f] = cf;
-            idx[sl] = cs;
-            const float val = to_f32(vol[(static_cast<int64_t>(idx[2]) * n[1] + idx[1]) * n[0] + idx[0]]);
-            acc += (tf ? wf : 1.0f - wf) * (ts ? ws : 1.0f - ws) * val;
-        }
-    return acc;
 }
 
 // Staged box of one chunk of planes: columns [f_al, f_al + nvec*VE) and rows
@@ -317,20 +283,22 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
 {
     static_assert(TU * TV == 256, "one pixel per thread");
     static_assert(4 * NVW <= 64, "corner rays of a view group");
-    constexpr int VE = Vec<S>::N;
+    constexpr int VE = 4;  // elements per staged vector
+    using PreT = typename Stage<S>::T;
     constexpr int VPR = FCAP / VE;
     constexpr int RPI = 256 / VPR;
     constexpr int PLANE = RCAP * FCAP;
     constexpr int NCR = 4 * NVW;  // corner rays
     static_assert(FCAP % VE == 0 && RPI >= RCAP, "one staged row per thread and plane");
-    // FP32 storage is staged with direct global-to-LDS loads (16 bytes per
-    // lane, lane i of a wave at the wave's base + 16 i: thread t's vector
-    // lands at float 4 t of the plane, its row-major place since a row holds
-    // exactly VPR vectors) into two buffers, chunk i + 1 arriving while chunk
-    // i is sampled; 16-bit storage goes through registers (widened to FP32)
-    // into one buffer.
+    // Two FP32 box buffers: chunk i is sampled from one while chunk i + 1
+    // is staged.  FP32 storage is staged with direct global-to-LDS loads (16
+    // bytes per lane, lane i of a wave at the wave's base + 16 i: thread t's
+    // vector lands at float 4 t of the plane, its row-major place since a row
+    // holds exactly VPR vectors); 16-bit storage with 8-byte loads into
+    // registers, widened to FP32 into the other buffer once chunk i has been
+    // sampled.
     constexpr bool DMA = std::is_same<S, float>::value;
-    constexpr int NBUF = DMA ? 2 : 1;
+    constexpr int NBUF = 2;
     static_assert(!DMA || VPR * VE == FCAP, "direct staging needs rows of exactly VPR vectors");
     __shared__ float box[NBUF][C * PLANE];
     constexpr int WIN = 64;      // chunks per window of boxes
@@ -537,7 +505,7 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
         // 16-byte loads of this thread's share of a box (one row per plane);
         // rows and vectors outside the padded work copy are zeros
         const int32_t srows = p.n[sl] + PADR_LO + PADR_HI;
-        uint4 pre[C];
+        PreT pre[C];
         auto issue = [&](const Box &bx) {
             if (!bx.lds || rrow >= bx.ns || vr >= bx.nvec) return;
             const int wr = bx.s_lo + PADR_LO + rrow;  // row of the work copy
@@ -551,7 +519,7 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
             const int kmax = bx.me - bx.mc;
 #pragma unroll
             for (int k = 0; k < C; ++k)
-                pre[k] = *reinterpret_cast<const uint4 *>(src + static_cast<int64_t>(min(k, kmax)) * plane);
+                pre[k] = *reinterpret_cast<const PreT *>(src + static_cast<int64_t>(min(k, kmax)) * plane);
         };
 
         // direct loads of this thread's share of a box into buffer `buf`
@@ -576,49 +544,24 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
 #endif
         };
 
-        int wb = 0;
-        window(0);
-        __syncthreads();
-        Box cur = box_at(0, 0);
-        if constexpr (DMA) {
-            issue_direct(cur, 0);
-            __builtin_amdgcn_s_waitcnt(0);  // this thread's loads have reached LDS
-            __syncthreads();
-        } else {
-            issue(cur);
-        }
-        for (int ci = 0, mc = M0; mc <= M1; ++ci, mc += C) {
-            int buf = 0;
-            if constexpr (DMA) {
-                buf = ci & 1;
-            } else {
-                __syncthreads();  // every ray is done with the previous box and window
-                if (cur.lds && rrow < cur.ns && vr < cur.nvec) {
+        // 16-bit storage: this thread's share of a box, widened to FP32, from
+        // the registers `issue` loaded into buffer `buf` (waits for the loads)
+        auto widen_store = [&](const Box &bx, int buf) {
+            if (!bx.lds || rrow >= bx.ns || vr >= bx.nvec) return;
 #pragma unroll
-                    for (int k = 0; k < C; ++k) {
-                        if (cur.mc + k > cur.me) break;
-                        float v[VE];
-                        unpack16<S>(pre[k], v);
-                        float *dst = box[0] + (k * RCAP + rrow) * FCAP + vr * VE;
+            for (int k = 0; k < C; ++k) {
+                if (bx.mc + k > bx.me) break;
+                float v[VE];
+                unpack4(pre[k], v, S{});
+                float *dst = box[buf] + (k * RCAP + rrow) * FCAP + vr * VE;
 #pragma unroll
-                        for (int e = 0; e < VE; e += 4)
-                            *reinterpret_cast<float4 *>(dst + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
-                    }
-                }
-                if (ci + 1 - wb == WIN) {  // uniform
-                    wb += WIN;
-                    window(wb);
-                }
-                __syncthreads();
+                for (int e = 0; e < VE; e += 4)
+                    *reinterpret_cast<float4 *>(dst + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
             }
-            const Box now = cur;
-            if (mc + C <= M1) {
-                cur = box_at(ci + 1, wb);
-                // in flight while this chunk is sampled; the direct loads go to
-                // the other buffer, last read for chunk i - 1
-                if constexpr (DMA) issue_direct(cur, buf ^ 1);
-                else issue(cur);
-            }
+        };
+
+        // samples chunk `now` of every ray from box buffer `buf`
+        auto sample_chunk = [&](const Box &now, int buf) {
 #pragma unroll
             for (int w = 0; w < NVW; ++w) {
                 // rays whose plane range misses the chunk sample nothing (a
@@ -681,6 +624,12 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                     }
                     acc[w] += sum;
                 } else {
+                    // gathers from the padded work copy.  A copy exists for
+                    // every axis a ray can take: the host builds one for each
+                    // axis of the views' masks, which it finds by clipping the
+                    // detector rectangle with |delta_a| >= |delta_b| - 1e-9
+                    // max|delta| from the same FP64 tables the rays use here
+                    // (the null test only keeps a broken mask from faulting)
                     const int ma = max(now.mc, sm0), mb = min(now.me, sm1);
                     if (p.lay[a] != nullptr) {
                         const S *lay = static_cast<const S *>(p.lay[a]) + b * p.lay_item[a];
@@ -689,17 +638,30 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                             acc[w] += sample_padded(lay + m * plane, row, fmaf(fm, sg.gf, sg.bf),
                                                     fmaf(fm, sg.gs, sg.bs), nf, ns);
                         }
-                    } else {
-                        const S *vol = static_cast<const S *>(p.vol) +
-                                       static_cast<int64_t>(b) * p.n[0] * static_cast<int64_t>(p.n[1]) * p.n[2];
-                        for (int m = ma; m <= mb; ++m) {
-                            const float fm = static_cast<float>(m);
-                            acc[w] += sample_raw(vol, p.n, a, m, fmaf(fm, sg.gf, sg.bf), fmaf(fm, sg.gs, sg.bs));
-                        }
                     }
                 }
             }
-            if constexpr (DMA) {
+        };
+
+        int wb = 0;
+        window(0);
+        __syncthreads();
+        Box cur = box_at(0, 0);
+        if constexpr (DMA) {
+            // chunk i is sampled from buffer i & 1 while chunk i + 1 goes
+            // straight into the other one (last read for chunk i - 1); one
+            // barrier per chunk
+            issue_direct(cur, 0);
+            __builtin_amdgcn_s_waitcnt(0);  // this thread's loads have reached LDS
+            __syncthreads();
+            for (int ci = 0, mc = M0; mc <= M1; ++ci, mc += C) {
+                const int buf = ci & 1;
+                const Box now = cur;
+                if (mc + C <= M1) {
+                    cur = box_at(ci + 1, wb);
+                    issue_direct(cur, buf ^ 1);
+                }
+                sample_chunk(now, buf);
                 if (ci + 2 - wb == WIN) {  // uniform: the next box lies past the window
                     __syncthreads();       // every box_at of this chunk has read the window
                     wb += WIN;
@@ -707,6 +669,31 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                 }
                 __builtin_amdgcn_s_waitcnt(0);  // chunk i + 1 has reached LDS
                 __syncthreads();                // ... for every thread; chunk i is done
+            }
+        } else {
+            // 16-bit storage: chunk i + 1 is loaded into registers while chunk
+            // i is sampled from buffer i & 1, then widened into the other
+            // buffer (last read for chunk i - 1); one barrier per chunk.
+            // Iteration ci samples chunk ci (none for ci = -1) and stages
+            // chunk ci + 1.
+            issue(cur);
+            Box smp = cur;
+            for (int ci = -1, mc = M0 - C; mc <= M1; ++ci, mc += C) {
+                if (ci >= 0) sample_chunk(smp, ci & 1);
+                if (mc + C <= M1) {
+                    smp = cur;
+                    widen_store(cur, (ci + 1) & 1);
+                }
+                if (mc + 2 * C <= M1) {
+                    cur = box_at(ci + 2, wb);
+                    issue(cur);  // in flight while chunk ci + 1 is sampled
+                }
+                if (ci + 3 - wb == WIN) {  // uniform: the next box_at lies past the window
+                    __syncthreads();       // every box_at of this iteration has read the window
+                    wb += WIN;
+                    window(wb);
+                }
+                __syncthreads();  // chunk ci + 1 is staged for every thread; chunk ci is done
             }
         }
     }
@@ -1557,10 +1544,11 @@ __global__ __launch_bounds__(256, 8) void backproject_batch_kernel(Batch<BpParam
 // registers (a z-column of BZ voxels per thread).  Per view, the block's
 // deposits collect in an LDS copy of the detector rectangle the block
 // projects into (the back-projection's rectangle), as 32-bit fixed point
-// with one power-of-two scale per view: the block's max |x| times the view's
-// largest weight (W0 / min W over the block's corners)^2 times the number of
-// voxels of the block stays below 2^30, so no sum can overflow; the error of
-// a deposit is at most 2^-31 of that bound.  Integer adds are exact, so the
+// with one power-of-two scale per view: the block's sum of |x| times the
+// view's largest weight (W0 / min W over the block's corners)^2 stays below
+// 2^30, so no cell's sum can overflow; the error of a deposit is at most
+// 2^-31 of that bound: relative to the block's mass, not to its largest
+// value times its voxel count.  Integer adds are exact, so the
 // rectangle is independent of the order of the deposits.  The rectangle is
 // then added to the FP32 sinogram with one hardware float atomic per non-zero
 // pixel, which a pixel receives from every block along its ray: the result
@@ -1578,6 +1566,7 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
     __shared__ int4 s_rect[CHUNK];
     __shared__ float s_scale[CHUNK];
     __shared__ uint32_t s_max[4];
+    __shared__ float s_sum[4];
     const int t = threadIdx.x;
     const int nbx = (p.n[0] + BX - 1) / BX, nby = (p.n[1] + BY - 1) / BY, nbz = (p.n[2] + BZ - 1) / BZ;
     int blk = bid;
@@ -1595,25 +1584,32 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
     const float fnu = static_cast<float>(p.nu), fnv = static_cast<float>(p.nv);
     float *sino = p.sino + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
 
-    // the thread's voxel values and the block's max |x|
+    // the thread's voxel values, the block's max |x| and its sum of |x|
     float x[BZ];
     uint32_t mbits = 0u;
+    float asum = 0.0f;
     const S *vol = static_cast<const S *>(p.vol) + static_cast<int64_t>(b) * p.n[0] * p.n[1] * static_cast<int64_t>(p.n[2]);
 #pragma unroll
     for (int z = 0; z < BZ; ++z) {
         const int k = k0 + z;
         x[z] = (own && k <= k1) ? to_f32(vol[(static_cast<int64_t>(k) * p.n[1] + j) * p.n[0] + i]) : 0.0f;
         mbits = max(mbits, __float_as_uint(fabsf(x[z])));
+        asum += fabsf(x[z]);
     }
     mbits = wave_max_u32(mbits);
-    if ((t & 63) == 0) s_max[t >> 6] = mbits;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) asum += __shfl_xor(asum, o);
+    if ((t & 63) == 0) {
+        s_max[t >> 6] = mbits;
+        s_sum[t >> 6] = asum;
+    }
     for (int e = t; e < 2 * NE; e += 256) s_acc[e / NE][e % NE] = 0;
     __syncthreads();
     mbits = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
     if (mbits == 0u) return;                       // nothing to deposit (uniform)
-    const bool finite = mbits < 0x7f800000u;       // else: straight float atomics
-    const float xmax = __uint_as_float(mbits);
-    constexpr float kVox = static_cast<float>(BX * BY * BZ);
+    const float xsum = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
+    // else (a non-finite value, or a sum beyond FP32): straight float atomics
+    const bool finite = mbits < 0x7f800000u && xsum <= 3.0e38f;
 
     // detector rectangle and fixed-point scale of the block for one view
     auto rect_of = [&](int view, float &scale) {
@@ -1642,10 +1638,12 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
         const int nc = static_cast<int>(floorf(umax)) + 2 - u0, nr = static_cast<int>(floorf(vmax)) + 2 - v0;
         const bool any = !(umax <= -1.0f || umin >= fnu || vmax <= -1.0f || vmin >= fnv);
         const bool lds = finite && nc <= CCAP && nr <= RCAP;
-        // bound of a rectangle cell's sum: every voxel's |x| (W0/W)^2 (a
-        // corner's W is the smallest over the convex block; 1% slack)
+        // bound of a rectangle cell's sum: a voxel deposits into a cell at
+        // most once per view, with a tap weight <= 1, so no cell exceeds the
+        // block's sum of |x| (W0/W)^2 (a corner's W is the smallest over the
+        // convex block; 1% slack for the FP32 sums)
         const float w0 = tf.W0 / wmin;
-        const float bound = xmax * w0 * w0 * 1.01f * kVox;
+        const float bound = xsum * w0 * w0 * 1.01f;
         const int e = min(126, max(-126, 30 - __builtin_amdgcn_frexp_expf(bound)));
         scale = exp2f(static_cast<float>(e));
         return make_int4(u0, v0, nc | nr << 16, static_cast<int>(any) | static_cast<int>(lds) << 1);
@@ -2006,23 +2004,32 @@ __global__ __launch_bounds__(256) void ring_kernel(RingParams p)
 // Detector jitter: every detector row moved by its own integer shift s in
 // -m .. m along the columns (zero where the source leaves the row).  s is
 // word 0 of the Philox block at counter (row, 0, 0, 0) under key (seed, 1),
-// reduced mod 2m + 1; each thread recomputes it for its row.
+// reduced mod 2m + 1, drawn once per row.
 template <typename T>
 __global__ __launch_bounds__(256) void jitter_kernel(JitterParams p)
 {
-    const int64_t total = p.n_rows * p.cols;
+    // each wave moves groups of 64 consecutive rows: lane l draws the shift
+    // of row g0 + l (one Philox block per row), then the wave copies the
+    // group's rows one after the other, lanes along the columns (coalesced)
     const T *src = static_cast<const T *>(p.in);
     T *dst = static_cast<T *>(p.out);
     const uint64_t span = static_cast<uint64_t>(2 * p.max_shift + 1);
-    for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
-         e += static_cast<int64_t>(gridDim.x) * 256) {
-        const int64_t g = e / p.cols;
-        const int c = static_cast<int>(e - g * p.cols);
-        uint64_t w[4] = {static_cast<uint64_t>(g), 0, 0, 0};
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * 4;
+    for (int64_t g0 = (static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6)) * 64; g0 < p.n_rows;
+         g0 += waves * 64) {
+        uint64_t w[4] = {static_cast<uint64_t>(g0 + lane), 0, 0, 0};
         philox4x64_10(w, p.seed, 1);
-        const int s = static_cast<int>(w[0] % span) - p.max_shift;
-        const int from = c - s;
-        dst[e] = (from >= 0 && from < p.cols) ? src[g * p.cols + from] : from_f32<T>(0.0f);
+        const int mine = static_cast<int>(w[0] % span) - p.max_shift;
+        const int nrow = static_cast<int>(min(static_cast<int64_t>(64), p.n_rows - g0));
+        for (int j = 0; j < nrow; ++j) {
+            const int sft = __builtin_amdgcn_readlane(mine, j);
+            const int64_t base = (g0 + j) * p.cols;
+            for (int c = lane; c < p.cols; c += 64) {
+                const int from = c - sft;
+                dst[base + c] = (from >= 0 && from < p.cols) ? src[base + from] : from_f32<T>(0.0f);
+            }
+        }
     }
 }
 
@@ -2030,7 +2037,8 @@ hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st);
 
 // Gantry motion blur: every output pixel is the mean of `taps` bilinear
 // samples at unit spacing along the view's acquisition direction
-// (cos a, sin a) in (column, row) pixel units, zeros outside the detector.
+// (cos a, sin a) in (column, row) pixel units, zeros outside the detector;
+// single-row detectors use (cos a, 0).
 template <typename T>
 __global__ __launch_bounds__(256) void blur_kernel(BlurParams p)
 {
@@ -2048,7 +2056,9 @@ __global__ __launch_bounds__(256) void blur_kernel(BlurParams p)
         const int v = static_cast<int>(img % p.n_views);
         double sd, cd;
         sincos(p.angle_start + v * p.angle_step, &sd, &cd);
-        const float du = static_cast<float>(cd), dv = static_cast<float>(sd);
+        // a single-row projection has no row direction: the kernel acts
+        // through its column component
+        const float du = static_cast<float>(cd), dv = p.rows > 1 ? static_cast<float>(sd) : 0.0f;
         const T *im = src + img * p.rows * p.cols;
         float acc = 0.0f;
         for (int t = -h; t <= h; ++t) {
@@ -2098,7 +2108,8 @@ hipError_t launch_noise(const NoiseParams &p, int32_t dt, hipStream_t st)
 
 hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st)
 {
-    return launch_elementwise(p, p.n_rows * p.cols, dt, jitter_kernel<float>, jitter_kernel<bf16>,
+    // one wave per group of 64 rows
+    return launch_elementwise(p, (p.n_rows + 63) / 64 * 64, dt, jitter_kernel<float>, jitter_kernel<bf16>,
                               jitter_kernel<f16>, st);
 }
 
@@ -2241,8 +2252,9 @@ void forward_tile_shape(bool two_d, int32_t &tu, int32_t &tv, int32_t &views)
 
 // Compiled adjoint block shapes (planes x rows x columns, candidates per
 // thread per batch); index 0 is 2-D; shape 3 runs 512 threads.
-static const int32_t kAdjShapes[][4] = {{32, 1, 64, 1}, {16, 16, 16, 2}, {32, 8, 16, 1}, {16, 16, 32, 1}};
-constexpr int kNumAdjShapes = 4;
+static const int32_t kAdjShapes[][4] = {{32, 1, 64, 1}, {16, 16, 16, 2}, {32, 8, 16, 1}, {16, 16, 32, 1},
+                                        {32, 16, 16, 1}};
+constexpr int kNumAdjShapes = 5;
 
 int adjoint_shape_count() { return kNumAdjShapes; }
 
@@ -2293,7 +2305,8 @@ static hipError_t adjoint_q(const Arg &a, int axis, int shape, uint32_t blocks, 
     case 0: return adjoint_axes<Q, 32, 1, 64, 0, 1, 1, 256>(a, axis, blocks, st);
     case 1: return adjoint_axes<Q, 16, 16, 16, 1, 2, 2, 256>(a, axis, blocks, st);
     case 2: return adjoint_axes<Q, 32, 8, 16, 1, 2, 1, 256>(a, axis, blocks, st);
-    default: return adjoint_axes<Q, 16, 16, 32, 1, 2, 1, 512>(a, axis, blocks, st);
+    case 3: return adjoint_axes<Q, 16, 16, 32, 1, 2, 1, 512>(a, axis, blocks, st);
+    default: return adjoint_axes<Q, 32, 16, 16, 1, 2, 1, 512>(a, axis, blocks, st);
     }
 }
 
