@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel (counter calibration)")
     ap.add_argument("--profile-once", action="store_true",
-                    help="run one forward and one adjoint only (for counter collection)")
+                    help="run one forward, adjoint, back-projection and filter only (for counter collection)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-problem batched variant")
     ap.add_argument("--unrolled512", action="store_true",
                     help="also time the 512^3 x 720 unrolled 10-step reconstruction (FP32 and BF16 storage)")
@@ -215,9 +215,11 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 268435456 bytes read + 268435456 bytes written")
     if args.profile_once:
-        step()
+        y, _ = step()
+        pn.backproject(y, geom)
+        pn.fbp_filter(y, geom, "shepp-logan")
         torch.cuda.synchronize()
-        log("profile-once: one forward + one adjoint done")
+        log("profile-once: one forward, adjoint, back-projection and Shepp-Logan filter done")
         return
 
     log(f"warmup {args.warmup}")
@@ -253,6 +255,22 @@ def main():
     t_noise, _ = timed(lambda: pn.gaussian_noise_(yn, 0.0, 0.01, seed=1), reps, stream)
     noise_gbs = 2 * yn.numel() * 4 / (t_noise * 1e-3) / 1e9
     log(f"Gaussian noise on the sinogram: {t_noise:.3f} ms ({noise_gbs:.0f} GB/s)")
+    # the other sinogram-domain simulators: detector jitter (shifted copy),
+    # gantry blur (9-tap line kernel per view), ring artifacts (32 columns
+    # over half of the views, in place)
+    t_jit, _ = timed(lambda: pn.detector_jitter(y, 2, seed=3), reps, stream)
+    t_blur, _ = timed(lambda: pn.gantry_blur(y, 0.0, 2 * math.pi / nviews, 9), reps, stream)
+    ring_cols = list(range(100, 420, 10))
+    t_ring, _ = timed(lambda: pn.ring_artifacts_(yn, ring_cols, 0.5, (0, nviews // 2)), reps, stream)
+    copy_bytes = 2 * y.numel() * 4
+    log(f"jitter {t_jit:.3f} ms ({copy_bytes / (t_jit * 1e-3) / 1e9:.0f} GB/s), blur {t_blur:.3f} ms "
+        f"({copy_bytes / (t_blur * 1e-3) / 1e9:.0f} GB/s), ring {t_ring:.3f} ms")
+    # a plain device-to-device copy of the sinogram (read + write), the
+    # achievable streaming bandwidth on this GPU
+    yc = torch.empty_like(y)
+    t_copy, _ = timed(lambda: yc.copy_(y), reps, stream)
+    copy_gbs = copy_bytes / (t_copy * 1e-3) / 1e9
+    log(f"copy of the sinogram: {t_copy:.3f} ms ({copy_gbs:.0f} GB/s)")
     log(f"FDK: Ram-Lak filter {t_filt:.3f} ms, Shepp-Logan filter {t_filt_sl:.3f} ms "
         f"({filt_flop / (t_filt_sl * 1e-3) / 1e12:.1f} TFLOP/s), filter + BP {t_fdk:.3f} ms")
 
@@ -269,6 +287,12 @@ def main():
         "fdk_ms": t_fdk,
         "noise_ms": t_noise,
         "noise_gbps": noise_gbs,
+        "jitter_ms": t_jit,
+        "jitter_gbps": copy_bytes / (t_jit * 1e-3) / 1e9,
+        "blur_ms": t_blur,
+        "blur_gbps": copy_bytes / (t_blur * 1e-3) / 1e9,
+        "ring_ms": t_ring,
+        "copy_gbps": copy_gbs,
     }
     if not args.no_variants:
         xb = x.to(torch.bfloat16)
@@ -296,7 +320,7 @@ def main():
     roofline = {
         "bound": "hbm",
         "kernel": "pn_forward (relayouts + forward_kernel)" if dom_name == "forward"
-        else "pn_adjoint (maxabs_kernel + adjoint_kernel per dominant axis)",
+        else "pn_adjoint (adjoint_kernel per dominant axis)",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
