@@ -77,6 +77,14 @@ struct AdjParams {
     int32_t point_source;  // 1: every ray of a view leaves one point (B has zero u and v columns)
 };
 
+// The passes of one 3-D adjoint in a single launch over cubic blocks:
+// pass[a].n_pass_views == 0 when axis a has no views; nb: blocks along x, y, z.
+struct AdjFused {
+    AdjParams pass[3];
+    int32_t nb[3];
+    int32_t batch;
+};
+
 struct BpParams {
     const ViewTabF *tabf;
     int32_t n_views, nu, nv, batch;

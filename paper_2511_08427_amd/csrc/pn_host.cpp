@@ -23,6 +23,8 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
                            int64_t item, int32_t row, int64_t plane, hipStream_t st);
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
+bool adjoint_fusable(bool two_d, int shape);
+hipError_t launch_adjoint_fused(const AdjFused &f, int32_t in_dt, hipStream_t st);
 hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_splat(const SplatParams &p, int32_t in_dt, hipStream_t st);
 int64_t splat_blocks(const SplatParams &p);
@@ -375,6 +377,34 @@ struct AdjJob {
     int64_t total;
 };
 
+// Launches the prepared passes of one adjoint (pass[a].n_pass_views == 0:
+// no pass a): a single fused launch over cubic blocks when the block shape
+// allows it, else one launch per pass axis, in axis order.
+int launch_adjoint_passes(const AdjParams pass[3], const Geo &g, int64_t batch, bool two_d, int32_t in_dt, int shape,
+                          hipStream_t st)
+{
+    hipError_t e;
+    if (adjoint_fusable(two_d, shape)) {
+        AdjFused f{};
+        int32_t L, TS, TF;
+        adjoint_shape(shape, L, TS, TF);
+        for (int a = 0; a < 3; ++a) {
+            f.pass[a] = pass[a];
+            f.nb[a] = (g.n[a] + L - 1) / L;
+        }
+        f.batch = (int32_t)batch;
+        if ((int64_t)f.nb[0] * f.nb[1] * f.nb[2] * batch > INT32_MAX)
+            return fail(PN_EINVAL, "problem too large for one launch");
+        if ((e = launch_adjoint_fused(f, in_dt, st)) != hipSuccess) return fail_hip(e, "adjoint launch");
+        return PN_OK;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (pass[a].n_pass_views == 0) continue;
+        if ((e = launch_adjoint(pass[a], in_dt, shape, st)) != hipSuccess) return fail_hip(e, "adjoint launch");
+    }
+    return PN_OK;
+}
+
 // kunits of the adjoint: a flush period holds >= 256 units of its first
 // batch's max|q ds| (and one view's worth at least), a power of two
 float adjoint_kunits(const HostTables &t)
@@ -544,12 +574,7 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
     auto run = [&](int force) -> int {
         int r = adjoint_prepare(batch, sino, vol, in_dt, out_dt, st, pl, job, none, force);
         if (r || none) return r;
-        for (int a = 0; a < 3; ++a) {
-            if (job.pass[a].n_pass_views == 0) continue;
-            hipError_t e = launch_adjoint(job.pass[a], in_dt, job.shape, st);
-            if (e != hipSuccess) return fail_hip(e, "adjoint launch");
-        }
-        return PN_OK;
+        return launch_adjoint_passes(job.pass, pl->g, batch, job.two_d, in_dt, job.shape, st);
     };
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (autotune_on() && pl->g.ndim == 3 && plan_adjoint_shape(pl) && pl->adj_shape == 0 &&
@@ -721,16 +746,17 @@ int adjoint_noalloc_impl(const pn_geometry *pg, int64_t batch, const void *sino,
     }
     float *target = out_dt == PN_F32 ? static_cast<float *>(vol) : reinterpret_cast<float *>(base + lay.acc);
     int done = 0;
+    AdjParams pass[3] = {};
     for (int a = 0; a < 3; ++a) {
         if (tt.pass_views[a].empty()) continue;
-        AdjParams p;
+        AdjParams &p = pass[a];
         adjoint_pass_params(pre, tt, a, L, TS, TF, d_tab, d_tabf,
                             reinterpret_cast<const int32_t *>(base + lay.views[a]), batch, sino, target, done > 0, p);
         if (adjoint_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
         p.cbox = reinterpret_cast<const uint32_t *>(base + lay.cbox[a]);
-        if ((e = launch_adjoint(p, in_dt, shape, st)) != hipSuccess) return fail_hip(e, "adjoint launch");
         ++done;
     }
+    if ((rc = launch_adjoint_passes(pass, pre, batch, two_d, in_dt, shape, st))) return rc;
     if (out_dt != PN_F32 && (e = launch_convert(target, vol, out_dt, total, st)) != hipSuccess)
         return fail_hip(e, "convert launch");
     return PN_OK;

@@ -933,8 +933,25 @@ constexpr int kQuietBits = 2;
 // besides the extra row below, 1/2 in general; 0/1 for 2-D problems, whose
 // rays have z == 0 exactly (the tap at z = 0 has weight 1 and the one at
 // z = 1 weight 0).
+// LDS of one adjoint workgroup (declared by the kernel, so that the passes
+// of a fused launch share it).
+template <int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
+struct AdjLds {
+    static constexpr int RW = TF + 4;              // LDS row (halo: 2 before, 2 after)
+    static constexpr int RP = TS + SLO + SHI + 1;  // LDS rows per plane
+    static constexpr int PL = RP * RW;             // LDS plane
+    static constexpr int MAXR = NT * CPT;          // rays per batch
+    static constexpr int MAXSEG = MAXR * ((L + 7) / 8);
+    float4 s_ray[MAXR];      // gf, bf, gs, bs (block-local frame)
+    int acc[L * PL];
+    float s_q[MAXR];         // q * ds
+    uint32_t s_seg[MAXSEG];  // slot | first local plane << 16 | planes << 24
+    uint32_t s_cnt[2][2];    // [parity][rays | segments << 16, max |q*ds| bits]
+};
+
 template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
-__device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
+__device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid,
+                                              AdjLds<L, TS, TF, SLO, SHI, CPT, NT> &sh)
 {
     using AX = PassAxes<A>;
     constexpr int F = AX::F, S = AX::S;
@@ -949,11 +966,13 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     constexpr int MAXSEG = MAXR * SPR;
     static_assert(L <= 32 && SPR <= 4, "segment record packing");
     static_assert(MAXR <= 1024 && MAXSEG < 65536, "packed counters");
-    __shared__ int acc[L * PL];
-    __shared__ float4 s_ray[MAXR];             // gf, bf, gs, bs (block-local frame)
-    __shared__ float s_q[MAXR];                // q * ds
-    __shared__ uint32_t s_seg[MAXSEG];         // slot | first local plane << 16 | planes << 24
-    __shared__ uint32_t s_cnt[2][2];           // [parity][rays | segments << 16, max |q*ds| bits]
+    static_assert(MAXSEG == AdjLds<L, TS, TF, SLO, SHI, CPT, NT>::MAXSEG && PL == AdjLds<L, TS, TF, SLO, SHI, CPT, NT>::PL,
+                  "LDS layout");
+    int *acc = sh.acc;
+    float4 *s_ray = sh.s_ray;
+    float *s_q = sh.s_q;
+    uint32_t *s_seg = sh.s_seg;
+    uint32_t(*s_cnt)[2] = sh.s_cnt;
 
     int blk = bid;
     const int bf_ = blk % p.blocks_f;
@@ -985,15 +1004,21 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
     float reg[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) reg[q] = 0.0f;
+    // (a cubic block maps thread t to the same voxels in every pass: x, then
+    // y, then z)
     auto cell_of = [](int e, int &la, int &ls, int &lf) {
-        if (A == 0) {  // x = a
+        if (A == 0) {  // x = a, y = f, z = s
             la = e % L;
             lf = (e / L) % TF;
             ls = e / (L * TF);
-        } else {       // x = f
+        } else if (A == 1 || L != TS) {  // x = f
             lf = e % TF;
             la = (e / TF) % L;
             ls = e / (TF * L);
+        } else {       // z pass of a cubic block: x = f, y = s, z = a
+            lf = e % TF;
+            ls = (e / TF) % TS;
+            la = e / (TF * TS);
         }
     };
 
@@ -1280,14 +1305,53 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid)
 template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
 __global__ __launch_bounds__(NT, 4) void adjoint_kernel(AdjParams p)
 {
-    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT, NT>(p, blockIdx.x);
+    __shared__ AdjLds<L, TS, TF, SLO, SHI, CPT, NT> sh;
+    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT, NT>(p, blockIdx.x, sh);
 }
 
 template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
 __global__ __launch_bounds__(NT, 4) void adjoint_batch_kernel(Batch<AdjParams> w)
 {
+    __shared__ AdjLds<L, TS, TF, SLO, SHI, CPT, NT> sh;
     const int i = batch_item(w, blockIdx.x);
-    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT, NT>(w.p[i], blockIdx.x - w.start[i]);
+    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT, NT>(w.p[i], blockIdx.x - w.start[i], sh);
+}
+
+// All passes of a 3-D adjoint in one launch: a workgroup owns one cubic
+// block (B^3 voxels, in x, y, z block coordinates) and runs the passes
+// present one after the other, each exactly as its own launch would (the
+// first overwrites the block, later ones add to it, in axis order, so the
+// result is bitwise that of one launch per pass).  One launch has one tail
+// instead of one per pass, and a block's passes share its LDS.
+template <typename Q, int B, int SLO, int SHI, int CPT, int NT>
+__global__ __launch_bounds__(NT, 4) void adjoint_fused_kernel(AdjFused f)
+{
+    __shared__ AdjLds<B, B, B, SLO, SHI, CPT, NT> sh;
+    int blk = blockIdx.x;
+    const int bx = blk % f.nb[0];
+    blk /= f.nb[0];
+    const int by = blk % f.nb[1];
+    blk /= f.nb[1];
+    const int bz = blk % f.nb[2];
+    const int b = blk / f.nb[2];
+    bool first = true;
+    // pass-local block index: ((b * blocks_a + ba) * blocks_s + bs) * blocks_f + bf
+    if (f.pass[0].n_pass_views > 0) {  // a = x, f = y, s = z
+        adjoint_block<Q, 0, B, B, B, SLO, SHI, CPT, NT>(
+            f.pass[0], ((b * f.nb[0] + bx) * f.nb[2] + bz) * f.nb[1] + by, sh);
+        first = false;
+    }
+    if (f.pass[1].n_pass_views > 0) {  // a = y, f = x, s = z
+        if (!first) __syncthreads();   // the previous pass is done with the LDS block
+        adjoint_block<Q, 1, B, B, B, SLO, SHI, CPT, NT>(
+            f.pass[1], ((b * f.nb[1] + by) * f.nb[2] + bz) * f.nb[0] + bx, sh);
+        first = false;
+    }
+    if (f.pass[2].n_pass_views > 0) {  // a = z, f = x, s = y
+        if (!first) __syncthreads();
+        adjoint_block<Q, 2, B, B, B, SLO, SHI, CPT, NT>(
+            f.pass[2], ((b * f.nb[2] + bz) * f.nb[1] + by) * f.nb[0] + bx, sh);
+    }
 }
 
 // ------------------------------------------------ back-projection --------
@@ -2323,6 +2387,21 @@ static hipError_t adjoint_any(const Arg &a, int axis, int32_t in_dt, int shape, 
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st)
 {
     return adjoint_any(p, p.axis, in_dt, shape, static_cast<uint32_t>(adjoint_blocks(p)), st);
+}
+
+bool adjoint_fusable(bool two_d, int shape) { return !two_d && shape == 1; }
+
+hipError_t launch_adjoint_fused(const AdjFused &f, int32_t in_dt, hipStream_t st)
+{
+    const int64_t blocks = static_cast<int64_t>(f.nb[0]) * f.nb[1] * f.nb[2] * f.batch;
+    if (blocks == 0) return hipSuccess;
+    const dim3 grid(static_cast<uint32_t>(blocks));
+    switch (in_dt) {
+    case DT_F32: adjoint_fused_kernel<float, 16, 1, 2, 2, 256><<<grid, 256, 0, st>>>(f); break;
+    case DT_BF16: adjoint_fused_kernel<bf16, 16, 1, 2, 2, 256><<<grid, 256, 0, st>>>(f); break;
+    default: adjoint_fused_kernel<f16, 16, 1, 2, 2, 256><<<grid, 256, 0, st>>>(f); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_batch(const Batch<AdjParams> &w, int axis, int32_t in_dt, int shape, hipStream_t st)
