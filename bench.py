@@ -118,11 +118,18 @@ def batched_variant(pn, W, np, torch, stream):
     tf, _ = timed(lambda: pn.forward_batched(pairs), 3, stream)
     ta, _ = timed(lambda: pn.adjoint_batched(sp), 3, stream)
     log(f"batched: A {tf:.2f} ms, AT {ta:.2f} ms over {upd / 1e9:.1f} G updates")
+    # the same 32 problems as one single call each, back to back
+    tsf, _ = timed(lambda: [pn.forward(x, g) for x, g in pairs], 3, stream)
+    tsa, _ = timed(lambda: [pn.adjoint(y, g) for y, g in sp], 3, stream)
+    log(f"single calls: A {tsf:.2f} ms, AT {tsa:.2f} ms")
     return {
         "batched_pair_gups": upd / ((tf + ta) * 1e-3) / 1e9,
         "batched_forward_ms": tf,
         "batched_adjoint_ms": ta,
         "batched_updates": upd,
+        "batched_list_single_calls_pair_gups": upd / ((tsf + tsa) * 1e-3) / 1e9,
+        "batched_list_single_forward_ms": tsf,
+        "batched_list_single_adjoint_ms": tsa,
     }
 
 

@@ -2106,15 +2106,16 @@ hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st);
 template <typename T>
 __global__ __launch_bounds__(256) void blur_kernel(BlurParams p)
 {
-    const int64_t total = p.batch * p.n_views * p.rows * p.cols;
+    // one wave per detector row (image, r): the view's direction is formed
+    // once per row, the lanes run along the columns
+    const int64_t n_rows = p.batch * p.n_views * p.rows;
     const T *src = static_cast<const T *>(p.in);
     T *dst = static_cast<T *>(p.out);
     const int h = (p.taps - 1) / 2;
     const float inv = 1.0f / static_cast<float>(p.taps);
-    for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
-         e += static_cast<int64_t>(gridDim.x) * 256) {
-        const int c = static_cast<int>(e % p.cols);
-        const int64_t rowi = e / p.cols;
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * 4;
+    for (int64_t rowi = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); rowi < n_rows; rowi += waves) {
         const int r = static_cast<int>(rowi % p.rows);
         const int64_t img = rowi / p.rows;
         const int v = static_cast<int>(img % p.n_views);
@@ -2124,28 +2125,30 @@ __global__ __launch_bounds__(256) void blur_kernel(BlurParams p)
         // through its column component
         const float du = static_cast<float>(cd), dv = p.rows > 1 ? static_cast<float>(sd) : 0.0f;
         const T *im = src + img * p.rows * p.cols;
-        float acc = 0.0f;
-        for (int t = -h; t <= h; ++t) {
-            // offsets from the pixel, split into whole and fractional parts
-            // before the pixel index is added, so the fractions keep full
-            // FP32 precision whatever the detector size
-            const float tu = static_cast<float>(t) * du, tv = static_cast<float>(t) * dv;
-            const float iu = floorf(tu), iv = floorf(tv);
-            const float fx = tu - iu, fy = tv - iv;
-            const int x0 = c + static_cast<int>(iu), y0 = r + static_cast<int>(iv);
-            float s = 0.0f;
+        for (int c = lane; c < p.cols; c += 64) {
+            float acc = 0.0f;
+            for (int t = -h; t <= h; ++t) {
+                // offsets from the pixel, split into whole and fractional
+                // parts before the pixel index is added, so the fractions
+                // keep full FP32 precision whatever the detector size
+                const float tu = static_cast<float>(t) * du, tv = static_cast<float>(t) * dv;
+                const float iu = floorf(tu), iv = floorf(tv);
+                const float fx = tu - iu, fy = tv - iv;
+                const int x0 = c + static_cast<int>(iu), y0 = r + static_cast<int>(iv);
+                float s = 0.0f;
 #pragma unroll
-            for (int oy = 0; oy < 2; ++oy)
+                for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
-                for (int ox = 0; ox < 2; ++ox) {
-                    const int xi = x0 + ox, yi = y0 + oy;
-                    const float w = (oy ? fy : 1.0f - fy) * (ox ? fx : 1.0f - fx);
-                    if (xi >= 0 && xi < p.cols && yi >= 0 && yi < p.rows)
-                        s = fmaf(w, to_f32(im[static_cast<int64_t>(yi) * p.cols + xi]), s);
-                }
-            acc += s;
+                    for (int ox = 0; ox < 2; ++ox) {
+                        const int xi = x0 + ox, yi = y0 + oy;
+                        const float w = (oy ? fy : 1.0f - fy) * (ox ? fx : 1.0f - fx);
+                        if (xi >= 0 && xi < p.cols && yi >= 0 && yi < p.rows)
+                            s = fmaf(w, to_f32(im[static_cast<int64_t>(yi) * p.cols + xi]), s);
+                    }
+                acc += s;
+            }
+            dst[(img * p.rows + r) * p.cols + c] = from_f32<T>(acc * inv);
         }
-        dst[e] = from_f32<T>(acc * inv);
     }
 }
 
@@ -2179,7 +2182,8 @@ hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st)
 
 hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st)
 {
-    return launch_elementwise(p, p.batch * p.n_views * p.rows * p.cols, dt, blur_kernel<float>, blur_kernel<bf16>,
+    // one wave per detector row
+    return launch_elementwise(p, p.batch * p.n_views * p.rows * 64, dt, blur_kernel<float>, blur_kernel<bf16>,
                               blur_kernel<f16>, st);
 }
 
