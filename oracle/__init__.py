@@ -212,8 +212,9 @@ def trajectory_vectors(kind, n_views, angular_range, sid, sdd, det_shape, det_sp
                        vol_spacing, pitch=0.5, draws=None):
     """Vectors of the non-circular trajectories of the batched workload.
 
-    helical: source and detector rise together, S_z = h (beta/2pi - 1/2)
-      with h = pitch * rows * row_spacing * SID/SDD (table feed per turn);
+    helical: source and detector rise together, S_z = h (beta/2pi - T/2)
+      with h = pitch * rows * row_spacing * SID/SDD (table feed per turn)
+      over T = angular_range / 2pi turns (long objects: several turns);
     sinusoidal: S_z = A sin(2 beta), A = nz * sz / 4, detector follows;
     perturbed: circular orbit plus the Gaussian draws ``draws`` (dS, dC in
       mm, dphi in rad rotating the detector axes within the panel).
@@ -221,8 +222,10 @@ def trajectory_vectors(kind, n_views, angular_range, sid, sdd, det_shape, det_sp
     S, C, eu, ev = circular_cone_vectors(n_views, angular_range, sid, sdd, det_spacing)
     beta = np.arange(n_views, dtype=np.float64) * (angular_range / n_views)
     if kind == "helical":
+        # T = angular_range / 2pi turns; the orbit is centred on z = 0
         h = pitch * det_shape[0] * det_spacing[0] * sid / sdd
-        dz = h * (beta / (2 * math.pi) - 0.5)
+        turns = angular_range / (2 * math.pi)
+        dz = h * (beta / (2 * math.pi) - 0.5 * turns)
         S[:, 2] += dz
         C[:, 2] += dz
     elif kind == "sinusoidal":
@@ -242,6 +245,33 @@ def trajectory_vectors(kind, n_views, angular_range, sid, sdd, det_shape, det_sp
     elif kind != "circular":
         raise ValueError(kind)
     return S, C, eu, ev
+
+
+def detector_pose(S, C, eu, ev, offset=(0.0, 0.0), tilt=(0.0, 0.0, 0.0)):
+    """A flat panel moved within its plane and turned about its centre
+    (Sec. 2.4, arbitrary detector positions and orientations).
+
+    offset = (o_u, o_v): mm along the panel's unit axes (u_hat, v_hat);
+    tilt = (roll, tilt_u, tilt_v) in rad: the panel frame
+    F = [u_hat, v_hat, n_hat] (n_hat = u_hat x v_hat) becomes
+    F Rz(roll) Rx(tilt_u) Ry(tilt_v), i.e. the panel turns about its own
+    normal, then about its u axis, then about its v axis, all through the
+    (shifted) centre.  Pixel pitches are kept.  Arrays of shape (n, 3).
+    """
+    S, C, eu, ev = (np.array(a, dtype=np.float64, ndmin=2) for a in (S, C, eu, ev))
+    du = np.linalg.norm(eu, axis=1)[:, None]
+    dv = np.linalg.norm(ev, axis=1)[:, None]
+    uh, vh = eu / du, ev / dv
+    nh = np.cross(uh, vh)
+    C = C + offset[0] * uh + offset[1] * vh
+    r, a, b = tilt
+    Rz = np.array([[math.cos(r), -math.sin(r), 0.0], [math.sin(r), math.cos(r), 0.0], [0.0, 0.0, 1.0]])
+    Rx = np.array([[1.0, 0.0, 0.0], [0.0, math.cos(a), -math.sin(a)], [0.0, math.sin(a), math.cos(a)]])
+    Ry = np.array([[math.cos(b), 0.0, math.sin(b)], [0.0, 1.0, 0.0], [-math.sin(b), 0.0, math.cos(b)]])
+    R = Rz @ Rx @ Ry
+    F = np.stack([uh, vh, nh], axis=2)          # columns u_hat, v_hat, n_hat per view
+    G = F @ R
+    return S, C, du * G[:, :, 0], dv * G[:, :, 1]
 
 
 # -------------------------------------------------------------- operators --
