@@ -1,6 +1,8 @@
 // gfx950 kernels of the CT projector library: work-copy relayout, the
-// ray-driven Joseph forward projector A, its exact adjoint A^T and the
-// voxel-driven distance-weighted back-projection.
+// ray-driven Joseph forward projector A, its exact adjoint A^T, the
+// voxel-driven distance-weighted back-projection and its transpose (the
+// splat projector), and the allocation-free adjoint's scratch array.  The
+// FBP filter and the artifact simulators are in pn_signal.hip.
 //
 // Arithmetic contract: per-ray set-up (direction, dominant axis, slopes,
 // entry parameters, plane range) in FP64; the per-plane loop in FP32 with
@@ -12,42 +14,9 @@
 #include <mutex>
 
 #include "pn_common.hpp"
+#include "pn_device.hpp"
 
 namespace pn {
-
-// ------------------------------------------------------------ dtypes ----
-
-struct bf16 {
-    uint16_t bits;
-};
-using f16 = _Float16;
-
-__device__ __forceinline__ float to_f32(float v) { return v; }
-__device__ __forceinline__ float to_f32(bf16 v) { return __uint_as_float(static_cast<uint32_t>(v.bits) << 16); }
-__device__ __forceinline__ float to_f32(f16 v) { return static_cast<float>(v); }
-
-template <typename T>
-__device__ __forceinline__ T from_f32(float f);
-template <>
-__device__ __forceinline__ float from_f32<float>(float f) { return f; }
-template <>
-__device__ __forceinline__ bf16 from_f32<bf16>(float f)
-{
-    // round to nearest, ties to even; NaN stays a (quiet) NaN
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{static_cast<uint16_t>((u >> 16) | 0x40u)};
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return bf16{static_cast<uint16_t>(u >> 16)};
-}
-template <>
-__device__ __forceinline__ f16 from_f32<f16>(float f)
-{
-    // the empty asm pins the FP32 value, so the store is the RNE rounding of
-    // the FP32 result (without it the compiler may fuse the producing
-    // multiply into a mixed-precision instruction that rounds only once)
-    asm volatile("" : "+v"(f));
-    return static_cast<f16>(f);  // v_cvt_f16_f32, round to nearest even
-}
 
 // ------------------------------------------------------ ray set-up -------
 
@@ -1828,369 +1797,6 @@ template <typename S, int BZ, int RCAP, int CCAP>
 __global__ __launch_bounds__(256, 6) void splat_kernel(SplatParams p)
 {
     splat_block<S, BZ, RCAP, CCAP>(p, blockIdx.x);
-}
-
-// ------------------------------------------------------- FBP filter ------
-
-// Row filter of the filtered back-projection: per detector row, the cosine
-// weight of each pixel's ray (divergent beams: 1 / (|q3| |d|), q3 the last
-// row of the view's 3x3 matrix, d the ray from the source to the pixel,
-// q3 . d = 1) and the linear convolution with the discrete kernel g
-// (Ram-Lak: g[0] = 1/4, g[k] = -1/(pi^2 k^2) for odd k, 0 for even k;
-// Shepp-Logan: g[k] = -2 / (pi^2 (4 k^2 - 1))), times `scale`.  One wave
-// per row, the row and the kernel in LDS.  Each lane computes FR adjacent
-// outputs; per step of FR inputs it reads the inputs once (broadcast) and a
-// window of 2 FR - 1 kernel values, then does FR^2 FMAs, so the loop is
-// bound by the FMAs.
-constexpr int kFiltMaxCols = 1024;
-constexpr int kFiltR = 8;
-constexpr int kFiltGOff = kFiltMaxCols + 2 * kFiltR - 1;        // g[k] at table entry k + kFiltGOff
-constexpr int kFiltGN = 2 * kFiltGOff + 1 + kFiltR;             // table entries
-constexpr int kFiltXW = kFiltMaxCols + kFiltR;                  // row buffer (zero tail)
-
-// Table position of entry e: one spare word after every eight, so the
-// reads of a wave (lane l at 8 l + c for a common c) fall on distinct banks.
-__device__ __forceinline__ int filt_pad(int e) { return e + (e >> 3); }
-
-// One wave per detector row; lane l computes outputs n0 .. n0 + 7 with
-// n0 = 8 l (+ 512 for a second pass when the row is longer than 512).  The
-// row, cosine-weighted, sits in LDS; out[n] = scale * sum_m g[n - m] x[m]
-// in 8 x 8 register blocks that share a window of 15 kernel taps, summed in
-// the order of m.  For the Ram-Lak kernel every even tap but g[0] is zero:
-// only the 32 odd-distance pairs of a block and its 8 same-index pairs (the
-// g[0] term when the block is the lane's own, zero otherwise) are formed.
-// The sum nearly cancels (the odd taps add up to -g[0]), so g[0] x[n] is
-// added where m reaches n, not first: that keeps the partial sums of the far
-// taps small and the FP32 error about ten times lower.  Workgroups stride
-// over the rows (four per pass).
-template <typename Q, typename O, int KIND>
-__global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
-{
-    constexpr int R = kFiltR, GOFF = kFiltGOff, GN = kFiltGN, XW = kFiltXW;
-    __shared__ float gtab[GN + GN / 8 + 1];
-    __shared__ __align__(16) float xs[4][XW];
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int nu = p.nu;
-    for (int e = t; e < GN; e += 256) {
-        const int k = e - GOFF, ak = k < 0 ? -k : k;
-        float g = 0.0f;
-        if (ak < nu) {
-            const double dk = static_cast<double>(ak);
-            if (KIND == 0) {
-                if (ak == 0) g = 0.25f;
-                else if (ak & 1) g = static_cast<float>(-1.0 / (M_PI * M_PI * dk * dk));
-            } else {
-                g = static_cast<float>(-2.0 / (M_PI * M_PI * (4.0 * dk * dk - 1.0)));
-            }
-        }
-        gtab[filt_pad(e)] = g;
-    }
-    const int64_t rows = static_cast<int64_t>(p.batch) * p.n_views * p.nv;
-    float *x = xs[wave];
-    for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * 4; r0 < rows; r0 += static_cast<int64_t>(gridDim.x) * 4) {
-        const int64_t row = r0 + wave;
-        const bool have = row < rows;
-        __syncthreads();  // the table is written; the previous rows are read
-        if (have) {
-            const int r = static_cast<int>(row % p.nv);
-            const int view = static_cast<int>((row / p.nv) % p.n_views);
-            const Q *src = static_cast<const Q *>(p.in) + row * nu;
-            float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, rq = 1.0f;
-            if (!p.parallel) {
-                // ray from the source to pixel (u, r) in world units: s (A (u, r, 1))
-                const ViewTab &tv = p.tab[view];
-                const double rr = static_cast<double>(r);
-                a0 = static_cast<float>(tv.A[0] * p.s[0]);
-                a1 = static_cast<float>(tv.A[3] * p.s[1]);
-                a2 = static_cast<float>(tv.A[6] * p.s[2]);
-                b0 = static_cast<float>((tv.A[1] * rr + tv.A[2]) * p.s[0]);
-                b1 = static_cast<float>((tv.A[4] * rr + tv.A[5]) * p.s[1]);
-                b2 = static_cast<float>((tv.A[7] * rr + tv.A[8]) * p.s[2]);
-                const double q0 = tv.Pi[8] / p.s[0], q1 = tv.Pi[9] / p.s[1], q2 = tv.Pi[10] / p.s[2];
-                rq = static_cast<float>(1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2));
-            }
-            for (int c = lane; c < XW; c += 64) {
-                float v = 0.0f;
-                if (c < nu) {
-                    v = to_f32(src[c]);
-                    if (!p.parallel) {
-                        const float fc = static_cast<float>(c);
-                        const float d0 = fmaf(fc, a0, b0), d1 = fmaf(fc, a1, b1), d2 = fmaf(fc, a2, b2);
-                        v *= __builtin_amdgcn_rsqf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2))) * rq;
-                    }
-                }
-                x[c] = v;
-            }
-        }
-        __syncthreads();
-        if (!have) continue;
-        O *dst = static_cast<O *>(p.out) + row * nu;
-        for (int n0 = lane * R; n0 < nu; n0 += 64 * R) {
-            float acc[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) acc[j] = 0.0f;
-            for (int m0 = 0; m0 < nu; m0 += R) {
-                const float4 xa = *reinterpret_cast<const float4 *>(x + m0);
-                const float4 xb = *reinterpret_cast<const float4 *>(x + m0 + 4);
-                const float xv[R] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-                // gv[w] = g[n0 - m0 - (R - 1) + w]; the window start is a multiple of 8
-                const int base = GOFF + n0 - m0 - (R - 1);
-                const float *gp = gtab + filt_pad(base);
-                float gv[2 * R - 1];
-#pragma unroll
-                for (int w = 0; w < 2 * R - 1; ++w)
-                    gv[w] = (KIND == 0 && (w & 1) && w != R - 1) ? 0.0f : gp[w + (w >> 3)];
-#pragma unroll
-                for (int i = 0; i < R; ++i)
-#pragma unroll
-                    for (int j = 0; j < R; ++j)
-                        if (KIND != 0 || ((j - i) & 1) || i == j) acc[j] = fmaf(gv[j - i + R - 1], xv[i], acc[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-                if (n0 + j < nu) dst[n0 + j] = from_f32<O>(acc[j] * p.scale);
-        }
-    }
-}
-
-template <typename Q, int KIND>
-static hipError_t filter_q(const FiltParams &p, uint32_t blocks, int32_t out_dt, hipStream_t st)
-{
-    switch (out_dt) {
-    case DT_F32: filter_kernel<Q, float, KIND><<<dim3(blocks), 256, 0, st>>>(p); break;
-    case DT_BF16: filter_kernel<Q, bf16, KIND><<<dim3(blocks), 256, 0, st>>>(p); break;
-    default: filter_kernel<Q, f16, KIND><<<dim3(blocks), 256, 0, st>>>(p); break;
-    }
-    return hipGetLastError();
-}
-
-template <int KIND>
-static hipError_t filter_k(const FiltParams &p, uint32_t blocks, int32_t in_dt, int32_t out_dt, hipStream_t st)
-{
-    switch (in_dt) {
-    case DT_F32: return filter_q<float, KIND>(p, blocks, out_dt, st);
-    case DT_BF16: return filter_q<bf16, KIND>(p, blocks, out_dt, st);
-    default: return filter_q<f16, KIND>(p, blocks, out_dt, st);
-    }
-}
-
-int32_t filter_max_cols() { return kFiltMaxCols; }
-
-hipError_t launch_filter(const FiltParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st)
-{
-    const int64_t rows = static_cast<int64_t>(p.batch) * p.n_views * p.nv;
-    // six workgroups fit a CU (26 KB of LDS each); the rest stride
-    const int64_t blocks = std::min<int64_t>((rows + 3) / 4, 256 * 6);
-    if (blocks == 0) return hipSuccess;
-    return p.kind == 0 ? filter_k<0>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st)
-                       : filter_k<1>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st);
-}
-
-// ------------------------------------------------ artifact simulation -----
-
-// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
-// 64 x 64 -> 128-bit multiplies; the key grows by the Weyl constants
-// between rounds.
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
-{
-    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t h0 = __umul64hi(M0, c[0]), l0 = M0 * c[0];
-        const uint64_t h1 = __umul64hi(M1, c[2]), l1 = M1 * c[2];
-        const uint64_t n0 = h1 ^ c[1] ^ k0, n2 = h0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = l1;
-        c[2] = n2;
-        c[3] = l0;
-    }
-}
-
-// Additive Gaussian noise: one thread per four consecutive elements, which
-// share the Philox block at counter (i / 4, 0, 0, 0) under key (seed, 0).
-// Words (0, 1) and (2, 3) become Box-Muller pairs (uniforms
-// ((w >> 11) + 1/2) 2^-53; the first of a pair takes the cosine).  The
-// normal draws are formed in FP64, the sum in FP32.
-template <typename T>
-__global__ __launch_bounds__(256) void noise_kernel(NoiseParams p)
-{
-    const int64_t nb = (p.n + 3) / 4;
-    T *d = static_cast<T *>(p.data);
-    for (int64_t b = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; b < nb;
-         b += static_cast<int64_t>(gridDim.x) * 256) {
-        uint64_t c[4] = {static_cast<uint64_t>(b), 0, 0, 0};
-        philox4x64_10(c, p.seed, 0);
-        double z[4];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const double ua = (static_cast<double>(c[2 * h] >> 11) + 0.5) * 0x1p-53;
-            const double ub = (static_cast<double>(c[2 * h + 1] >> 11) + 0.5) * 0x1p-53;
-            const double r = sqrt(-2.0 * log(ua));
-            double sn, cs;
-            sincospi(2.0 * ub, &sn, &cs);
-            z[2 * h] = r * cs;
-            z[2 * h + 1] = r * sn;
-        }
-        const int64_t e0 = b * 4;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (e0 + q < p.n)
-                d[e0 + q] = from_f32<T>(to_f32(d[e0 + q]) + static_cast<float>(p.mean + p.sigma * z[q]));
-    }
-}
-
-// Ring artifacts: the chosen detector columns of views v0 .. v1 - 1 scaled
-// by gain (FP32 product), one thread per touched element.
-template <typename T>
-__global__ __launch_bounds__(256) void ring_kernel(RingParams p)
-{
-    const int64_t nvs = p.v1 - p.v0;
-    const int64_t total = p.batch * nvs * p.rows * p.n_sel;
-    T *d = static_cast<T *>(p.data);
-    for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
-         e += static_cast<int64_t>(gridDim.x) * 256) {
-        const int j = static_cast<int>(e % p.n_sel);
-        int64_t t = e / p.n_sel;
-        const int r = static_cast<int>(t % p.rows);
-        t /= p.rows;
-        const int v = p.v0 + static_cast<int>(t % nvs);
-        const int64_t bb = t / nvs;
-        const int64_t at = ((bb * p.n_views + v) * p.rows + r) * p.cols + p.sel[j];
-        d[at] = from_f32<T>(to_f32(d[at]) * p.gain);
-    }
-}
-
-// Detector jitter: every detector row moved by its own integer shift s in
-// -m .. m along the columns (zero where the source leaves the row).  s is
-// word 0 of the Philox block at counter (row, 0, 0, 0) under key (seed, 1),
-// reduced mod 2m + 1, drawn once per row.
-template <typename T>
-__global__ __launch_bounds__(256) void jitter_kernel(JitterParams p)
-{
-    // each wave moves groups of 64 consecutive rows: lane l draws the shift
-    // of row g0 + l (one Philox block per row), then the wave copies the
-    // group's rows one after the other, lanes along the columns (coalesced)
-    const T *src = static_cast<const T *>(p.in);
-    T *dst = static_cast<T *>(p.out);
-    const uint64_t span = static_cast<uint64_t>(2 * p.max_shift + 1);
-    const int lane = threadIdx.x & 63;
-    const int64_t waves = static_cast<int64_t>(gridDim.x) * 4;
-    for (int64_t g0 = (static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6)) * 64; g0 < p.n_rows;
-         g0 += waves * 64) {
-        uint64_t w[4] = {static_cast<uint64_t>(g0 + lane), 0, 0, 0};
-        philox4x64_10(w, p.seed, 1);
-        const int mine = static_cast<int>(w[0] % span) - p.max_shift;
-        const int nrow = static_cast<int>(min(static_cast<int64_t>(64), p.n_rows - g0));
-        for (int j = 0; j < nrow; ++j) {
-            const int sft = __builtin_amdgcn_readlane(mine, j);
-            const int64_t base = (g0 + j) * p.cols;
-            for (int c = lane; c < p.cols; c += 64) {
-                const int from = c - sft;
-                dst[base + c] = (from >= 0 && from < p.cols) ? src[base + from] : from_f32<T>(0.0f);
-            }
-        }
-    }
-}
-
-hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st);
-
-// Gantry motion blur: every output pixel is the mean of `taps` bilinear
-// samples at unit spacing along the view's acquisition direction
-// (cos a, sin a) in (column, row) pixel units, zeros outside the detector;
-// single-row detectors use (cos a, 0).
-template <typename T>
-__global__ __launch_bounds__(256) void blur_kernel(BlurParams p)
-{
-    // one wave per detector row (image, r): the view's direction is formed
-    // once per row, the lanes run along the columns
-    const int64_t n_rows = p.batch * p.n_views * p.rows;
-    const T *src = static_cast<const T *>(p.in);
-    T *dst = static_cast<T *>(p.out);
-    const int h = (p.taps - 1) / 2;
-    const float inv = 1.0f / static_cast<float>(p.taps);
-    const int lane = threadIdx.x & 63;
-    const int64_t waves = static_cast<int64_t>(gridDim.x) * 4;
-    for (int64_t rowi = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); rowi < n_rows; rowi += waves) {
-        const int r = static_cast<int>(rowi % p.rows);
-        const int64_t img = rowi / p.rows;
-        const int v = static_cast<int>(img % p.n_views);
-        double sd, cd;
-        sincos(p.angle_start + v * p.angle_step, &sd, &cd);
-        // a single-row projection has no row direction: the kernel acts
-        // through its column component
-        const float du = static_cast<float>(cd), dv = p.rows > 1 ? static_cast<float>(sd) : 0.0f;
-        const T *im = src + img * p.rows * p.cols;
-        for (int c = lane; c < p.cols; c += 64) {
-            float acc = 0.0f;
-            for (int t = -h; t <= h; ++t) {
-                // offsets from the pixel, split into whole and fractional
-                // parts before the pixel index is added, so the fractions
-                // keep full FP32 precision whatever the detector size
-                const float tu = static_cast<float>(t) * du, tv = static_cast<float>(t) * dv;
-                const float iu = floorf(tu), iv = floorf(tv);
-                const float fx = tu - iu, fy = tv - iv;
-                const int x0 = c + static_cast<int>(iu), y0 = r + static_cast<int>(iv);
-                float s = 0.0f;
-#pragma unroll
-                for (int oy = 0; oy < 2; ++oy)
-#pragma unroll
-                    for (int ox = 0; ox < 2; ++ox) {
-                        const int xi = x0 + ox, yi = y0 + oy;
-                        const float w = (oy ? fy : 1.0f - fy) * (ox ? fx : 1.0f - fx);
-                        if (xi >= 0 && xi < p.cols && yi >= 0 && yi < p.rows)
-                            s = fmaf(w, to_f32(im[static_cast<int64_t>(yi) * p.cols + xi]), s);
-                    }
-                acc += s;
-            }
-            dst[(img * p.rows + r) * p.cols + c] = from_f32<T>(acc * inv);
-        }
-    }
-}
-
-hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st);
-
-template <typename P, typename F32K, typename B16K, typename F16K>
-static hipError_t launch_elementwise(const P &p, int64_t items, int32_t dt, F32K kf, B16K kb, F16K kh, hipStream_t st)
-{
-    const int64_t blocks = std::min<int64_t>((items + 255) / 256, 256 * 32);
-    if (blocks <= 0) return hipSuccess;
-    const dim3 grid(static_cast<uint32_t>(blocks));
-    switch (dt) {
-    case DT_F32: kf<<<grid, 256, 0, st>>>(p); break;
-    case DT_BF16: kb<<<grid, 256, 0, st>>>(p); break;
-    default: kh<<<grid, 256, 0, st>>>(p); break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_noise(const NoiseParams &p, int32_t dt, hipStream_t st)
-{
-    return launch_elementwise(p, (p.n + 3) / 4, dt, noise_kernel<float>, noise_kernel<bf16>, noise_kernel<f16>, st);
-}
-
-hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st)
-{
-    // one wave per group of 64 rows
-    return launch_elementwise(p, (p.n_rows + 63) / 64 * 64, dt, jitter_kernel<float>, jitter_kernel<bf16>,
-                              jitter_kernel<f16>, st);
-}
-
-hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st)
-{
-    // one wave per detector row
-    return launch_elementwise(p, p.batch * p.n_views * p.rows * 64, dt, blur_kernel<float>, blur_kernel<bf16>,
-                              blur_kernel<f16>, st);
-}
-
-hipError_t launch_ring(const RingParams &p, int32_t dt, hipStream_t st)
-{
-    const int64_t items = p.batch * (p.v1 - p.v0) * p.rows * p.n_sel;
-    return launch_elementwise(p, items, dt, ring_kernel<float>, ring_kernel<bf16>, ring_kernel<f16>, st);
 }
 
 // ------------------------------------------------------- utilities -------
