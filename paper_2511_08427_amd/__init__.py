@@ -8,9 +8,12 @@ this package marshals torch tensors into it.
 from . import _native
 from .geometry import (
     Geometry,
+    calibrated_geometry,
     circular_vectors,
     cone_geometry,
     cone_matrices,
+    decompose_cone_matrix,
+    detector_pose,
     fan_geometry,
     fan_matrices,
     parallel2d_matrices,

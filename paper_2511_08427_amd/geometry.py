@@ -158,7 +158,9 @@ def trajectory_vectors(kind, n_views, angular_range, sid, sdd, det_shape, det_sp
     circular trajectory.
 
     helical: source and detector rise by h = pitch * rows * dv * SID/SDD per
-    turn, S_z = h (beta / 2pi - 1/2); sinusoidal: S_z = (nz sz / 4) sin(2 beta),
+    turn over angular_range / 2pi turns (several for long objects), centred
+    on z = 0: S_z = h (beta - angular_range / 2) / 2pi; sinusoidal:
+    S_z = (nz sz / 4) sin(2 beta),
     detector following; perturbed: circular plus ``draws`` = {dS, dC (mm),
     dphi (rad, in-panel rotation of e_u/e_v)}.
     """
@@ -167,7 +169,9 @@ def trajectory_vectors(kind, n_views, angular_range, sid, sdd, det_shape, det_sp
     if kind == "circular":
         pass
     elif kind == "helical":
-        dz = pitch * det_shape[0] * det_spacing[0] * sid / sdd * (b / (2 * math.pi) - 0.5)
+        # feed h per turn over angular_range / 2pi turns, centred on z = 0
+        h = pitch * det_shape[0] * det_spacing[0] * sid / sdd
+        dz = h * (b - 0.5 * float(angular_range)) / (2 * math.pi)
         S[:, 2] += dz
         C[:, 2] += dz
     elif kind == "sinusoidal":
@@ -187,13 +191,46 @@ def trajectory_vectors(kind, n_views, angular_range, sid, sdd, det_shape, det_sp
     return S, C, eu, ev
 
 
+def _rotate(v, axis, angle):
+    """Rodrigues rotation of the rows of v about the unit rows of axis."""
+    c, s = math.cos(angle), math.sin(angle)
+    k = axis
+    return v * c + np.cross(k, v) * s + k * np.sum(k * v, axis=1, keepdims=True) * (1.0 - c)
+
+
+def detector_pose(S, C, eu, ev, offset=(0.0, 0.0), tilt=(0.0, 0.0, 0.0)):
+    """Moves each flat panel within its plane and turns it about its centre
+    (Sec. 2.4: arbitrary detector positions and orientations).
+
+    offset (o_u, o_v): mm along the panel's unit axes u_hat, v_hat.
+    tilt (roll, tilt_u, tilt_v), rad: the panel turns by `roll` about its
+    normal n_hat = u_hat x v_hat, then by `tilt_u` about its (new) u axis,
+    then by `tilt_v` about its (new) v axis, all through the shifted centre;
+    the pixel pitches stay.  Vectors of shape (n_views, 3).
+    """
+    S, C, eu, ev = (np.array(a, dtype=np.float64, ndmin=2) for a in (S, C, eu, ev))
+    du = np.linalg.norm(eu, axis=1, keepdims=True)
+    dv = np.linalg.norm(ev, axis=1, keepdims=True)
+    u, v = eu / du, ev / dv
+    C = C + float(offset[0]) * u + float(offset[1]) * v
+    n = np.cross(u, v)
+    roll, tu, tv = (float(a) for a in tilt)
+    u, v = _rotate(u, n, roll), _rotate(v, n, roll)
+    v, n = _rotate(v, u, tu), _rotate(n, u, tu)
+    u = _rotate(u, v, tv)
+    return S, C, du * u, dv * v
+
+
 def cone_geometry(vol_shape, vol_spacing, det_shape, det_spacing, n_views, sid, sdd,
                   angular_range=2 * math.pi, trajectory="circular", pitch=0.5, draws=None,
-                  vol_origin=(math.nan,) * 3) -> Geometry:
+                  vol_origin=(math.nan,) * 3, det_offset=(0.0, 0.0), det_tilt=(0.0, 0.0, 0.0)) -> Geometry:
     """3-D cone beam on a generated trajectory (Listing 1: GeometryCone3D +
-    circular_trajectory_3d)."""
+    circular_trajectory_3d), optionally with the panel moved by det_offset
+    and turned by det_tilt (see detector_pose)."""
     S, C, eu, ev = trajectory_vectors(trajectory, n_views, angular_range, sid, sdd, det_shape, det_spacing,
                                       vol_shape, vol_spacing, pitch, draws)
+    if any(det_offset) or any(det_tilt):
+        S, C, eu, ev = detector_pose(S, C, eu, ev, det_offset, det_tilt)
     P = cone_matrices(S, C, eu, ev, det_shape)
     return Geometry(3, "cone", vol_shape, vol_spacing, det_shape, P, det_spacing, vol_origin, sid, sdd)
 
@@ -222,3 +259,37 @@ def parallel_geometry(img_shape, img_spacing, n_cols, det_spacing, n_views, angu
     ny, nx = img_shape
     return Geometry(2, "parallel", (1, ny, nx), (1.0,) + tuple(img_spacing), (1, n_cols), P,
                     (1.0, float(det_spacing)))
+
+
+# ------------------------------------------------- calibrated matrices ---
+
+
+def calibrated_geometry(matrices, vol_shape, vol_spacing, det_shape, det_spacing=(1.0, 1.0),
+                        vol_origin=(math.nan,) * 3, beam="cone") -> Geometry:
+    """A geometry from measured projection matrices (Sec. 2.1: calibrated
+    matrices of a real system), checked by the library before use: finite,
+    non-singular, the volume (dilated by a voxel) in front of every source
+    and the source outside it (PnError otherwise).  matrices: (n, 3, 4)
+    mapping world mm to detector pixel indices (column, row)."""
+    ndim = 3 if np.asarray(matrices).shape[-2:] == (3, 4) else 2
+    g = Geometry(ndim, beam, vol_shape, vol_spacing, det_shape, matrices, det_spacing, vol_origin)
+    N.check(N.lib.pn_check_geometry(g.c_struct()), "pn_check_geometry")
+    return g
+
+
+def decompose_cone_matrix(P, det_shape, det_spacing):
+    """Source, detector centre and pixel steps (S, C, e_u, e_v) of a 3x4
+    cone-beam matrix, the inverse of cone_matrices for a panel with the given
+    pixel pitch (det_spacing = (row, column) mm); the overall scale and sign
+    of P do not matter."""
+    P = np.asarray(P, dtype=np.float64).reshape(3, 4)
+    A = P[:, :3]
+    S = -np.linalg.solve(A, P[:, 3])
+    Ai = np.linalg.inv(A)               # columns: e_u, e_v, d00 - S, up to one scale
+    k = float(det_spacing[1]) / np.linalg.norm(Ai[:, 0])
+    if np.dot(Ai[:, 2], -S) < 0:        # the pixel (0, 0) lies beyond the source, not behind it
+        k = -k
+    eu, ev, d00 = k * Ai[:, 0], k * Ai[:, 1], S + k * Ai[:, 2]
+    rows, cols = det_shape
+    C = d00 + 0.5 * (cols - 1) * eu + 0.5 * (rows - 1) * ev
+    return S, C, eu, ev
