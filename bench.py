@@ -122,7 +122,21 @@ def batched_variant(pn, W, np, torch, stream):
     tsf, _ = timed(lambda: [pn.forward(x, g) for x, g in pairs], 3, stream)
     tsa, _ = timed(lambda: [pn.adjoint(y, g) for y, g in sp], 3, stream)
     log(f"single calls: A {tsf:.2f} ms, AT {tsa:.2f} ms")
+    # batch plans: one launch per kernel group, replayed from the library's graph
+    fplan = pn.BatchPlan("forward", pairs)
+    aplan = pn.BatchPlan("adjoint", sp)
+    fplan.run()
+    aplan.run()
+    torch.cuda.synchronize()
+    tpf, _ = timed(fplan.run, 3, stream)
+    tpa, _ = timed(aplan.run, 3, stream)
+    log(f"batch plans (graph replay): A {tpf:.2f} ms, AT {tpa:.2f} ms")
+    fplan.close()
+    aplan.close()
     return {
+        "batch_plan_pair_gups": upd / ((tpf + tpa) * 1e-3) / 1e9,
+        "batch_plan_forward_ms": tpf,
+        "batch_plan_adjoint_ms": tpa,
         "batched_pair_gups": upd / ((tf + ta) * 1e-3) / 1e9,
         "batched_forward_ms": tf,
         "batched_adjoint_ms": ta,

@@ -262,14 +262,45 @@ int pn_ring_artifacts(int64_t batch, int32_t n_views, int32_t rows, int32_t cols
  * validated before anything is enqueued; the problems are ordered by
  * estimated cost, largest first, and run as work lists of up to 12 problems
  * per kernel launch (per dominant axis for the adjoint).  Each problem's
- * result equals its single-problem call bit for bit.  Graph capture follows
- * the rules above. */
+ * result equals its single-problem call bit for bit.  The work lists travel
+ * as kernel arguments, so these calls can be captured (the rules above);
+ * for one launch per kernel group over any number of problems, replayed
+ * from a graph the library captures, see the batch plans below. */
 int pn_forward_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
                        void *hip_stream);
 int pn_adjoint_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
                        void *hip_stream);
 int pn_backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
                            void *hip_stream);
+
+/* Batch plans: one fixed problem set run many times (the batch axis of the
+ * layers, Sec. 2.3 Listing 1; uneven problem lists).  pn_batch_create
+ * validates the problems, readies their plans (pinned and held by the
+ * batch plan, so pn_release_caches keeps them), builds every work buffer and
+ * candidate table on a stream of its own, writes one work list per kernel
+ * group into device memory (problems largest first, all of a group in ONE
+ * launch) and captures the whole operator -- relayouts, fills, main
+ * kernels, 16-bit conversions -- in a HIP graph.  pn_batch_run replays that
+ * graph on hip_stream: it reads the problems' current input buffers and
+ * overwrites their output buffers, with results equal to pn_*_batched bit
+ * for bit.  The buffers of `probs` are fixed at creation: they must stay
+ * allocated, and the caller changes the inputs' contents between runs, not
+ * their addresses.  Problems that share a geometry share work buffers, so
+ * they run in successive groups of launches.
+ *   op: PN_OP_FORWARD (in = volume, out = sinogram), PN_OP_ADJOINT or
+ *       PN_OP_BACKPROJECT (in = sinogram, out = volume).
+ *   Errors: those of the batched calls, PN_EINVAL for n == 0 or an unknown
+ *   op, PN_ENOMEM, PN_EHIP (graph capture or instantiation).
+ * pn_batch_run from a device other than the creating one returns
+ * PN_EINVAL.  pn_batch_destroy frees the graph and the work lists and
+ * releases the plans (NULL is allowed); runs already enqueued must have
+ * completed. */
+typedef enum { PN_OP_FORWARD = 0, PN_OP_ADJOINT = 1, PN_OP_BACKPROJECT = 2 } pn_op;
+typedef struct pn_batch pn_batch;
+int pn_batch_create(int32_t op, const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
+                    pn_batch **out);
+int pn_batch_run(pn_batch *b, void *hip_stream);
+int pn_batch_destroy(pn_batch *b);
 
 /* Host-only validation of a geometry (no device work): 0 or a PN_E* code. */
 int pn_check_geometry(const pn_geometry *pg);

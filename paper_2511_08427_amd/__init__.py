@@ -24,6 +24,7 @@ from .geometry import (
 from .ops import (
     AdjointProjection,
     BackProjection,
+    BatchPlan,
     ConeBackProjection3D,
     ConeProjection3D,
     FanBackProjection2D,

@@ -35,6 +35,9 @@ EXPORTS = (
     "pn_forward_batched",
     "pn_adjoint_batched",
     "pn_backproject_batched",
+    "pn_batch_create",
+    "pn_batch_run",
+    "pn_batch_destroy",
     "pn_filter",
     "pn_gaussian_noise",
     "pn_detector_jitter",
@@ -95,6 +98,12 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [ctypes.POINTER(PnProblem), i32, i32, i32, vp]
         f.restype = ctypes.c_int
+    lib.pn_batch_create.argtypes = [i32, ctypes.POINTER(PnProblem), i32, i32, i32, ctypes.POINTER(vp)]
+    lib.pn_batch_create.restype = ctypes.c_int
+    lib.pn_batch_run.argtypes = [vp, vp]
+    lib.pn_batch_run.restype = ctypes.c_int
+    lib.pn_batch_destroy.argtypes = [vp]
+    lib.pn_batch_destroy.restype = ctypes.c_int
     lib.pn_filter.argtypes = [gp, i64, vp, vp, i32, i32, i32, vp]
     lib.pn_filter.restype = ctypes.c_int
     lib.pn_gaussian_noise.argtypes = [i64, vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, vp]

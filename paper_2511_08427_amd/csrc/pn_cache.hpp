@@ -90,7 +90,8 @@ private:
     std::vector<void *> retired_;
 };
 
-// Least-recently-used list of plans.  P needs a member `bool pinned`.
+// Least-recently-used list of plans.  P needs `bool held() const`: a held
+// plan (used under capture, or by a live batch plan) is never evicted.
 template <class P>
 class PlanLru {
 public:
@@ -109,26 +110,42 @@ public:
     }
 
     // Inserts a plan as the most recently used one, then evicts the least
-    // recently used unpinned plans while more than `limit` are held.
+    // recently used plans that are not held while more than `limit` are
+    // kept; the new plan itself is never evicted (when every other plan is
+    // held the list grows past the limit).
     P *insert(std::unique_ptr<P> p, size_t limit)
     {
         plans_.push_front(std::move(p));
         P *front = plans_.front().get();
-        trim(limit);
+        trim(limit, 1);
         return front;
     }
 
-    void trim(size_t limit)
+    // Evicts the least recently used plans that are not held, sparing the
+    // `spare` most recently used ones, while more than `limit` are kept.
+    void trim(size_t limit, size_t spare = 0)
     {
         auto it = plans_.end();
-        while (plans_.size() > limit && it != plans_.begin()) {
+        size_t left = plans_.size();  // plans at or before `it`
+        while (plans_.size() > limit && left > spare) {
             --it;
-            if ((*it)->pinned) continue;
+            --left;
+            if ((*it)->held()) continue;
             it = plans_.erase(it);
         }
     }
 
     void clear() { plans_.clear(); }
+
+    // Destroys every plan for which keep() is false.
+    template <class Keep>
+    void remove_unless(Keep keep)
+    {
+        for (auto it = plans_.begin(); it != plans_.end();) {
+            if (keep(**it)) ++it;
+            else it = plans_.erase(it);
+        }
+    }
     size_t size() const { return plans_.size(); }
 
 private:

@@ -150,6 +150,16 @@ struct FiltParams {
     void *out;             // same shape
 };
 
+// Work list in device memory (a batch plan's table): workgroups
+// [start[i], start[i + 1]) run problem p[i]; one launch covers any number of
+// problems.
+template <typename P>
+struct Table {
+    const P *p;
+    const uint32_t *start;  // n + 1 entries
+    int32_t n;
+};
+
 // Work list of a batched launch, passed by value as the kernel argument
 // (no device allocation or copy, so a batched call can be captured in a
 // graph): workgroups [start[i], start[i+1]) run problem i.

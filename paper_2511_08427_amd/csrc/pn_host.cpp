@@ -24,6 +24,13 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
 bool adjoint_fusable(bool two_d, int shape);
+hipError_t launch_forward_table(const Table<FwdParams> &w, uint32_t blocks, bool two_d, int32_t in_dt,
+                                int32_t out_dt, hipStream_t st);
+hipError_t launch_adjoint_table(const Table<AdjParams> &w, uint32_t blocks, int axis, int32_t in_dt, int shape,
+                                hipStream_t st);
+hipError_t launch_adjoint_fused_table(const Table<AdjFused> &w, uint32_t blocks, int32_t in_dt, hipStream_t st);
+hipError_t launch_backproject_table(const Table<BpParams> &w, uint32_t blocks, bool two_d, int32_t in_dt,
+                                    int32_t out_dt, hipStream_t st);
 hipError_t launch_adjoint_fused(const AdjFused &f, int32_t in_dt, hipStream_t st);
 hipError_t launch_backproject(const BpParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_splat(const SplatParams &p, int32_t in_dt, hipStream_t st);
@@ -84,6 +91,10 @@ struct Plan : HostTables {
     // used by a call under stream capture: never evicted, buffers never
     // freed or re-purposed before pn_release_caches
     bool pinned = false;
+    // batch plans (pn_batch_create) that use this plan: while any does, the
+    // plan is held like a pinned one and outlives pn_release_caches
+    int refs = 0;
+    bool held() const { return pinned || refs > 0; }
     ViewTab *d_tab = nullptr;
     ViewTabF *d_tabf = nullptr;
     int32_t *d_views[3] = {nullptr, nullptr, nullptr};
@@ -119,6 +130,7 @@ struct Plan : HostTables {
 
 std::mutex g_mu;
 PlanLru<Plan> g_plans;
+int g_live_batches = 0;  // batch plans not yet destroyed; guarded by g_mu
 const size_t kMaxPlans = 32;
 
 // True when work enqueued on `st` is being captured into a graph.
@@ -141,7 +153,7 @@ int ensure_buf(Plan &pl, DevBuf &b, size_t need, int32_t tag, bool zero, hipStre
                bool &fresh)
 {
     fresh = false;
-    switch (g_keeper.ensure(b, need, tag, pl.pinned, capturing(st))) {
+    switch (g_keeper.ensure(b, need, tag, pl.held(), capturing(st))) {
     case Ensure::kReady: return PN_OK;
     case Ensure::kCapturing: return capture_error(what);
     case Ensure::kNoMem: return fail(PN_ENOMEM, "%s: hipMalloc(%zu) failed", what, need);
@@ -1148,6 +1160,326 @@ int backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dt, int32
     return run_batched(probs, order, st, prepare, launch);
 }
 
+// ------------------------------------------------------- batch plans -----
+//
+// A batch plan fixes a problem set (geometries, buffers, types) once:
+// its plans are pinned and referenced, every kernel group of the operator
+// runs as ONE launch over a work list in device memory (largest problems
+// first), and the whole operator -- relayouts, fills, candidate tables,
+// main kernels, 16-bit conversions -- is captured in a HIP graph on a
+// library stream, which pn_batch_run replays on the caller's stream.
+// Problems that share a plan (same geometry) share its work buffers, so
+// they go to successive groups, each group its own set of launches.
+
+enum TableKind { TK_FWD = 0, TK_ADJ = 1, TK_FUSED = 2, TK_BP = 3 };
+
+struct TableSlice {
+    int kind = 0;
+    bool two_d = false;
+    int axis = 0, shape = 0;
+    size_t off_p = 0, off_start = 0;  // byte offsets in the device table
+    int32_t n = 0;
+    uint32_t blocks = 0;
+};
+
+struct BatchGroup {
+    std::vector<int32_t> probs;       // problem indices, largest first
+    std::vector<TableSlice> slices;
+};
+
+}  // namespace
+
+struct pn_batch {
+    int32_t op = 0, in_dt = 0, out_dt = 0;
+    int device = 0;
+    std::vector<pn_problem> probs;
+    std::vector<Plan *> plans;         // per problem
+    std::vector<BatchGroup> groups;
+    std::vector<unsigned char> host_table;
+    void *d_table = nullptr;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+template <typename P>
+void append_list(std::vector<unsigned char> &buf, const std::vector<P> &items, const std::vector<uint32_t> &start,
+                 TableSlice &sl)
+{
+    auto align = [&](size_t a) { buf.resize((buf.size() + a - 1) / a * a); };
+    align(256);
+    sl.off_p = buf.size();
+    buf.resize(buf.size() + sizeof(P) * items.size());
+    std::memcpy(buf.data() + sl.off_p, items.data(), sizeof(P) * items.size());
+    align(16);
+    sl.off_start = buf.size();
+    buf.resize(buf.size() + sizeof(uint32_t) * start.size());
+    std::memcpy(buf.data() + sl.off_start, start.data(), sizeof(uint32_t) * start.size());
+    sl.n = (int32_t)items.size();
+    sl.blocks = start.back();
+}
+
+// Work list of `items` with blocks(item) workgroups each, problems starting
+// at multiples of `align`.
+template <typename P, typename BlocksFn>
+int list_starts(const std::vector<P> &items, BlocksFn blocks, int64_t align, std::vector<uint32_t> &start)
+{
+    start.assign(1, 0u);
+    int64_t at = 0;
+    for (const P &p : items) {
+        at += (blocks(p) + align - 1) / align * align;
+        if (at > INT32_MAX) return fail(PN_EINVAL, "batch plan: a kernel group is too large for one launch");
+        start.push_back((uint32_t)at);
+    }
+    return PN_OK;
+}
+
+// Prepares every problem of batch plan B on stream st (enqueueing its
+// relayouts, fills and candidate tables) and either records the kernel
+// groups' work lists into B.host_table (build) or launches them from the
+// device table (!build).  The prepared parameters must be the same in both
+// phases: they depend only on the pinned plans and the fixed buffers.
+int batch_enqueue(pn_batch &B, hipStream_t st, bool build)
+{
+    const int n = (int)B.probs.size();
+    std::vector<FwdJob> fj(B.op == PN_OP_FORWARD ? n : 0);
+    std::vector<AdjJob> aj(B.op == PN_OP_ADJOINT ? n : 0);
+    std::vector<BpJob> bj(B.op == PN_OP_BACKPROJECT ? n : 0);
+    if (build) B.host_table.clear();
+    char *dt = static_cast<char *>(B.d_table);
+    for (BatchGroup &G : B.groups) {
+        std::vector<char> live(n, 0);
+        for (int32_t i : G.probs) {
+            const pn_problem &pr = B.probs[i];
+            bool none = false;
+            int rc = PN_OK;
+            if (B.op == PN_OP_FORWARD)
+                rc = forward_prepare(&pr.geom, 1, pr.in, pr.out, B.in_dt, B.out_dt, st, B.plans[i], fj[i], none);
+            else if (B.op == PN_OP_ADJOINT)
+                rc = adjoint_prepare(1, pr.in, pr.out, B.in_dt, B.out_dt, st, B.plans[i], aj[i], none);
+            else
+                backproject_prepare(1, pr.in, pr.out, B.plans[i], bj[i]);
+            if (rc) {
+                std::string msg = pn_last_error();
+                return fail(rc, "batch plan, problem %d: %s", i, msg.c_str());
+            }
+            live[i] = !none;
+        }
+        if (build) G.slices.clear();
+        size_t k = 0;  // slice index within the group (launch phase)
+        auto take = [&](int kind, bool two_d, int axis, int shape) -> TableSlice * {
+            if (build) {
+                G.slices.push_back(TableSlice{});
+                TableSlice &sl = G.slices.back();
+                sl.kind = kind;
+                sl.two_d = two_d;
+                sl.axis = axis;
+                sl.shape = shape;
+                return &sl;
+            }
+            if (k >= G.slices.size()) return nullptr;
+            TableSlice &sl = G.slices[k++];
+            if (sl.kind != kind || sl.two_d != two_d || sl.axis != axis || sl.shape != shape) return nullptr;
+            return &sl;
+        };
+        auto mismatch = [] { return fail(PN_EINVAL, "batch plan: prepared state changed between build and capture"); };
+        // one list: the items it would hold, checked against (or recorded
+        // into) the table, then launched from the device table
+        auto list = [&](auto items, auto blocks, int64_t align, int kind, bool two_d, int axis, int shape,
+                        auto launch) -> int {
+            using P = typename decltype(items)::value_type;
+            if (items.empty()) return PN_OK;
+            std::vector<uint32_t> start;
+            int r = list_starts(items, blocks, align, start);
+            if (r) return r;
+            TableSlice *sl = take(kind, two_d, axis, shape);
+            if (!sl) return mismatch();
+            if (build) {
+                append_list(B.host_table, items, start, *sl);
+                return PN_OK;
+            }
+            if (sl->n != (int32_t)items.size() || sl->blocks != start.back() ||
+                std::memcmp(B.host_table.data() + sl->off_p, items.data(), sizeof(P) * items.size()) != 0)
+                return mismatch();
+            Table<P> w;
+            w.p = reinterpret_cast<const P *>(dt + sl->off_p);
+            w.start = reinterpret_cast<const uint32_t *>(dt + sl->off_start);
+            w.n = sl->n;
+            hipError_t e = launch(w, sl->blocks);
+            return e == hipSuccess ? PN_OK : fail_hip(e, "batch plan launch");
+        };
+        int rc = PN_OK;
+        if (B.op == PN_OP_FORWARD) {
+            for (int td = 0; td < 2 && !rc; ++td) {
+                std::vector<FwdParams> items;
+                for (int32_t i : G.probs)
+                    if (live[i] && fj[i].two_d == (td != 0)) items.push_back(fj[i].p);
+                rc = list(items, [](const FwdParams &p) { return forward_blocks(p); }, 8, TK_FWD, td != 0, 0, 0,
+                          [&](const Table<FwdParams> &w, uint32_t blocks) {
+                              return launch_forward_table(w, blocks, td != 0, B.in_dt, B.out_dt, st);
+                          });
+            }
+        } else if (B.op == PN_OP_ADJOINT) {
+            std::vector<AdjFused> fused;
+            for (int32_t i : G.probs) {
+                if (!live[i] || !adjoint_fusable(aj[i].two_d, aj[i].shape)) continue;
+                const Geo &g = B.plans[i]->g;
+                AdjFused f{};
+                int32_t L, TS, TF;
+                adjoint_shape(aj[i].shape, L, TS, TF);
+                for (int a = 0; a < 3; ++a) {
+                    f.pass[a] = aj[i].pass[a];
+                    f.nb[a] = (g.n[a] + L - 1) / L;
+                }
+                f.batch = 1;
+                fused.push_back(f);
+            }
+            rc = list(fused, [](const AdjFused &f) { return (int64_t)f.nb[0] * f.nb[1] * f.nb[2] * f.batch; }, 1,
+                      TK_FUSED, false, 0, 0, [&](const Table<AdjFused> &w, uint32_t blocks) {
+                          return launch_adjoint_fused_table(w, blocks, B.in_dt, st);
+                      });
+            // passes in axis order: a problem's later passes add to its earlier ones
+            for (int a = 0; a < 3 && !rc; ++a)
+                for (int shape = 0; shape < adjoint_shape_count() && !rc; ++shape) {
+                    std::vector<AdjParams> items;
+                    for (int32_t i : G.probs)
+                        if (live[i] && !adjoint_fusable(aj[i].two_d, aj[i].shape) && aj[i].shape == shape &&
+                            aj[i].pass[a].n_pass_views > 0)
+                            items.push_back(aj[i].pass[a]);
+                    rc = list(items, [](const AdjParams &p) { return adjoint_blocks(p); }, 1, TK_ADJ, false, a,
+                              shape, [&](const Table<AdjParams> &w, uint32_t blocks) {
+                                  return launch_adjoint_table(w, blocks, a, B.in_dt, shape, st);
+                              });
+                }
+            for (int32_t i : G.probs)
+                if (!rc && live[i]) rc = adjoint_finish(aj[i], st);
+        } else {
+            for (int td = 0; td < 2 && !rc; ++td) {
+                std::vector<BpParams> items;
+                for (int32_t i : G.probs)
+                    if (bj[i].two_d == (td != 0)) items.push_back(bj[i].p);
+                rc = list(items, [](const BpParams &p) { return backproject_blocks(p); }, 1, TK_BP, td != 0, 0, 0,
+                          [&](const Table<BpParams> &w, uint32_t blocks) {
+                              return launch_backproject_table(w, blocks, td != 0, B.in_dt, B.out_dt, st);
+                          });
+            }
+        }
+        if (rc) return rc;
+        if (!build && k != G.slices.size()) return mismatch();
+    }
+    return PN_OK;
+}
+
+void batch_free(pn_batch *B)
+{
+    if (!B) return;
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    if (B->cs) (void)hipStreamDestroy(B->cs);
+    dev_free(B->d_table);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (Plan *pl : B->plans)
+            if (pl) --pl->refs;
+        --g_live_batches;
+    }
+    delete B;
+}
+
+int batch_create(int32_t op, const pn_problem *probs, int32_t n, int32_t in_dt, int32_t out_dt, pn_batch **out)
+{
+    if (!out) return fail(PN_EINVAL, "pn_batch_create: output pointer is NULL");
+    *out = nullptr;
+    if (op != PN_OP_FORWARD && op != PN_OP_ADJOINT && op != PN_OP_BACKPROJECT)
+        return fail(PN_EINVAL, "pn_batch_create: unknown operator %d", op);
+    std::vector<int32_t> order;
+    int rc = batch_order(probs, n, in_dt, out_dt, op != PN_OP_FORWARD, order);
+    if (rc) return rc;
+    if (n == 0) return fail(PN_EINVAL, "pn_batch_create: no problems");
+    auto *B = new pn_batch();
+    B->op = op;
+    B->in_dt = in_dt;
+    B->out_dt = out_dt;
+    B->probs.assign(probs, probs + n);
+    B->plans.assign(n, nullptr);
+    hipError_t e = hipGetDevice(&B->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->cs, hipStreamNonBlocking);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ++g_live_batches;
+    }
+    if (e != hipSuccess) {
+        batch_free(B);
+        return fail_hip(e, "pn_batch_create");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        std::vector<Plan *> in_group;
+        for (int32_t i : order) {
+            Plan *pl;
+            if ((rc = get_plan(&B->probs[i].geom, B->cs, &pl))) {
+                std::string msg = pn_last_error();
+                rc = fail(rc, "problem %d: %s", i, msg.c_str());
+                break;
+            }
+            ++pl->refs;
+            B->plans[i] = pl;
+            if (B->groups.empty() || std::find(in_group.begin(), in_group.end(), pl) != in_group.end()) {
+                B->groups.emplace_back();
+                in_group.clear();
+            }
+            B->groups.back().probs.push_back(i);
+            in_group.push_back(pl);
+        }
+        // build: every buffer and candidate table is made on the library
+        // stream (eagerly), and the work lists are recorded
+        if (!rc) rc = batch_enqueue(*B, B->cs, true);
+    }
+    if (!rc && (e = hipStreamSynchronize(B->cs)) != hipSuccess) rc = fail_hip(e, "pn_batch_create");
+    if (!rc && (e = hipMalloc(&B->d_table, std::max<size_t>(B->host_table.size(), 256))) != hipSuccess)
+        rc = fail(PN_ENOMEM, "pn_batch_create: hipMalloc(%zu) failed", B->host_table.size());
+    if (!rc && !B->host_table.empty() &&
+        (e = hipMemcpy(B->d_table, B->host_table.data(), B->host_table.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        rc = fail_hip(e, "pn_batch_create: table copy");
+    if (!rc) {
+        // capture the operator on the library stream
+        if ((e = hipStreamBeginCapture(B->cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+            rc = fail_hip(e, "pn_batch_create: begin capture");
+        } else {
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                rc = batch_enqueue(*B, B->cs, false);
+            }
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(B->cs, &g);
+            B->graph = g;
+            if (!rc && e != hipSuccess) rc = fail_hip(e, "pn_batch_create: end capture");
+            if (!rc && (e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0)) != hipSuccess)
+                rc = fail_hip(e, "pn_batch_create: graph instantiation");
+        }
+    }
+    if (rc) {
+        std::string msg = pn_last_error();
+        batch_free(B);
+        return fail(rc, "%s", msg.c_str());
+    }
+    *out = B;
+    return PN_OK;
+}
+
+int batch_run(pn_batch *B, hipStream_t st)
+{
+    if (!B) return fail(PN_EINVAL, "pn_batch_run: batch plan is NULL");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev != B->device) return fail(PN_EINVAL, "pn_batch_run: the batch plan belongs to device %d", B->device);
+    if ((e = hipGraphLaunch(B->exec, st)) != hipSuccess) return fail_hip(e, "pn_batch_run: graph launch");
+    return PN_OK;
+}
+
 }  // namespace
 
 // ==================================================== extern "C" ABI =====
@@ -1246,12 +1578,33 @@ int pn_backproject_batched(const pn_problem *probs, int32_t n, int32_t in_dtype,
     return backproject_batched(probs, n, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
 }
 
+int pn_batch_create(int32_t op, const pn_problem *probs, int32_t n, int32_t in_dtype, int32_t out_dtype,
+                    pn_batch **out)
+{
+    clear_error();
+    return batch_create(op, probs, n, in_dtype, out_dtype, out);
+}
+
+int pn_batch_run(pn_batch *b, void *hip_stream)
+{
+    clear_error();
+    return batch_run(b, static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_batch_destroy(pn_batch *b)
+{
+    clear_error();
+    batch_free(b);
+    return PN_OK;
+}
+
 int pn_release_caches(void)
 {
     clear_error();
     std::lock_guard<std::mutex> lk(g_mu);
-    g_plans.clear();
-    g_keeper.release_retired();
+    // plans and retired buffers that live batch plans' graphs use stay
+    g_plans.remove_unless([](const Plan &p) { return p.refs > 0; });
+    if (g_live_batches == 0) g_keeper.release_retired();
     return PN_OK;
 }
 

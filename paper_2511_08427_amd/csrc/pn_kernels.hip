@@ -116,6 +116,20 @@ __device__ __forceinline__ int batch_item(const Batch<P> &w, int bid)
     return lo;
 }
 
+// The problem of workgroup `bid` in a device-memory work list (the search
+// reads wave-uniform addresses: scalar loads).
+template <typename P>
+__device__ __forceinline__ int table_item(const Table<P> &w, int bid)
+{
+    int lo = 0, hi = w.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (static_cast<int>(w.start[mid]) <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------- relayout --------
 
 // a = x: out[b][i][k + PADR_LO][j + PADC] = in[b][k][j][i] (tiled transpose)
@@ -692,6 +706,13 @@ template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP, int
 __global__ __launch_bounds__(256, 5) void forward_batch_kernel(Batch<FwdParams> w)
 {
     const int i = batch_item(w, blockIdx.x);
+    forward_block<S, O, TU, TV, C, RCAP, FCAP, NVW>(w.p[i], blockIdx.x - w.start[i]);
+}
+
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP, int NVW>
+__global__ __launch_bounds__(256, 5) void forward_table_kernel(Table<FwdParams> w)
+{
+    const int i = table_item(w, blockIdx.x);
     forward_block<S, O, TU, TV, C, RCAP, FCAP, NVW>(w.p[i], blockIdx.x - w.start[i]);
 }
 
@@ -1286,6 +1307,14 @@ __global__ __launch_bounds__(NT, 4) void adjoint_batch_kernel(Batch<AdjParams> w
     adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT, NT>(w.p[i], blockIdx.x - w.start[i], sh);
 }
 
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
+__global__ __launch_bounds__(NT, 4) void adjoint_table_kernel(Table<AdjParams> w)
+{
+    __shared__ AdjLds<L, TS, TF, SLO, SHI, CPT, NT> sh;
+    const int i = table_item(w, blockIdx.x);
+    adjoint_block<Q, A, L, TS, TF, SLO, SHI, CPT, NT>(w.p[i], blockIdx.x - w.start[i], sh);
+}
+
 // All passes of a 3-D adjoint in one launch: a workgroup owns one cubic
 // block (B^3 voxels, in x, y, z block coordinates) and runs the passes
 // present one after the other, each exactly as its own launch would (the
@@ -1293,10 +1322,8 @@ __global__ __launch_bounds__(NT, 4) void adjoint_batch_kernel(Batch<AdjParams> w
 // result is bitwise that of one launch per pass).  One launch has one tail
 // instead of one per pass, and a block's passes share its LDS.
 template <typename Q, int B, int SLO, int SHI, int CPT, int NT>
-__global__ __launch_bounds__(NT, 4) void adjoint_fused_kernel(AdjFused f)
+__device__ __forceinline__ void adjoint_fused_block(const AdjFused &f, int blk, AdjLds<B, B, B, SLO, SHI, CPT, NT> &sh)
 {
-    __shared__ AdjLds<B, B, B, SLO, SHI, CPT, NT> sh;
-    int blk = blockIdx.x;
     const int bx = blk % f.nb[0];
     blk /= f.nb[0];
     const int by = blk % f.nb[1];
@@ -1321,6 +1348,21 @@ __global__ __launch_bounds__(NT, 4) void adjoint_fused_kernel(AdjFused f)
         adjoint_block<Q, 2, B, B, B, SLO, SHI, CPT, NT>(
             f.pass[2], ((b * f.nb[2] + bz) * f.nb[1] + by) * f.nb[0] + bx, sh);
     }
+}
+
+template <typename Q, int B, int SLO, int SHI, int CPT, int NT>
+__global__ __launch_bounds__(NT, 4) void adjoint_fused_kernel(AdjFused f)
+{
+    __shared__ AdjLds<B, B, B, SLO, SHI, CPT, NT> sh;
+    adjoint_fused_block<Q, B, SLO, SHI, CPT, NT>(f, blockIdx.x, sh);
+}
+
+template <typename Q, int B, int SLO, int SHI, int CPT, int NT>
+__global__ __launch_bounds__(NT, 4) void adjoint_fused_table_kernel(Table<AdjFused> w)
+{
+    __shared__ AdjLds<B, B, B, SLO, SHI, CPT, NT> sh;
+    const int i = table_item(w, blockIdx.x);
+    adjoint_fused_block<Q, B, SLO, SHI, CPT, NT>(w.p[i], blockIdx.x - w.start[i], sh);
 }
 
 // ------------------------------------------------ back-projection --------
@@ -1565,6 +1607,13 @@ template <typename Q, typename O, int BZ, int RCAP, int CCAP>
 __global__ __launch_bounds__(256, 8) void backproject_batch_kernel(Batch<BpParams> w)
 {
     const int i = batch_item(w, blockIdx.x);
+    backproject_block<Q, O, BZ, RCAP, CCAP>(w.p[i], blockIdx.x - w.start[i]);
+}
+
+template <typename Q, typename O, int BZ, int RCAP, int CCAP>
+__global__ __launch_bounds__(256, 8) void backproject_table_kernel(Table<BpParams> w)
+{
+    const int i = table_item(w, blockIdx.x);
     backproject_block<Q, O, BZ, RCAP, CCAP>(w.p[i], blockIdx.x - w.start[i]);
 }
 
@@ -1877,6 +1926,11 @@ static void fwd_go(const Batch<FwdParams> &w, uint32_t blocks, hipStream_t st)
 {
     forward_batch_kernel<S, O, TU, TV, C, RCAP, FCAP, NVW><<<dim3(blocks), 256, 0, st>>>(w);
 }
+template <typename S, typename O, int TU, int TV, int C, int RCAP, int FCAP, int NVW>
+static void fwd_go(const Table<FwdParams> &w, uint32_t blocks, hipStream_t st)
+{
+    forward_table_kernel<S, O, TU, TV, C, RCAP, FCAP, NVW><<<dim3(blocks), 256, 0, st>>>(w);
+}
 
 template <typename S, typename O, typename Arg>
 static hipError_t forward_t(const Arg &a, bool two_d, uint32_t blocks, hipStream_t st)
@@ -1953,6 +2007,11 @@ template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, i
 static void adj_go(const Batch<AdjParams> &w, uint32_t blocks, hipStream_t st)
 {
     adjoint_batch_kernel<Q, A, L, TS, TF, SLO, SHI, CPT, NT><<<dim3(blocks), NT, 0, st>>>(w);
+}
+template <typename Q, int A, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
+static void adj_go(const Table<AdjParams> &w, uint32_t blocks, hipStream_t st)
+{
+    adjoint_table_kernel<Q, A, L, TS, TF, SLO, SHI, CPT, NT><<<dim3(blocks), NT, 0, st>>>(w);
 }
 
 template <typename Q, int L, int TS, int TF, int SLO, int SHI, int CPT, int NT, typename Arg>
@@ -2040,6 +2099,11 @@ static void bp_go(const Batch<BpParams> &w, uint32_t blocks, hipStream_t st)
 {
     backproject_batch_kernel<Q, O, BZ, RCAP, CCAP><<<dim3(blocks), 256, 0, st>>>(w);
 }
+template <typename Q, typename O, int BZ, int RCAP, int CCAP>
+static void bp_go(const Table<BpParams> &w, uint32_t blocks, hipStream_t st)
+{
+    backproject_table_kernel<Q, O, BZ, RCAP, CCAP><<<dim3(blocks), 256, 0, st>>>(w);
+}
 
 template <typename Q, typename O, typename Arg>
 static hipError_t bp_t(const Arg &a, bool two_d, uint32_t blocks, hipStream_t st)
@@ -2080,6 +2144,36 @@ hipError_t launch_backproject_batch(const Batch<BpParams> &w, bool two_d, int32_
                                     hipStream_t st)
 {
     return bp_any(w, two_d, w.start[w.n], in_dt, out_dt, st);
+}
+
+// Launchers of device-memory work lists (`blocks`: the list's workgroups).
+hipError_t launch_forward_table(const Table<FwdParams> &w, uint32_t blocks, bool two_d, int32_t in_dt,
+                                int32_t out_dt, hipStream_t st)
+{
+    return forward_any(w, two_d, blocks, in_dt, out_dt, st);
+}
+
+hipError_t launch_adjoint_table(const Table<AdjParams> &w, uint32_t blocks, int axis, int32_t in_dt, int shape,
+                                hipStream_t st)
+{
+    return adjoint_any(w, axis, in_dt, shape, blocks, st);
+}
+
+hipError_t launch_adjoint_fused_table(const Table<AdjFused> &w, uint32_t blocks, int32_t in_dt, hipStream_t st)
+{
+    if (blocks == 0) return hipSuccess;
+    switch (in_dt) {
+    case DT_F32: adjoint_fused_table_kernel<float, 16, 1, 2, 2, 256><<<dim3(blocks), 256, 0, st>>>(w); break;
+    case DT_BF16: adjoint_fused_table_kernel<bf16, 16, 1, 2, 2, 256><<<dim3(blocks), 256, 0, st>>>(w); break;
+    default: adjoint_fused_table_kernel<f16, 16, 1, 2, 2, 256><<<dim3(blocks), 256, 0, st>>>(w); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject_table(const Table<BpParams> &w, uint32_t blocks, bool two_d, int32_t in_dt,
+                                    int32_t out_dt, hipStream_t st)
+{
+    return bp_any(w, two_d, blocks, in_dt, out_dt, st);
 }
 
 int64_t splat_blocks(const SplatParams &p)

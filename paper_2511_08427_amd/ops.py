@@ -217,6 +217,73 @@ def backproject_batched(pairs, out_dtype=None):
                     lambda g: g.vol_shape, out_dtype)
 
 
+class BatchPlan:
+    """A fixed problem set run many times (pn_batch_create / pn_batch_run):
+    one launch per kernel group over all problems, replayed from a HIP graph
+    the library captures.  ``op`` is "forward", "adjoint" or "backproject";
+    ``pairs`` are (input tensor, geometry) with one problem each.  The
+    outputs are allocated here; ``run()`` re-reads the inputs' current
+    contents (change them in place, not by rebinding) and returns the
+    outputs."""
+
+    _OPS = {"forward": 0, "adjoint": 1, "backproject": 2}
+
+    def __init__(self, op, pairs, out_dtype=None):
+        if op not in self._OPS:
+            raise ValueError(f"unknown operator {op!r}")
+        if not pairs:
+            raise ValueError("a batch plan needs at least one problem")
+        fwd = op == "forward"
+        src = (lambda g: g.vol_shape) if fwd else (lambda g: g.sino_shape())
+        dst = (lambda g: g.sino_shape()) if fwd else (lambda g: g.vol_shape)
+        dts = {t.dtype for t, _ in pairs}
+        devs = {t.device for t, _ in pairs}
+        if len(dts) != 1 or len(devs) != 1:
+            raise ValueError("all problems must share dtype and device")
+        dt, self.device = dts.pop(), devs.pop()
+        out_dtype = out_dtype or dt
+        probs = (N.PnProblem * len(pairs))()
+        self.inputs, self.outputs, self.geometries = [], [], []
+        for i, (t, g) in enumerate(pairs):
+            x, batched = _prep(t, "BatchPlan", src(g))
+            if batched:
+                raise ValueError("batch plans take one volume/sinogram per problem")
+            if x.data_ptr() != t.data_ptr():
+                raise ValueError("batch plan inputs must be contiguous tensors (they are read in place)")
+            o = torch.empty(dst(g), dtype=out_dtype, device=self.device)
+            probs[i].geom = g.c_struct()
+            probs[i].in_ = x.data_ptr()
+            probs[i].out = o.data_ptr()
+            self.inputs.append(x)
+            self.outputs.append(o)
+            self.geometries.append(g)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = N.lib.pn_batch_create(self._OPS[op], probs, len(pairs), _DT[dt], _DT[out_dtype], ctypes.byref(h))
+        N.check(rc, "pn_batch_create")
+        self._h = h
+
+    def run(self):
+        if self._h is None:
+            raise RuntimeError("batch plan already closed")
+        with torch.cuda.device(self.device):
+            N.check(N.lib.pn_batch_run(self._h, _stream(self.device)), "pn_batch_run")
+        return self.outputs
+
+    def close(self):
+        """Frees the graph and work lists (after waiting for the device)."""
+        if getattr(self, "_h", None) is not None:
+            torch.cuda.synchronize(self.device)
+            N.lib.pn_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # --------------------------------------------------------------- autograd --
 
 

@@ -57,6 +57,7 @@ using Keeper = pn::BufferKeeper<FakeMem>;
 struct FakePlan {
     int key = 0;
     bool pinned = false;
+    bool held() const { return pinned; }
     pn::DevBuf buf;
     Keeper *keeper = nullptr;
     ~FakePlan() { keeper->free(buf); }
@@ -123,6 +124,40 @@ void check_plans()
     // a limit no unpinned plan can satisfy: the pinned ones remain
     lru.trim(0);
     CHECK(lru.size() == 2);
+    lru.clear();
+    CHECK(FakeMem::live.empty());
+
+    // every plan held: the list grows past its limit, and a new plan is
+    // never evicted by its own insertion (its pointer stays valid)
+    for (int i = 0; i < 40; ++i) {
+        auto p = std::make_unique<FakePlan>();
+        p->key = 100 + i;
+        p->keeper = &k;
+        CHECK(k.ensure(p->buf, 16, 0, false, false) == pn::Ensure::kFresh);
+        FakePlan *q = lru.insert(std::move(p), 32);
+        CHECK(q->key == 100 + i && FakeMem::live.count(q->buf.ptr) == 1);
+        CHECK(lru.find([i](const FakePlan &f) { return f.key == 100 + i; }) == q);
+        q->pinned = true;
+    }
+    CHECK(lru.size() == 40);
+    // one unheld plan among held ones survives its insertion, and the next
+    // insertion evicts it
+    {
+        auto p = std::make_unique<FakePlan>();
+        p->key = 500;
+        p->keeper = &k;
+        CHECK(k.ensure(p->buf, 16, 0, false, false) == pn::Ensure::kFresh);
+        CHECK(lru.insert(std::move(p), 32)->key == 500);
+        auto r = std::make_unique<FakePlan>();
+        r->key = 501;
+        r->keeper = &k;
+        CHECK(k.ensure(r->buf, 16, 0, false, false) == pn::Ensure::kFresh);
+        CHECK(lru.insert(std::move(r), 32)->key == 501);
+        CHECK(lru.find([](const FakePlan &f) { return f.key == 500; }) == nullptr);
+        CHECK(lru.find([](const FakePlan &f) { return f.key == 501; }) != nullptr);
+    }
+    lru.remove_unless([](const FakePlan &f) { return f.key % 2 == 0; });
+    CHECK(lru.size() == 20);
     lru.clear();
     CHECK(FakeMem::live.empty());
 }
