@@ -91,6 +91,7 @@ struct BpParams {
     int32_t n[3];
     const void *sino;
     void *vol;
+    int32_t bz;            // 3-D block depth along z (8, 16 or 32); 0: the default 16
 };
 
 // Splat projector (transpose of the voxel-driven back-projection).

@@ -107,8 +107,11 @@ struct Plan : HostTables {
     // FP32 accumulation buffers for 16-bit outputs: the adjoint's volume,
     // the splat projector's sinogram
     DevBuf acc, sacc;
-    // 3-D adjoint block shape chosen by the autotuner (0: not tuned)
+    // choices of the autotuner (0: not tuned): the 3-D adjoint block shape,
+    // the forward's views per workgroup, the back-projection's block depth
     int adj_shape = 0;
+    int fwd_vg = 0;
+    int bp_bz = 0;
     // adjoint candidate pixel boxes per pass axis (tag: block shape)
     DevBuf cbox[3];
 
@@ -245,13 +248,17 @@ int adjoint_shape_3d()
 
 // ------------------------------------------------------------ autotuner --
 //
-// With PN_AUTOTUNE=1 the first 3-D adjoint of a plan (outside graph
-// capture) times every compiled block shape on the caller's stream and keeps
-// the fastest for the plan.  PN_TUNE_CACHE=<file> keeps the choices across
-// processes, one line per geometry: "nz ny nx rows cols views beam shape".
-// Different shapes round the fixed-point sums at different points, so with
-// tuning on, the last bits of the adjoint can differ between processes
-// whose choices differ; without it the shape is fixed (PN_ADJ_SHAPE or 16^3).
+// With PN_AUTOTUNE=1 the first 3-D single call of a plan (outside graph
+// capture) times the compiled variants of its operator on the caller's
+// stream and keeps the fastest for the plan: the adjoint's block shapes, the
+// forward's views per workgroup (3 or 2), the back-projection's block depth
+// along z (16, 8 or 32).  PN_TUNE_CACHE=<file> keeps the choices across
+// processes, one line per choice: "<op> nz ny nx rows cols views beam
+// value".  Different adjoint shapes round the fixed-point sums at different
+// points, so with tuning on the last bits of the adjoint can differ between
+// processes whose choices differ (forward and back-projection variants sum
+// in the same order); without it every variant is the default one (or
+// PN_ADJ_SHAPE).  Batched calls and batch plans use the defaults.
 
 bool autotune_on()
 {
@@ -270,40 +277,86 @@ std::string tune_key(const Geo &g)
     return buf;
 }
 
-int tune_cache_lookup(const Geo &g)
+// The cache file holds one line per tuned choice: "<op> <geometry key>
+// <value>" with op "fwd", "adj" or "bp" (lines without an op are adjoint
+// choices of earlier versions).  A later line wins.
+int tune_cache_lookup(const Geo &g, const char *op, int lo, int hi)
 {
     const char *path = std::getenv("PN_TUNE_CACHE");
     if (!path) return 0;
     FILE *f = std::fopen(path, "r");
     if (!f) return 0;
     const std::string key = tune_key(g);
+    const std::string tagged = std::string(op) + " " + key;
     char line[256];
     int found = 0;
     while (std::fgets(line, sizeof line, f)) {
         const std::string l(line);
-        if (l.compare(0, key.size(), key) == 0 && l.size() > key.size() && l[key.size()] == ' ') {
-            const int v = std::atoi(l.c_str() + key.size() + 1);
-            if (v >= 1 && v < adjoint_shape_count()) found = v;
+        for (const std::string *k : {&tagged, &key}) {
+            if (k == &key && std::strcmp(op, "adj") != 0) continue;
+            if (l.compare(0, k->size(), *k) == 0 && l.size() > k->size() && l[k->size()] == ' ') {
+                const int v = std::atoi(l.c_str() + k->size() + 1);
+                if (v >= lo && v <= hi) found = v;
+            }
         }
     }
     std::fclose(f);
     return found;
 }
 
-void tune_cache_store(const Geo &g, int shape)
+void tune_cache_store(const Geo &g, const char *op, int value)
 {
     const char *path = std::getenv("PN_TUNE_CACHE");
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d\n", tune_key(g).c_str(), shape);
+    std::fprintf(f, "%s %s %d\n", op, tune_key(g).c_str(), value);
     std::fclose(f);
+}
+
+// Times run(v) for every variant v on stream st with HIP events (one call
+// each, back to back, then one synchronisation) and returns the fastest, or
+// 0 with the error set.
+template <typename Run>
+int time_variants(const std::vector<int> &vars, Run run, hipStream_t st, int &best)
+{
+    best = 0;
+    std::vector<hipEvent_t> ev(2 * vars.size(), nullptr);
+    int rc = PN_OK;
+    for (size_t k = 0; k < vars.size() && rc == PN_OK; ++k) {
+        if (hipEventCreate(&ev[2 * k]) != hipSuccess || hipEventCreate(&ev[2 * k + 1]) != hipSuccess) {
+            rc = fail(PN_EHIP, "autotune: hipEventCreate failed");
+            break;
+        }
+        if (hipEventRecord(ev[2 * k], st) != hipSuccess) {
+            rc = fail(PN_EHIP, "autotune: hipEventRecord failed");
+            break;
+        }
+        if ((rc = run(vars[k]))) break;
+        if (hipEventRecord(ev[2 * k + 1], st) != hipSuccess) rc = fail(PN_EHIP, "autotune: hipEventRecord failed");
+    }
+    float best_ms = 0.0f;
+    for (size_t k = 0; k < vars.size() && rc == PN_OK; ++k) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(ev[2 * k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) {
+            rc = fail(PN_EHIP, "autotune: event timing failed");
+            break;
+        }
+        if (best == 0 || ms < best_ms) {
+            best = vars[k];
+            best_ms = ms;
+        }
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
 }
 
 // The 3-D adjoint block shape of a plan: tuned, cached, or the fixed one.
 int plan_adjoint_shape(Plan *pl)
 {
-    if (pl->adj_shape == 0 && autotune_on()) pl->adj_shape = tune_cache_lookup(pl->g);
+    if (pl->adj_shape == 0 && autotune_on()) pl->adj_shape = tune_cache_lookup(pl->g, "adj", 1, adjoint_shape_count() - 1);
     return pl->adj_shape ? pl->adj_shape : adjoint_shape_3d();
 }
 
@@ -567,9 +620,24 @@ int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *si
     FwdJob job;
     bool none;
     if ((rc = forward_prepare(pg, batch, vol, sino, in_dt, out_dt, st, pl, job, none)) || none) return rc;
-    hipError_t e = launch_forward(job.p, in_dt, out_dt, st);
-    if (e != hipSuccess) return fail_hip(e, "forward launch");
-    return PN_OK;
+    auto run = [&](int vg) -> int {
+        FwdParams p = job.p;
+        p.view_group = vg;
+        hipError_t e = launch_forward(p, in_dt, out_dt, st);
+        return e == hipSuccess ? PN_OK : fail_hip(e, "forward launch");
+    };
+    if (!job.two_d && autotune_on()) {
+        // views per workgroup: 3 (default) or 2, tuned once per plan
+        if (pl->fwd_vg == 0) pl->fwd_vg = tune_cache_lookup(pl->g, "fwd", 2, 3);
+        if (pl->fwd_vg == 0 && !capturing(st)) {
+            int best = 0;
+            if ((rc = time_variants({3, 2}, run, st, best))) return rc;
+            pl->fwd_vg = best;
+            tune_cache_store(pl->g, "fwd", best);
+        }
+        if (pl->fwd_vg) job.p.view_group = pl->fwd_vg;
+    }
+    return run(job.p.view_group);
 }
 
 int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt, int32_t out_dt,
@@ -588,46 +656,14 @@ int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *v
         if (r || none) return r;
         return launch_adjoint_passes(job.pass, pl->g, batch, job.two_d, in_dt, job.shape, st);
     };
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (autotune_on() && pl->g.ndim == 3 && plan_adjoint_shape(pl) && pl->adj_shape == 0 &&
-        hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+    if (autotune_on() && pl->g.ndim == 3 && plan_adjoint_shape(pl) && pl->adj_shape == 0 && !capturing(st)) {
         // time every shape (each run overwrites the output), keep the fastest
-        const int ns = adjoint_shape_count();
-        std::vector<hipEvent_t> ev(2 * ns, nullptr);
+        std::vector<int> vars;
+        for (int k = 1; k < adjoint_shape_count(); ++k) vars.push_back(k);
         int best = 0;
-        float best_ms = 0.0f;
-        for (int k = 1; k < ns && rc == PN_OK; ++k) {
-            if (hipEventCreate(&ev[2 * k]) != hipSuccess || hipEventCreate(&ev[2 * k + 1]) != hipSuccess) {
-                rc = fail(PN_EHIP, "autotune: hipEventCreate failed");
-                break;
-            }
-            if (hipEventRecord(ev[2 * k], st) != hipSuccess) {
-                rc = fail(PN_EHIP, "autotune: hipEventRecord failed");
-                break;
-            }
-            if ((rc = run(k))) break;
-            if (hipEventRecord(ev[2 * k + 1], st) != hipSuccess) {
-                rc = fail(PN_EHIP, "autotune: hipEventRecord failed");
-                break;
-            }
-        }
-        for (int k = 1; k < ns && rc == PN_OK; ++k) {
-            float ms = 0.0f;
-            if (hipEventSynchronize(ev[2 * k + 1]) != hipSuccess ||
-                hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) {
-                rc = fail(PN_EHIP, "autotune: event timing failed");
-                break;
-            }
-            if (best == 0 || ms < best_ms) {
-                best = k;
-                best_ms = ms;
-            }
-        }
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
-        if (rc) return rc;
+        if ((rc = time_variants(vars, run, st, best))) return rc;
         pl->adj_shape = best;
-        tune_cache_store(pl->g, best);
+        tune_cache_store(pl->g, "adj", best);
     }
     if ((rc = run(0)) || none) return rc;
     return adjoint_finish(job, st);
@@ -785,9 +821,24 @@ int backproject_impl(const pn_geometry *pg, int64_t batch, const void *sino, voi
     if ((rc = get_plan(pg, st, &pl))) return rc;
     BpJob job;
     backproject_prepare(batch, sino, vol, pl, job);
-    hipError_t e = launch_backproject(job.p, in_dt, out_dt, st);
-    if (e != hipSuccess) return fail_hip(e, "backproject launch");
-    return PN_OK;
+    auto run = [&](int bz) -> int {
+        BpParams p = job.p;
+        p.bz = bz;
+        hipError_t e = launch_backproject(p, in_dt, out_dt, st);
+        return e == hipSuccess ? PN_OK : fail_hip(e, "backproject launch");
+    };
+    if (!job.two_d && autotune_on()) {
+        // block depth along z: 16 (default), 8 or 32, tuned once per plan
+        if (pl->bp_bz == 0) pl->bp_bz = tune_cache_lookup(pl->g, "bp", 8, 32);
+        if (pl->bp_bz == 0 && !capturing(st)) {
+            int best = 0;
+            if ((rc = time_variants({16, 8, 32}, run, st, best))) return rc;
+            pl->bp_bz = best;
+            tune_cache_store(pl->g, "bp", best);
+        }
+        job.p.bz = pl->bp_bz;
+    }
+    return run(job.p.bz);
 }
 
 int splat_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt, int32_t out_dt,

@@ -1598,7 +1598,7 @@ __device__ __forceinline__ void backproject_block(const BpParams &p, const int b
 
 // 8 waves per SIMD: 64 VGPRs at most
 template <typename Q, typename O, int BZ, int RCAP, int CCAP>
-__global__ __launch_bounds__(256, 8) void backproject_kernel(BpParams p)
+__global__ __launch_bounds__(256, BZ > 16 ? 4 : 8) void backproject_kernel(BpParams p)
 {
     backproject_block<Q, O, BZ, RCAP, CCAP>(p, blockIdx.x);
 }
@@ -1932,13 +1932,19 @@ static void fwd_go(const Table<FwdParams> &w, uint32_t blocks, hipStream_t st)
     forward_table_kernel<S, O, TU, TV, C, RCAP, FCAP, NVW><<<dim3(blocks), 256, 0, st>>>(w);
 }
 
+// views per 3-D workgroup: a single call may take a tuned group of 2, work
+// lists always use the default
 template <typename S, typename O, typename Arg>
 static hipError_t forward_t(const Arg &a, bool two_d, uint32_t blocks, hipStream_t st)
 {
     if (two_d)
         fwd_go<S, O, 256, 1, 4, 3, 320, 1>(a, blocks, st);
-    else
+    else if constexpr (std::is_same<Arg, FwdParams>::value) {
+        if (a.view_group == 2) fwd_go<S, O, 16, 16, 4, 24, 40, 2>(a, blocks, st);
+        else fwd_go<S, O, 16, 16, 4, 24, 40, kFwdViews>(a, blocks, st);
+    } else {
         fwd_go<S, O, 16, 16, 4, 24, 40, kFwdViews>(a, blocks, st);
+    }
     return hipGetLastError();
 }
 
@@ -2082,11 +2088,13 @@ hipError_t launch_adjoint_batch(const Batch<AdjParams> &w, int axis, int32_t in_
 // rectangles of up to kBpRows x kBpCols pixels in LDS
 constexpr int kBpDepth = 16, kBpRows = 20, kBpCols = 24;
 
+static int bp_depth(const BpParams &p) { return p.bz == 8 || p.bz == 32 ? p.bz : kBpDepth; }
+
 int64_t backproject_blocks(const BpParams &p)
 {
     if (p.n[2] == 1) return static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * p.batch;
-    return static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * ((p.n[2] + kBpDepth - 1) / kBpDepth) *
-           p.batch;
+    const int bz = bp_depth(p);
+    return static_cast<int64_t>((p.n[0] + 15) / 16) * ((p.n[1] + 15) / 16) * ((p.n[2] + bz - 1) / bz) * p.batch;
 }
 
 template <typename Q, typename O, int BZ, int RCAP, int CCAP>
@@ -2108,10 +2116,19 @@ static void bp_go(const Table<BpParams> &w, uint32_t blocks, hipStream_t st)
 template <typename Q, typename O, typename Arg>
 static hipError_t bp_t(const Arg &a, bool two_d, uint32_t blocks, hipStream_t st)
 {
-    if (two_d)
+    if (two_d) {
         bp_go<Q, O, 1, 4, 64>(a, blocks, st);
-    else
+    } else if constexpr (std::is_same<Arg, BpParams>::value) {
+        // a single call may take a tuned block depth (rectangles of 20 rows
+        // hold a 16-voxel column's projection; 36 a 32-voxel one)
+        switch (bp_depth(a)) {
+        case 8: bp_go<Q, O, 8, kBpRows, kBpCols>(a, blocks, st); break;
+        case 32: bp_go<Q, O, 32, 36, kBpCols>(a, blocks, st); break;
+        default: bp_go<Q, O, kBpDepth, kBpRows, kBpCols>(a, blocks, st); break;
+        }
+    } else {
         bp_go<Q, O, kBpDepth, kBpRows, kBpCols>(a, blocks, st);
+    }
     return hipGetLastError();
 }
 

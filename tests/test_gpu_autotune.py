@@ -1,9 +1,11 @@
-"""Adjoint block-shape autotuner (PN_AUTOTUNE=1, PN_TUNE_CACHE=<file>).
+"""Autotuner (PN_AUTOTUNE=1, PN_TUNE_CACHE=<file>): the adjoint's block
+shape, the forward's views per workgroup and the back-projection's block
+depth.
 
 The switches are read once per process, so the tuned runs happen in a child
-process.  The tuned adjoint must agree with the oracle as any other shape
-does, the choice must be written to the cache file, and a second process
-must take it from the file without timing again.
+process.  Each tuned operator must agree with the oracle as any other
+variant does, each choice must be written to the cache file, and a second
+process must take them from the file without timing again.
 """
 import os
 import subprocess
@@ -26,12 +28,22 @@ g = pn.cone_geometry(shp, sp, det, ds, 30, 750.0, 1200.0)
 go = O.circular_cone(shp, sp, det, ds, 30, 2 * math.pi, 750.0, 1200.0)
 q = O.forward(W.ellipsoid_phantom_3d(3, shp, sp)[0], go)
 ref = O.adjoint(q, go)
-at = pn.adjoint(torch.from_numpy(q).float().cuda(), g)   # tunes (first call of the plan)
-at2 = pn.adjoint(torch.from_numpy(q).float().cuda(), g)  # uses the choice
+x = torch.from_numpy(W.ellipsoid_phantom_3d(3, shp, sp)[0]).float().cuda()
+y = pn.forward(x, g)                                      # tunes the forward
+assert torch.equal(y, pn.forward(x, g))
+e_f = np.linalg.norm(y.double().cpu().numpy() - q) / np.linalg.norm(q)
+assert e_f <= 1e-5, e_f
+qd = torch.from_numpy(q).float().cuda()
+at = pn.adjoint(qd, g)                                    # tunes (first call of the plan)
+at2 = pn.adjoint(qd, g)                                   # uses the choice
 err = np.linalg.norm(at.double().cpu().numpy() - ref) / np.linalg.norm(ref)
 assert err <= 1e-5, err
 assert torch.equal(at, at2)
-print("OK", err, flush=True)
+bp = pn.backproject(qd, g)                                # tunes the back-projection
+assert torch.equal(bp, pn.backproject(qd, g))
+e_b = np.linalg.norm(bp.double().cpu().numpy() - O.backproject(q, go)) / np.linalg.norm(O.backproject(q, go))
+assert e_b <= 1e-5, e_b
+print("OK", e_f, err, e_b, flush=True)
 """
 
 
@@ -47,7 +59,9 @@ def _child(tmp_path, cache):
 def test_autotune_choice_and_cache(tmp_path):
     cache = tmp_path / "tune.txt"
     _child(tmp_path, cache)
-    lines = cache.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("36 44 40 37 45 30 1 ")
-    _child(tmp_path, cache)  # the second process reads the choice
-    assert len(cache.read_text().splitlines()) == 1
+    lines = sorted(cache.read_text().splitlines())
+    assert len(lines) == 3, lines
+    for op, line in zip(("adj", "bp", "fwd"), lines):
+        assert line.startswith(op + " 36 44 40 37 45 30 1 "), line
+    _child(tmp_path, cache)  # the second process reads the choices
+    assert len(cache.read_text().splitlines()) == 3
