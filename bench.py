@@ -29,10 +29,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_08427_amd", "csrc", "pn_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cone3d_256_hbm_traffic.md")
-VALU_FILE = os.path.join(ROOT, "profiles", "cone3d_256_valu.md")
-# VALU issue ceiling: one wave64 instruction per CU per clock (each of the 4
-# SIMDs takes 4 cycles per wave instruction), 256 CUs at 2.4 GHz
-VALU_PEAK_PER_S = 256 * 2.4e9
+COUNTER_FILE = os.path.join(ROOT, "profiles", "cone3d_256_counters.md")
 
 
 def log(msg):
@@ -341,7 +338,7 @@ def main():
     roofline = {
         "bound": "hbm",
         "kernel": "pn_forward (relayouts + forward_kernel)" if dom_name == "forward"
-        else "pn_adjoint (adjoint_kernel per dominant axis)",
+        else "pn_adjoint (adjoint_fused_kernel: all pass axes in one launch)",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -351,17 +348,21 @@ def main():
         "algorithmic_bytes_per_call": bytes_per_upd * upd,
         "call_ms": round(dom_ms, 4),
     }
-    # the bound the kernels actually meet: VALU issue (wave instructions per
-    # call from the committed SQ_INSTS_VALU summary, over the measured time)
-    n_valu = profiled_value(VALU_FILE, f"valu_instructions_per_call {dom_name}")
-    if n_valu is not None:
-        roofline["valu"] = {
-            "instructions_per_call": n_valu,
-            "achieved": n_valu / (dom_ms * 1e-3),
-            "peak": VALU_PEAK_PER_S,
-            "unit": "wave instructions/s",
-            "frac": round(n_valu / (dom_ms * 1e-3) / VALU_PEAK_PER_S, 4),
+    # what the counters say about the same kernel (committed rocprofv3
+    # summary of the same source; null once the kernels have changed)
+    busy = profiled_value(COUNTER_FILE, f"valu_busy_percent {dom_name}")
+    if busy is not None:
+        roofline["counters"] = {
+            "valu_busy_percent": busy,
+            "valu_instructions_per_call": profiled_value(COUNTER_FILE, f"valu_instructions_per_call {dom_name}"),
+            "lds_bank_conflict_percent": profiled_value(COUNTER_FILE, f"lds_bank_conflict_percent {dom_name}"),
+            "l2_hit_percent": profiled_value(COUNTER_FILE, f"l2_hit_percent {dom_name}"),
+            "occupancy_percent": profiled_value(COUNTER_FILE, f"occupancy_percent {dom_name}"),
+            "source": "profiles/cone3d_256_counters.md",
         }
+    # the same achieved rate against a plain device copy measured here
+    if variants.get("copy_gbps"):
+        roofline["frac_of_measured_copy"] = round(achieved / variants["copy_gbps"], 4)
 
     cpu = None
     if not args.no_cpu_baseline:
