@@ -286,8 +286,12 @@ def _geo_args(g):
     return keep, pn, ps, po, pP
 
 
-def forward(vol, g, nthreads=0):
-    """A vol.  vol: [nz][ny][nx] (2-D: [1][ny][nx]); returns [n_views][rows][cols]."""
+def forward(vol, g, nthreads=0, weight_bits=0):
+    """A vol.  vol: [nz][ny][nx] (2-D: [1][ny][nx]); returns [n_views][rows][cols].
+
+    weight_bits = B > 0: the sampler variant (paper Sec. 2.1, texture versus
+    kernel interpolation), whose in-plane interpolation weights are rounded
+    to the nearest multiple of 2^-B, ties upward; 0 is A itself."""
     lib = _load()
     keep, pn, ps, po, pP = _geo_args(g)
     nv, nu = g["det"]
@@ -295,16 +299,18 @@ def forward(vol, g, nthreads=0):
     v, pv = _f64(vol)
     assert v.size == g["n"][0] * g["n"][1] * g["n"][2]
     out = np.zeros((nviews, nv, nu), dtype=np.float64)
-    rc = lib.oracle_forward(
+    rc = lib.oracle_forward_q(
         ctypes.c_int(g["dims"]), ctypes.c_int(int(g["parallel"])), pn, ps, po, ctypes.c_int64(nviews), pP,
-        ctypes.c_int64(nv), ctypes.c_int64(nu), pv, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads))
+        ctypes.c_int64(nv), ctypes.c_int64(nu), pv, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads),
+        ctypes.c_int(int(weight_bits)))
     if rc:
         raise MemoryError("oracle_forward")
     return out
 
 
-def forward_rays(vol, g, view, row, col, nthreads=0):
-    """Selected entries of A vol at (view[t], row[t], col[t])."""
+def forward_rays(vol, g, view, row, col, nthreads=0, weight_bits=0):
+    """Selected entries of A vol at (view[t], row[t], col[t]) (weight_bits as
+    ``forward``)."""
     lib = _load()
     keep, pn, ps, po, pP = _geo_args(g)
     v, pv = _f64(vol)
@@ -312,9 +318,9 @@ def forward_rays(vol, g, view, row, col, nthreads=0):
     rw, prw = _i64(row)
     cl, pcl = _i64(col)
     out = np.zeros(vw.size, dtype=np.float64)
-    rc = lib.oracle_forward_rays(
+    rc = lib.oracle_forward_rays_q(
         ctypes.c_int(g["dims"]), ctypes.c_int(int(g["parallel"])), pn, ps, po, pP, pv, ctypes.c_int64(vw.size),
-        pvw, prw, pcl, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads))
+        pvw, prw, pcl, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads), ctypes.c_int(int(weight_bits)))
     if rc:
         raise MemoryError("oracle_forward_rays")
     return out

@@ -153,8 +153,21 @@ static void ray_2d(int parallel, const double P[6], double u, ray_t *ray)
  * dims = 2 uses linear interpolation in the single in-plane axis (nz == 1),
  * dims = 3 bilinear interpolation in the two in-plane axes.  Taps outside
  * the grid are dropped (zero padding).  Capacity needed: 4 * max(n). */
+/* Upper-tap weight of a crossing at fraction wf of a voxel: wf itself, or,
+ * with wbits = B > 0 (the sampler variant's reduced-precision weights), wf
+ * rounded to the nearest multiple of 2^-B, ties upward.  t = wf 2^B, its
+ * floor q and t - q are exact, so the rounding decision is exact. */
+static double tap_weight(double wf, int wbits)
+{
+    if (wbits <= 0) return wf;
+    double sc = ldexp(1.0, wbits);
+    double t = wf * sc, q = floor(t);
+    if (t - q >= 0.5) q += 1.0;
+    return q / sc;
+}
+
 static int64_t ray_taps_planes(const grid_t *g, int dims, const ray_t *ray, const int64_t *plane_box,
-                               int64_t *idx, double *w)
+                               int wbits, int64_t *idx, double *w)
 {
     double xi0[3], de[3];
     for (int i = 0; i < 3; ++i) {
@@ -186,7 +199,7 @@ static int64_t ray_taps_planes(const grid_t *g, int dims, const ray_t *ray, cons
     for (int64_t m = m_lo; m < m_hi; ++m) {
         double t = ((double)m - xi0[a]) / de[a];
         double pb = xi0[b] + t * de[b];
-        double fb = floor(pb), wb = pb - fb;
+        double fb = floor(pb), wb = tap_weight(pb - fb, wbits);
         int64_t ib = (int64_t)fb;
         if (dims == 2) {
             for (int tb = 0; tb < 2; ++tb) {
@@ -200,7 +213,7 @@ static int64_t ray_taps_planes(const grid_t *g, int dims, const ray_t *ray, cons
             }
         } else {
             double pc = xi0[c] + t * de[c];
-            double fc = floor(pc), wc = pc - fc;
+            double fc = floor(pc), wc = tap_weight(pc - fc, wbits);
             int64_t ic = (int64_t)fc;
             for (int tc = 0; tc < 2; ++tc) {
                 int64_t jc = ic + tc;
@@ -222,7 +235,7 @@ static int64_t ray_taps_planes(const grid_t *g, int dims, const ray_t *ray, cons
 
 static int64_t ray_taps(const grid_t *g, int dims, const ray_t *ray, int64_t *idx, double *w)
 {
-    return ray_taps_planes(g, dims, ray, NULL, idx, w);
+    return ray_taps_planes(g, dims, ray, NULL, 0, idx, w);
 }
 
 static void make_grid(grid_t *g, const int64_t n[3], const double s[3], const double o[3])
@@ -249,10 +262,12 @@ static void pixel_ray(const grid_t *g, int dims, int parallel, const double *P, 
 
 /* Forward projection A.  n = (nx, ny, nz), s, o in (x, y, z) order.
  * P: n_views matrices (2x3 when dims == 2, else 3x4).  sino: [n_views][nv][nu]
- * (nv == 1 when dims == 2). */
-int oracle_forward(int dims, int parallel, const int64_t n[3], const double s[3], const double o[3],
-                   int64_t n_views, const double *P, int64_t nv, int64_t nu,
-                   const double *vol, double *sino, int nthreads)
+ * (nv == 1 when dims == 2).  wbits > 0: the sampler variant, whose in-plane
+ * interpolation weights are rounded to multiples of 2^-wbits (tap_weight);
+ * oracle_forward is wbits = 0, the operator A itself. */
+int oracle_forward_q(int dims, int parallel, const int64_t n[3], const double s[3], const double o[3],
+                     int64_t n_views, const double *P, int64_t nv, int64_t nu,
+                     const double *vol, double *sino, int nthreads, int wbits)
 {
     grid_t g;
     make_grid(&g, n, s, o);
@@ -274,7 +289,7 @@ int oracle_forward(int dims, int parallel, const int64_t n[3], const double s[3]
                 for (int64_t c = 0; c < nu; ++c) {
                     ray_t ray;
                     pixel_ray(&g, dims, parallel, P + k * psz, r, c, &ray);
-                    int64_t cnt = ray_taps(&g, dims, &ray, idx, w);
+                    int64_t cnt = ray_taps_planes(&g, dims, &ray, NULL, wbits, idx, w);
                     double acc = 0.0;
                     for (int64_t t = 0; t < cnt; ++t) acc += w[t] * vol[idx[t]];
                     sino[(k * nv + r) * nu + c] = acc;
@@ -286,10 +301,18 @@ int oracle_forward(int dims, int parallel, const int64_t n[3], const double s[3]
     return err;
 }
 
-/* Forward projection of selected rays only: out[t] = (A vol)[view[t], row[t], col[t]]. */
-int oracle_forward_rays(int dims, int parallel, const int64_t n[3], const double s[3], const double o[3],
-                        const double *P, const double *vol, int64_t n_rays, const int64_t *view,
-                        const int64_t *row, const int64_t *col, double *out, int nthreads)
+int oracle_forward(int dims, int parallel, const int64_t n[3], const double s[3], const double o[3],
+                   int64_t n_views, const double *P, int64_t nv, int64_t nu,
+                   const double *vol, double *sino, int nthreads)
+{
+    return oracle_forward_q(dims, parallel, n, s, o, n_views, P, nv, nu, vol, sino, nthreads, 0);
+}
+
+/* Forward projection of selected rays only: out[t] = (A vol)[view[t], row[t], col[t]]
+ * (wbits as oracle_forward_q). */
+int oracle_forward_rays_q(int dims, int parallel, const int64_t n[3], const double s[3], const double o[3],
+                          const double *P, const double *vol, int64_t n_rays, const int64_t *view,
+                          const int64_t *row, const int64_t *col, double *out, int nthreads, int wbits)
 {
     grid_t g;
     make_grid(&g, n, s, o);
@@ -309,7 +332,7 @@ int oracle_forward_rays(int dims, int parallel, const int64_t n[3], const double
             if (!idx || !w) continue;
             ray_t ray;
             pixel_ray(&g, dims, parallel, P + view[t] * psz, row[t], col[t], &ray);
-            int64_t cnt = ray_taps(&g, dims, &ray, idx, w);
+            int64_t cnt = ray_taps_planes(&g, dims, &ray, NULL, wbits, idx, w);
             double acc = 0.0;
             for (int64_t q = 0; q < cnt; ++q) acc += w[q] * vol[idx[q]];
             out[t] = acc;
@@ -318,6 +341,13 @@ int oracle_forward_rays(int dims, int parallel, const int64_t n[3], const double
         free(w);
     }
     return err;
+}
+
+int oracle_forward_rays(int dims, int parallel, const int64_t n[3], const double s[3], const double o[3],
+                        const double *P, const double *vol, int64_t n_rays, const int64_t *view,
+                        const int64_t *row, const int64_t *col, double *out, int nthreads)
+{
+    return oracle_forward_rays_q(dims, parallel, n, s, o, P, vol, n_rays, view, row, col, out, nthreads, 0);
 }
 
 /* Adjoint A^T restricted to a box of voxels.  box = (i0, i1, j0, j1, k0, k1),
@@ -360,7 +390,7 @@ int oracle_adjoint(int dims, int parallel, const int64_t n[3], const double s[3]
                     double q = sino[(k * nv + r) * nu + c];
                     ray_t ray;
                     pixel_ray(&g, dims, parallel, P + k * psz, r, c, &ray);
-                    int64_t cnt = ray_taps_planes(&g, dims, &ray, box, idx, w);
+                    int64_t cnt = ray_taps_planes(&g, dims, &ray, box, 0, idx, w);
                     for (int64_t t = 0; t < cnt; ++t) {
                         int64_t e = idx[t];
                         int64_t i = e % g.n[0], j = (e / g.n[0]) % g.n[1], kk = e / (g.n[0] * g.n[1]);

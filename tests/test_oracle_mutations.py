@@ -38,6 +38,11 @@ C_MUTANTS = [
     ("splat distance weight dropped", "const double wt = (W0 / W) * (W0 / W) * val;", "const double wt = val;"),
     ("splat column taps swapped", "img[r * nu + c] += wt * fvw * (tu ? wu : 1.0 - wu);",
      "img[r * nu + c] += wt * fvw * (tu ? 1.0 - wu : wu);"),
+    ("rounded weights truncated instead of rounded", "if (t - q >= 0.5) q += 1.0;", "if (t - q > 1.0) q += 1.0;"),
+    ("rounded weights with one bit fewer", "double sc = ldexp(1.0, wbits);", "double sc = ldexp(1.0, wbits - 1);"),
+    ("second in-plane weight not rounded", "double fc = floor(pc), wc = tap_weight(pc - fc, wbits);",
+     "double fc = floor(pc), wc = pc - fc;"),
+    ("ties rounded downward", "if (t - q >= 0.5) q += 1.0;", "if (t - q > 0.5) q += 1.0;"),
 ]
 
 

@@ -136,6 +136,126 @@ def test_samples_match_padded_interp_fan(O):
             assert abs(p[k, 0, c] - ref) <= 1e-12 * max(1.0, abs(ref))
 
 
+# ------------------------------- sampler variant: quantised weights -------
+#
+# With weight_bits = B the oracle's sampler variant rounds each in-plane
+# weight (the fraction of the crossing position) to the nearest multiple of
+# 2^-B, ties upward.  Because floor(p) is an integer, that is linear
+# interpolation at the position itself rounded to the 2^-B lattice, so a
+# library interpolator evaluated at the rounded positions must agree.
+
+
+def _snap(p, bits):
+    """p rounded to the nearest multiple of 2^-bits, ties upward (every step
+    exact in FP64)."""
+    t = np.asarray(p, float) * 2.0 ** bits
+    q = np.floor(t)
+    return np.where(t - q >= 0.5, q + 1.0, q) / 2.0 ** bits
+
+
+@pytest.mark.parametrize("bits", [3, 8])
+def test_quantised_samples_match_map_coordinates_at_snapped_positions(O, bits):
+    rng = np.random.default_rng(15)
+    shape, sp = (9, 10, 12), (0.9, 1.1, 1.0)
+    vol = rng.random(shape)
+    nv, nu, views = 9, 11, 5
+    S, C, eu, ev = O.circular_cone_vectors(views, 2 * math.pi, 60.0, 95.0, (1.3, 1.2))
+    P = np.stack([O.cone_matrix(S[k], C[k], eu[k], ev[k], (nv, nu)) for k in range(views)])
+    g = O.cone_geometry(shape, sp, (nv, nu), (1.3, 1.2), P)
+    p = O.forward(vol, g, weight_bits=bits)
+    exact = O.forward(vol, g)
+    nz, ny, nx = shape
+    s = np.array([sp[2], sp[1], sp[0]])
+    o = -0.5 * (np.array([nx, ny, nz]) - 1) * s
+    for k in range(views):
+        for r in range(nv):
+            for c in range(nu):
+                X = C[k] + (c - 0.5 * (nu - 1)) * eu[k] + (r - 0.5 * (nv - 1)) * ev[k]
+                xi0 = (S[k] - o) / s
+                de = (X - S[k]) / s
+                a = int(np.argmax(np.abs(de)))
+                m = np.arange([nx, ny, nz][a], dtype=float)
+                pts = xi0[None, :] + ((m - xi0[a]) / de[a])[:, None] * de[None, :]
+                inplane = [i for i in range(3) if i != a]
+                pts[:, inplane] = _snap(pts[:, inplane], bits)
+                vals = map_coordinates(vol, pts[:, ::-1].T, order=1, mode="grid-constant", cval=0.0)
+                D = X - S[k]
+                ref = s[a] * np.linalg.norm(D) / abs(D[a]) * vals.sum()
+                assert abs(p[k, r, c] - ref) <= 1e-12 * max(1.0, abs(ref))
+    # the rounding is visible, and bounded: each of the two weights moves by
+    # at most 2^-(B+1), which moves a sample by at most 2^-B max|v|; a ray
+    # has at most 12 samples of at most 1.1 sqrt(3) mm each
+    err = np.abs(p - exact)
+    assert err.max() > 1e-3 * 2.0 ** -bits * np.abs(exact).max()
+    assert err.max() <= 2.0 ** -bits * np.abs(vol).max() * 12 * 1.1 * math.sqrt(3)
+
+
+def test_quantised_fan_samples_match_padded_interp_at_snapped_positions(O):
+    rng = np.random.default_rng(16)
+    ny, nx, sy, sx = 13, 11, 0.8, 1.1
+    img = rng.random((1, ny, nx))
+    n_cols, du, views, sid, sdd, bits = 17, 0.9, 7, 40.0, 70.0, 4
+    g = O.circular_fan((ny, nx), (sy, sx), n_cols, du, views, 2 * math.pi, sid, sdd)
+    p = O.forward(img, g, weight_bits=bits)
+    o = np.array([-0.5 * (nx - 1) * sx, -0.5 * (ny - 1) * sy])
+    s = np.array([sx, sy])
+    for k in range(views):
+        b = 2 * math.pi * k / views
+        S = sid * np.array([math.cos(b), math.sin(b)])
+        Cc = -(sdd - sid) * np.array([math.cos(b), math.sin(b)])
+        eu = du * np.array([-math.sin(b), math.cos(b)])
+        for c in range(n_cols):
+            X = Cc + (c - 0.5 * (n_cols - 1)) * eu
+            xi0, de = (S - o) / s, (X - S) / s
+            a = 0 if abs(de[0]) >= abs(de[1]) else 1
+            bax = 1 - a
+            acc = 0.0
+            for m in range(img.shape[2] if a == 0 else img.shape[1]):
+                q = _snap(xi0[bax] + (m - xi0[a]) / de[a] * de[bax], bits)
+                line = img[0, :, m] if a == 0 else img[0, m, :]
+                acc += np.interp(q, np.arange(-1, line.size + 1), np.pad(line, 1), left=0.0, right=0.0)
+            D = X - S
+            ref = s[a] * np.linalg.norm(D) / abs(D[a]) * acc
+            assert abs(p[k, 0, c] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def _exact_tie_case(O):
+    """Rays along +x through index rows (j + 3/16, k + 5/16): every entry is
+    dyadic, so each crossing sits exactly on a rounding tie of the 2^-3
+    lattice (3/16 * 8 = 1.5, 5/16 * 8 = 2.5)."""
+    shape = (6, 7, 8)  # z, y, x
+    P = O.parallel3d_matrix([1.0, 0, 0], [0, 3 / 16, 5 / 16], [0, 1.0, 0], [0, 0, 1.0], (6, 7))
+    g = O.cone_geometry(shape, (1.0, 1.0, 1.0), (6, 7), (1.0, 1.0), P[None], parallel=True)
+    return shape, g
+
+
+def _exact_tie_expected(vol, wy, wz):
+    """Bilinear rows of the zero-padded volume with weights wy, wz, summed
+    along x: the ray of pixel (c, r) reads rows (j, k) = (c, r)."""
+    pad = np.pad(vol, ((0, 1), (0, 1), (0, 0)))
+    s = pad.sum(axis=2)  # [z][y]
+    return ((1 - wy) * (1 - wz) * s[:-1, :-1] + wy * (1 - wz) * s[:-1, 1:] + (1 - wy) * wz * s[1:, :-1]
+            + wy * wz * s[1:, 1:])
+
+
+def test_exact_ties_round_upward(O):
+    shape, g = _exact_tie_case(O)
+    vol = np.random.default_rng(18).random(shape)
+    got = O.forward(vol, g, weight_bits=3)[0]
+    assert np.abs(got - _exact_tie_expected(vol, 2 / 8, 3 / 8)).max() < 1e-12
+    assert np.abs(O.forward(vol, g)[0] - _exact_tie_expected(vol, 3 / 16, 5 / 16)).max() < 1e-12
+
+
+def test_fine_weight_lattice_converges_to_the_operator(O):
+    """Rounding to 2^-40 moves each weight by at most 2^-41: A itself to
+    ~1e-11, while a coarse lattice does not."""
+    vol, _ = W.ellipsoid_phantom_3d(17, shape=(10, 11, 12), spacing=(1.0, 1.0, 1.0), n_ellipsoids=6)
+    g = O.circular_cone((10, 11, 12), (1.0, 1.0, 1.0), (9, 13), (1.4, 1.4), 6, 2 * math.pi, 70.0, 110.0)
+    exact = O.forward(vol, g)
+    assert _rel(O.forward(vol, g, weight_bits=40), exact) < 1e-10
+    assert _rel(O.forward(vol, g, weight_bits=2), exact) > 1e-4
+
+
 # -------------------------------------------- P3/P4: transpose, dot test --
 
 
