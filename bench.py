@@ -321,6 +321,16 @@ def main():
         variants["bf16_forward_ms"] = tb_f
         variants["bf16_adjoint_ms"] = tb_a
         log(f"bf16: A {tb_f:.3f} ms, AT {tb_a:.3f} ms")
+        # sampler interpolation: every tap a load through the caches, from
+        # the bordered copies (extra memory, as the staged projector) or from
+        # the volume itself (none); with FP32 and with 8-bit weights
+        for key, src, bits in (("sampler_bordered", "bordered", 0), ("sampler_volume", "volume", 0),
+                               ("sampler_bordered_w8", "bordered", 8)):
+            pn.forward_sampled(x, geom, src, bits)
+            t_s, _ = timed(lambda: pn.forward_sampled(x, geom, src, bits), reps, stream)
+            variants[f"{key}_forward_ms"] = t_s
+            variants[f"{key}_forward_gups"] = upd / (t_s * 1e-3) / 1e9
+            log(f"sampler ({src}, weight_bits {bits}): A {t_s:.3f} ms")
 
     if not args.no_variants and not args.no_batched:
         variants.update(batched_variant(pn, W, np, torch, stream))

@@ -132,6 +132,32 @@ typedef struct {
 int pn_forward(const pn_geometry *pg, int64_t batch, const void *vol, void *sino,
                int32_t in_dtype, int32_t out_dtype, void *hip_stream);
 
+/* A with sampler interpolation (Sec. 2.1, interpolation: sampling through a
+ * texture is faster but needs extra memory; interpolation written in the
+ * kernel saves memory).  The same operator as pn_forward -- same rays,
+ * planes and FP64 ray set-up -- but every bilinear tap is a separate load
+ * through the caches instead of being staged through LDS, from the image
+ * chosen by `source`:
+ *   PN_SAMPLE_BORDERED  zero-bordered copies of the volume, one per dominant
+ *                       axis a that occurs (the copies pn_forward builds:
+ *                       8 ((n_f + 24) / 8) (n_s + 3) n_a elements per axis
+ *                       and batch item, n_f and n_s the in-plane sizes, held
+ *                       by the geometry's plan);
+ *   PN_SAMPLE_VOLUME    the caller's volume itself, every tap bounds-checked;
+ *                       no extra memory besides the view tables.
+ * weight_bits = 0 interpolates with FP32 weights (the result then matches
+ * pn_forward to FP32 rounding); 1 <= weight_bits <= 16 rounds each of the
+ * two in-plane weights to a multiple of 2^-weight_bits, ties upward (the
+ * upper tap's weight round(frac(position) * 2^B) / 2^B), the way fixed-
+ * function filtering hardware quantises its weights, so that this loss of
+ * precision can be measured.  Shapes, types, streams and capture rules as
+ * pn_forward; additionally PN_EINVAL for an unknown source, weight_bits
+ * outside [0, 16], or an image of 2^31 elements or more per batch item. */
+enum { PN_SAMPLE_BORDERED = 0, PN_SAMPLE_VOLUME = 1 };
+int pn_forward_sampled(const pn_geometry *pg, int64_t batch, const void *vol, void *sino,
+                       int32_t in_dtype, int32_t out_dtype, int32_t source, int32_t weight_bits,
+                       void *hip_stream);
+
 /* A^T: sino [batch][n_views][rows][cols] (in_dtype) -> vol [batch][nz][ny][nx]
  * (out_dtype).  Exact transpose of pn_forward up to rounding: each block of
  * output voxels sums its rays' contributions in 32-bit fixed point whose

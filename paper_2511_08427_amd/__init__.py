@@ -42,6 +42,7 @@ from .ops import (
     fbp_filter,
     forward,
     forward_batched,
+    forward_sampled,
     gantry_blur,
     gaussian_noise_,
     ring_artifacts_,

@@ -28,6 +28,7 @@ ERROR_NAMES = {
 # every symbol the header declares
 EXPORTS = (
     "pn_forward",
+    "pn_forward_sampled",
     "pn_adjoint",
     "pn_adjoint_noalloc",
     "pn_backproject",
@@ -98,6 +99,8 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [ctypes.POINTER(PnProblem), i32, i32, i32, vp]
         f.restype = ctypes.c_int
+    lib.pn_forward_sampled.argtypes = [gp, i64, vp, vp, i32, i32, i32, i32, vp]
+    lib.pn_forward_sampled.restype = ctypes.c_int
     lib.pn_batch_create.argtypes = [i32, ctypes.POINTER(PnProblem), i32, i32, i32, ctypes.POINTER(vp)]
     lib.pn_batch_create.restype = ctypes.c_int
     lib.pn_batch_run.argtypes = [vp, vp]

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libpyronn_mi.so")
-SOURCES = ["pn_kernels.hip", "pn_signal.hip", "pn_host.cpp", "pn_geometry.cpp"]
+SOURCES = ["pn_kernels.hip", "pn_sampler.hip", "pn_signal.hip", "pn_host.cpp", "pn_geometry.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,5 +1,5 @@
 // Internal types shared by the host library (pn_host.cpp) and the gfx950
-// kernels (pn_kernels.hip).  Not part of the public ABI.
+// kernels (pn_kernels.hip, pn_sampler.hip, pn_signal.hip).  Not part of the public ABI.
 #pragma once
 
 #include <cstdint>
@@ -57,6 +57,25 @@ struct FwdParams {
     int32_t c_lo, r_lo;        // first column and row of the window
     const int32_t *vwin;       // per view: detector window of the view (c0, c1, r0, r1), or nullptr
     int32_t point_source;      // 1: every ray of a view leaves one point (B has zero u and v columns)
+};
+
+// Sampler-interpolation forward projector (pn_sampler.hip): one thread per
+// ray, every tap gathered through the cache hierarchy from an "image" of the
+// volume per dominant axis a.  Element (m, s, f) of image a (plane m along
+// a, in-plane slow index s, fast index f) of batch item b sits at
+// img[a] + b*item[a] + org[a] + m*plane[a] + s*row[a] + f*col[a].
+struct SampParams {
+    const ViewTab *tab;
+    int32_t n_views, nu, nv, batch;
+    int32_t n[3];
+    double s[3];
+    const void *img[3];    // per dominant axis (nullptr: no ray takes it)
+    int64_t item[3], plane[3], row[3], col[3], org[3];
+    void *sino;            // [batch][n_views][nv][nu]
+    int32_t tile_u, tile_v, tiles_u, tiles_v;
+    int32_t bordered;      // 1: images with a zero border (work copies), 0: the caller's volume, taps checked
+    int32_t weight_bits;   // 0: FP32 weights; B > 0: weights rounded to multiples of 2^-B (ties up)
+    int32_t point_source;  // 1: every ray of a view leaves one point (B has zero u and v columns)
 };
 
 struct AdjParams {

@@ -22,6 +22,9 @@ namespace pn {
 hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32_t n[3], int axis, int32_t batch,
                            int64_t item, int32_t row, int64_t plane, hipStream_t st);
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
+hipError_t launch_forward_sampled(const SampParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
+int64_t forward_sampled_blocks(const SampParams &p);
+void forward_sampled_tile(bool two_d, int32_t &tu, int32_t &tv);
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
 bool adjoint_fusable(bool two_d, int shape);
 hipError_t launch_forward_table(const Table<FwdParams> &w, uint32_t blocks, bool two_d, int32_t in_dt,
@@ -638,6 +641,82 @@ int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *si
         if (pl->fwd_vg) job.p.view_group = pl->fwd_vg;
     }
     return run(job.p.view_group);
+}
+
+// A with sampler interpolation: every tap gathered through the caches from
+// the zero-bordered work copies (the ones pn_forward builds) or from the
+// caller's volume with checked taps.
+int forward_sampled_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt,
+                         int32_t out_dt, int32_t source, int32_t wbits, hipStream_t st)
+{
+    if (source != PN_SAMPLE_BORDERED && source != PN_SAMPLE_VOLUME)
+        return fail(PN_EINVAL, "pn_forward_sampled: unknown source %d", source);
+    if (wbits < 0 || wbits > 16) return fail(PN_EINVAL, "pn_forward_sampled: weight_bits %d outside [0, 16]", wbits);
+    Geo pre;
+    int rc = preflight(pg, batch, vol, sino, in_dt, out_dt, false, pre);
+    if (rc || batch == 0) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *pl;
+    if ((rc = get_plan(pg, st, &pl))) return rc;
+    const Geo &g = pl->g;
+    if (g.n_views == 0) return PN_OK;
+    SampParams p{};
+    p.tab = pl->d_tab;
+    p.n_views = g.n_views;
+    p.nu = g.nu;
+    p.nv = g.nv;
+    p.batch = (int32_t)batch;
+    p.bordered = source == PN_SAMPLE_BORDERED;
+    p.weight_bits = wbits;
+    p.point_source = g.parallel ? 0 : 1;
+    const int64_t st3[3] = {1, (int64_t)g.n[0], (int64_t)g.n[0] * g.n[1]};
+    for (int a = 0; a < 3; ++a) {
+        p.n[a] = g.n[a];
+        p.s[a] = g.s[a];
+    }
+    // every work copy is made ready before anything is launched, so a call
+    // refused under capture enqueues nothing
+    if (p.bordered)
+        for (int a = 0; a < 3; ++a)
+            if ((pl->axes_union >> a & 1) && (rc = ensure_work_copy(*pl, a, in_dt, batch, st))) return rc;
+    for (int a = 0; a < 3; ++a) {
+        if (!(pl->axes_union >> a & 1)) continue;
+        const int f = a == 0 ? 1 : 0, sl = a == 2 ? 1 : 2;
+        if (p.bordered) {
+            p.item[a] = pl->lay_item[a];
+            p.plane[a] = pl->lay_plane[a];
+            p.row[a] = pl->lay_row[a];
+            p.col[a] = 1;
+            p.org[a] = (int64_t)PADR_LO * pl->lay_row[a] + PADC;
+        } else {
+            p.item[a] = st3[2] * g.n[2];
+            p.plane[a] = st3[a];
+            p.row[a] = st3[sl];
+            p.col[a] = st3[f];
+            p.org[a] = 0;
+        }
+        if (p.item[a] >= ((int64_t)1 << 31))
+            return fail(PN_EINVAL, "pn_forward_sampled: image of %lld elements per batch item (limit 2^31 - 1)",
+                        (long long)p.item[a]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (!(pl->axes_union >> a & 1)) continue;
+        if (p.bordered) {
+            hipError_t e = launch_relayout(in_dt, vol, pl->lay[a].ptr, g.n, a, (int32_t)batch, pl->lay_item[a],
+                                           pl->lay_row[a], pl->lay_plane[a], st);
+            if (e != hipSuccess) return fail_hip(e, "relayout launch");
+            p.img[a] = pl->lay[a].ptr;
+        } else {
+            p.img[a] = vol;
+        }
+    }
+    p.sino = sino;
+    forward_sampled_tile(g.ndim == 2, p.tile_u, p.tile_v);
+    p.tiles_u = (g.nu + p.tile_u - 1) / p.tile_u;
+    p.tiles_v = (g.nv + p.tile_v - 1) / p.tile_v;
+    if (forward_sampled_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
+    hipError_t e = launch_forward_sampled(p, in_dt, out_dt, st);
+    return e == hipSuccess ? PN_OK : fail_hip(e, "sampled forward launch");
 }
 
 int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt, int32_t out_dt,
@@ -1542,6 +1621,14 @@ int pn_forward(const pn_geometry *pg, int64_t batch, const void *vol, void *sino
 {
     clear_error();
     return forward_impl(pg, batch, vol, sino, in_dtype, out_dtype, static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_forward_sampled(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dtype,
+                       int32_t out_dtype, int32_t source, int32_t weight_bits, void *hip_stream)
+{
+    clear_error();
+    return forward_sampled_impl(pg, batch, vol, sino, in_dtype, out_dtype, source, weight_bits,
+                                static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dtype,

@@ -4,6 +4,7 @@ Torch supplies device memory and the current stream; every operator is one
 call into the native library, which runs the gfx950 kernels:
 
   forward(vol, geom)      A     -> pn_forward
+  forward_sampled(...)    A     -> pn_forward_sampled (sampler interpolation)
   adjoint(sino, geom)     A^T   -> pn_adjoint
   backproject(sino, geom)       -> pn_backproject (voxel-driven, (W0/W)^2)
   splat(vol, geom)        B^T   -> pn_splat (transpose of the back-projection)
@@ -63,6 +64,27 @@ def _run(fn, where, geom: Geometry, src, src_tail, dst_tail, out_dtype):
 def forward(vol, geom: Geometry, out_dtype=None):
     """A vol: [B,]nz,ny,nx -> [B,]n_views,rows,cols (ray-driven Joseph)."""
     return _run(N.lib.pn_forward, "pn_forward", geom, vol, geom.vol_shape, geom.sino_shape(), out_dtype)
+
+
+_SOURCES = {"bordered": 0, "volume": 1}
+
+
+def forward_sampled(vol, geom: Geometry, source="bordered", weight_bits=0, out_dtype=None):
+    """A vol with sampler interpolation (pn_forward_sampled): every bilinear
+    tap is a separate load through the caches, from zero-bordered copies of
+    the volume (``source="bordered"``, extra device memory, no bounds
+    checks) or from ``vol`` itself (``"volume"``, no extra memory).
+    ``weight_bits`` = B > 0 rounds the interpolation weights to multiples of
+    2^-B, as fixed-function filtering hardware does; 0 keeps FP32 weights
+    (then the result matches ``forward`` to FP32 rounding)."""
+    if source not in _SOURCES:
+        raise ValueError(f"source must be one of {sorted(_SOURCES)}")
+    src, bits = _SOURCES[source], int(weight_bits)
+
+    def fn(g, b, x, o, dti, dto, st):
+        return N.lib.pn_forward_sampled(g, b, x, o, dti, dto, src, bits, st)
+
+    return _run(fn, "pn_forward_sampled", geom, vol, geom.vol_shape, geom.sino_shape(), out_dtype)
 
 
 def adjoint(sino, geom: Geometry, out_dtype=None):
@@ -287,18 +309,32 @@ class BatchPlan:
 # --------------------------------------------------------------- autograd --
 
 
+_INTERP = {"staged": None, "sampler": "bordered", "sampler-volume": "volume"}
+
+
 class Projection(torch.autograd.Function):
-    """y = A x; dL/dx = A^T dL/dy (the adjoint kernel)."""
+    """y = A x; dL/dx = A^T dL/dy (the adjoint kernel).
+
+    ``interp`` picks how A interpolates: "staged" (the default, volume tiles
+    staged through LDS), "sampler" or "sampler-volume" (``forward_sampled``
+    from the bordered copies or from the volume itself, ``weight_bits`` as
+    there).  The gradient is the exact adjoint of A with FP32 weights in
+    every case; with weight_bits > 0 it is therefore the adjoint of the
+    unquantised operator."""
 
     @staticmethod
-    def forward(ctx, vol, geom):
+    def forward(ctx, vol, geom, interp="staged", weight_bits=0):
+        if interp not in _INTERP:
+            raise ValueError(f"interp must be one of {sorted(_INTERP)}")
         ctx.geom = geom
         ctx.vol_dtype = vol.dtype
-        return forward(vol, geom)
+        if _INTERP[interp] is None:
+            return forward(vol, geom)
+        return forward_sampled(vol, geom, _INTERP[interp], weight_bits)
 
     @staticmethod
     def backward(ctx, grad):
-        return adjoint(grad.contiguous(), ctx.geom, out_dtype=ctx.vol_dtype), None
+        return adjoint(grad.contiguous(), ctx.geom, out_dtype=ctx.vol_dtype), None, None, None
 
 
 class AdjointProjection(torch.autograd.Function):
@@ -350,19 +386,29 @@ class _Layer(torch.nn.Module):
         self.geom = geom
 
 
-class ParallelProjection2D(_Layer):
+class _ProjLayer(_Layer):
+    """A projection layer; ``interp`` and ``weight_bits`` as ``Projection``."""
+
+    def __init__(self, geom: Geometry, interp="staged", weight_bits=0):
+        super().__init__(geom)
+        if interp not in _INTERP:
+            raise ValueError(f"interp must be one of {sorted(_INTERP)}")
+        self.interp, self.weight_bits = interp, int(weight_bits)
+
     def forward(self, x):
-        return Projection.apply(x, self.geom)
+        return Projection.apply(x, self.geom, self.interp, self.weight_bits)
 
 
-class FanProjection2D(_Layer):
-    def forward(self, x):
-        return Projection.apply(x, self.geom)
+class ParallelProjection2D(_ProjLayer):
+    pass
 
 
-class ConeProjection3D(_Layer):
-    def forward(self, x):
-        return Projection.apply(x, self.geom)
+class FanProjection2D(_ProjLayer):
+    pass
+
+
+class ConeProjection3D(_ProjLayer):
+    pass
 
 
 class ParallelBackProjection2D(_Layer):
