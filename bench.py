@@ -27,7 +27,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-KERNEL_SRC = os.path.join(ROOT, "paper_2511_08427_amd", "csrc", "pn_kernels.hip")
+# the projector kernels' sources: the counters in profiles/ hold for the
+# sha256 of these files, concatenated in this order
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2511_08427_amd", "csrc", f) for f in ("pn_kernels.hip", "pn_ray.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cone3d_256_hbm_traffic.md")
 COUNTER_FILE = os.path.join(ROOT, "profiles", "cone3d_256_counters.md")
 
@@ -61,7 +63,10 @@ def profiled_value(path, key):
 
     try:
         text = open(path).read()
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in KERNEL_SRCS:
+            h.update(open(f, "rb").read())
+        src = h.hexdigest()
     except OSError:
         return None
     sha = val = None

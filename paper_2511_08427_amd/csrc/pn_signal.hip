@@ -333,6 +333,76 @@ __global__ __launch_bounds__(256) void blur_kernel(BlurParams p)
     }
 }
 
+// The same blur for detectors of >= 16 rows and up to 49 taps, as a
+// stencil: the taps' offsets and bilinear weights depend on the view only,
+// so a workgroup (one 64 x 16 pixel tile of one view) forms the <= 4 taps
+// (integer offset, weight) entries once, stages the tile with its halo (zeros
+// outside the detector) into LDS, and every output is a sum of LDS reads.
+// Per view the taps reach at most h = (taps - 1) / 2 pixels (|cos|, |sin| <=
+// 1) plus one for the bilinear corner, so the staged region is
+// (16 + 2h + 2) x (64 + 2h + 2).  Each thread computes 4 rows of one column.
+constexpr int kBlurTileC = 64, kBlurTileR = 16, kBlurTiledMaxHalf = 24;
+
+template <typename T>
+__global__ __launch_bounds__(256) void blur_tiled_kernel(BlurParams p)
+{
+    extern __shared__ float blur_lds[];
+    const int h = (p.taps - 1) / 2;
+    const int W = kBlurTileC + 2 * h + 2, H = kBlurTileR + 2 * h + 2;
+    const int ne = 4 * p.taps;
+    float *tile = blur_lds;
+    float *s_w = tile + H * W;
+    int *s_off = reinterpret_cast<int *>(s_w + ne);
+    const int tiles_c = (p.cols + kBlurTileC - 1) / kBlurTileC, tiles_r = (p.rows + kBlurTileR - 1) / kBlurTileR;
+    int64_t bid = blockIdx.x;
+    const int tc = static_cast<int>(bid % tiles_c);
+    bid /= tiles_c;
+    const int tr = static_cast<int>(bid % tiles_r);
+    const int64_t img = bid / tiles_r;
+    const int v = static_cast<int>(img % p.n_views);
+    const int c0 = tc * kBlurTileC, r0 = tr * kBlurTileR;
+    const int t = threadIdx.x;
+    const T *im = static_cast<const T *>(p.in) + img * p.rows * p.cols;
+    if (t < ne) {
+        // entry t: tap t / 4 (offset t / 4 - h along the direction), corner
+        // (ox, oy) = (t & 1, t >> 1 & 1); offsets and fractions as the
+        // per-pixel kernel forms them
+        double sd, cd;
+        sincos(p.angle_start + v * p.angle_step, &sd, &cd);
+        const float du = static_cast<float>(cd), dv = static_cast<float>(sd);
+        const int ox = t & 1, oy = (t >> 1) & 1;
+        const float tf = static_cast<float>((t >> 2) - h);
+        const float tu = tf * du, tv = tf * dv;
+        const float iu = floorf(tu), iv = floorf(tv);
+        const float fx = tu - iu, fy = tv - iv;
+        s_w[t] = (oy ? fy : 1.0f - fy) * (ox ? fx : 1.0f - fx);
+        s_off[t] = (static_cast<int>(iv) + oy + h) * W + static_cast<int>(iu) + ox + h;
+    }
+    for (int i = t; i < H * W; i += 256) {
+        const int gr = r0 - h + i / W, gc = c0 - h + i % W;
+        tile[i] = gr >= 0 && gr < p.rows && gc >= 0 && gc < p.cols
+                      ? to_f32(im[static_cast<int64_t>(gr) * p.cols + gc])
+                      : 0.0f;
+    }
+    __syncthreads();
+    const int lx = t & 63, ly0 = (t >> 6) * 4;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int e = 0; e < ne; ++e) {
+        const float w = s_w[e];
+        const float *q = tile + ly0 * W + lx + s_off[e];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = fmaf(w, q[j * W], acc[j]);
+    }
+    const float inv = 1.0f / static_cast<float>(p.taps);
+    T *dst = static_cast<T *>(p.out) + img * p.rows * p.cols;
+    const int c = c0 + lx;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = r0 + ly0 + j;
+        if (r < p.rows && c < p.cols) dst[static_cast<int64_t>(r) * p.cols + c] = from_f32<T>(acc[j] * inv);
+    }
+}
+
 hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st);
 
 template <typename P, typename F32K, typename B16K, typename F16K>
@@ -363,6 +433,22 @@ hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st)
 
 hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st)
 {
+    const int h = (p.taps - 1) / 2;
+    if (p.rows >= kBlurTileR && h <= kBlurTiledMaxHalf) {
+        // one workgroup per 64 x 16 pixel tile of a view
+        const int64_t tiles = static_cast<int64_t>((p.cols + kBlurTileC - 1) / kBlurTileC) *
+                              ((p.rows + kBlurTileR - 1) / kBlurTileR) * p.batch * p.n_views;
+        if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+        const size_t lds = sizeof(float) * (static_cast<size_t>(kBlurTileC + 2 * h + 2) * (kBlurTileR + 2 * h + 2) +
+                                            8 * static_cast<size_t>(p.taps));
+        const dim3 grid(static_cast<uint32_t>(tiles));
+        switch (dt) {
+        case DT_F32: blur_tiled_kernel<float><<<grid, 256, lds, st>>>(p); break;
+        case DT_BF16: blur_tiled_kernel<bf16><<<grid, 256, lds, st>>>(p); break;
+        default: blur_tiled_kernel<f16><<<grid, 256, lds, st>>>(p); break;
+        }
+        return hipGetLastError();
+    }
     // one wave per detector row
     return launch_elementwise(p, p.batch * p.n_views * p.rows * 64, dt, blur_kernel<float>, blur_kernel<bf16>,
                               blur_kernel<f16>, st);

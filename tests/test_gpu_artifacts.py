@@ -179,7 +179,9 @@ def test_graph_capture_filter_and_artifacts(pn):
 
 
 @pytest.mark.parametrize("shape,taps,a0,da", [((2, 6, 9, 13), 5, 0.2, 0.7), ((1, 4, 1, 50), 7, 0.0, math.pi / 2),
-                                              ((1, 3, 5, 5), 1, 1.0, 1.0), ((1, 8, 16, 40), 31, -0.4, 0.9)])
+                                              ((1, 3, 5, 5), 1, 1.0, 1.0), ((1, 8, 16, 40), 31, -0.4, 0.9),
+                                              ((2, 5, 37, 70), 9, 0.3, 1.1), ((1, 3, 20, 130), 49, -1.0, 0.5),
+                                              ((1, 2, 18, 33), 51, 0.4, 2.0), ((1, 4, 16, 64), 1, 0.0, 0.3)])
 def test_gantry_blur_matches_oracle(pn, shape, taps, a0, da):
     _say(f"gantry blur {shape} taps={taps}")
     x = np.random.default_rng(taps).random(shape).astype(np.float32)
