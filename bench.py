@@ -50,6 +50,9 @@ def parse():
                     help="also run a plain 256 MiB elementwise copy kernel (counter calibration)")
     ap.add_argument("--profile-once", action="store_true",
                     help="run one forward, adjoint, back-projection and filter only (for counter collection)")
+    ap.add_argument("--profile-sampler", action="store_true",
+                    help="run one staged forward and one sampler-interpolation forward per image only "
+                         "(for counter collection)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-problem batched variant")
     ap.add_argument("--unrolled512", action="store_true",
                     help="also time the 512^3 x 720 unrolled 10-step reconstruction (FP32 and BF16 storage)")
@@ -237,6 +240,13 @@ def main():
         torch.mul(src, 1.0, out=dst)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         log("calibration copy: 268435456 bytes read + 268435456 bytes written")
+    if args.profile_sampler:
+        pn.forward(x, geom)
+        pn.forward_sampled(x, geom, "bordered")
+        pn.forward_sampled(x, geom, "volume")
+        torch.cuda.synchronize()
+        log("profile-sampler: one staged forward and one sampler forward per image done")
+        return
     if args.profile_once:
         y, _ = step()
         pn.backproject(y, geom)

@@ -73,6 +73,7 @@ struct SampParams {
     int64_t item[3], plane[3], row[3], col[3], org[3];
     void *sino;            // [batch][n_views][nv][nu]
     int32_t tile_u, tile_v, tiles_u, tiles_v;
+    int32_t view_group;    // consecutive views per workgroup (tile_u * tile_v * view_group == 256)
     int32_t bordered;      // 1: images with a zero border (work copies), 0: the caller's volume, taps checked
     int32_t weight_bits;   // 0: FP32 weights; B > 0: weights rounded to multiples of 2^-B (ties up)
     int32_t point_source;  // 1: every ray of a view leaves one point (B has zero u and v columns)

@@ -24,7 +24,7 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_forward_sampled(const SampParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 int64_t forward_sampled_blocks(const SampParams &p);
-void forward_sampled_tile(bool two_d, int32_t &tu, int32_t &tv);
+void forward_sampled_tile(bool two_d, int32_t &tu, int32_t &tv, int32_t &views);
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
 bool adjoint_fusable(bool two_d, int shape);
 hipError_t launch_forward_table(const Table<FwdParams> &w, uint32_t blocks, bool two_d, int32_t in_dt,
@@ -711,7 +711,7 @@ int forward_sampled_impl(const pn_geometry *pg, int64_t batch, const void *vol, 
         }
     }
     p.sino = sino;
-    forward_sampled_tile(g.ndim == 2, p.tile_u, p.tile_v);
+    forward_sampled_tile(g.ndim == 2, p.tile_u, p.tile_v, p.view_group);
     p.tiles_u = (g.nu + p.tile_u - 1) / p.tile_u;
     p.tiles_v = (g.nv + p.tile_v - 1) / p.tile_v;
     if (forward_sampled_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");

@@ -30,10 +30,13 @@
 
 namespace pn {
 
-// One thread per ray, a tile_u x tile_v tile of detector pixels of one view
-// per workgroup.  Consecutive workgroup ids go round-robin to the 8 XCDs;
-// each XCD takes every 8th tile and runs all views of a tile back to back,
-// so its L2 holds the slab of volume those rays cross.
+// One thread per ray: a workgroup takes a tile_u x tile_v tile of detector
+// pixels in view_group consecutive views (one view per tile_u x tile_v
+// threads).  Rays of neighbouring views cross nearly the same voxels, so
+// the waves of a workgroup, which run side by side on one CU, share their
+// cache lines in L1.  Consecutive workgroup ids go round-robin to the 8
+// XCDs; each XCD takes every 8th tile and runs all view groups of a tile
+// back to back, so its L2 holds the slab of volume those rays cross.
 template <typename S, typename O, bool BORDER, bool QUANT>
 __global__ __launch_bounds__(256) void forward_sampled_kernel(SampParams p)
 {
@@ -41,15 +44,18 @@ __global__ __launch_bounds__(256) void forward_sampled_kernel(SampParams p)
     const int bid = blockIdx.x;
     const int tiles = p.tiles_u * p.tiles_v;
     const int tpx = (tiles + 7) >> 3;
+    const int n_vg = (p.n_views + p.view_group - 1) / p.view_group;
     const int xcd = bid & 7, slot = bid >> 3;
-    const int per_b = tpx * p.n_views;
+    const int per_b = tpx * n_vg;
     const int b = slot / per_b;
     const int rem = slot - b * per_b;
-    const int tile = (rem / p.n_views) * 8 + xcd;
-    const int view = rem % p.n_views;
-    if (tile >= tiles || b >= p.batch) return;  // padding workgroups
-    const int c = (tile % p.tiles_u) * p.tile_u + t % p.tile_u;
-    const int r = (tile / p.tiles_u) * p.tile_v + t / p.tile_u;
+    const int tile = (rem / n_vg) * 8 + xcd;
+    const int tpix = p.tile_u * p.tile_v;
+    const int view = (rem % n_vg) * p.view_group + t / tpix;
+    if (tile >= tiles || b >= p.batch || view >= p.n_views) return;  // padding
+    const int tt = t % tpix;
+    const int c = (tile % p.tiles_u) * p.tile_u + tt % p.tile_u;
+    const int r = (tile / p.tiles_u) * p.tile_v + tt / p.tile_u;
     if (c >= p.nu || r >= p.nv) return;
 
     RaySeg rs;
@@ -131,15 +137,18 @@ __global__ __launch_bounds__(256) void forward_sampled_kernel(SampParams p)
 int64_t forward_sampled_blocks(const SampParams &p)
 {
     const int64_t tiles = static_cast<int64_t>(p.tiles_u) * p.tiles_v;
-    return 8 * ((tiles + 7) / 8) * p.n_views * static_cast<int64_t>(p.batch);
+    const int64_t n_vg = (p.n_views + p.view_group - 1) / p.view_group;
+    return 8 * ((tiles + 7) / 8) * n_vg * static_cast<int64_t>(p.batch);
 }
 
-// Ray tile of the sampler: 64 x 4 pixels (a wave is one row of 64 pixels),
-// 256 x 1 for 2-D problems.
-void forward_sampled_tile(bool two_d, int32_t &tu, int32_t &tv)
+// Workgroup shape of the sampler: 64 x 1 pixels in 4 consecutive views (a
+// wave is one row of 64 pixels of one view); 256 x 1 pixels of one view for
+// 2-D problems.
+void forward_sampled_tile(bool two_d, int32_t &tu, int32_t &tv, int32_t &views)
 {
     tu = two_d ? 256 : 64;
-    tv = two_d ? 1 : 4;
+    tv = 1;
+    views = two_d ? 1 : 4;
 }
 
 template <typename S, typename O, bool BORDER>
