@@ -477,6 +477,10 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                     // padded grid, so no clamp is needed; positions are >= 0,
                     // so truncation is floor.  The offset is capped to keep
                     // the reads inside the box array whatever the positions.
+                    // LDS row pitch in bytes, in a VGPR (the multiply-add takes
+                    // the plane offset as its one scalar operand)
+                    uint32_t row_bytes = FCAP * 4;
+                    asm volatile("" : "+v"(row_bytes));
                     const float fo = static_cast<float>(now.f_al), so = static_cast<float>(now.s_lo);
                     const float fmc = static_cast<float>(now.mc);
                     const float pf0 = fmaf(fmc, sg.gf, sg.bf - fo);
@@ -492,12 +496,18 @@ __device__ __forceinline__ void forward_block(const FwdParams &p, const int bid)
                         const float ps = fmaf(static_cast<float>(k), sg.gs, ps0);
                         twf[sl_] = __builtin_amdgcn_fractf(pf);
                         tws[sl_] = __builtin_amdgcn_fractf(ps);
-                        uint32_t off = __mul24(static_cast<uint32_t>(ps), static_cast<uint32_t>(FCAP * 4)) +
-                                       static_cast<uint32_t>(k * PLANE * 4);
-                        off = min(off + (static_cast<uint32_t>(pf) << 2),
-                                  static_cast<uint32_t>((C * PLANE - FCAP - 2) * 4));
+                        // byte offset in the whole box array (both buffers):
+                        // row and column of the tap in two ops, the buffer
+                        // and plane in the uniform addend; the array's own
+                        // LDS address folds into the reads' offset fields
+                        uint32_t off;
+                        asm("v_mad_u32_u24 %0, %1, %2, %3\n\tv_lshl_add_u32 %0, %4, 2, %0"
+                            : "=&v"(off)
+                            : "v"(static_cast<uint32_t>(ps)), "v"(row_bytes),
+                              "s"(static_cast<uint32_t>((buf * C + k) * PLANE * 4)), "v"(static_cast<uint32_t>(pf)));
+                        off = min(off, static_cast<uint32_t>((NBUF * C * PLANE - FCAP - 2) * 4));
                         asm volatile("" : "+v"(off));  // one base register for all four taps
-                        const float *q = reinterpret_cast<const float *>(reinterpret_cast<const char *>(box[buf]) + off);
+                        const float *q = reinterpret_cast<const float *>(reinterpret_cast<const char *>(&box[0][0]) + off);
                         tv[sl_][0] = q[0];
                         tv[sl_][1] = q[1];
                         tv[sl_][2] = q[FCAP];
