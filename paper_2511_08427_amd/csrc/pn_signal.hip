@@ -246,6 +246,8 @@ __global__ __launch_bounds__(256) void ring_kernel(RingParams p)
     }
 }
 
+constexpr int kJitterRows = 16;  // rows per wave and group
+
 // Detector jitter: every detector row moved by its own integer shift s in
 // -m .. m along the columns (zero where the source leaves the row).  s is
 // word 0 of the Philox block at counter (row, 0, 0, 0) under key (seed, 1),
@@ -253,26 +255,40 @@ __global__ __launch_bounds__(256) void ring_kernel(RingParams p)
 template <typename T>
 __global__ __launch_bounds__(256) void jitter_kernel(JitterParams p)
 {
-    // each wave moves groups of 64 consecutive rows: lane l draws the shift
-    // of row g0 + l (one Philox block per row), then the wave copies the
-    // group's rows one after the other, lanes along the columns (coalesced)
-    const T *src = static_cast<const T *>(p.in);
-    T *dst = static_cast<T *>(p.out);
+    // each wave moves groups of kJitterRows consecutive rows: lane l <
+    // kJitterRows draws the shift of row g0 + l (one Philox block per row),
+    // then the wave copies the group's rows one after the other, lanes along
+    // the columns (coalesced), four columns per lane in flight at a time
+    const T *__restrict__ src = static_cast<const T *>(p.in);
+    T *__restrict__ dst = static_cast<T *>(p.out);
     const uint64_t span = static_cast<uint64_t>(2 * p.max_shift + 1);
     const int lane = threadIdx.x & 63;
     const int64_t waves = static_cast<int64_t>(gridDim.x) * 4;
-    for (int64_t g0 = (static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6)) * 64; g0 < p.n_rows;
-         g0 += waves * 64) {
-        uint64_t w[4] = {static_cast<uint64_t>(g0 + lane), 0, 0, 0};
-        philox4x64_10(w, p.seed, 1);
-        const int mine = static_cast<int>(w[0] % span) - p.max_shift;
-        const int nrow = static_cast<int>(min(static_cast<int64_t>(64), p.n_rows - g0));
+    for (int64_t g0 = (static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6)) * kJitterRows; g0 < p.n_rows;
+         g0 += waves * kJitterRows) {
+        int mine = 0;
+        if (lane < kJitterRows) {
+            uint64_t w[4] = {static_cast<uint64_t>(g0 + lane), 0, 0, 0};
+            philox4x64_10(w, p.seed, 1);
+            mine = static_cast<int>(w[0] % span) - p.max_shift;
+        }
+        const int nrow = static_cast<int>(min(static_cast<int64_t>(kJitterRows), p.n_rows - g0));
         for (int j = 0; j < nrow; ++j) {
             const int sft = __builtin_amdgcn_readlane(mine, j);
-            const int64_t base = (g0 + j) * p.cols;
-            for (int c = lane; c < p.cols; c += 64) {
-                const int from = c - sft;
-                dst[base + c] = (from >= 0 && from < p.cols) ? src[base + from] : from_f32<T>(0.0f);
+            const T *in = src + (g0 + j) * p.cols;
+            T *out = dst + (g0 + j) * p.cols;
+            for (int c0 = 0; c0 < p.cols; c0 += 4 * 64) {
+                T v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = c0 + lane + 64 * k, from = c - sft;
+                    v[k] = (c < p.cols && from >= 0 && from < p.cols) ? in[from] : from_f32<T>(0.0f);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = c0 + lane + 64 * k;
+                    if (c < p.cols) out[c] = v[k];
+                }
             }
         }
     }
@@ -426,9 +442,9 @@ hipError_t launch_noise(const NoiseParams &p, int32_t dt, hipStream_t st)
 
 hipError_t launch_jitter(const JitterParams &p, int32_t dt, hipStream_t st)
 {
-    // one wave per group of 64 rows
-    return launch_elementwise(p, (p.n_rows + 63) / 64 * 64, dt, jitter_kernel<float>, jitter_kernel<bf16>,
-                              jitter_kernel<f16>, st);
+    // one wave per group of kJitterRows rows
+    return launch_elementwise(p, (p.n_rows + kJitterRows - 1) / kJitterRows * 64, dt, jitter_kernel<float>,
+                              jitter_kernel<bf16>, jitter_kernel<f16>, st);
 }
 
 hipError_t launch_blur(const BlurParams &p, int32_t dt, hipStream_t st)
