@@ -857,7 +857,11 @@ template <int L, int TS, int TF, int SLO, int SHI, int CPT, int NT>
 struct AdjLds {
     static constexpr int RW = TF + 4;              // LDS row (halo: 2 before, 2 after)
     static constexpr int RP = TS + SLO + SHI + 1;  // LDS rows per plane
-    static constexpr int PL = RP * RW;             // LDS plane
+    // LDS plane: RP rows plus 2 or 3 padding cells, so that a plane is 2
+    // cells past a multiple of 4: the two segments of one ray, 8 planes
+    // apart and scattered by neighbouring lanes, then fall into different
+    // LDS banks
+    static constexpr int PL = RP * RW + (6 - (RP * RW) % 4) % 4;
     static constexpr int MAXR = NT * CPT;          // rays per batch
     static constexpr int MAXSEG = MAXR * ((L + 7) / 8);
     float4 s_ray[MAXR];      // gf, bf, gs, bs (block-local frame)
@@ -876,7 +880,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid,
     constexpr int K = 8;                       // planes per segment
     constexpr int RW = TF + 4;                 // LDS row (halo: 2 before, 2 after)
     constexpr int RP = TS + SLO + SHI + 1;     // LDS rows per plane
-    constexpr int PL = RP * RW;                // LDS plane
+    constexpr int PL = RP * RW + (6 - (RP * RW) % 4) % 4;  // LDS plane (padded, as AdjLds)
     constexpr int NV = L * TS * TF;            // voxels of the block
     constexpr int NQ = (NV + NT - 1) / NT;     // voxels per thread
     constexpr int MAXR = NT * CPT;             // rays per batch
@@ -963,7 +967,7 @@ __device__ __forceinline__ void adjoint_block(const AdjParams &p, const int bid,
             if (el < NV) {
                 int la, ls, lf;
                 cell_of(el, la, ls, lf);
-                int *cellp = acc + (la * RP + ls + SLO + 1) * RW + lf + 2;
+                int *cellp = acc + la * PL + (ls + SLO + 1) * RW + lf + 2;
                 reg[q] = fmaf(static_cast<float>(*cellp), inv_scale, reg[q]);
                 *cellp = 0;
             }
