@@ -29,7 +29,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # the projector kernels' sources: the counters in profiles/ hold for the
 # sha256 of these files, concatenated in this order
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2511_08427_amd", "csrc", f) for f in ("pn_kernels.hip", "pn_ray.hpp")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2511_08427_amd", "csrc", f)
+               for f in ("pn_kernels.hip", "pn_ray.hpp", "pn_common.hpp", "pn_device.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cone3d_256_hbm_traffic.md")
 COUNTER_FILE = os.path.join(ROOT, "profiles", "cone3d_256_counters.md")
 
