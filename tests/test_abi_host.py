@@ -113,6 +113,17 @@ def test_entry_points_validate_before_device_work(pn, N):
         mis = ctypes.c_void_p(ctypes.cast(buf, vp).value + 2)
         assert fn(g, 1, mis, q, 0, 0, None) == N.PN_EINVAL
         assert fn(g, 0, None, None, 0, 0, None) == 0  # empty batch: nothing to do
+    # the sampler forward: its own arguments first, then those of pn_forward
+    fs = N.lib.pn_forward_sampled
+    assert fs(g, 1, p, q, 0, 0, 2, 0, None) == N.PN_EINVAL
+    assert "source" in N.last_error()
+    for bits in (-1, 17):
+        assert fs(g, 1, p, q, 0, 0, 0, bits, None) == N.PN_EINVAL
+        assert "weight_bits" in N.last_error()
+    assert fs(g, 1, p, q, 9, 0, 1, 8, None) == N.PN_EDTYPE
+    assert fs(g, 1, None, q, 0, 0, 0, 0, None) == N.PN_EINVAL
+    assert fs(g, 1, p, p, 0, 0, 1, 0, None) == N.PN_EINVAL
+    assert fs(g, 0, None, None, 0, 0, 1, 16, None) == 0  # empty batch: nothing to do
     # the row filter: kind, dtypes, pointers, then its own limits
     f = N.lib.pn_filter
     assert f(g, 1, p, q, 0, 0, 2, None) == N.PN_EINVAL
