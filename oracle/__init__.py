@@ -347,8 +347,12 @@ def adjoint(sino, g, box=None, nthreads=0):
     return out
 
 
-def backproject(sino, g, nthreads=0):
-    """Voxel-driven (W0/W)^2-weighted back-projection; returns [nz][ny][nx]."""
+def backproject(sino, g, nthreads=0, weight_bits=0):
+    """Voxel-driven (W0/W)^2-weighted back-projection; returns [nz][ny][nx].
+
+    weight_bits = B > 0: the sampler variant (paper Sec. 2.1), detector
+    interpolation weights rounded to the nearest multiple of 2^-B, ties
+    upward; 0 is the back-projection itself."""
     lib = _load()
     keep, pn, ps, po, pP = _geo_args(g)
     nv, nu = g["det"]
@@ -357,14 +361,15 @@ def backproject(sino, g, nthreads=0):
     assert sn.size == nviews * nv * nu
     nx, ny, nz = g["n"]
     out = np.zeros((nz, ny, nx), dtype=np.float64)
-    lib.oracle_backproject(
+    lib.oracle_backproject_q(
         ctypes.c_int(g["dims"]), pn, ps, po, ctypes.c_int64(nviews), pP, ctypes.c_int64(nv),
-        ctypes.c_int64(nu), psn, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads))
+        ctypes.c_int64(nu), psn, out.ctypes.data_as(_F64P), ctypes.c_int(nthreads), ctypes.c_int(int(weight_bits)))
     return out
 
 
-def backproject_voxels(sino, g, i, j, k, nthreads=0):
-    """Back-projection at voxels (i[t], j[t], k[t]) only."""
+def backproject_voxels(sino, g, i, j, k, nthreads=0, weight_bits=0):
+    """Back-projection at voxels (i[t], j[t], k[t]) only (weight_bits as
+    ``backproject``)."""
     lib = _load()
     keep, pn, ps, po, pP = _geo_args(g)
     nv, nu = g["det"]
@@ -374,10 +379,10 @@ def backproject_voxels(sino, g, i, j, k, nthreads=0):
     jj, pj = _i64(j)
     kk, pk = _i64(k)
     out = np.zeros(ii.size, dtype=np.float64)
-    lib.oracle_backproject_voxels(
+    lib.oracle_backproject_voxels_q(
         ctypes.c_int(g["dims"]), pn, ps, po, ctypes.c_int64(nviews), pP, ctypes.c_int64(nv),
         ctypes.c_int64(nu), psn, ctypes.c_int64(ii.size), pi, pj, pk, out.ctypes.data_as(_F64P),
-        ctypes.c_int(nthreads))
+        ctypes.c_int(nthreads), ctypes.c_int(int(weight_bits)))
     return out
 
 

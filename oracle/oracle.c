@@ -413,9 +413,9 @@ int oracle_adjoint(int dims, int parallel, const int64_t n[3], const double s[3]
 }
 
 /* Zero-padded linear (dims 2) / bilinear (dims 3) detector sample. */
-static double detector_sample(const double *img, int64_t nv, int64_t nu, double u, double v, int dims)
+static double detector_sample(const double *img, int64_t nv, int64_t nu, double u, double v, int dims, int wbits)
 {
-    double fu = floor(u), wu = u - fu;
+    double fu = floor(u), wu = tap_weight(u - fu, wbits);
     int64_t iu = (int64_t)fu;
     if (dims == 2) {
         double val = 0.0;
@@ -423,7 +423,7 @@ static double detector_sample(const double *img, int64_t nv, int64_t nu, double 
         if (iu + 1 >= 0 && iu + 1 < nu) val += wu * img[iu + 1];
         return val;
     }
-    double fv = floor(v), wv = v - fv;
+    double fv = floor(v), wv = tap_weight(v - fv, wbits);
     int64_t iv = (int64_t)fv;
     double val = 0.0;
     for (int tv = 0; tv < 2; ++tv) {
@@ -439,9 +439,10 @@ static double detector_sample(const double *img, int64_t nv, int64_t nu, double 
 }
 
 /* Back-projection value at voxel (i, j, k): sum over views of
- * (W0/W)^2 * interp(sino_view, U/W, V/W). */
+ * (W0/W)^2 * interp(sino_view, U/W, V/W).  wbits > 0: the sampler variant,
+ * detector weights rounded to multiples of 2^-wbits (tap_weight). */
 static double bp_voxel(const grid_t *g, int dims, int64_t n_views, const double *P, int64_t nv, int64_t nu,
-                       const double *sino, int64_t i, int64_t j, int64_t k)
+                       const double *sino, int64_t i, int64_t j, int64_t k, int wbits)
 {
     double x = g->o[0] + (double)i * g->s[0];
     double y = g->o[1] + (double)j * g->s[1];
@@ -455,7 +456,7 @@ static double bp_voxel(const grid_t *g, int dims, int64_t n_views, const double 
             double W = p[3] * x + p[4] * y + p[5];
             double W0 = p[5];
             double wt = (W0 / W) * (W0 / W);
-            acc += wt * detector_sample(img, 1, nu, U / W, 0.0, 2);
+            acc += wt * detector_sample(img, 1, nu, U / W, 0.0, 2, wbits);
         } else {
             const double *p = P + view * 12;
             double U = p[0] * x + p[1] * y + p[2] * z + p[3];
@@ -463,16 +464,17 @@ static double bp_voxel(const grid_t *g, int dims, int64_t n_views, const double 
             double W = p[8] * x + p[9] * y + p[10] * z + p[11];
             double W0 = p[11];
             double wt = (W0 / W) * (W0 / W);
-            acc += wt * detector_sample(img, nv, nu, U / W, V / W, 3);
+            acc += wt * detector_sample(img, nv, nu, U / W, V / W, 3, wbits);
         }
     }
     return acc;
 }
 
-/* Voxel-driven back-projection of the whole volume. */
-int oracle_backproject(int dims, const int64_t n[3], const double s[3], const double o[3],
-                       int64_t n_views, const double *P, int64_t nv, int64_t nu,
-                       const double *sino, double *vol, int nthreads)
+/* Voxel-driven back-projection of the whole volume (wbits as bp_voxel;
+ * oracle_backproject is wbits = 0). */
+int oracle_backproject_q(int dims, const int64_t n[3], const double s[3], const double o[3],
+                         int64_t n_views, const double *P, int64_t nv, int64_t nu,
+                         const double *sino, double *vol, int nthreads, int wbits)
 {
     grid_t g;
     make_grid(&g, n, s, o);
@@ -483,15 +485,22 @@ int oracle_backproject(int dims, const int64_t n[3], const double s[3], const do
     for (int64_t k = 0; k < g.n[2]; ++k)
         for (int64_t j = 0; j < g.n[1]; ++j)
             for (int64_t i = 0; i < g.n[0]; ++i)
-                vol[(k * g.n[1] + j) * g.n[0] + i] = bp_voxel(&g, dims, n_views, P, nv, nu, sino, i, j, k);
+                vol[(k * g.n[1] + j) * g.n[0] + i] = bp_voxel(&g, dims, n_views, P, nv, nu, sino, i, j, k, wbits);
     return 0;
 }
 
-/* Back-projection at selected voxels only. */
-int oracle_backproject_voxels(int dims, const int64_t n[3], const double s[3], const double o[3],
-                              int64_t n_views, const double *P, int64_t nv, int64_t nu,
-                              const double *sino, int64_t n_vox, const int64_t *vi, const int64_t *vj,
-                              const int64_t *vk, double *out, int nthreads)
+int oracle_backproject(int dims, const int64_t n[3], const double s[3], const double o[3],
+                       int64_t n_views, const double *P, int64_t nv, int64_t nu,
+                       const double *sino, double *vol, int nthreads)
+{
+    return oracle_backproject_q(dims, n, s, o, n_views, P, nv, nu, sino, vol, nthreads, 0);
+}
+
+/* Back-projection at selected voxels only (wbits as bp_voxel). */
+int oracle_backproject_voxels_q(int dims, const int64_t n[3], const double s[3], const double o[3],
+                                int64_t n_views, const double *P, int64_t nv, int64_t nu,
+                                const double *sino, int64_t n_vox, const int64_t *vi, const int64_t *vj,
+                                const int64_t *vk, double *out, int nthreads, int wbits)
 {
     grid_t g;
     make_grid(&g, n, s, o);
@@ -500,8 +509,17 @@ int oracle_backproject_voxels(int dims, const int64_t n[3], const double s[3], c
 #endif
 #pragma omp parallel for schedule(static)
     for (int64_t t = 0; t < n_vox; ++t)
-        out[t] = bp_voxel(&g, dims, n_views, P, nv, nu, sino, vi[t], vj[t], vk[t]);
+        out[t] = bp_voxel(&g, dims, n_views, P, nv, nu, sino, vi[t], vj[t], vk[t], wbits);
     return 0;
+}
+
+int oracle_backproject_voxels(int dims, const int64_t n[3], const double s[3], const double o[3],
+                              int64_t n_views, const double *P, int64_t nv, int64_t nu,
+                              const double *sino, int64_t n_vox, const int64_t *vi, const int64_t *vj,
+                              const int64_t *vk, double *out, int nthreads)
+{
+    return oracle_backproject_voxels_q(dims, n, s, o, n_views, P, nv, nu, sino, n_vox, vi, vj, vk, out,
+                                       nthreads, 0);
 }
 
 /* Transpose of the voxel-driven back-projection (the splat projector):

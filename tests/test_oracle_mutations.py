@@ -29,7 +29,8 @@ C_MUTANTS = [
     ("origin sign", "xi0[i] = (ray->x0[i] - g->o[i]) / g->s[i];", "xi0[i] = (ray->x0[i] + g->o[i]) / g->s[i];"),
     ("BP distance weight inverted", "double W0 = p[11];\n            double wt = (W0 / W) * (W0 / W);",
      "double W0 = p[11];\n            double wt = (W / W0) * (W / W0);"),
-    ("u and v swapped in BP", "detector_sample(img, nv, nu, U / W, V / W, 3)", "detector_sample(img, nv, nu, V / W, U / W, 3)"),
+    ("u and v swapped in BP", "detector_sample(img, nv, nu, U / W, V / W, 3, wbits)",
+     "detector_sample(img, nv, nu, V / W, U / W, 3, wbits)"),
     ("fan direction component", "ray->d[1] = i10 * u + i11;", "ray->d[1] = i10 * u - i11;"),
     ("adjoint reads a mirrored column", "double q = sino[(k * nv + r) * nu + c];",
      "double q = sino[(k * nv + r) * nu + (nu - 1 - c)];"),
@@ -43,6 +44,8 @@ C_MUTANTS = [
     ("second in-plane weight not rounded", "double fc = floor(pc), wc = tap_weight(pc - fc, wbits);",
      "double fc = floor(pc), wc = pc - fc;"),
     ("ties rounded downward", "if (t - q >= 0.5) q += 1.0;", "if (t - q > 0.5) q += 1.0;"),
+    ("back-projection row weight not rounded", "double fv = floor(v), wv = tap_weight(v - fv, wbits);",
+     "double fv = floor(v), wv = v - fv;"),
 ]
 
 

@@ -516,6 +516,56 @@ def test_bp_of_linear_sinogram_matches_pinhole_model(O):
     assert np.abs(b - ref).max() < 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("bits", [3, 8])
+def test_quantised_bp_matches_map_coordinates_at_snapped_positions(O, bits):
+    """The sampler variant of the back-projection rounds both detector
+    weights to the 2^-B lattice: linear interpolation of each view at the
+    projected position rounded to that lattice, the projection taken from
+    an independent central-projection model."""
+    shape, sp = (5, 6, 7), (1.5, 1.5, 1.5)
+    nv, nu, views, sid, sdd, du, dv = 14, 16, 7, 150.0, 240.0, 1.1, 0.9
+    S, C, eu, ev = O.circular_cone_vectors(views, 2 * math.pi, sid, sdd, (dv, du))
+    P = np.stack([O.cone_matrix(S[k], C[k], eu[k], ev[k], (nv, nu)) for k in range(views)])
+    g = O.cone_geometry(shape, sp, (nv, nu), (dv, du), P)
+    sino = np.random.default_rng(19).random((views, nv, nu))
+    b = O.backproject(sino, g, weight_bits=bits)
+    zc, yc, xc = W.voxel_centres(shape, sp)
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    pts = np.stack([X, Y, Z], axis=-1)
+    ref = np.zeros(shape)
+    for k in range(views):
+        n = np.cross(eu[k], ev[k])
+        n = n / np.linalg.norm(n)
+        depth = (pts - S[k]) @ n
+        Xd = S[k] + ((C[k] - S[k]) @ n / depth)[..., None] * (pts - S[k])
+        u = _snap((Xd - C[k]) @ eu[k] / (eu[k] @ eu[k]) + 0.5 * (nu - 1), bits)
+        v = _snap((Xd - C[k]) @ ev[k] / (ev[k] @ ev[k]) + 0.5 * (nv - 1), bits)
+        w = ((0 - S[k]) @ n / depth) ** 2
+        vals = map_coordinates(sino[k], np.stack([v.ravel(), u.ravel()]), order=1, mode="grid-constant", cval=0.0)
+        ref += w * vals.reshape(shape)
+    assert np.abs(b - ref).max() < 1e-11 * np.abs(ref).max()
+    assert np.abs(b - O.backproject(sino, g)).max() > 1e-4 * 2.0 ** -bits * np.abs(ref).max()
+
+
+def test_quantised_bp_exact_ties_round_upward(O):
+    """Rays along +x onto a panel shifted by (3/16, 5/16) pixel: voxel
+    (i, j, k) projects to (c, r) = (j - 3/16, k - 5/16) exactly, fractions
+    13/16 and 11/16, both ties of the 2^-3 lattice, which round up to 7/8
+    and 6/8 (unrounded: 13/16 and 11/16)."""
+    shape, det = (6, 7, 8), (6, 7)
+    P = O.parallel3d_matrix([1.0, 0, 0], [0, 3 / 16, 5 / 16], [0, 1.0, 0], [0, 0, 1.0], det)
+    g = O.cone_geometry(shape, (1.0, 1.0, 1.0), det, (1.0, 1.0), P[None], parallel=True)
+    img = np.random.default_rng(20).random(det)
+    pad = np.pad(img, ((1, 0), (1, 0)))  # row k - 1 and column j - 1 of index 0 are zero
+    for bits, (wu, wv) in ((3, (7 / 8, 6 / 8)), (0, (13 / 16, 11 / 16))):
+        # rows k, columns j of the detector for voxel (i, j, k); j < 7 = cols, k < 6 = rows
+        col = (1 - wu) * pad[:, :-1] + wu * pad[:, 1:]        # [rows + 1][cols]
+        e2 = (1 - wv) * col[:-1, :] + wv * col[1:, :]          # [rows][cols] at (k, j)
+        expect = np.broadcast_to(e2[:, :, None], shape)
+        got = O.backproject(img[None], g, weight_bits=bits)
+        assert np.abs(got - expect).max() < 1e-12, bits
+
+
 # ------------------------------------------------ P8: geometry identities --
 
 
