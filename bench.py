@@ -52,8 +52,8 @@ def parse():
     ap.add_argument("--profile-once", action="store_true",
                     help="run one forward, adjoint, back-projection and filter only (for counter collection)")
     ap.add_argument("--profile-sampler", action="store_true",
-                    help="run one staged forward and one sampler-interpolation forward per image only "
-                         "(for counter collection)")
+                    help="run one staged forward and back-projection and one sampler-interpolation forward "
+                         "and back-projection per image only (for counter collection)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-problem batched variant")
     ap.add_argument("--unrolled512", action="store_true",
                     help="also time the 512^3 x 720 unrolled 10-step reconstruction (FP32 and BF16 storage)")
@@ -244,9 +244,13 @@ def main():
     if args.profile_sampler:
         pn.forward(x, geom)
         pn.forward_sampled(x, geom, "bordered")
-        pn.forward_sampled(x, geom, "volume")
+        pn.forward_sampled(x, geom, "direct")
+        y = pn.forward(x, geom)
+        pn.backproject(y, geom)
+        pn.backproject_sampled(y, geom, "bordered")
+        pn.backproject_sampled(y, geom, "direct")
         torch.cuda.synchronize()
-        log("profile-sampler: one staged forward and one sampler forward per image done")
+        log("profile-sampler: staged and sampler forward and back-projection done")
         return
     if args.profile_once:
         y, _ = step()
@@ -340,13 +344,20 @@ def main():
         # sampler interpolation: every tap a load through the caches, from
         # the bordered copies (extra memory, as the staged projector) or from
         # the volume itself (none); with FP32 and with 8-bit weights
-        for key, src, bits in (("sampler_bordered", "bordered", 0), ("sampler_volume", "volume", 0),
+        for key, src, bits in (("sampler_bordered", "bordered", 0), ("sampler_direct", "direct", 0),
                                ("sampler_bordered_w8", "bordered", 8)):
             pn.forward_sampled(x, geom, src, bits)
             t_s, _ = timed(lambda: pn.forward_sampled(x, geom, src, bits), reps, stream)
             variants[f"{key}_forward_ms"] = t_s
             variants[f"{key}_forward_gups"] = upd / (t_s * 1e-3) / 1e9
             log(f"sampler ({src}, weight_bits {bits}): A {t_s:.3f} ms")
+        # the back-projection with sampler interpolation (no LDS rectangles)
+        for key, src in (("bp_sampler_bordered", "bordered"), ("bp_sampler_direct", "direct")):
+            pn.backproject_sampled(y, geom, src)
+            t_s, _ = timed(lambda: pn.backproject_sampled(y, geom, src), reps, stream)
+            variants[f"{key}_ms"] = t_s
+            variants[f"{key}_gups"] = upd / (t_s * 1e-3) / 1e9
+            log(f"sampler ({src}): BP {t_s:.3f} ms")
 
     if not args.no_variants and not args.no_batched:
         variants.update(batched_variant(pn, W, np, torch, stream))

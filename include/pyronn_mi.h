@@ -143,7 +143,7 @@ int pn_forward(const pn_geometry *pg, int64_t batch, const void *vol, void *sino
  *                       8 ((n_f + 24) / 8) (n_s + 3) n_a elements per axis
  *                       and batch item, n_f and n_s the in-plane sizes, held
  *                       by the geometry's plan);
- *   PN_SAMPLE_VOLUME    the caller's volume itself, every tap bounds-checked;
+ *   PN_SAMPLE_DIRECT    the caller's volume itself, every tap bounds-checked;
  *                       no extra memory besides the view tables.
  * weight_bits = 0 interpolates with FP32 weights (the result then matches
  * pn_forward to FP32 rounding); 1 <= weight_bits <= 16 rounds each of the
@@ -153,7 +153,7 @@ int pn_forward(const pn_geometry *pg, int64_t batch, const void *vol, void *sino
  * precision can be measured.  Shapes, types, streams and capture rules as
  * pn_forward; additionally PN_EINVAL for an unknown source, weight_bits
  * outside [0, 16], or an image of 2^31 elements or more per batch item. */
-enum { PN_SAMPLE_BORDERED = 0, PN_SAMPLE_VOLUME = 1 };
+enum { PN_SAMPLE_BORDERED = 0, PN_SAMPLE_DIRECT = 1 };
 int pn_forward_sampled(const pn_geometry *pg, int64_t batch, const void *vol, void *sino,
                        int32_t in_dtype, int32_t out_dtype, int32_t source, int32_t weight_bits,
                        void *hip_stream);
@@ -201,6 +201,27 @@ int pn_adjoint_noalloc(const pn_geometry *pg, int64_t batch, const void *sino, v
  * request PN_F32 output in that case. */
 int pn_backproject(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
                    int32_t in_dtype, int32_t out_dtype, void *hip_stream);
+
+/* pn_backproject with sampler interpolation (Sec. 2.1, interpolation: the
+ * texture path and the kernel path, as for pn_forward_sampled): the same
+ * operator -- each voxel centre projected with the view's matrix, (W0/W)^2
+ * weight -- with every bilinear detector tap a separate load through the
+ * caches, from the image chosen by `source`:
+ *   PN_SAMPLE_BORDERED  a zero-bordered copy of the sinogram (rows and
+ *                       columns padded by one before and two after: extra
+ *                       device memory of (rows + 3)(cols + 3) elements per
+ *                       view and batch item, held by the geometry's plan);
+ *   PN_SAMPLE_DIRECT    the caller's sinogram itself, every tap
+ *                       bounds-checked; no extra memory.
+ * weight_bits as pn_forward_sampled (0: FP32 weights, the result then
+ * matches pn_backproject to FP32 rounding; 1..16: each detector weight
+ * rounded to a multiple of 2^-weight_bits, ties upward).  Shapes, types,
+ * streams and capture rules as pn_backproject; additionally PN_EINVAL for
+ * an unknown source, weight_bits outside [0, 16], or a bordered view of
+ * 2^31 elements or more. */
+int pn_backproject_sampled(const pn_geometry *pg, int64_t batch, const void *sino, void *vol,
+                           int32_t in_dtype, int32_t out_dtype, int32_t source, int32_t weight_bits,
+                           void *hip_stream);
 
 /* Transpose of pn_backproject (the splat projector), the analytic gradient
  * of the back-projection with respect to its sinogram (Sec. 2: gradients

@@ -37,6 +37,7 @@ from .ops import (
     adjoint_noalloc,
     backproject,
     backproject_batched,
+    backproject_sampled,
     detector_jitter,
     fbp,
     fbp_filter,

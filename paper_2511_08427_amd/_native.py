@@ -32,6 +32,7 @@ EXPORTS = (
     "pn_adjoint",
     "pn_adjoint_noalloc",
     "pn_backproject",
+    "pn_backproject_sampled",
     "pn_splat",
     "pn_forward_batched",
     "pn_adjoint_batched",
@@ -101,6 +102,8 @@ def _load():
         f.restype = ctypes.c_int
     lib.pn_forward_sampled.argtypes = [gp, i64, vp, vp, i32, i32, i32, i32, vp]
     lib.pn_forward_sampled.restype = ctypes.c_int
+    lib.pn_backproject_sampled.argtypes = [gp, i64, vp, vp, i32, i32, i32, i32, vp]
+    lib.pn_backproject_sampled.restype = ctypes.c_int
     lib.pn_batch_create.argtypes = [i32, ctypes.POINTER(PnProblem), i32, i32, i32, ctypes.POINTER(vp)]
     lib.pn_batch_create.restype = ctypes.c_int
     lib.pn_batch_run.argtypes = [vp, vp]

@@ -79,6 +79,21 @@ struct SampParams {
     int32_t point_source;  // 1: every ray of a view leaves one point (B has zero u and v columns)
 };
 
+// Sampler-interpolation back-projection (pn_sampler.hip): every bilinear
+// detector tap a load through the caches.  Detector pixel (r, c) of view v
+// of batch item b sits at img + b*item + v*view + org + r*row + c.
+struct BpSampParams {
+    const ViewTabF *tabf;
+    int32_t n_views, nu, nv, batch;
+    int32_t n[3];
+    const void *img;       // zero-bordered copy of the sinogram, or the caller's sinogram
+    int64_t item, view, org;
+    int32_t row;
+    int32_t bordered;      // 1: bordered copy (taps unchecked), 0: the caller's sinogram, taps checked
+    int32_t weight_bits;   // 0: FP32 weights; B > 0: weights rounded to multiples of 2^-B (ties up)
+    void *vol;             // [batch][nz][ny][nx]
+};
+
 struct AdjParams {
     const ViewTab *tab;
     const ViewTabF *tabf;

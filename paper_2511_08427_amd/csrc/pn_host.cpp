@@ -23,6 +23,10 @@ hipError_t launch_relayout(int32_t dtype, const void *in, void *out, const int32
                            int64_t item, int32_t row, int64_t plane, hipStream_t st);
 hipError_t launch_forward(const FwdParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
 hipError_t launch_forward_sampled(const SampParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
+hipError_t launch_backproject_sampled(const BpSampParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st);
+int64_t backproject_sampled_blocks(const BpSampParams &p);
+hipError_t launch_pad_sino(int32_t dt, const void *in, void *out, int64_t n_img, int32_t nv, int32_t nu, int32_t row,
+                           int64_t view, hipStream_t st);
 int64_t forward_sampled_blocks(const SampParams &p);
 void forward_sampled_tile(bool two_d, int32_t &tu, int32_t &tv, int32_t &views);
 hipError_t launch_adjoint(const AdjParams &p, int32_t in_dt, int shape, hipStream_t st);
@@ -117,6 +121,8 @@ struct Plan : HostTables {
     int bp_bz = 0;
     // adjoint candidate pixel boxes per pass axis (tag: block shape)
     DevBuf cbox[3];
+    // zero-bordered sinogram of the sampler back-projection (tag: storage type)
+    DevBuf spad;
 
     ~Plan()
     {
@@ -131,6 +137,7 @@ struct Plan : HostTables {
         }
         g_keeper.free(acc);
         g_keeper.free(sacc);
+        g_keeper.free(spad);
     }
 };
 
@@ -649,7 +656,7 @@ int forward_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *si
 int forward_sampled_impl(const pn_geometry *pg, int64_t batch, const void *vol, void *sino, int32_t in_dt,
                          int32_t out_dt, int32_t source, int32_t wbits, hipStream_t st)
 {
-    if (source != PN_SAMPLE_BORDERED && source != PN_SAMPLE_VOLUME)
+    if (source != PN_SAMPLE_BORDERED && source != PN_SAMPLE_DIRECT)
         return fail(PN_EINVAL, "pn_forward_sampled: unknown source %d", source);
     if (wbits < 0 || wbits > 16) return fail(PN_EINVAL, "pn_forward_sampled: weight_bits %d outside [0, 16]", wbits);
     Geo pre;
@@ -717,6 +724,61 @@ int forward_sampled_impl(const pn_geometry *pg, int64_t batch, const void *vol, 
     if (forward_sampled_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
     hipError_t e = launch_forward_sampled(p, in_dt, out_dt, st);
     return e == hipSuccess ? PN_OK : fail_hip(e, "sampled forward launch");
+}
+
+// The voxel-driven back-projection with sampler interpolation: every
+// detector tap gathered through the caches from a zero-bordered copy of the
+// sinogram (rows and columns padded by 1 before and 2 after) or from the
+// caller's sinogram with checked taps.
+int backproject_sampled_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt,
+                             int32_t out_dt, int32_t source, int32_t wbits, hipStream_t st)
+{
+    if (source != PN_SAMPLE_BORDERED && source != PN_SAMPLE_DIRECT)
+        return fail(PN_EINVAL, "pn_backproject_sampled: unknown source %d", source);
+    if (wbits < 0 || wbits > 16)
+        return fail(PN_EINVAL, "pn_backproject_sampled: weight_bits %d outside [0, 16]", wbits);
+    Geo pre;
+    int rc = preflight(pg, batch, sino, vol, in_dt, out_dt, true, pre);
+    if (rc || batch == 0) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *pl;
+    if ((rc = get_plan(pg, st, &pl))) return rc;
+    const Geo &g = pl->g;
+    BpSampParams p{};
+    p.tabf = pl->d_tabf;
+    p.n_views = g.n_views;
+    p.nu = g.nu;
+    p.nv = g.nv;
+    p.batch = (int32_t)batch;
+    for (int a = 0; a < 3; ++a) p.n[a] = g.n[a];
+    p.weight_bits = wbits;
+    p.vol = vol;
+    // a call without views writes zeros and reads no image
+    p.bordered = source == PN_SAMPLE_BORDERED && g.n_views > 0;
+    if (p.bordered) {
+        p.row = g.nu + 3;
+        p.view = (int64_t)p.row * (g.nv + 3);
+        p.item = p.view * g.n_views;
+        p.org = (int64_t)p.row + 1;
+        if (p.view >= ((int64_t)1 << 31))
+            return fail(PN_EINVAL, "pn_backproject_sampled: padded view of %lld elements (limit 2^31 - 1)",
+                        (long long)p.view);
+        bool fresh;
+        const size_t need = (size_t)(p.item * batch * esize(in_dt));
+        if ((rc = ensure_buf(*pl, pl->spad, need, in_dt, true, st, "bordered sinogram", fresh))) return rc;
+        hipError_t e = launch_pad_sino(in_dt, sino, pl->spad.ptr, batch * g.n_views, g.nv, g.nu, p.row, p.view, st);
+        if (e != hipSuccess) return fail_hip(e, "sinogram border launch");
+        p.img = pl->spad.ptr;
+    } else {
+        p.row = g.nu;
+        p.view = (int64_t)g.nu * g.nv;
+        p.item = p.view * g.n_views;
+        p.org = 0;
+        p.img = sino;
+    }
+    if (backproject_sampled_blocks(p) > INT32_MAX) return fail(PN_EINVAL, "problem too large for one launch");
+    hipError_t e = launch_backproject_sampled(p, in_dt, out_dt, st);
+    return e == hipSuccess ? PN_OK : fail_hip(e, "sampled back-projection launch");
 }
 
 int adjoint_impl(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dt, int32_t out_dt,
@@ -1629,6 +1691,14 @@ int pn_forward_sampled(const pn_geometry *pg, int64_t batch, const void *vol, vo
     clear_error();
     return forward_sampled_impl(pg, batch, vol, sino, in_dtype, out_dtype, source, weight_bits,
                                 static_cast<hipStream_t>(hip_stream));
+}
+
+int pn_backproject_sampled(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dtype,
+                           int32_t out_dtype, int32_t source, int32_t weight_bits, void *hip_stream)
+{
+    clear_error();
+    return backproject_sampled_impl(pg, batch, sino, vol, in_dtype, out_dtype, source, weight_bits,
+                                    static_cast<hipStream_t>(hip_stream));
 }
 
 int pn_adjoint(const pn_geometry *pg, int64_t batch, const void *sino, void *vol, int32_t in_dtype,

@@ -5,6 +5,7 @@ call into the native library, which runs the gfx950 kernels:
 
   forward(vol, geom)      A     -> pn_forward
   forward_sampled(...)    A     -> pn_forward_sampled (sampler interpolation)
+  backproject_sampled(...)      -> pn_backproject_sampled (sampler interpolation)
   adjoint(sino, geom)     A^T   -> pn_adjoint
   backproject(sino, geom)       -> pn_backproject (voxel-driven, (W0/W)^2)
   splat(vol, geom)        B^T   -> pn_splat (transpose of the back-projection)
@@ -66,14 +67,14 @@ def forward(vol, geom: Geometry, out_dtype=None):
     return _run(N.lib.pn_forward, "pn_forward", geom, vol, geom.vol_shape, geom.sino_shape(), out_dtype)
 
 
-_SOURCES = {"bordered": 0, "volume": 1}
+_SOURCES = {"bordered": 0, "direct": 1}
 
 
 def forward_sampled(vol, geom: Geometry, source="bordered", weight_bits=0, out_dtype=None):
     """A vol with sampler interpolation (pn_forward_sampled): every bilinear
     tap is a separate load through the caches, from zero-bordered copies of
     the volume (``source="bordered"``, extra device memory, no bounds
-    checks) or from ``vol`` itself (``"volume"``, no extra memory).
+    checks) or from ``vol`` itself (``"direct"``, no extra memory).
     ``weight_bits`` = B > 0 rounds the interpolation weights to multiples of
     2^-B, as fixed-function filtering hardware does; 0 keeps FP32 weights
     (then the result matches ``forward`` to FP32 rounding)."""
@@ -103,6 +104,22 @@ def adjoint_noalloc(sino, geom: Geometry, out_dtype=None):
 def backproject(sino, geom: Geometry, out_dtype=None):
     """Voxel-driven (W0/W)^2-weighted back-projection: sino -> volume."""
     return _run(N.lib.pn_backproject, "pn_backproject", geom, sino, geom.sino_shape(), geom.vol_shape, out_dtype)
+
+
+def backproject_sampled(sino, geom: Geometry, source="bordered", weight_bits=0, out_dtype=None):
+    """Back-projection with sampler interpolation (pn_backproject_sampled):
+    every bilinear detector tap a separate load through the caches, from a
+    zero-bordered copy of the sinogram (``source="bordered"``, extra device
+    memory) or from ``sino`` itself (``"direct"``: the caller's data, no
+    extra memory).  ``weight_bits`` as ``forward_sampled``."""
+    if source not in _SOURCES:
+        raise ValueError(f"source must be one of {sorted(_SOURCES)}")
+    src, bits = _SOURCES[source], int(weight_bits)
+
+    def fn(g, b, x, o, dti, dto, st):
+        return N.lib.pn_backproject_sampled(g, b, x, o, dti, dto, src, bits, st)
+
+    return _run(fn, "pn_backproject_sampled", geom, sino, geom.sino_shape(), geom.vol_shape, out_dtype)
 
 
 def splat(vol, geom: Geometry, out_dtype=None):
@@ -309,14 +326,14 @@ class BatchPlan:
 # --------------------------------------------------------------- autograd --
 
 
-_INTERP = {"staged": None, "sampler": "bordered", "sampler-volume": "volume"}
+_INTERP = {"staged": None, "sampler": "bordered", "sampler-direct": "direct"}
 
 
 class Projection(torch.autograd.Function):
     """y = A x; dL/dx = A^T dL/dy (the adjoint kernel).
 
     ``interp`` picks how A interpolates: "staged" (the default, volume tiles
-    staged through LDS), "sampler" or "sampler-volume" (``forward_sampled``
+    staged through LDS), "sampler" or "sampler-direct" (``forward_sampled``
     from the bordered copies or from the volume itself, ``weight_bits`` as
     there).  The gradient is the exact adjoint of A with FP32 weights in
     every case; with weight_bits > 0 it is therefore the adjoint of the
@@ -353,17 +370,23 @@ class AdjointProjection(torch.autograd.Function):
 
 class BackProjection(torch.autograd.Function):
     """x = B q (voxel-driven back-projection); dL/dq = B^T dL/dx (the splat
-    projector)."""
+    projector).  ``interp`` and ``weight_bits`` as ``Projection`` (the
+    sampler variants are ``backproject_sampled``); the gradient is the
+    transpose of B with FP32 weights in every case."""
 
     @staticmethod
-    def forward(ctx, sino, geom):
+    def forward(ctx, sino, geom, interp="staged", weight_bits=0):
+        if interp not in _INTERP:
+            raise ValueError(f"interp must be one of {sorted(_INTERP)}")
         ctx.geom = geom
         ctx.sino_dtype = sino.dtype
-        return backproject(sino, geom)
+        if _INTERP[interp] is None:
+            return backproject(sino, geom)
+        return backproject_sampled(sino, geom, _INTERP[interp], weight_bits)
 
     @staticmethod
     def backward(ctx, grad):
-        return splat(grad.contiguous(), ctx.geom, out_dtype=ctx.sino_dtype), None
+        return splat(grad.contiguous(), ctx.geom, out_dtype=ctx.sino_dtype), None, None, None
 
 
 class SplatProjection(torch.autograd.Function):
@@ -411,19 +434,23 @@ class ConeProjection3D(_ProjLayer):
     pass
 
 
-class ParallelBackProjection2D(_Layer):
+class _BackProjLayer(_ProjLayer):
+    """A back-projection layer; ``interp`` and ``weight_bits`` as ``Projection``."""
+
     def forward(self, y):
-        return BackProjection.apply(y, self.geom)
+        return BackProjection.apply(y, self.geom, self.interp, self.weight_bits)
 
 
-class FanBackProjection2D(_Layer):
-    def forward(self, y):
-        return BackProjection.apply(y, self.geom)
+class ParallelBackProjection2D(_BackProjLayer):
+    pass
 
 
-class ConeBackProjection3D(_Layer):
-    def forward(self, y):
-        return BackProjection.apply(y, self.geom)
+class FanBackProjection2D(_BackProjLayer):
+    pass
+
+
+class ConeBackProjection3D(_BackProjLayer):
+    pass
 
 
 def unrolled_gd(x0, y, geom: Geometry, alpha: float, steps: int, checkpoint: bool = True):

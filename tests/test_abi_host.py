@@ -124,6 +124,14 @@ def test_entry_points_validate_before_device_work(pn, N):
     assert fs(g, 1, None, q, 0, 0, 0, 0, None) == N.PN_EINVAL
     assert fs(g, 1, p, p, 0, 0, 1, 0, None) == N.PN_EINVAL
     assert fs(g, 0, None, None, 0, 0, 1, 16, None) == 0  # empty batch: nothing to do
+    bs = N.lib.pn_backproject_sampled
+    assert bs(g, 1, p, q, 0, 0, 5, 0, None) == N.PN_EINVAL
+    assert "source" in N.last_error()
+    assert bs(g, 1, p, q, 0, 0, 1, 17, None) == N.PN_EINVAL
+    assert "weight_bits" in N.last_error()
+    assert bs(g, 1, p, q, 0, 7, 0, 0, None) == N.PN_EDTYPE
+    assert bs(g, 1, p, None, 0, 0, 0, 0, None) == N.PN_EINVAL
+    assert bs(g, 0, None, None, 0, 0, 0, 3, None) == 0
     # the row filter: kind, dtypes, pointers, then its own limits
     f = N.lib.pn_filter
     assert f(g, 1, p, q, 0, 0, 2, None) == N.PN_EINVAL

@@ -68,7 +68,7 @@ def test_sampler_fp32_weights_match_oracle(pn, name):
     x = gpu(np.stack(vols))
     ref = np.stack([O.forward(v, go) for v in vols])
     yb = pn.forward_sampled(x, gp, "bordered")
-    yv = pn.forward_sampled(x, gp, "volume")
+    yv = pn.forward_sampled(x, gp, "direct")
     torch.cuda.synchronize()
     assert rel(cpu(yb), ref) <= TOL32, rel(cpu(yb), ref)
     assert torch.equal(yb, yv)
@@ -82,11 +82,11 @@ def test_sampler_16bit_storage(pn, dt):
     gp, go, vols = P.make_case(pn, "cone3d_ragged")
     x = gpu(np.stack(vols), dt)
     ref = np.stack([O.forward(v, go) for v in vols])
-    for src in ("bordered", "volume"):
+    for src in ("bordered", "direct"):
         y = pn.forward_sampled(x, gp, src)
         assert y.dtype == dt
         assert rel(cpu(y), ref) <= TOL16
-    y32 = pn.forward_sampled(x, gp, "volume", out_dtype=torch.float32)
+    y32 = pn.forward_sampled(x, gp, "direct", out_dtype=torch.float32)
     # FP32 output of a 16-bit volume: the oracle of the rounded volume
     ref_r = np.stack([O.forward(v, go) for v in cpu(x)])
     assert rel(cpu(y32), ref_r) <= TOL32
@@ -142,7 +142,7 @@ def test_rounded_weights_tie_free_geometry(pn, bits):
     x = gpu(vols)
     ref_q = np.stack([O.forward(v, go, weight_bits=bits) for v in vols])
     ref = np.stack([O.forward(v, go) for v in vols])
-    for src in ("bordered", "volume"):
+    for src in ("bordered", "direct"):
         y = cpu(pn.forward_sampled(x, gp, src, weight_bits=bits))
         assert rel(y, ref_q) <= TOL32, (src, rel(y, ref_q))
         assert rel(y, ref) > 10 * TOL32  # the rounding is there
@@ -167,7 +167,7 @@ def test_rounded_weights_exact_ties_round_upward(pn):
     expect = ((1 - wy) * (1 - wz) * pad[:-1, :-1] + wy * (1 - wz) * pad[:-1, 1:] + (1 - wy) * wz * pad[1:, :-1]
               + wy * wz * pad[1:, 1:])
     assert np.abs(O.forward(vol, go, weight_bits=3)[0] - expect).max() < 1e-12
-    for src in ("bordered", "volume"):
+    for src in ("bordered", "direct"):
         y = cpu(pn.forward_sampled(gpu(vol), gp, src, weight_bits=3))[0]
         assert np.abs(y - expect).max() <= 1e-5 * np.abs(expect).max(), src
 
@@ -183,7 +183,7 @@ def test_rounded_weights_general_geometry(pn, name, bits):
     ref = np.stack([O.forward(v, go) for v in vols])
     ref_q = np.stack([O.forward(v, go, weight_bits=bits) for v in vols])
     yb = pn.forward_sampled(x, gp, "bordered", weight_bits=bits)
-    yv = pn.forward_sampled(x, gp, "volume", weight_bits=bits)
+    yv = pn.forward_sampled(x, gp, "direct", weight_bits=bits)
     assert torch.equal(yb, yv)
     y = cpu(yb)
     effect = rel(ref_q, ref)
@@ -205,7 +205,7 @@ def test_sampler_full_size_cone256_sampled(pn):
     n = 3000
     view, row, col = rng.integers(0, 360, n), rng.integers(0, 512, n), rng.integers(0, 512, n)
     ref = O.forward_rays(vol, go, view, row, col)
-    for src in ("bordered", "volume"):
+    for src in ("bordered", "direct"):
         _say(f"full-size cone 256^3 x 360: sampler ({src})")
         y = pn.forward_sampled(x, gp, src).cpu().numpy()
         assert rel(y[view, row, col], ref) <= TOL32
@@ -230,7 +230,7 @@ def test_sampler_layer_and_gradient(pn):
     _say("ConeProjection3D(interp='sampler'): values and gradient")
     gp, go, vols = P.make_case(pn, "cone3d_anisotropic")
     x = gpu(np.stack(vols)).requires_grad_(True)
-    for interp, src in (("sampler", "bordered"), ("sampler-volume", "volume")):
+    for interp, src in (("sampler", "bordered"), ("sampler-direct", "direct")):
         layer = pn.ConeProjection3D(gp, interp=interp, weight_bits=8)
         y = layer(x)
         assert torch.equal(y.detach(), pn.forward_sampled(x.detach(), gp, src, weight_bits=8))
@@ -244,7 +244,7 @@ def test_sampler_edge_cases_and_errors(pn):
     _say("sampler edge cases")
     shp = (8, 8, 8)
     g = pn.cone_geometry(shp, (1.0, 1.0, 1.0), (6, 6), (1.0, 1.0), 5, 100.0, 160.0, vol_origin=(200.0, 0.0, 0.0))
-    for src in ("bordered", "volume"):
+    for src in ("bordered", "direct"):
         y = pn.forward_sampled(torch.ones((1,) + shp, device="cuda"), g, src, weight_bits=3)
         assert float(y.abs().max()) == 0.0
     g0 = pn.Geometry(3, "cone", shp, (1.0,) * 3, (6, 6), np.zeros((0, 3, 4)))
@@ -253,10 +253,138 @@ def test_sampler_edge_cases_and_errors(pn):
     g1 = pn.cone_geometry((1, 1, 1), (1.0, 1.0, 1.0), (1, 1), (1.0, 1.0), 4, 50.0, 80.0)
     go1 = O.circular_cone((1, 1, 1), (1.0, 1.0, 1.0), (1, 1), (1.0, 1.0), 4, 2 * math.pi, 50.0, 80.0)
     v = np.full((1, 1, 1), 2.5)
-    for src in ("bordered", "volume"):
+    for src in ("bordered", "direct"):
         assert rel(cpu(pn.forward_sampled(gpu(v), g1, src)), O.forward(v, go1)) <= TOL32
     with pytest.raises(ValueError):
         pn.forward_sampled(torch.ones(shp, device="cuda"), g, "texture")
     for bad in (-1, 17):
         with pytest.raises(pn.PnError):
-            pn.forward_sampled(torch.ones(shp, device="cuda"), g, "volume", weight_bits=bad)
+            pn.forward_sampled(torch.ones(shp, device="cuda"), g, "direct", weight_bits=bad)
+
+
+# ------------------------------------------------ sampler back-projection --
+
+
+def _sino_case(pn, name):
+    gp, go, vols = P.make_case(pn, name)
+    q = np.stack([O.forward(v, go) for v in vols]).astype(np.float32).astype(np.float64)
+    return gp, go, q
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_bp_sampler_fp32_weights_match_oracle(pn, name):
+    _say(f"{name}: sampler back-projection, FP32 weights")
+    gp, go, q = _sino_case(pn, name)
+    y = gpu(q)
+    ref = np.stack([O.backproject(qq, go) for qq in q])
+    bb = pn.backproject_sampled(y, gp, "bordered")
+    bd = pn.backproject_sampled(y, gp, "direct")
+    torch.cuda.synchronize()
+    assert rel(cpu(bb), ref) <= TOL32, rel(cpu(bb), ref)
+    assert torch.equal(bb, bd)
+    assert rel(cpu(bb), cpu(pn.backproject(y, gp))) <= TOL32
+
+
+@pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16])
+def test_bp_sampler_16bit_storage(pn, dt):
+    _say(f"cone3d_ragged: sampler back-projection, {dt} storage")
+    gp, go, q = _sino_case(pn, "cone3d_ragged")
+    y = gpu(q, dt)
+    ref_r = np.stack([O.backproject(qq, go) for qq in cpu(y)])
+    for src in ("bordered", "direct"):
+        b = pn.backproject_sampled(y, gp, src, out_dtype=torch.float32)
+        assert rel(cpu(b), ref_r) <= TOL32
+    b16 = pn.backproject_sampled(y, gp, "bordered")
+    assert b16.dtype == dt and rel(cpu(b16), ref_r) <= TOL16
+
+
+def test_bp_rounded_weights_exact_ties_round_upward(pn):
+    """Rays along +x onto a panel shifted by (3/16, 5/16) pixel: every
+    voxel projects exactly onto ties of the 2^-3 lattice (fractions 13/16
+    and 11/16), which round up to 7/8 and 6/8."""
+    _say("sampler back-projection, exact rounding ties")
+    shape, det = (6, 7, 8), (6, 7)
+    d, C, eu, ev = [1.0, 0, 0], [0, 3 / 16, 5 / 16], [0, 1.0, 0], [0, 0, 1.0]
+    gp = pn.Geometry(3, "parallel", shape, (1.0, 1.0, 1.0), det, pn.parallel3d_matrices(
+        np.array([d]), np.array([C]), np.array([eu]), np.array([ev]), det))
+    img = np.random.default_rng(20).random(det)
+    pad = np.pad(img, ((1, 0), (1, 0)))
+    for bits, (wu, wv) in ((3, (7 / 8, 6 / 8)), (0, (13 / 16, 11 / 16))):
+        col = (1 - wu) * pad[:, :-1] + wu * pad[:, 1:]
+        expect = np.broadcast_to(((1 - wv) * col[:-1, :] + wv * col[1:, :])[:, :, None], shape)
+        for src in ("bordered", "direct"):
+            got = cpu(pn.backproject_sampled(gpu(img[None]), gp, src, weight_bits=bits))
+            assert np.abs(got - expect).max() <= 1e-5 * np.abs(expect).max(), (bits, src)
+
+
+@pytest.mark.parametrize("name,bits", [("cone3d_ragged", 8), ("fan2d_ragged", 6), ("cone3d_anisotropic", 4)])
+def test_bp_rounded_weights_general_geometry(pn, name, bits):
+    """The flip bound of the module docstring, for detector positions U/W."""
+    _say(f"{name}: sampler back-projection, weight_bits {bits}")
+    gp, go, _ = _sino_case(pn, name)
+    rng = np.random.default_rng(33)
+    q = rng.random((1,) + gp.sino_shape())
+    ref = O.backproject(q[0], go)
+    ref_q = O.backproject(q[0], go, weight_bits=bits)
+    bb = pn.backproject_sampled(gpu(q), gp, "bordered", weight_bits=bits)
+    assert torch.equal(bb, pn.backproject_sampled(gpu(q), gp, "direct", weight_bits=bits))
+    y = cpu(bb)[0]
+    effect = rel(ref_q, ref)
+    assert effect > 10 * TOL32
+    assert rel(y, ref_q) <= 0.5 * effect, (rel(y, ref_q), effect)
+    assert abs(rel(y, ref) / effect - 1.0) <= 0.2
+    _say(f"{name}: BP B={bits} rounding error vs B {rel(y, ref):.3e} (oracle {effect:.3e}), "
+         f"GPU vs rounded oracle {rel(y, ref_q):.3e}")
+
+
+def test_bp_sampler_full_size_cone256_sampled(pn):
+    cfg = W.CONFIGS["cone3d_256"]
+    shp, sp, det, ds = cfg["vol_shape"], cfg["vol_spacing"], cfg["det_shape"], cfg["det_spacing"]
+    gp = pn.cone_geometry(shp, sp, det, ds, cfg["n_views"], cfg["sid"], cfg["sdd"])
+    go = O.circular_cone(shp, sp, det, ds, cfg["n_views"], cfg["angular_range"], cfg["sid"], cfg["sdd"])
+    vol = W.ellipsoid_phantom_3d(cfg["seeds"][0], shp, sp, cfg["n_ellipsoids"])[0]
+    y = pn.forward(gpu(vol), gp)
+    yc = y.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(125)
+    i, j, k = rng.integers(0, 256, 1500), rng.integers(0, 256, 1500), rng.integers(0, 256, 1500)
+    ref = O.backproject_voxels(yc, go, i, j, k)
+    for src in ("bordered", "direct"):
+        _say(f"full-size cone 256^3 x 360: sampler back-projection ({src})")
+        b = pn.backproject_sampled(y, gp, src).cpu().numpy()
+        assert rel(b[k, j, i], ref) <= TOL32
+
+
+def test_bp_sampler_layer_and_gradient(pn):
+    _say("ConeBackProjection3D(interp='sampler'): values and gradient")
+    gp, go, q = _sino_case(pn, "cone3d_anisotropic")
+    y = gpu(q).requires_grad_(True)
+    for interp, src in (("sampler", "bordered"), ("sampler-direct", "direct")):
+        layer = pn.ConeBackProjection3D(gp, interp=interp, weight_bits=8)
+        x = layer(y)
+        assert torch.equal(x.detach(), pn.backproject_sampled(y.detach(), gp, src, weight_bits=8))
+        g = torch.rand_like(x)
+        (x * g).sum().backward()
+        # the splat adds with float atomics: equal up to FP32 rounding
+        assert rel(cpu(y.grad), cpu(pn.splat(g, gp))) <= 1e-6
+        y.grad = None
+
+
+def test_bp_sampler_edge_cases_and_errors(pn):
+    _say("sampler back-projection edge cases")
+    shp = (8, 8, 8)
+    g0 = pn.Geometry(3, "cone", shp, (1.0,) * 3, (6, 6), np.zeros((0, 3, 4)))
+    for src in ("bordered", "direct"):
+        z = pn.backproject_sampled(torch.zeros((1,) + g0.sino_shape(), device="cuda"), g0, src)
+        assert z.shape == (1,) + shp and float(z.abs().max()) == 0.0
+    g = pn.cone_geometry(shp, (1.0, 1.0, 1.0), (6, 6), (1.0, 1.0), 5, 100.0, 160.0)
+    assert pn.backproject_sampled(torch.ones((0,) + g.sino_shape(), device="cuda"), g).shape[0] == 0
+    g1 = pn.cone_geometry((1, 1, 1), (1.0, 1.0, 1.0), (1, 1), (1.0, 1.0), 4, 50.0, 80.0)
+    go1 = O.circular_cone((1, 1, 1), (1.0, 1.0, 1.0), (1, 1), (1.0, 1.0), 4, 2 * math.pi, 50.0, 80.0)
+    s1 = np.full((4, 1, 1), 1.5)
+    for src in ("bordered", "direct"):
+        assert rel(cpu(pn.backproject_sampled(gpu(s1), g1, src)), O.backproject(s1, go1)) <= TOL32
+    with pytest.raises(ValueError):
+        pn.backproject_sampled(torch.ones(g.sino_shape(), device="cuda"), g, "texture")
+    for bad in (-1, 17):
+        with pytest.raises(pn.PnError):
+            pn.backproject_sampled(torch.ones(g.sino_shape(), device="cuda"), g, "direct", weight_bits=bad)
