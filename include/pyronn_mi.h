@@ -21,6 +21,13 @@
  *                   the third homogeneous coordinate of the voxel centre and
  *                   W0 that of the world origin.
  *
+ * Besides them: the splat projector (pn_splat, the back-projection's
+ * transpose), sampler-interpolation variants of A and of the back-projection
+ * (pn_forward_sampled, pn_backproject_sampled: the texture path of Sec. 2.1
+ * written out for a GPU without texture samplers), the FBP/FDK row filter,
+ * sinogram artifact simulation, batched calls and batch plans, the
+ * allocation-free adjoint and the trajectory helpers.
+ *
  * Geometry follows the paper's description (Listing 1 and Sec. 2.1/2.3):
  * volume shape and spacing, detector shape and spacing, SID/SDD, and one
  * projection matrix per view for arbitrary trajectories (calibrated matrices
