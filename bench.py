@@ -281,6 +281,10 @@ def main():
     t_adj, t_adj_mean = timed(lambda: pn.adjoint(y, geom), reps, stream)
     t_bp, _ = timed(lambda: pn.backproject(y, geom), reps, stream)
     log(f"A {t_fwd:.3f} ms, AT {t_adj:.3f} ms, BP {t_bp:.3f} ms")
+    # the back-projection's transpose (its gradient), volume -> sinogram
+    bpv = pn.backproject(y, geom)
+    t_splat, _ = timed(lambda: pn.splat(bpv, geom), reps, stream)
+    log(f"splat (BP transpose) {t_splat:.3f} ms")
     # FDK: the row filter (a direct linear convolution, nu^2 multiply-adds
     # per detector row) followed by the back-projection
     t_filt, _ = timed(lambda: pn.fbp_filter(y, geom), reps, stream)
@@ -319,6 +323,8 @@ def main():
         "forward_ms": t_fwd,
         "adjoint_ms": t_adj,
         "backproject_ms": t_bp,
+        "splat_ms": t_splat,
+        "splat_gups": upd / (t_splat * 1e-3) / 1e9,
         "fdk_filter_ms": t_filt,
         "fdk_filter_shepp_logan_ms": t_filt_sl,
         "fdk_filter_shepp_logan_tflops": filt_flop / (t_filt_sl * 1e-3) / 1e12,

@@ -1598,14 +1598,21 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
     const float fnu = static_cast<float>(p.nu), fnv = static_cast<float>(p.nv);
     float *sino = p.sino + static_cast<int64_t>(b) * p.n_views * p.nv * p.nu;
 
-    // the thread's voxel values, the block's max |x| and its sum of |x|
+    // the thread's voxel values, the block's max |x| and its sum of |x|.
+    // Register z of a thread holds the voxel at height (z + skew) mod BZ of
+    // its column, the skew varying with i and j: voxels on one ray (along x,
+    // y or a diagonal) that the lanes of a wave deposit in the same step then
+    // sit at different heights, so their taps fall on different detector
+    // rows rather than on one LDS cell (same-address atomics serialise).
+    static_assert((BZ & (BZ - 1)) == 0, "power-of-two column");
+    const int skew = (i + 5 * j) & (BZ - 1);
     float x[BZ];
     uint32_t mbits = 0u;
     float asum = 0.0f;
     const S *vol = static_cast<const S *>(p.vol) + static_cast<int64_t>(b) * p.n[0] * p.n[1] * static_cast<int64_t>(p.n[2]);
 #pragma unroll
     for (int z = 0; z < BZ; ++z) {
-        const int k = k0 + z;
+        const int k = k0 + ((z + skew) & (BZ - 1));
         x[z] = (own && k <= k1) ? to_f32(vol[(static_cast<int64_t>(k) * p.n[1] + j) * p.n[0] + i]) : 0.0f;
         mbits = max(mbits, __float_as_uint(fabsf(x[z])));
         asum += fabsf(x[z]);
@@ -1721,7 +1728,7 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
 #pragma unroll
                     for (int z = 0; z < BZ; ++z) {
                         if (x[z] == 0.0f) continue;
-                        const float fz = static_cast<float>(z);
+                        const float fz = static_cast<float>((z + skew) & (BZ - 1));
                         const float rw = __builtin_amdgcn_rcpf(column ? Wb : fmaf(fz, tf.Pi[10], Wb));
                         const float u = __builtin_amdgcn_fmed3f(fmaf(column ? U0 : fmaf(fz, tf.Pi[2], U0), rw, -uo), lu, hu);
                         const float v = __builtin_amdgcn_fmed3f(fmaf(fmaf(fz, tf.Pi[6], V0), rw, -vo), lv, hv);
@@ -1741,7 +1748,7 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
 #pragma unroll 1
                     for (int z = 0; z < BZ; ++z) {
                         if (x[z] == 0.0f) continue;
-                        const float fz = static_cast<float>(z);
+                        const float fz = static_cast<float>((z + skew) & (BZ - 1));
                         const float Wc = fmaf(fz, tf.Pi[10], Wb);
                         const float rw = 1.0f / Wc;
                         const float u = fminf(fmaxf(fmaf(fz, tf.Pi[2], U0) * rw, -2.0f), fnu + 1.0f);
