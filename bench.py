@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--profile-sampler", action="store_true",
                     help="run one staged forward and back-projection and one sampler-interpolation forward "
                          "and back-projection per image only (for counter collection)")
+    ap.add_argument("--profile-splat", action="store_true",
+                    help="run the splat of the back-projected sinogram twice only (for counter collection)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-problem batched variant")
     ap.add_argument("--unrolled512", action="store_true",
                     help="also time the 512^3 x 720 unrolled 10-step reconstruction (FP32 and BF16 storage)")
@@ -251,6 +253,13 @@ def main():
         pn.backproject_sampled(y, geom, "direct")
         torch.cuda.synchronize()
         log("profile-sampler: staged and sampler forward and back-projection done")
+        return
+    if args.profile_splat:
+        bpv = pn.backproject(pn.forward(x, geom), geom)
+        pn.splat(bpv, geom)
+        pn.splat(bpv, geom)
+        torch.cuda.synchronize()
+        log("profile-splat: two splats of the back-projected sinogram done")
         return
     if args.profile_once:
         y, _ = step()

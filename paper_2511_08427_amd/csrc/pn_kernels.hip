@@ -655,6 +655,12 @@ __device__ __forceinline__ int round_fixed(float x)
     return r;
 }
 
+// A value known to be the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform_f32(float x)
+{
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x)));
+}
+
 // Wave-wide helpers for the adjoint's ray-list compaction.  They are called
 // with every lane of the wave active.
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
@@ -1604,8 +1610,11 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
     // y or a diagonal) that the lanes of a wave deposit in the same step then
     // sit at different heights, so their taps fall on different detector
     // rows rather than on one LDS cell (same-address atomics serialise).
+    // Neighbours along x differ by 3 heights and along y by 5 (about 2.4
+    // and 4 detector rows at a magnification near 1), and with the odd row
+    // stride of the rectangle the lanes' cells spread over the LDS banks.
     static_assert((BZ & (BZ - 1)) == 0, "power-of-two column");
-    const int skew = (i + 5 * j) & (BZ - 1);
+    const int skew = (3 * i + 5 * j) & (BZ - 1);
     float x[BZ];
     uint32_t mbits = 0u;
     float asum = 0.0f;
@@ -1709,14 +1718,25 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
             const int4 now = rect_at(vi);
             const float scale = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(s_scale[vi])));
             if (own && (now.w & 1)) {
+                // the view's table entries, uniform over the workgroup, held in
+                // scalar registers (one load per view, none per deposit)
                 const ViewTabF &tf = p.tabf[view];
+                float pi[12];
+#pragma unroll
+                for (int m = 0; m < 12; ++m) pi[m] = uniform_f32(tf.Pi[m]);
+                const float W0 = uniform_f32(tf.W0);
                 const float uo = static_cast<float>(now.x), vo = static_cast<float>(now.y);
                 const int nc = now.z & 0xffff, nr = now.z >> 16;
                 float *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
-                const bool column = BZ > 1 && tf.Pi[2] == 0.0f && tf.Pi[10] == 0.0f;
-                const float U0 = fmaf(tf.Pi[0], fi, fmaf(tf.Pi[1], fj, fmaf(tf.Pi[2], fk0, tf.Pi[3])));
-                const float V0 = fmaf(tf.Pi[4], fi, fmaf(tf.Pi[5], fj, fmaf(tf.Pi[6], fk0, tf.Pi[7])));
-                const float Wb = fmaf(tf.Pi[8], fi, fmaf(tf.Pi[9], fj, fmaf(tf.Pi[10], fk0, tf.Pi[11])));
+                const float U0 = fmaf(pi[0], fi, fmaf(pi[1], fj, fmaf(pi[2], fk0, pi[3])));
+                const float V0 = fmaf(pi[4], fi, fmaf(pi[5], fj, fmaf(pi[6], fk0, pi[7])));
+                const float Wb = fmaf(pi[8], fi, fmaf(pi[9], fj, fmaf(pi[10], fk0, pi[11])));
+                // height (z + skew) mod BZ of register z as 16 fract(skew/BZ +
+                // z/BZ): the sum is exact (multiples of 1/BZ below 2), so is the
+                // fraction, and the factor BZ is folded into the coefficients
+                // it multiplies (exact power-of-two scaling)
+                const float fsk = static_cast<float>(skew) * (1.0f / BZ);
+                auto height = [&](int z) { return __builtin_amdgcn_fractf(fsk + static_cast<float>(z) * (1.0f / BZ)); };
                 if (now.w & 2) {
                     // positions relative to the rectangle, clamped to it as in
                     // the back-projection (a clamped position deposits only
@@ -1724,24 +1744,54 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
                     const float hu = fminf(fnu - uo, static_cast<float>(nc - 1) - 1e-3f);
                     const float hv = fminf(fnv - vo, static_cast<float>(nr - 1) - 1e-3f);
                     const float lu = fmaxf(-1.0f - uo, 0.0f), lv = fmaxf(-1.0f - vo, 0.0f);
+                    const float wsc = W0 * W0 * scale;
                     int *acc = s_acc[buf];
+                    if (BZ > 1 && pi[2] == 0.0f && pi[10] == 0.0f) {
+                        // column path, the back-projection's: u and W fixed,
+                        // v linear in the height
+                        const float Uc = fmaf(pi[0], fi, fmaf(pi[1], fj, pi[3]));
+                        const float Wc = fmaf(pi[8], fi, fmaf(pi[9], fj, pi[11]));
+                        const float rw = __builtin_amdgcn_rcpf(Wc);
+                        const float u = __builtin_amdgcn_fmed3f(fmaf(Uc, rw, -uo), lu, hu);
+                        const float wu = __builtin_amdgcn_fractf(u);
+                        int *col = acc + static_cast<int>(u);
+                        const float dv = pi[6] * rw, v0 = fmaf(V0, rw, -vo);
+                        const float dvb = dv * static_cast<float>(BZ);
+                        const float w2 = rw * rw * wsc;
 #pragma unroll
-                    for (int z = 0; z < BZ; ++z) {
-                        if (x[z] == 0.0f) continue;
-                        const float fz = static_cast<float>((z + skew) & (BZ - 1));
-                        const float rw = __builtin_amdgcn_rcpf(column ? Wb : fmaf(fz, tf.Pi[10], Wb));
-                        const float u = __builtin_amdgcn_fmed3f(fmaf(column ? U0 : fmaf(fz, tf.Pi[2], U0), rw, -uo), lu, hu);
-                        const float v = __builtin_amdgcn_fmed3f(fmaf(fmaf(fz, tf.Pi[6], V0), rw, -vo), lv, hv);
-                        const float wu = __builtin_amdgcn_fractf(u), wv = __builtin_amdgcn_fractf(v);
-                        const float w = tf.W0 * rw;
-                        const float qs = x[z] * (w * w) * scale;
-                        const float t1 = qs * wv, t0 = qs - t1;
-                        const float c01 = t0 * wu, c11 = t1 * wu;
-                        int *q = acc + __mul24(static_cast<int>(v), CCAP) + static_cast<int>(u);
-                        atomicAdd(q, round_fixed(t0 - c01));
-                        atomicAdd(q + 1, round_fixed(c01));
-                        atomicAdd(q + CCAP, round_fixed(t1 - c11));
-                        atomicAdd(q + CCAP + 1, round_fixed(c11));
+                        for (int z = 0; z < BZ; ++z) {
+                            if (x[z] == 0.0f) continue;
+                            const float v = __builtin_amdgcn_fmed3f(fmaf(height(z), dvb, v0), lv, hv);
+                            const float wv = __builtin_amdgcn_fractf(v);
+                            const float qs = x[z] * w2;
+                            const float t1 = qs * wv, t0 = qs - t1;
+                            const float c01 = t0 * wu, c11 = t1 * wu;
+                            int *q = col + __mul24(static_cast<int>(v), CCAP);
+                            atomicAdd(q, round_fixed(t0 - c01));
+                            atomicAdd(q + 1, round_fixed(c01));
+                            atomicAdd(q + CCAP, round_fixed(t1 - c11));
+                            atomicAdd(q + CCAP + 1, round_fixed(c11));
+                        }
+                    } else {
+                        const float p2 = pi[2] * static_cast<float>(BZ), p6 = pi[6] * static_cast<float>(BZ);
+                        const float p10 = pi[10] * static_cast<float>(BZ);
+#pragma unroll
+                        for (int z = 0; z < BZ; ++z) {
+                            if (x[z] == 0.0f) continue;
+                            const float hz = height(z);
+                            const float rw = __builtin_amdgcn_rcpf(fmaf(hz, p10, Wb));
+                            const float u = __builtin_amdgcn_fmed3f(fmaf(fmaf(hz, p2, U0), rw, -uo), lu, hu);
+                            const float v = __builtin_amdgcn_fmed3f(fmaf(fmaf(hz, p6, V0), rw, -vo), lv, hv);
+                            const float wu = __builtin_amdgcn_fractf(u), wv = __builtin_amdgcn_fractf(v);
+                            const float qs = x[z] * (rw * rw * wsc);
+                            const float t1 = qs * wv, t0 = qs - t1;
+                            const float c01 = t0 * wu, c11 = t1 * wu;
+                            int *q = acc + __mul24(static_cast<int>(v), CCAP) + static_cast<int>(u);
+                            atomicAdd(q, round_fixed(t0 - c01));
+                            atomicAdd(q + 1, round_fixed(c01));
+                            atomicAdd(q + CCAP, round_fixed(t1 - c11));
+                            atomicAdd(q + CCAP + 1, round_fixed(c11));
+                        }
                     }
                 } else {
                     // straight to the sinogram, bounds-checked, one atomic per tap
@@ -1749,14 +1799,14 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
                     for (int z = 0; z < BZ; ++z) {
                         if (x[z] == 0.0f) continue;
                         const float fz = static_cast<float>((z + skew) & (BZ - 1));
-                        const float Wc = fmaf(fz, tf.Pi[10], Wb);
-                        const float rw = 1.0f / Wc;
-                        const float u = fminf(fmaxf(fmaf(fz, tf.Pi[2], U0) * rw, -2.0f), fnu + 1.0f);
-                        const float v = fminf(fmaxf(fmaf(fz, tf.Pi[6], V0) * rw, -2.0f), fnv + 1.0f);
+                        const float Wz = fmaf(fz, pi[10], Wb);
+                        const float rw = 1.0f / Wz;
+                        const float u = fminf(fmaxf(fmaf(fz, pi[2], U0) * rw, -2.0f), fnu + 1.0f);
+                        const float v = fminf(fmaxf(fmaf(fz, pi[6], V0) * rw, -2.0f), fnv + 1.0f);
                         const float fu = floorf(u), fv = floorf(v);
                         const float wu = u - fu, wv = v - fv;
                         const int iu = static_cast<int>(fu), iv = static_cast<int>(fv);
-                        const float w = tf.W0 * rw;
+                        const float w = W0 * rw;
                         const float val = x[z] * w * w;
 #pragma unroll
                         for (int tv = 0; tv < 2; ++tv) {
@@ -2132,6 +2182,12 @@ hipError_t launch_backproject_table(const Table<BpParams> &w, uint32_t blocks, b
     return bp_any(w, two_d, blocks, in_dt, out_dt, st);
 }
 
+// The splat's rectangles: the back-projection's rows, an odd row stride of
+// 27 columns (27 x 4 bytes) so that the deposits of a wave, a few rows
+// apart, fall into different LDS banks (24 columns: 1.5x the time on cone
+// 256^3 x 360).
+constexpr int kSplatCols = 27;
+
 int64_t splat_blocks(const SplatParams &p)
 {
     const int64_t bz = p.n[2] == 1 ? 1 : (p.n[2] + kBpDepth - 1) / kBpDepth;
@@ -2144,7 +2200,7 @@ static hipError_t splat_s(const SplatParams &p, uint32_t blocks, hipStream_t st)
     if (p.n[2] == 1)
         splat_kernel<S, 1, 4, 64><<<dim3(blocks), 256, 0, st>>>(p);
     else
-        splat_kernel<S, kBpDepth, kBpRows, kBpCols><<<dim3(blocks), 256, 0, st>>>(p);
+        splat_kernel<S, kBpDepth, kBpRows, kSplatCols><<<dim3(blocks), 256, 0, st>>>(p);
     return hipGetLastError();
 }
 

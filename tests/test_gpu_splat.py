@@ -77,6 +77,35 @@ def test_splat_is_the_transpose_of_backproject_gpu(pn, name):
     assert abs(lhs - rhs) <= 1e-5 * scale, (lhs, rhs)
 
 
+@pytest.mark.parametrize("pix,sid,sdd,shp,det,tol", [
+    # 16^3 blocks project into 19-30 detector columns: some views' rectangles
+    # fit the LDS accumulator, the others deposit with float atomics
+    (0.65, 750.0, 1200.0, (32, 48, 48), (80, 100), TOL32),
+    # magnification 4: nearly every rectangle is too large for the LDS.  A
+    # voxel spans 8 pixels, so a pixel takes few taps per view and the FP32
+    # rounding of the tap positions does not average out: rounding the
+    # projection matrices alone (relative 2^-24) moves the FP64 oracle's
+    # result by 6-7e-6 here, and evaluating them in FP32 adds as much again
+    (0.5, 120.0, 480.0, (20, 30, 36), (120, 150), 3 * TOL32),
+])
+def test_splat_lds_and_direct_deposits(pn, pix, sid, sdd, shp, det, tol):
+    """Blocks whose detector rectangle exceeds the LDS accumulator take the
+    straight float-atomic path; both paths in one call match the oracle and
+    the transpose of pn_backproject."""
+    _say(f"rectangles pix={pix} sid={sid}")
+    sp = (0.5, 0.5, 0.5) if sid > 500 else (1.0, 1.0, 1.0)
+    gp = pn.cone_geometry(shp, sp, det, (pix, pix), 24, sid, sdd)
+    go = O.circular_cone(shp, sp, det, (pix, pix), 24, 2 * math.pi, sid, sdd)
+    rng = np.random.default_rng(12)
+    x = f32(W.ellipsoid_phantom_3d(8, shp, sp)[0] + 0.1 * rng.random(shp))
+    y = pn.splat(torch.from_numpy(x).float().cuda(), gp).double().cpu().numpy()
+    assert rel(y, O.splat(x, go)) <= tol
+    q = rng.standard_normal(gp.sino_shape()).astype(np.float32)
+    bq = pn.backproject(torch.from_numpy(q).cuda(), gp).double().cpu().numpy()
+    lhs, rhs = float(np.sum(bq * x)), float(np.sum(q * y))
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(bq) * np.linalg.norm(x), (lhs, rhs)
+
+
 @pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16])
 def test_splat_reduced_precision_storage(pn, dt):
     gp, go, vols = make_case(pn, "cone3d_ragged")
