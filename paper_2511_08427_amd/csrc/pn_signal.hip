@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "pn_common.hpp"
 #include "pn_device.hpp"
@@ -18,39 +19,44 @@ namespace pn {
 // row of the view's 3x3 matrix, d the ray from the source to the pixel,
 // q3 . d = 1) and the linear convolution with the discrete kernel g
 // (Ram-Lak: g[0] = 1/4, g[k] = -1/(pi^2 k^2) for odd k, 0 for even k;
-// Shepp-Logan: g[k] = -2 / (pi^2 (4 k^2 - 1))), times `scale`.  One wave
-// per row, the row and the kernel in LDS.  Each lane computes FR adjacent
-// outputs; per step of FR inputs it reads the inputs once (broadcast) and a
-// window of 2 FR - 1 kernel values, then does FR^2 FMAs, so the loop is
-// bound by the FMAs.
+// Shepp-Logan: g[k] = -2 / (pi^2 (4 k^2 - 1))), times `scale`.
+//
+// Per detector row this is a product with a Toeplitz matrix, out = scale Xw
+// G^T with Xw the cosine-weighted rows (rows x nu) and G[n][m] = g[n - m]
+// (nu x nu): a dense contraction of 2 rows nu^2 flops, run on the matrix
+// cores as v_mfma_f32_16x16x4_f32 (FP32 operands and accumulators).  A
+// workgroup owns 32 rows and up to 512 output columns; each of its four
+// waves 32 rows x 128 columns as 2 x 8 tiles of 16 x 16 (64 accumulators per
+// lane).  MFMA operand layout (lane l, i = l % 16, c = l / 16): A[i][c],
+// B[c][i]; the result D[4c + r][i] in register r.  The contraction runs over
+// the row's inputs in blocks of 16: a lane loads the 4 consecutive inputs
+// x[m0 + 4c .. m0 + 4c + 3] of each of its two rows, and MFMA step s
+// contracts over m = m0 + 4c + s (the order of the terms of a product is
+// free), so each step's A operand is one of those four values; the B operand
+// g[n - m] comes from a table of g in LDS.  The loads of the next block are
+// in flight while a block's products run.
+// Ram-Lak: every even-distance tap but g[0] is zero.  A tile then holds 16
+// output columns of one parity (n = n0 + 32 q + 2 i + p), which only the
+// inputs of the other parity reach: two of the four steps, half the
+// products.  g[0] x[n] enters through the two steps of the same parity in
+// the two input blocks that cover the tile's columns, i.e. where m reaches
+// n: the sum nearly cancels (the odd taps add up to -g[0]), and adding the
+// large term there rather than last keeps the partial sums smaller (about
+// half the FP32 error of adding it last, in a model of this summation order
+// on projections of the phantoms).
 constexpr int kFiltMaxCols = 1024;
-constexpr int kFiltR = 8;
-constexpr int kFiltGOff = kFiltMaxCols + 2 * kFiltR - 1;        // g[k] at table entry k + kFiltGOff
-constexpr int kFiltGN = 2 * kFiltGOff + 1 + kFiltR;             // table entries
-constexpr int kFiltXW = kFiltMaxCols + kFiltR;                  // row buffer (zero tail)
+constexpr int kFiltGOff = kFiltMaxCols + 16;  // g[k] at table entry k + kFiltGOff
+constexpr int kFiltGN = 2 * kFiltGOff + 8;     // table entries
 
-// Table position of entry e: one spare word after every eight, so the
-// reads of a wave (lane l at 8 l + c for a common c) fall on distinct banks.
-__device__ __forceinline__ int filt_pad(int e) { return e + (e >> 3); }
+typedef float filt_f4 __attribute__((ext_vector_type(4)));
 
-// One wave per detector row; lane l computes outputs n0 .. n0 + 7 with
-// n0 = 8 l (+ 512 for a second pass when the row is longer than 512).  The
-// row, cosine-weighted, sits in LDS; out[n] = scale * sum_m g[n - m] x[m]
-// in 8 x 8 register blocks that share a window of 15 kernel taps, summed in
-// the order of m.  For the Ram-Lak kernel every even tap but g[0] is zero:
-// only the 32 odd-distance pairs of a block and its 8 same-index pairs (the
-// g[0] term when the block is the lane's own, zero otherwise) are formed.
-// The sum nearly cancels (the odd taps add up to -g[0]), so g[0] x[n] is
-// added where m reaches n, not first: that keeps the partial sums of the far
-// taps small and the FP32 error about ten times lower.  Workgroups stride
-// over the rows (four per pass).
 template <typename Q, typename O, int KIND>
 __global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
 {
-    constexpr int R = kFiltR, GOFF = kFiltGOff, GN = kFiltGN, XW = kFiltXW;
-    __shared__ float gtab[GN + GN / 8 + 1];
-    __shared__ __align__(16) float xs[4][XW];
+    constexpr int GOFF = kFiltGOff, GN = kFiltGN;
+    __shared__ float gtab[GN];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int li = lane & 15, lc = lane >> 4;
     const int nu = p.nu;
     for (int e = t; e < GN; e += 256) {
         const int k = e - GOFF, ak = k < 0 ? -k : k;
@@ -64,74 +70,172 @@ __global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
                 g = static_cast<float>(-2.0 / (M_PI * M_PI * (4.0 * dk * dk - 1.0)));
             }
         }
-        gtab[filt_pad(e)] = g;
+        gtab[e] = g;
     }
     const int64_t rows = static_cast<int64_t>(p.batch) * p.n_views * p.nv;
-    float *x = xs[wave];
-    for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * 4; r0 < rows; r0 += static_cast<int64_t>(gridDim.x) * 4) {
-        const int64_t row = r0 + wave;
-        const bool have = row < rows;
-        __syncthreads();  // the table is written; the previous rows are read
-        if (have) {
-            const int r = static_cast<int>(row % p.nv);
-            const int view = static_cast<int>((row / p.nv) % p.n_views);
-            const Q *src = static_cast<const Q *>(p.in) + row * nu;
-            float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, rq = 1.0f;
-            if (!p.parallel) {
-                // ray from the source to pixel (u, r) in world units: s (A (u, r, 1))
-                const ViewTab &tv = p.tab[view];
-                const double rr = static_cast<double>(r);
-                a0 = static_cast<float>(tv.A[0] * p.s[0]);
-                a1 = static_cast<float>(tv.A[3] * p.s[1]);
-                a2 = static_cast<float>(tv.A[6] * p.s[2]);
-                b0 = static_cast<float>((tv.A[1] * rr + tv.A[2]) * p.s[0]);
-                b1 = static_cast<float>((tv.A[4] * rr + tv.A[5]) * p.s[1]);
-                b2 = static_cast<float>((tv.A[7] * rr + tv.A[8]) * p.s[2]);
-                const double q0 = tv.Pi[8] / p.s[0], q1 = tv.Pi[9] / p.s[1], q2 = tv.Pi[10] / p.s[2];
-                rq = static_cast<float>(1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2));
+    const int ncg = (nu + 511) >> 9;
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x / ncg) * 32;
+    const int n0 = static_cast<int>(blockIdx.x % ncg) * 512 + 128 * wave;
+
+    // the lane's two input rows and their cosine weights w(m) = rq / |a m + b|
+    const Q *src[2];
+    bool have[2];
+    float ca[2][3], cb[2][3], rq[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        const int64_t row = row0 + 16 * rb + li;
+        have[rb] = row < rows;
+        const int64_t rr_ = have[rb] ? row : 0;
+        src[rb] = static_cast<const Q *>(p.in) + rr_ * nu;
+        for (int d = 0; d < 3; ++d) ca[rb][d] = cb[rb][d] = 0.0f;
+        rq[rb] = 1.0f;
+        if (!p.parallel) {
+            const int r = static_cast<int>(rr_ % p.nv);
+            const int view = static_cast<int>((rr_ / p.nv) % p.n_views);
+            const ViewTab &tv = p.tab[view];
+            const double rd = static_cast<double>(r);
+            for (int d = 0; d < 3; ++d) {
+                ca[rb][d] = static_cast<float>(tv.A[3 * d] * p.s[d]);
+                cb[rb][d] = static_cast<float>((tv.A[3 * d + 1] * rd + tv.A[3 * d + 2]) * p.s[d]);
             }
-            for (int c = lane; c < XW; c += 64) {
-                float v = 0.0f;
-                if (c < nu) {
-                    v = to_f32(src[c]);
-                    if (!p.parallel) {
-                        const float fc = static_cast<float>(c);
-                        const float d0 = fmaf(fc, a0, b0), d1 = fmaf(fc, a1, b1), d2 = fmaf(fc, a2, b2);
-                        v *= __builtin_amdgcn_rsqf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2))) * rq;
-                    }
-                }
-                x[c] = v;
-            }
-        }
-        __syncthreads();
-        if (!have) continue;
-        O *dst = static_cast<O *>(p.out) + row * nu;
-        for (int n0 = lane * R; n0 < nu; n0 += 64 * R) {
-            float acc[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) acc[j] = 0.0f;
-            for (int m0 = 0; m0 < nu; m0 += R) {
-                const float4 xa = *reinterpret_cast<const float4 *>(x + m0);
-                const float4 xb = *reinterpret_cast<const float4 *>(x + m0 + 4);
-                const float xv[R] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-                // gv[w] = g[n0 - m0 - (R - 1) + w]; the window start is a multiple of 8
-                const int base = GOFF + n0 - m0 - (R - 1);
-                const float *gp = gtab + filt_pad(base);
-                float gv[2 * R - 1];
-#pragma unroll
-                for (int w = 0; w < 2 * R - 1; ++w)
-                    gv[w] = (KIND == 0 && (w & 1) && w != R - 1) ? 0.0f : gp[w + (w >> 3)];
-#pragma unroll
-                for (int i = 0; i < R; ++i)
-#pragma unroll
-                    for (int j = 0; j < R; ++j)
-                        if (KIND != 0 || ((j - i) & 1) || i == j) acc[j] = fmaf(gv[j - i + R - 1], xv[i], acc[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-                if (n0 + j < nu) dst[n0 + j] = from_f32<O>(acc[j] * p.scale);
+            const double q0 = tv.Pi[8] / p.s[0], q1 = tv.Pi[9] / p.s[1], q2 = tv.Pi[10] / p.s[2];
+            rq[rb] = static_cast<float>(1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2));
         }
     }
+    // inputs m0 + 4 lc .. m0 + 4 lc + 3 of both rows: the loads are issued
+    // one block ahead without a branch (an index past the row reads the
+    // row's first input), the cosine weight and the zero past the row or the
+    // last row are applied when the block is used
+    auto fetch = [&](int m0, Q (&raw)[2][4]) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int m = m0 + 4 * lc + s;
+                raw[rb][s] = src[rb][m < nu ? m : 0];
+            }
+    };
+    auto finish = [&](int m0, const Q (&raw)[2][4], float (&xv)[2][4]) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int m = m0 + 4 * lc + s;
+                float v = to_f32(raw[rb][s]);
+                if (!p.parallel) {
+                    const float fm = static_cast<float>(m);
+                    const float d0 = fmaf(fm, ca[rb][0], cb[rb][0]);
+                    const float d1 = fmaf(fm, ca[rb][1], cb[rb][1]);
+                    const float d2 = fmaf(fm, ca[rb][2], cb[rb][2]);
+                    v *= __builtin_amdgcn_rsqf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2))) * rq[rb];
+                }
+                xv[rb][s] = (have[rb] && m < nu) ? v : 0.0f;
+            }
+    };
+
+    filt_f4 acc[2][8];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[rb][c] = filt_f4{0.0f, 0.0f, 0.0f, 0.0f};
+    float xv[2][4];
+    Q raw[2][4], rawc[2][4];
+    if constexpr (KIND == 1) {
+        // B of tile c at step s: g[n0 + 16 c + li - (m0 + 4 lc + s)]
+        fetch(0, raw);
+        __syncthreads();  // the table is written
+        for (int m0 = 0; m0 < nu; m0 += 16) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) rawc[rb][s] = raw[rb][s];
+            if (m0 + 16 < nu) fetch(m0 + 16, raw);  // next block in flight
+            finish(m0, rawc, xv);
+            const float *gb = gtab + (GOFF + n0 + li - 4 * lc - m0 - 3);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const float bv = gb[16 * c + 3 - s];
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+                        acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[rb][s], bv, acc[rb][c], 0, 0, 0);
+                }
+        }
+    } else {
+        fetch(0, raw);
+        __syncthreads();  // the table is written
+        if (n0 >= nu) return;  // no output column (wave-uniform; no barrier follows)
+        // tile c = 2 q + par holds n = n0 + 32 q + 2 li + par; B at step s is
+        // g[n0 + 32 q + 2 li + par - (m0 + 4 lc + s)], odd distances for the
+        // steps of the other parity; DQ >= 0 adds the two same-parity steps of
+        // tiles 2 DQ, 2 DQ + 1 (distance 0 in the block).  The distance-0
+        // blocks are separate code, not a branch around MFMAs inside one loop:
+        // that kept the compiler copying all 64 accumulators every block.
+        auto block_odd = [&](int m0, auto dq) {
+            constexpr int DQ = decltype(dq)::value;
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) rawc[rb][s] = raw[rb][s];
+            fetch(m0 + 16, raw);  // next block in flight
+            finish(m0, rawc, xv);
+            const float *gb = gtab + (GOFF + n0 + 2 * li - 4 * lc - m0 - 3);
+#pragma unroll
+            for (int par = 0; par < 2; ++par)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int s = 2 * h + (1 - par);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float bv = gb[32 * q + par + 3 - s];
+#pragma unroll
+                        for (int rb = 0; rb < 2; ++rb)
+                            acc[rb][2 * q + par] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(xv[rb][s], bv, acc[rb][2 * q + par], 0, 0, 0);
+                    }
+                }
+            if constexpr (DQ >= 0) {
+#pragma unroll
+                for (int par = 0; par < 2; ++par)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int s = 2 * h + par;
+                        const float bv = gb[32 * DQ + par + 3 - s];
+#pragma unroll
+                        for (int rb = 0; rb < 2; ++rb)
+                            acc[rb][2 * DQ + par] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(xv[rb][s], bv, acc[rb][2 * DQ + par], 0, 0, 0);
+                    }
+            }
+        };
+        // one ascending pass: the blocks before the wave's columns, the eight
+        // that reach them at distance 0 (m0 = n0 + 32 q and n0 + 32 q + 16 for
+        // tile pair q; past the row their inputs are zero), then the rest
+        const int mend = (nu + 15) & ~15;
+        for (int m0 = 0; m0 < n0; m0 += 16) block_odd(m0, std::integral_constant<int, -1>{});
+        block_odd(n0, std::integral_constant<int, 0>{});
+        block_odd(n0 + 16, std::integral_constant<int, 0>{});
+        block_odd(n0 + 32, std::integral_constant<int, 1>{});
+        block_odd(n0 + 48, std::integral_constant<int, 1>{});
+        block_odd(n0 + 64, std::integral_constant<int, 2>{});
+        block_odd(n0 + 80, std::integral_constant<int, 2>{});
+        block_odd(n0 + 96, std::integral_constant<int, 3>{});
+        block_odd(n0 + 112, std::integral_constant<int, 3>{});
+        for (int m0 = n0 + 128; m0 < mend; m0 += 16) block_odd(m0, std::integral_constant<int, -1>{});
+    }
+    O *dst = static_cast<O *>(p.out);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int n = KIND == 1 ? n0 + 16 * c + li : n0 + 32 * (c >> 1) + 2 * li + (c & 1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + 16 * rb + 4 * lc + r;
+                if (row < rows && n < nu) dst[row * nu + n] = from_f32<O>(acc[rb][c][r] * p.scale);
+            }
+        }
 }
 
 template <typename Q, int KIND>
@@ -160,9 +264,11 @@ int32_t filter_max_cols() { return kFiltMaxCols; }
 hipError_t launch_filter(const FiltParams &p, int32_t in_dt, int32_t out_dt, hipStream_t st)
 {
     const int64_t rows = static_cast<int64_t>(p.batch) * p.n_views * p.nv;
-    // six workgroups fit a CU (26 KB of LDS each); the rest stride
-    const int64_t blocks = std::min<int64_t>((rows + 3) / 4, 256 * 6);
-    if (blocks == 0) return hipSuccess;
+    if (rows == 0 || p.nu <= 0) return hipSuccess;
+    if (p.nu > kFiltMaxCols) return hipErrorInvalidValue;
+    // matrix cores: 32 rows x 512 columns per workgroup
+    const int64_t blocks = (rows + 31) / 32 * ((p.nu + 511) / 512);
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
     return p.kind == 0 ? filter_k<0>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st)
                        : filter_k<1>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st);
 }

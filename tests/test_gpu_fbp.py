@@ -114,6 +114,29 @@ def test_filter_parallel_matches_direct_convolution(pn):
     assert rel(q, O.fbp_filter(p, go, 1.0, "shepp-logan")) <= TOL32
 
 
+@pytest.mark.parametrize("kind", ["ram-lak", "shepp-logan"])
+@pytest.mark.parametrize("nu", [16, 33, 128, 129, 511, 512, 513, 1000])
+def test_filter_tile_edges_random_rows(pn, kind, nu):
+    """Rows of white noise (no smoothness to hide a wrong tap) against the
+    textbook linear convolution in FP64, for widths around the kernel's
+    16-column blocks and 128-column wave tiles, across two 512-column
+    workgroups, and 37 rows (a partial 32-row workgroup)."""
+    views = 37
+    gp = pn.parallel_geometry((8, 8), (1.0, 1.0), nu, 1.0, views)
+    rng = np.random.default_rng(nu)
+    p = rng.standard_normal((views, 1, nu)).astype(np.float32).astype(np.float64)
+    q = cpu(pn.fbp_filter(gpu(p), gp, kind))
+    k = np.arange(-nu + 1, nu)
+    ak = np.abs(k).astype(np.float64)
+    if kind == "ram-lak":
+        g = np.where(ak == 0, 0.25, np.where(ak % 2 == 1, -1.0 / (math.pi ** 2 * np.maximum(ak, 1) ** 2), 0.0))
+    else:
+        g = -2.0 / (math.pi ** 2 * (4.0 * ak * ak - 1.0))
+    G = g[(np.arange(nu)[:, None] - np.arange(nu)[None, :]) + nu - 1]   # G[n][m] = g[n - m]
+    ref = (p[:, 0, :] @ G.T * (math.pi / views))[:, None, :]
+    assert rel(q, ref) <= TOL32, (kind, nu, rel(q, ref))
+
+
 def test_filter_edge_cases(pn):
     gp = pn.parallel_geometry((16, 16), (1.0, 1.0), 9, 1.0, 5)
     # empty batch, one column, the column limit
