@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <type_traits>
+#include <utility>
 
 #include "pn_common.hpp"
 #include "pn_device.hpp"
@@ -25,9 +26,10 @@ namespace pn {
 // G^T with Xw the cosine-weighted rows (rows x nu) and G[n][m] = g[n - m]
 // (nu x nu): a dense contraction of 2 rows nu^2 flops, run on the matrix
 // cores as v_mfma_f32_16x16x4_f32 (FP32 operands and accumulators).  A
-// workgroup owns 32 rows and up to 512 output columns; each of its four
-// waves 32 rows x 128 columns as 2 x 8 tiles of 16 x 16 (64 accumulators per
-// lane).  MFMA operand layout (lane l, i = l % 16, c = l / 16): A[i][c],
+// workgroup owns 64 rows and up to 512 output columns; each of its four
+// waves 32 rows x 256 columns as 2 x 16 tiles of 16 x 16 (128 accumulators
+// per lane: a block of inputs feeds 128 products, which hides the loads and
+// the cosine weights; 128 columns per wave measured 0.93 against 0.86 ms).  MFMA operand layout (lane l, i = l % 16, c = l / 16): A[i][c],
 // B[c][i]; the result D[4c + r][i] in register r.  The contraction runs over
 // the row's inputs in blocks of 16: a lane loads the 4 consecutive inputs
 // x[m0 + 4c .. m0 + 4c + 3] of each of its two rows, and MFMA step s
@@ -50,8 +52,19 @@ constexpr int kFiltGN = 2 * kFiltGOff + 8;     // table entries
 
 typedef float filt_f4 __attribute__((ext_vector_type(4)));
 
+// Calls block(n0 + 16 i, i / 2) for i = 0 .. sizeof...(I) - 1, the tile
+// pair as a compile-time constant.
+template <typename B, int... I>
+__device__ __forceinline__ void diag_blocks_at(B &block, int n0, std::integer_sequence<int, I...>)
+{
+    (block(n0 + 16 * I, std::integral_constant<int, I / 2>{}), ...);
+}
+
+// At least two waves per SIMD: the waves' 128 accumulators then live in
+// VGPRs (no AGPR copies) instead of 332 registers at one wave per SIMD
+// (Ram-Lak 0.56 against 0.67 ms on cone 256^3 x 360).
 template <typename Q, typename O, int KIND>
-__global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
+__global__ __launch_bounds__(256, 2) void filter_kernel(FiltParams p)
 {
     constexpr int GOFF = kFiltGOff, GN = kFiltGN;
     __shared__ float gtab[GN];
@@ -74,8 +87,12 @@ __global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
     }
     const int64_t rows = static_cast<int64_t>(p.batch) * p.n_views * p.nv;
     const int ncg = (nu + 511) >> 9;
-    const int64_t row0 = static_cast<int64_t>(blockIdx.x / ncg) * 32;
-    const int n0 = static_cast<int>(blockIdx.x % ncg) * 512 + 128 * wave;
+    // 64 rows x 512 columns per workgroup: two waves of 256 columns per 32
+    // rows (16 tiles of 16 x 16 per row block, 128 accumulators per lane)
+    constexpr int NT = 16;        // tiles per row block of a wave
+    constexpr int WROWS = 64;     // rows per workgroup
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x / ncg) * WROWS + 32 * (wave >> 1);
+    const int n0 = static_cast<int>(blockIdx.x % ncg) * 512 + 256 * (wave & 1);
 
     // the lane's two input rows and their cosine weights w(m) = rq / |a m + b|
     const Q *src[2];
@@ -133,11 +150,11 @@ __global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
             }
     };
 
-    filt_f4 acc[2][8];
+    filt_f4 acc[2][NT];
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[rb][c] = filt_f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int c = 0; c < NT; ++c) acc[rb][c] = filt_f4{0.0f, 0.0f, 0.0f, 0.0f};
     float xv[2][4];
     Q raw[2][4], rawc[2][4];
     if constexpr (KIND == 1) {
@@ -155,7 +172,7 @@ __global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
+                for (int c = 0; c < NT; ++c) {
                     const float bv = gb[16 * c + 3 - s];
 #pragma unroll
                     for (int rb = 0; rb < 2; ++rb)
@@ -171,7 +188,7 @@ __global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
         // steps of the other parity; DQ >= 0 adds the two same-parity steps of
         // tiles 2 DQ, 2 DQ + 1 (distance 0 in the block).  The distance-0
         // blocks are separate code, not a branch around MFMAs inside one loop:
-        // that kept the compiler copying all 64 accumulators every block.
+        // that kept the compiler copying all the accumulators every block.
         auto block_odd = [&](int m0, auto dq) {
             constexpr int DQ = decltype(dq)::value;
 #pragma unroll
@@ -187,7 +204,7 @@ __global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
                 for (int h = 0; h < 2; ++h) {
                     const int s = 2 * h + (1 - par);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
+                    for (int q = 0; q < NT / 2; ++q) {
                         const float bv = gb[32 * q + par + 3 - s];
 #pragma unroll
                         for (int rb = 0; rb < 2; ++rb)
@@ -209,26 +226,20 @@ __global__ __launch_bounds__(256) void filter_kernel(FiltParams p)
                     }
             }
         };
-        // one ascending pass: the blocks before the wave's columns, the eight
-        // that reach them at distance 0 (m0 = n0 + 32 q and n0 + 32 q + 16 for
-        // tile pair q; past the row their inputs are zero), then the rest
+        // one ascending pass: the blocks before the wave's columns, the
+        // sixteen that reach them at distance 0 (m0 = n0 + 32 q and
+        // n0 + 32 q + 16 for tile pair q; past the row their inputs are zero),
+        // then the rest
         const int mend = (nu + 15) & ~15;
         for (int m0 = 0; m0 < n0; m0 += 16) block_odd(m0, std::integral_constant<int, -1>{});
-        block_odd(n0, std::integral_constant<int, 0>{});
-        block_odd(n0 + 16, std::integral_constant<int, 0>{});
-        block_odd(n0 + 32, std::integral_constant<int, 1>{});
-        block_odd(n0 + 48, std::integral_constant<int, 1>{});
-        block_odd(n0 + 64, std::integral_constant<int, 2>{});
-        block_odd(n0 + 80, std::integral_constant<int, 2>{});
-        block_odd(n0 + 96, std::integral_constant<int, 3>{});
-        block_odd(n0 + 112, std::integral_constant<int, 3>{});
-        for (int m0 = n0 + 128; m0 < mend; m0 += 16) block_odd(m0, std::integral_constant<int, -1>{});
+        diag_blocks_at(block_odd, n0, std::make_integer_sequence<int, NT>{});
+        for (int m0 = n0 + 16 * NT; m0 < mend; m0 += 16) block_odd(m0, std::integral_constant<int, -1>{});
     }
     O *dst = static_cast<O *>(p.out);
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int c = 0; c < NT; ++c) {
             const int n = KIND == 1 ? n0 + 16 * c + li : n0 + 32 * (c >> 1) + 2 * li + (c & 1);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -267,7 +278,7 @@ hipError_t launch_filter(const FiltParams &p, int32_t in_dt, int32_t out_dt, hip
     if (rows == 0 || p.nu <= 0) return hipSuccess;
     if (p.nu > kFiltMaxCols) return hipErrorInvalidValue;
     // matrix cores: 32 rows x 512 columns per workgroup
-    const int64_t blocks = (rows + 31) / 32 * ((p.nu + 511) / 512);
+    const int64_t blocks = (rows + 63) / 64 * ((p.nu + 511) / 512);
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     return p.kind == 0 ? filter_k<0>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st)
                        : filter_k<1>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st);
