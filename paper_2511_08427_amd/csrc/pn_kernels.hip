@@ -1557,6 +1557,23 @@ __global__ __launch_bounds__(256, 8) void backproject_table_kernel(Table<BpParam
 
 // ------------------------------------------------------ splat (BP^T) ----
 
+// Two 32-bit fixed-point cells in one 64-bit LDS word, added with one
+// ds_add_u64: the word holds lo + 2^32 hi as a signed 64-bit integer, so a
+// sum of such words is (sum lo) + 2^32 (sum hi) exactly; while both sums
+// stay inside (-2^31, 2^31) the halves are recovered as the low word read as
+// signed and the rest shifted down.
+__device__ __forceinline__ unsigned long long pair_word(int lo, int hi)
+{
+    return (static_cast<unsigned long long>(static_cast<uint32_t>(hi + (lo >> 31))) << 32) |
+           static_cast<uint32_t>(lo);
+}
+__device__ __forceinline__ int lo_half(unsigned long long w) { return static_cast<int>(static_cast<uint32_t>(w)); }
+__device__ __forceinline__ int hi_half(unsigned long long w)
+{
+    const long long sw = static_cast<long long>(w);
+    return static_cast<int>((sw - lo_half(w)) >> 32);
+}
+
 // Transpose of the voxel-driven back-projection: every voxel's value times
 // the distance weight (W0/W)^2 is spread over the bilinear taps of its
 // projection in each view; taps off the detector are dropped.  A workgroup
@@ -1572,8 +1589,12 @@ __global__ __launch_bounds__(256, 8) void backproject_table_kernel(Table<BpParam
 // rectangle is independent of the order of the deposits.  The rectangle is
 // then added to the FP32 sinogram with one hardware float atomic per non-zero
 // pixel, which a pixel receives from every block along its ray: the result
-// is not bitwise reproducible (the order of those adds varies).  Two LDS
-// rectangles alternate between views, one barrier per view.  Rectangles
+// is not bitwise reproducible (the order of those adds varies).  The cells
+// of rows r and r + 1 of a column share one 64-bit word (pair_word), so a
+// deposit is two ds_add_u64 instead of four ds_add_u32, and a cell is the
+// low half of its word plus the high half of the word above.  Three LDS
+// rectangles rotate between views, one barrier per view: a view's rectangle
+// is flushed after its barrier and cleared after the next one.  Rectangles
 // larger than RCAP x CCAP, and blocks holding a non-finite value, deposit
 // straight into the sinogram with one float atomic per tap.
 template <typename S, int BZ, int RCAP, int CCAP>
@@ -1582,7 +1603,7 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
     constexpr int BX = 16, BY = 16, CHUNK = 256;
     constexpr int NE = RCAP * CCAP;
     constexpr int PER = (NE + 255) / 256;
-    __shared__ int s_acc[2][NE];
+    __shared__ unsigned long long s_acc[3][NE];
     __shared__ int4 s_rect[CHUNK];
     __shared__ float s_scale[CHUNK];
     __shared__ uint32_t s_max[4];
@@ -1633,7 +1654,7 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
         s_max[t >> 6] = mbits;
         s_sum[t >> 6] = asum;
     }
-    for (int e = t; e < 2 * NE; e += 256) s_acc[e / NE][e % NE] = 0;
+    for (int e = t; e < 3 * NE; e += 256) s_acc[e / NE][e % NE] = 0ull;
     __syncthreads();
     mbits = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
     if (mbits == 0u) return;                       // nothing to deposit (uniform)
@@ -1683,9 +1704,19 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
         return make_int4(__builtin_amdgcn_readfirstlane(r.x), __builtin_amdgcn_readfirstlane(r.y),
                          __builtin_amdgcn_readfirstlane(r.z), __builtin_amdgcn_readfirstlane(r.w));
     };
-    // deposits the rectangle of view `view` (buffer buf) into the sinogram
-    // and clears it
-    auto flush = [&](int view, const int4 &rc, float inv, int buf) {
+    // deposits the rectangle of view `view` (buffer buf) into the sinogram:
+    // cell (r, c) is the low half of word (r, c) plus the high half of word
+    // (r - 1, c).  The words read one view earlier (buffer pbuf, if that view
+    // used the LDS) are cleared now: every thread has read them (barrier
+    // since), and that buffer is next written two views later.
+    auto flush = [&](int view, const int4 &rc, float inv, int buf, bool plds, int pbuf) {
+        if (plds) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int e = t + 256 * q;
+                if (e < NE) s_acc[pbuf][e] = 0ull;
+            }
+        }
         if ((rc.w & 3) != 3) return;
         const int nc = rc.z & 0xffff, nr = rc.z >> 16;
         float *img = sino + static_cast<int64_t>(view) * p.nv * p.nu;
@@ -1693,10 +1724,10 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
         for (int q = 0; q < PER; ++q) {
             const int e = t + 256 * q;
             if (e >= NE) break;
-            const int v = s_acc[buf][e];
-            if (v == 0) continue;
-            s_acc[buf][e] = 0;
             const int rr = e / CCAP, cc = e - rr * CCAP;
+            int v = lo_half(s_acc[buf][e]);
+            if (rr > 0) v += hi_half(s_acc[buf][e - CCAP]);
+            if (v == 0) continue;
             const int r = rc.y + rr, c = rc.x + cc;
             if (rr < nr && cc < nc && static_cast<uint32_t>(r) < static_cast<uint32_t>(p.nv) &&
                 static_cast<uint32_t>(c) < static_cast<uint32_t>(p.nu))
@@ -1704,6 +1735,7 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
         }
     };
 
+    bool plds = false;  // the previous view deposited into the LDS
     for (int c0 = 0; c0 < p.n_views; c0 += CHUNK) {
         const int cn = min(CHUNK, p.n_views - c0);
         __syncthreads();  // the previous chunk's table is no longer read
@@ -1714,7 +1746,7 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
         }
         __syncthreads();
         for (int vi = 0; vi < cn; ++vi) {
-            const int view = c0 + vi, buf = view & 1;
+            const int view = c0 + vi, buf = view % 3;
             const int4 now = rect_at(vi);
             const float scale = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(s_scale[vi])));
             if (own && (now.w & 1)) {
@@ -1745,7 +1777,7 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
                     const float hv = fminf(fnv - vo, static_cast<float>(nr - 1) - 1e-3f);
                     const float lu = fmaxf(-1.0f - uo, 0.0f), lv = fmaxf(-1.0f - vo, 0.0f);
                     const float wsc = W0 * W0 * scale;
-                    int *acc = s_acc[buf];
+                    unsigned long long *acc = s_acc[buf];
                     if (BZ > 1 && pi[2] == 0.0f && pi[10] == 0.0f) {
                         // column path, the back-projection's: u and W fixed,
                         // v linear in the height
@@ -1754,7 +1786,7 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
                         const float rw = __builtin_amdgcn_rcpf(Wc);
                         const float u = __builtin_amdgcn_fmed3f(fmaf(Uc, rw, -uo), lu, hu);
                         const float wu = __builtin_amdgcn_fractf(u);
-                        int *col = acc + static_cast<int>(u);
+                        const int cu = static_cast<int>(u);
                         const float dv = pi[6] * rw, v0 = fmaf(V0, rw, -vo);
                         const float dvb = dv * static_cast<float>(BZ);
                         const float w2 = rw * rw * wsc;
@@ -1766,11 +1798,9 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
                             const float qs = x[z] * w2;
                             const float t1 = qs * wv, t0 = qs - t1;
                             const float c01 = t0 * wu, c11 = t1 * wu;
-                            int *q = col + __mul24(static_cast<int>(v), CCAP);
-                            atomicAdd(q, round_fixed(t0 - c01));
-                            atomicAdd(q + 1, round_fixed(c01));
-                            atomicAdd(q + CCAP, round_fixed(t1 - c11));
-                            atomicAdd(q + CCAP + 1, round_fixed(c11));
+                            unsigned long long *q = acc + (__mul24(static_cast<int>(v), CCAP) + cu);
+                            atomicAdd(q, pair_word(round_fixed(t0 - c01), round_fixed(t1 - c11)));
+                            atomicAdd(q + 1, pair_word(round_fixed(c01), round_fixed(c11)));
                         }
                     } else {
                         const float p2 = pi[2] * static_cast<float>(BZ), p6 = pi[6] * static_cast<float>(BZ);
@@ -1786,11 +1816,9 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
                             const float qs = x[z] * (rw * rw * wsc);
                             const float t1 = qs * wv, t0 = qs - t1;
                             const float c01 = t0 * wu, c11 = t1 * wu;
-                            int *q = acc + __mul24(static_cast<int>(v), CCAP) + static_cast<int>(u);
-                            atomicAdd(q, round_fixed(t0 - c01));
-                            atomicAdd(q + 1, round_fixed(c01));
-                            atomicAdd(q + CCAP, round_fixed(t1 - c11));
-                            atomicAdd(q + CCAP + 1, round_fixed(c11));
+                            unsigned long long *q = acc + (__mul24(static_cast<int>(v), CCAP) + static_cast<int>(u));
+                            atomicAdd(q, pair_word(round_fixed(t0 - c01), round_fixed(t1 - c11)));
+                            atomicAdd(q + 1, pair_word(round_fixed(c01), round_fixed(c11)));
                         }
                     }
                 } else {
@@ -1824,9 +1852,10 @@ __device__ __forceinline__ void splat_block(const SplatParams &p, const int bid)
                 }
             }
             __syncthreads();  // this view's deposits are complete
-            // flush this view's rectangle now; the next view deposits into the
-            // other buffer, flushed and cleared one view ago
-            flush(view, now, 1.0f / scale, buf);
+            // flush this view's rectangle now and clear the previous view's;
+            // the next view deposits into the third buffer
+            flush(view, now, 1.0f / scale, buf, plds, (view + 2) % 3);
+            plds = (now.w & 3) == 3;
         }
     }
 }
@@ -2182,11 +2211,10 @@ hipError_t launch_backproject_table(const Table<BpParams> &w, uint32_t blocks, b
     return bp_any(w, two_d, blocks, in_dt, out_dt, st);
 }
 
-// The splat's rectangles: the back-projection's rows, an odd row stride of
-// 27 columns (27 x 4 bytes) so that the deposits of a wave, a few rows
-// apart, fall into different LDS banks (24 columns: 1.5x the time on cone
-// 256^3 x 360).
-constexpr int kSplatCols = 27;
+// The splat's rectangles: the back-projection's rows and an odd row stride
+// of 25 words, so that the deposits of a wave, a few rows apart, fall into
+// different LDS banks (measured on cone 256^3 x 360 over strides 24-37).
+constexpr int kSplatCols = 25;
 
 int64_t splat_blocks(const SplatParams &p)
 {

@@ -119,13 +119,15 @@ def test_filter_parallel_matches_direct_convolution(pn):
 def test_filter_tile_edges_random_rows(pn, kind, nu):
     """Rows of white noise (no smoothness to hide a wrong tap) against the
     textbook linear convolution in FP64, for widths around the kernel's
-    16-column blocks and 128-column wave tiles, across two 512-column
-    workgroups, and 37 rows (a partial 32-row workgroup)."""
+    16-column blocks and 256-column wave tiles, across two 512-column
+    workgroups, and a batch of 2 x 37 rows (partial 64-row workgroups)."""
     views = 37
     gp = pn.parallel_geometry((8, 8), (1.0, 1.0), nu, 1.0, views)
     rng = np.random.default_rng(nu)
-    p = rng.standard_normal((views, 1, nu)).astype(np.float32).astype(np.float64)
-    q = cpu(pn.fbp_filter(gpu(p), gp, kind))
+    pb = rng.standard_normal((2, views, 1, nu)).astype(np.float32).astype(np.float64)
+    qb = cpu(pn.fbp_filter(gpu(pb), gp, kind))
+    assert rel(qb[1], cpu(pn.fbp_filter(gpu(pb[1]), gp, kind))) == 0.0  # batch items are independent rows
+    p, q = pb[0], qb[0]
     k = np.arange(-nu + 1, nu)
     ak = np.abs(k).astype(np.float64)
     if kind == "ram-lak":
