@@ -294,8 +294,9 @@ def main():
     bpv = pn.backproject(y, geom)
     t_splat, _ = timed(lambda: pn.splat(bpv, geom), reps, stream)
     log(f"splat (BP transpose) {t_splat:.3f} ms")
-    # FDK: the row filter (a direct linear convolution, nu^2 multiply-adds
-    # per detector row) followed by the back-projection
+    # FDK: the row filter (a linear convolution, nu^2 multiply-adds per
+    # detector row, as a Toeplitz product on the matrix cores) followed by
+    # the back-projection
     t_filt, _ = timed(lambda: pn.fbp_filter(y, geom), reps, stream)
     t_filt_sl, _ = timed(lambda: pn.fbp_filter(y, geom, "shepp-logan"), reps, stream)
     t_fdk, _ = timed(lambda: pn.fbp(y, geom), reps, stream)

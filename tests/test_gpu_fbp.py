@@ -3,7 +3,8 @@ against the FP64 oracle.
 
 The filter is a linear convolution of each cosine-weighted detector row with
 the discrete Ram-Lak or Shepp-Logan kernel, scaled by pi / N / a.  The
-kernel computes it directly in FP32 (nu multiply-adds per output with
+kernel computes it as a Toeplitz product on the matrix cores, FP32
+operands and accumulators (nu multiply-adds per output with
 |g[k]| <= 1/4 and sum_k |g[k]| < 1), so the expected FP32 rounding error of
 an output is ~sqrt(nu) * 6e-8 * ||row||; the bar is relative L2 <= 1e-5 on
 the whole filtered sinogram, as for the projectors.
