@@ -63,7 +63,10 @@ __device__ __forceinline__ void diag_blocks_at(B &block, int n0, std::integer_se
 // At least two waves per SIMD: the waves' 128 accumulators then live in
 // VGPRs (no AGPR copies) instead of 332 registers at one wave per SIMD
 // (Ram-Lak 0.56 against 0.67 ms on cone 256^3 x 360).
-template <typename Q, typename O, int KIND>
+// TRIM: a wave whose 256 columns lie past the row returns at once (the full
+// kernel is instantiated without it for rows whose last 512-column group has
+// work for both waves: the early exit cost 2-4% there).
+template <typename Q, typename O, int KIND, bool TRIM>
 __global__ __launch_bounds__(256, 2) void filter_kernel(FiltParams p)
 {
     constexpr int GOFF = kFiltGOff, GN = kFiltGN;
@@ -161,6 +164,8 @@ __global__ __launch_bounds__(256, 2) void filter_kernel(FiltParams p)
         // B of tile c at step s: g[n0 + 16 c + li - (m0 + 4 lc + s)]
         fetch(0, raw);
         __syncthreads();  // the table is written
+        if constexpr (TRIM)
+            if (n0 >= nu) return;  // no output column (wave-uniform; no barrier follows)
         for (int m0 = 0; m0 < nu; m0 += 16) {
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb)
@@ -249,24 +254,24 @@ __global__ __launch_bounds__(256, 2) void filter_kernel(FiltParams p)
         }
 }
 
-template <typename Q, int KIND>
+template <typename Q, int KIND, bool TRIM>
 static hipError_t filter_q(const FiltParams &p, uint32_t blocks, int32_t out_dt, hipStream_t st)
 {
     switch (out_dt) {
-    case DT_F32: filter_kernel<Q, float, KIND><<<dim3(blocks), 256, 0, st>>>(p); break;
-    case DT_BF16: filter_kernel<Q, bf16, KIND><<<dim3(blocks), 256, 0, st>>>(p); break;
-    default: filter_kernel<Q, f16, KIND><<<dim3(blocks), 256, 0, st>>>(p); break;
+    case DT_F32: filter_kernel<Q, float, KIND, TRIM><<<dim3(blocks), 256, 0, st>>>(p); break;
+    case DT_BF16: filter_kernel<Q, bf16, KIND, TRIM><<<dim3(blocks), 256, 0, st>>>(p); break;
+    default: filter_kernel<Q, f16, KIND, TRIM><<<dim3(blocks), 256, 0, st>>>(p); break;
     }
     return hipGetLastError();
 }
 
-template <int KIND>
+template <int KIND, bool TRIM>
 static hipError_t filter_k(const FiltParams &p, uint32_t blocks, int32_t in_dt, int32_t out_dt, hipStream_t st)
 {
     switch (in_dt) {
-    case DT_F32: return filter_q<float, KIND>(p, blocks, out_dt, st);
-    case DT_BF16: return filter_q<bf16, KIND>(p, blocks, out_dt, st);
-    default: return filter_q<f16, KIND>(p, blocks, out_dt, st);
+    case DT_F32: return filter_q<float, KIND, TRIM>(p, blocks, out_dt, st);
+    case DT_BF16: return filter_q<bf16, KIND, TRIM>(p, blocks, out_dt, st);
+    default: return filter_q<f16, KIND, TRIM>(p, blocks, out_dt, st);
     }
 }
 
@@ -280,8 +285,11 @@ hipError_t launch_filter(const FiltParams &p, int32_t in_dt, int32_t out_dt, hip
     // matrix cores: 32 rows x 512 columns per workgroup
     const int64_t blocks = (rows + 63) / 64 * ((p.nu + 511) / 512);
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
-    return p.kind == 0 ? filter_k<0>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st)
-                       : filter_k<1>(p, static_cast<uint32_t>(blocks), in_dt, out_dt, st);
+    const uint32_t nb = static_cast<uint32_t>(blocks);
+    if (p.kind == 0) return filter_k<0, true>(p, nb, in_dt, out_dt, st);
+    // the last column group's second wave (columns 256..511 of the group) idle?
+    const bool trim = (p.nu - 1) % 512 < 256;
+    return trim ? filter_k<1, true>(p, nb, in_dt, out_dt, st) : filter_k<1, false>(p, nb, in_dt, out_dt, st);
 }
 
 // ------------------------------------------------ artifact simulation -----
